@@ -1,0 +1,116 @@
+"""Exact periodic r^-6 dispersion energy and forces (TEST INFRASTRUCTURE ONLY).
+
+The quantity MLS approximates (Sec. II.A.1, eq:pot-vec-mat-vec with
+G_ij = r_ij^-6 and G_ii = 0, summed over periodic images):
+
+    E* = -1/2 sum_i sum_{(j,n) != (i,0)} xi_i xi_j |x_i - x_j - n o L|^-6,
+    xi_i = sqrt(C6_i),   F*_i = -dE*/dx_i.
+
+Two independent evaluations are provided: ``exact_ewald`` (Gaussian-screened
+split, exponentially convergent; see ``lattice``) and ``exact_direct`` (plain
+image summation inside a sphere plus a continuum tail; tiny systems only).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .lattice import ewald_fhat
+
+__all__ = ["exact_ewald", "exact_direct"]
+
+
+def exact_ewald(pos, c6, box, beta=None, tol=1e-16, chunk=2048):
+    """E*, F*, and the per-atom potential u*_i = sum' xi_j r^-6 by Ewald."""
+    pos = np.asarray(pos, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    xi = np.sqrt(np.asarray(c6, dtype=np.float64))
+    n = len(pos)
+    V = float(np.prod(box))
+    if beta is None:
+        beta = 3.0 / float(np.min(box))
+    # ---- real space
+    rc = math.sqrt(-math.log(tol)) / beta
+    nr = np.ceil(rc / box).astype(int) + 1
+    u = np.zeros(n)
+    F = np.zeros((n, 3))
+    for i0 in range(0, n, chunk):
+        i1 = min(n, i0 + chunk)
+        for nx in range(-nr[0], nr[0] + 1):
+            for ny in range(-nr[1], nr[1] + 1):
+                for nz in range(-nr[2], nr[2] + 1):
+                    s = np.array([nx, ny, nz]) * box
+                    d = pos[i0:i1, None, :] - pos[None, :, :] - s   # (ci, n, 3)
+                    r2 = np.sum(d * d, axis=2)
+                    if nx == 0 and ny == 0 and nz == 0:
+                        ar = np.arange(i0, i1)
+                        r2[ar - i0, ar] = np.inf
+                    m = r2 < rc * rc
+                    if not m.any():
+                        continue
+                    r2m = np.where(m, r2, 1.0)
+                    x = beta * beta * r2m
+                    ex = np.exp(-x)
+                    phi = np.where(m, ex * (1.0 + x + 0.5 * x * x) / r2m ** 3, 0.0)
+                    r = np.sqrt(r2m)
+                    dphi = np.where(m, -6.0 * ex * (1.0 + x + 0.5 * x * x) / r ** 7
+                                    - beta ** 6 * ex / r, 0.0)
+                    u[i0:i1] += phi @ xi
+                    coef = dphi / r * xi[None, :]
+                    F[i0:i1] += xi[i0:i1, None] * np.einsum("ij,ijk->ik", coef, d)
+    # ---- reciprocal space
+    kc = 2.0 * beta * math.sqrt(-math.log(tol))
+    nk = np.ceil(kc * box / (2.0 * math.pi)).astype(int)
+    mx, my, mz = (np.arange(-m, m + 1) for m in nk)
+    MX, MY, MZ = np.meshgrid(mx, my, mz, indexing="ij")
+    kvec = 2.0 * math.pi * np.stack([MX.ravel(), MY.ravel(), MZ.ravel()], axis=1) / box
+    kn = np.sqrt(np.sum(kvec * kvec, axis=1))
+    fh = ewald_fhat(kn, beta)
+    keep = fh > tol * fh.max()
+    kvec, fh = kvec[keep], fh[keep]
+    for k0 in range(0, len(kvec), 512):
+        kv = kvec[k0:k0 + 512]
+        f = fh[k0:k0 + 512]
+        ph = pos @ kv.T                                # (n, K)
+        c, s = np.cos(ph), np.sin(ph)
+        Sc = xi @ c                                    # Re S(k)
+        Ss = xi @ s                                    # Im S(k)
+        # u_i gets (1/V) sum_k fhat Re(e^{-ik x_i} S(k))
+        u += (c * Sc + s * Ss) @ f / V
+        # F_i = -(xi_i / V) sum_k fhat k sum_j xi_j sin(k.(x_i - x_j))
+        sinterm = s * Sc - c * Ss                       # sum_j xi_j sin(k.(x_i-x_j))
+        F -= xi[:, None] * ((sinterm * f) @ kv) / V
+    # remove the r = 0 term of the smooth part
+    u -= beta ** 6 / 6.0 * xi
+    E = -0.5 * float(np.dot(xi, u))
+    return E, F, u
+
+
+def exact_direct(pos, c6, box, R):
+    """E* and F* by direct image summation to radius R (+ energy tail)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    xi = np.sqrt(np.asarray(c6, dtype=np.float64))
+    n = len(pos)
+    V = float(np.prod(box))
+    nr = np.ceil(R / box).astype(int) + 1
+    u = np.zeros(n)
+    F = np.zeros((n, 3))
+    for nx in range(-nr[0], nr[0] + 1):
+        for ny in range(-nr[1], nr[1] + 1):
+            for nz in range(-nr[2], nr[2] + 1):
+                s = np.array([nx, ny, nz]) * box
+                d = pos[:, None, :] - pos[None, :, :] - s
+                r2 = np.sum(d * d, axis=2)
+                if nx == 0 and ny == 0 and nz == 0:
+                    np.fill_diagonal(r2, np.inf)
+                m = r2 <= R * R
+                r2m = np.where(m, r2, 1.0)
+                phi = np.where(m, r2m ** -3, 0.0)
+                u += phi @ xi
+                coef = np.where(m, -6.0 * r2m ** -4, 0.0) * xi[None, :]
+                F += xi[:, None] * np.einsum("ij,ijk->ik", coef, d)
+    u += 4.0 * math.pi / (3.0 * V * R ** 3) * np.sum(xi)
+    E = -0.5 * float(np.dot(xi, u))
+    return E, F, u
