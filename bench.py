@@ -1,0 +1,241 @@
+#!/usr/bin/env python
+"""Benchmark: MLS r^-6 energy-and-force evaluations per second on one MI355X.
+
+One step = one full evaluation (binning, local pair sum, anterpolation,
+restrictions, level stencils, coarsest all-to-all, prolongations,
+interpolation, energy) of the 1,000,000-atom homogeneous LJ cube at density
+0.8 (a = 3, h = 1 -> 112^3 finest grid, cubic basis, 5 levels), inputs
+resident in HBM.  Both precisions are timed; ``value`` is the FP32-mixed
+rate, with the FP64 rate, their ratio and the accuracy of each beside it.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32": 157.3}   # GB/s, TFLOP/s (MI355X published)
+PAIR_FLOPS = 39        # flops of one ordered in-cutoff pair in the pair kernel's formula
+STENCIL_FLOPS = 2      # one multiply-add per tap and grid point
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def count_pairs(pos, box, a):
+    """Ordered pairs (i != j) closer than a (minimum image; a < L/2)."""
+    from scipy.spatial import cKDTree
+    import numpy as np
+    t = cKDTree(np.mod(pos, box), boxsize=box)
+    return int(t.count_neighbors(t, a)) - len(pos)
+
+
+def work_model(plan_info, n, pairs, order):
+    """Algorithmic work per evaluation for each stage (flops or bytes)."""
+    g = plan_info["grid"]
+    l = plan_info["levels"]
+    pts = [(g[0] >> k) * (g[1] >> k) * (g[2] >> k) for k in range(l)]
+    sum_lt = sum(pts[:-1])
+    p3 = order ** 3
+    return {
+        "pair": dict(bound="alu", flops=PAIR_FLOPS * pairs),
+        "stencil": dict(bound="alu", flops=STENCIL_FLOPS * plan_info["taps"] * sum_lt),
+        # read sorted x,y,z,xi (32 B) per atom, p^3 grid updates (8 B read + 8 B write)
+        "anterpolation": dict(bound="hbm", bytes=32 * n + 16 * min(p3 * n, pts[0])),
+        # read atoms + E^1 once, write F (24), u, dE/dc6 (8+8), read e0/floc (32)
+        "interpolation": dict(bound="hbm", bytes=32 * n + 8 * pts[0] + 40 * n + 32 * n),
+        "restriction": dict(bound="hbm", bytes=8 * sum(pts[:-1]) + 8 * sum(pts[1:])),
+        "prolongation": dict(bound="hbm", bytes=16 * sum(pts[:-1]) + 8 * sum(pts[1:])),
+        "binning": dict(bound="hbm", bytes=112 * n),
+        "coarsest": dict(bound="alu", flops=2 * pts[-1] ** 2),
+    }
+
+
+def time_precision(w, prm, precision, steps, warmup, dev):
+    import torch
+    from paper_1308_4005_amd import Plan, Result
+    plan = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], precision=precision,
+                n_max=w.n, device=dev.index)
+    pos = torch.tensor(w.pos, dtype=torch.float64, device=dev)
+    c6 = torch.tensor(w.c6, dtype=torch.float64, device=dev)
+    out = Result(torch.empty(1, dtype=torch.float64, device=dev),
+                 torch.empty((w.n, 3), dtype=torch.float64, device=dev))
+    for _ in range(warmup):
+        plan.evaluate(pos, c6, out=out)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    stream = torch.cuda.current_stream(dev)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(steps):
+        plan.evaluate(pos, c6, out=out)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    stage_ms, cnt = plan.read_timing()
+    plan.set_timing(False)
+    stage_ms = {k: v / max(cnt, 1) for k, v in stage_ms.items()}
+    E = float(out.energy.cpu()[0])
+    F = out.forces.cpu().numpy()
+    info = plan.info
+    plan.close()
+    return dict(ms=ms, stage_ms=stage_ms, E=E, F=F, info=info)
+
+
+def golden_errors(E, F, gold):
+    import numpy as np
+    if gold is None:
+        return None
+    idx = np.asarray(gold["sample"])
+    Fr = np.asarray(gold["forces"])
+    Fs = F[idx]
+    diff = np.linalg.norm(Fs - Fr, axis=1)
+    nref = np.linalg.norm(Fr, axis=1)
+    return dict(dE=abs(E - gold["energy"]) / abs(gold["energy"]),
+                rms_rel_F=float(np.sqrt(np.sum(diff ** 2) / np.sum(nref ** 2))),
+                paper_dF=float(np.mean(diff / nref)),
+                max_F=float(np.max(diff) / gold["force_rms"]),
+                sampled_atoms=int(len(idx)))
+
+
+def cpu_baseline(prm, target_n):
+    """The FP64 oracle, timed on a bounded sample: a 32,000-atom cube of the
+    same density with the same a, h, p (3 levels), scaled by the atom ratio
+    to evaluations of the full workload (the method is linear in N)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import mls as oracle_mls
+    from paper_1308_4005_amd import workloads as W
+    w = W.cube(32000, 0.8, seed=31)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle_mls.mls(w.pos, w.c6, w.box, prm["a"], prm["h"], prm["order"], 3)
+        dt = time.perf_counter() - t0
+    return {"value": (1.0 / dt) * (w.n / target_n), "unit": "evals/s (1M-atom equivalent)",
+            "cores": 1, "kind": "oracle",
+            "sample": f"oracle.mls FP64 on a {w.n}-atom cube (rho 0.8, a={prm['a']}, h={prm['h']}, "
+                      f"p={prm['order']}, 3 levels): {dt:.2f} s per evaluation, scaled by "
+                      f"{w.n}/{target_n} atoms; numpy single thread (BLAS limited to 1)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="cube1M")
+    ap.add_argument("--a", type=float, default=3.0)
+    ap.add_argument("--h", type=float, default=1.0)
+    ap.add_argument("--order", type=int, default=4)
+    ap.add_argument("--levels", type=int, default=5)
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: MLS here is a single-GPU path "
+              "(the multi-GPU decomposition is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1308_4005_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t = time.time()
+    w = W.named(args.workload)
+    log(f"[bench] workload {w.name}: n={w.n} box={w.box.round(4).tolist()} ({time.time() - t:.1f}s)")
+    prm = dict(a=args.a, h=args.h, order=args.order, levels=args.levels)
+    gname = f"{args.workload}_a{args.a:g}_h{args.h:g}_p{args.order}_l{args.levels}"
+    gpath = os.path.join(ROOT, "tests", "golden", gname + ".json")
+    gold = json.load(open(gpath)) if os.path.exists(gpath) else None
+
+    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    res = {}
+    for p in precisions:
+        log(f"[bench] timing {p}: warmup {args.warmup}, steps {args.steps}")
+        res[p] = time_precision(w, prm, p, args.steps, args.warmup, dev)
+        log(f"[bench] {p}: {res[p]['ms']:.3f} ms/eval stages {json.dumps({k: round(v, 4) for k, v in res[p]['stage_ms'].items()})}")
+
+    head = "mixed" if "mixed" in res else precisions[0]
+    info = res[head]["info"]
+    pairs = count_pairs(w.pos, w.box, args.a) if min(w.box) > 2 * args.a else None
+    model = work_model(info, w.n, pairs or 0, args.order)
+    # dominant kernel of the headline precision
+    sm = res[head]["stage_ms"]
+    dom = max(sm, key=sm.get)
+    m = model[dom]
+    dt_s = sm[dom] * 1e-3
+    if m["bound"] == "hbm":
+        achieved = m["bytes"] / dt_s / 1e9
+        peak = PEAK["hbm"]
+        unit = "GB/s"
+    else:
+        achieved = m["flops"] / dt_s / 1e12
+        peak = PEAK["fp32" if head == "mixed" else "fp64"]
+        unit = "TFLOP/s"
+    roofline = {"bound": m["bound"], "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": None,
+                "work_per_launch": m.get("flops", m.get("bytes")),
+                "avg_launch_ms": sm[dom]}
+
+    accuracy = {}
+    for p in res:
+        accuracy[p] = golden_errors(res[p]["E"], res[p]["F"], gold)
+    if "mixed" in res and "fp64" in res:
+        Fd, Fm = res["fp64"]["F"], res["mixed"]["F"]
+        dif = np.linalg.norm(Fm - Fd, axis=1)
+        accuracy["mixed_vs_fp64_gpu"] = dict(
+            dE=abs(res["mixed"]["E"] - res["fp64"]["E"]) / abs(res["fp64"]["E"]),
+            rms_rel_F=float(np.sqrt(np.sum(dif ** 2) / np.sum(Fd ** 2))))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle on a bounded sample)")
+        cpu = cpu_baseline(prm, w.n)
+
+    ms = res[head]["ms"]
+    line = {
+        "metric": "MLS E+F evals/s at 1M atoms, FP32-mixed vs FP64, at stated RMS force error",
+        "value": 1000.0 / ms,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-mixed" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.n} LJ atoms, periodic cube L={w.box[0]:.4f}, density 0.8, "
+                               f"RSA min distance 0.8, C6=4",
+                   "a": args.a, "h": args.h, "h_eff": list(info["h_eff"]), "grid": list(info["grid"]),
+                   "order": args.order, "levels": info["levels"], "taps": info["taps"],
+                   "in_cutoff_pairs": pairs},
+        "particle_evals_per_s": w.n * 1000.0 / ms,
+        "per_precision": {p: {"evals_per_s": 1000.0 / r["ms"], "ms_per_step": r["ms"],
+                              "stage_ms": r["stage_ms"], "energy": r["E"]} for p, r in res.items()},
+        "mixed_over_fp64": (res["fp64"]["ms"] / res["mixed"]["ms"]) if len(res) == 2 else None,
+        "accuracy": accuracy,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

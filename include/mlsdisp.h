@@ -1,0 +1,214 @@
+/*
+ * mlsdisp.h -- C ABI of the MI355X (gfx950) multilevel summation library for
+ * periodic r^-6 dispersion.
+ *
+ * Method: Tameling, Springer, Bientinesi, Ismail, "Multilevel Summation for
+ * Dispersion: A Linear-Time Algorithm for r^-6 Potentials", J. Chem. Phys.
+ * 2014 (arXiv 1308.4005).  One call to mls_evaluate runs the algorithm of
+ * Sec. II.B on the GPU: linked-cell binning (Sec. III.D), the local pair sum
+ * with g_0 (eq:g_0, eq:evaluation with k = 0), anterpolation
+ * (eq:anterpolation), l-1 restrictions, the cutoff stencils of levels
+ * 1..l-1 (eq:g_k), the all-to-all sum on the periodic coarsest grid with its
+ * pre-summed kernel (eq:last-grid-periodic-transformed), l-1 prolongations,
+ * interpolation (eq:interpolation) and the energy with the self-interaction
+ * term removed (eq:interpolation-pot, eq:self-interaction-energy).
+ *
+ * Problem statement the calls follow (Sec. II.A.1, II.D):
+ *   E = -1/2 sum_i sum_{(j,n) != (i,0)} xi_i xi_j |x_i - x_j - n o L|^-6,
+ *   xi_i = sqrt(C6_i)  (geometric mixing, eq:xi-general: C6_ij = sqrt(C6_i C6_j)),
+ * approximated by MLS with cutoff a, finest spacing h, p-point Hermite basis
+ * (p = 4: the cubic of eq:Phi-Hermite; p = 6: the C1 quintic Hermite) and l
+ * grid levels.  Forces are F_i = -dE_MLS/dx_i, exact derivatives of the MLS
+ * energy.  E is negative (attractive dispersion).
+ *
+ * Conventions for every call:
+ *   - All array arguments are DEVICE pointers (memory of the device current
+ *     when the plan was created) unless a comment says "host".
+ *   - Positions are (n,3) row-major float64, any real values (wrapped into
+ *     the box internally); C6 are (n) float64, >= 0.
+ *   - Outputs are overwritten, never accumulated; inputs and outputs are
+ *     float64 in both precisions; the precision only changes internal
+ *     arithmetic.
+ *   - The caller owns every array it passes; the plan owns its workspace
+ *     (allocated in mls_plan_create, freed in mls_plan_destroy).
+ *   - A plan is not thread safe; distinct plans are independent.  Two
+ *     evaluations on one plan must be ordered (same stream, or synchronised).
+ *   - Argument errors are reported synchronously by the return code with a
+ *     detail string in mls_last_error() (thread local).  Errors in the data
+ *     (non-finite positions or C6, negative C6) raise a device flag that
+ *     mls_plan_status reads.  No call aborts the process.
+ */
+#ifndef MLSDISP_H
+#define MLSDISP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mls_plan_s* mls_plan_t;
+typedef struct mls_batch_s* mls_batch_t;
+
+typedef enum {
+  MLS_OK = 0,
+  MLS_ERR_INVALID_ARG = -1, /* a parameter or pointer is out of range */
+  MLS_ERR_UNSUPPORTED = -2, /* valid request this build does not handle */
+  MLS_ERR_HIP = -3,         /* a HIP runtime call failed */
+  MLS_ERR_OOM = -4,         /* device allocation failed */
+  MLS_ERR_NONFINITE = -5    /* device flag: non-finite or negative input */
+} mls_status;
+
+typedef enum { MLS_FP64 = 0, MLS_MIXED = 1 } mls_precision;
+
+/* Method parameters (Sec. III.D lists a, h, p, l as the knobs). */
+typedef struct {
+  double box[3];  /* L_x, L_y, L_z > 0: orthorhombic, periodic in all three
+                     dimensions (Sec. II.C), origin at the box corner */
+  double cutoff;  /* a > 0: local cutoff (eq:g_0); level k reaches 2^k a */
+  double h;       /* target finest spacing > 0; each finest dimension gets
+                     n = 2^(l-1) max(1, floor(L/(2^(l-1) h) + 1/2)) points
+                     (uniform grids, Sec. III.A; spacing 2^(k-1) L/n on
+                     level k) unless grid[] is given */
+  int order;      /* p: 4 (cubic Hermite, eq:Phi-Hermite) or 6 (quintic) */
+  int levels;     /* l >= 1 grids, or 0: the largest l whose coarsest grid
+                     keeps >= p points per dimension */
+  int grid[3];    /* explicit finest grid (each divisible by 2^(l-1)), or
+                     all 0 to derive it from h */
+  int precision;  /* mls_precision: MLS_FP64 computes everything in FP64;
+                     MLS_MIXED does pair, grid-transfer and stencil
+                     arithmetic in FP32 with FP64 accumulation of energy,
+                     forces and grid charges, and keeps the coarsest level
+                     and the energy reduction in FP64 */
+} mls_params;
+
+/* Resolved plan geometry (host struct filled by mls_plan_get_info). */
+typedef struct {
+  int levels;              /* l */
+  int grid[3];             /* finest grid n_1 */
+  int coarsest[3];         /* n_l */
+  int cells[3];            /* linked cells per dimension */
+  double h_eff[3];         /* finest spacing L_d / n_1,d */
+  int64_t taps;            /* stencil offsets of levels 1..l-1 */
+  int64_t n_max;           /* largest n mls_evaluate accepts */
+  int64_t workspace_bytes; /* device memory the plan holds */
+  int precision;
+  int order;
+} mls_plan_info;
+
+/* Build a plan on the current HIP device: resolves grids, levels and linked
+ * cells, tabulates the level-1 stencil g_1 (eq:g_k; the same table serves
+ * every level k < l scaled by 2^(-6(k-1)), Sec. II.A.4) and the coarsest
+ * kernel K_l[delta] = sum_n g_l(|delta o h_l + n o L|) by an Ewald-type r^-6
+ * lattice sum (eq:last-grid-periodic-transformed; precomputed once, Sec.
+ * II.C), and allocates the workspace for up to n_max atoms.
+ * params: host pointer; out: host pointer receiving the plan.
+ * Errors: MLS_ERR_INVALID_ARG (bad parameter), MLS_ERR_OOM, MLS_ERR_HIP. */
+mls_status mls_plan_create(const mls_params* params, int64_t n_max, mls_plan_t* out);
+
+/* Copy the resolved geometry into *info (host). */
+mls_status mls_plan_get_info(mls_plan_t plan, mls_plan_info* info);
+
+/* One MLS energy-and-force evaluation (Sec. II.B), enqueued on `stream`
+ * (a hipStream_t; NULL = the null stream).  No host synchronisation and no
+ * allocation.
+ *   n          0 <= n <= n_max atoms (n = 0 gives E = 0)
+ *   pos        device (n,3) float64, row-major
+ *   c6         device (n) float64, >= 0
+ *   energy     device, 1 float64: E (required)
+ *   forces     device (n,3) float64 F = -dE/dx, or NULL
+ *   potential  device (n) float64: u_i = e^{0,tot}_i of eq:interpolation,
+ *              including the grid self term gamma(0)/a^6 xi_i, or NULL
+ *   dE_dc6     device (n) float64: dE/dC6_i = -(u_i - gamma(0) a^-6 xi_i) /
+ *              (2 xi_i) (infinite where C6_i = 0), or NULL
+ * Errors: MLS_ERR_INVALID_ARG (null plan/pos/c6/energy, n out of range),
+ * MLS_ERR_HIP (launch failure). */
+mls_status mls_evaluate(mls_plan_t plan, int64_t n, const double* pos, const double* c6,
+                        double* energy, double* forces, double* potential, double* dE_dc6,
+                        void* stream);
+
+/* Intermediate results of the last evaluation, for per-stage checks.
+ * `what` selects the array, written to device memory `dst` of `capacity`
+ * bytes (MLS_ERR_INVALID_ARG if too small), enqueued on `stream`:
+ *   MLS_STAGE_PERM        int32 (n): original index of the s-th cell-sorted atom
+ *   MLS_STAGE_CELL_START  int32 (cells+1): first sorted atom of each cell
+ *   MLS_STAGE_E0          float64 (n), original order: local potential e^0_i
+ *   MLS_STAGE_FLOC        float64 (n,3), original order: local forces
+ *   MLS_STAGE_Q           float64 grid of level `level`: q^k (charges)
+ *   MLS_STAGE_E_LEVEL     float64 grid of level `level`: e^k (evaluation)
+ *   MLS_STAGE_E_TOTAL     float64 grid of level `level`: E^k (after prolongation)
+ * Grids are x fastest (index (z*ny + y)*nx + x), level 1 = finest. */
+enum {
+  MLS_STAGE_PERM = 0,
+  MLS_STAGE_CELL_START = 1,
+  MLS_STAGE_E0 = 2,
+  MLS_STAGE_FLOC = 3,
+  MLS_STAGE_Q = 4,
+  MLS_STAGE_E_LEVEL = 5,
+  MLS_STAGE_E_TOTAL = 6
+};
+mls_status mls_plan_copy_stage(mls_plan_t plan, int what, int level, void* dst, int64_t capacity,
+                               void* stream);
+
+/* Synchronise the plan's last stream and report the device flags set by
+ * evaluations since the previous call (bit 0: non-finite position, bit 1:
+ * non-finite or negative C6), then clear them.  *flags: host.  Returns
+ * MLS_ERR_NONFINITE when a flag is set, else MLS_OK. */
+mls_status mls_plan_status(mls_plan_t plan, int* flags);
+
+/* Per-stage device timing for measurement: with timing enabled, each
+ * following evaluation (up to 256) records hipEvents on its own stream
+ * between the stages listed below.  mls_plan_read_timing synchronises, writes
+ * the summed milliseconds of every stage over the recorded evaluations into
+ * ms[MLS_NUM_STAGES] (host) and the evaluation count into *count (host),
+ * and starts a new recording window.  Enabling timing creates the events;
+ * evaluations themselves never allocate. */
+enum {
+  MLS_T_BINNING = 0,   /* wrap, cell count, scan, scatter, in-cell order */
+  MLS_T_PAIR = 1,      /* local g_0 pair sum */
+  MLS_T_ANTERP = 2,    /* anterpolation */
+  MLS_T_RESTRICT = 3,  /* all restrictions */
+  MLS_T_STENCIL = 4,   /* cutoff stencils of levels 1..l-1 */
+  MLS_T_COARSEST = 5,  /* all-to-all on the coarsest grid */
+  MLS_T_PROLONG = 6,   /* all prolongations */
+  MLS_T_INTERP = 7,    /* interpolation, outputs, energy reduction */
+  MLS_NUM_STAGES = 8
+};
+mls_status mls_plan_set_timing(mls_plan_t plan, int enable);
+mls_status mls_plan_read_timing(mls_plan_t plan, double* ms, int* count);
+
+/* Release the plan and its workspace (NULL is accepted). */
+mls_status mls_plan_destroy(mls_plan_t plan);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent periodic boxes, each with its own plan
+ * parameters, evaluated by one sequence of persistent launches that walk a
+ * (box, tile) work list built at creation.  The list and launch shapes are
+ * chosen by an autotuner run in mls_batch_create; mls_batch_evaluate can be
+ * captured into a hipGraph by the caller.
+ *   per_box   host (nbox) parameter sets (precision must agree)
+ *   n_per_box host (nbox) atom counts
+ * Atoms of box b occupy rows offsets[b]..offsets[b+1]-1 of pos/c6/forces,
+ * offsets being the exclusive prefix sum of n_per_box (computed by the
+ * library).  energies: device (nbox).
+ * ------------------------------------------------------------------------- */
+mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* n_per_box,
+                            int autotune, mls_batch_t* out);
+mls_status mls_batch_evaluate(mls_batch_t batch, const double* pos, const double* c6,
+                              double* energies, double* forces, double* dE_dc6, void* stream);
+/* Autotuned launch shape (host out-params), for reporting. */
+mls_status mls_batch_get_tuning(mls_batch_t batch, int* pair_block, int* stencil_block,
+                                double* tuned_ms);
+mls_status mls_batch_destroy(mls_batch_t batch);
+
+/* Static description of a status code. */
+const char* mls_status_string(int status);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char* mls_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLSDISP_H */

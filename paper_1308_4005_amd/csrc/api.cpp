@@ -1,0 +1,197 @@
+// extern "C" entry points of the MLS dispersion library (include/mlsdisp.h).
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mls_internal.h"
+
+namespace mls {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+mls_status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return MLS_ERR_HIP;
+}
+
+}  // namespace mls
+
+using namespace mls;
+
+static constexpr int kTimingSlots = 256;
+
+#define HIP_TRY(call, what)                    \
+  do {                                         \
+    hipError_t _e = (call);                    \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+extern "C" {
+
+const char* mls_status_string(int status) {
+  switch (status) {
+    case MLS_OK: return "success";
+    case MLS_ERR_INVALID_ARG: return "invalid argument";
+    case MLS_ERR_UNSUPPORTED: return "unsupported request";
+    case MLS_ERR_HIP: return "HIP runtime error";
+    case MLS_ERR_OOM: return "device out of memory";
+    case MLS_ERR_NONFINITE: return "non-finite or negative input data";
+    default: return "unknown status";
+  }
+}
+
+const char* mls_last_error(void) { return g_last_error.c_str(); }
+
+mls_status mls_plan_create(const mls_params* params, int64_t n_max, mls_plan_t* out) {
+  g_last_error.clear();
+  if (!params || !out) { set_error("mls_plan_create: null params or out"); return MLS_ERR_INVALID_ARG; }
+  *out = nullptr;
+  mls_plan_s* P = new (std::nothrow) mls_plan_s();
+  if (!P) { set_error("host allocation failed"); return MLS_ERR_OOM; }
+  mls_status st = build_plan(*params, n_max, P);
+  if (st != MLS_OK) {
+    free_plan(P);
+    delete P;
+    return st;
+  }
+  *out = P;
+  return MLS_OK;
+}
+
+mls_status mls_plan_get_info(mls_plan_t P, mls_plan_info* info) {
+  if (!P || !info) { set_error("mls_plan_get_info: null argument"); return MLS_ERR_INVALID_ARG; }
+  std::memset(info, 0, sizeof(*info));
+  info->levels = P->levels;
+  for (int d = 0; d < 3; ++d) {
+    info->grid[d] = P->lv[0].g.n[d];
+    info->coarsest[d] = P->lv[P->levels - 1].g.n[d];
+    info->cells[d] = P->cg.nc[d];
+    info->h_eff[d] = P->lv[0].h[d];
+  }
+  info->taps = (int64_t)P->taps.size();
+  info->n_max = P->n_max;
+  info->workspace_bytes = P->bytes;
+  info->precision = P->precision;
+  info->order = P->order;
+  return MLS_OK;
+}
+
+mls_status mls_evaluate(mls_plan_t P, int64_t n, const double* pos, const double* c6, double* energy,
+                        double* forces, double* potential, double* dE_dc6, void* stream) {
+  if (!P) { set_error("mls_evaluate: null plan"); return MLS_ERR_INVALID_ARG; }
+  if (n < 0 || n > P->n_max) {
+    set_error("mls_evaluate: n = " + std::to_string(n) + " outside [0, n_max = " + std::to_string(P->n_max) + "]");
+    return MLS_ERR_INVALID_ARG;
+  }
+  if (!energy) { set_error("mls_evaluate: energy pointer is required"); return MLS_ERR_INVALID_ARG; }
+  if (n > 0 && (!pos || !c6)) { set_error("mls_evaluate: null pos or c6"); return MLS_ERR_INVALID_ARG; }
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != P->device) {
+    set_error("mls_evaluate: current device differs from the plan's device");
+    return MLS_ERR_INVALID_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  P->last_stream = s;
+  P->last_n = n;
+  const int ni = (int)n;
+  hipEvent_t* ev = nullptr;
+  if (P->timing && P->timing_slots < kTimingSlots) {
+    ev = &P->events[(size_t)P->timing_slots * (MLS_NUM_STAGES + 1)];
+    ++P->timing_slots;
+  }
+  auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
+  HIP_TRY(mark(0), "timing event");
+  HIP_TRY(launch_binning(P, ni, pos, c6, s), "binning");
+  HIP_TRY(mark(1 + MLS_T_BINNING), "timing event");
+  HIP_TRY(launch_pair(P, ni, s), "pair kernel");
+  HIP_TRY(mark(1 + MLS_T_PAIR), "timing event");
+  HIP_TRY(launch_anterpolate(P, ni, s), "anterpolation");
+  HIP_TRY(mark(1 + MLS_T_ANTERP), "timing event");
+  for (int k = 2; k <= P->levels; ++k) HIP_TRY(launch_restrict(P, k - 1, s), "restriction");
+  HIP_TRY(mark(1 + MLS_T_RESTRICT), "timing event");
+  HIP_TRY(launch_stencils(P, s), "level stencils");
+  HIP_TRY(mark(1 + MLS_T_STENCIL), "timing event");
+  HIP_TRY(launch_coarsest(P, s), "coarsest grid");
+  HIP_TRY(mark(1 + MLS_T_COARSEST), "timing event");
+  for (int k = P->levels - 1; k >= 1; --k) HIP_TRY(launch_prolong(P, k, s), "prolongation");
+  HIP_TRY(mark(1 + MLS_T_PROLONG), "timing event");
+  HIP_TRY(launch_interpolate(P, ni, energy, forces, potential, dE_dc6, s), "interpolation");
+  HIP_TRY(mark(1 + MLS_T_INTERP), "timing event");
+  return MLS_OK;
+}
+
+mls_status mls_plan_set_timing(mls_plan_t P, int enable) {
+  if (!P) { set_error("mls_plan_set_timing: null plan"); return MLS_ERR_INVALID_ARG; }
+  if (enable && P->events.empty()) {
+    P->events.resize((size_t)kTimingSlots * (MLS_NUM_STAGES + 1));
+    for (auto& e : P->events) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+  }
+  P->timing = enable != 0;
+  P->timing_slots = 0;
+  return MLS_OK;
+}
+
+mls_status mls_plan_read_timing(mls_plan_t P, double* ms, int* count) {
+  if (!P || !ms || !count) { set_error("mls_plan_read_timing: null argument"); return MLS_ERR_INVALID_ARG; }
+  for (int k = 0; k < MLS_NUM_STAGES; ++k) ms[k] = 0.0;
+  *count = P->timing_slots;
+  for (int sl = 0; sl < P->timing_slots; ++sl) {
+    hipEvent_t* ev = &P->events[(size_t)sl * (MLS_NUM_STAGES + 1)];
+    HIP_TRY(hipEventSynchronize(ev[MLS_NUM_STAGES]), "hipEventSynchronize");
+    for (int k = 0; k < MLS_NUM_STAGES; ++k) {
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, ev[k], ev[k + 1]), "hipEventElapsedTime");
+      ms[k] += t;
+    }
+  }
+  P->timing_slots = 0;
+  return MLS_OK;
+}
+
+mls_status mls_plan_copy_stage(mls_plan_t P, int what, int level, void* dst, int64_t capacity, void* stream) {
+  if (!P || !dst) { set_error("mls_plan_copy_stage: null argument"); return MLS_ERR_INVALID_ARG; }
+  int64_t need = 0;
+  const int64_t n = P->last_n < 0 ? 0 : P->last_n;
+  switch (what) {
+    case MLS_STAGE_PERM: need = 4 * n; break;
+    case MLS_STAGE_CELL_START: need = 4 * ((int64_t)P->cg.ncell + 1); break;
+    case MLS_STAGE_E0: need = 8 * n; break;
+    case MLS_STAGE_FLOC: need = 24 * n; break;
+    case MLS_STAGE_Q:
+    case MLS_STAGE_E_LEVEL:
+    case MLS_STAGE_E_TOTAL:
+      if (level < 1 || level > P->levels) { set_error("mls_plan_copy_stage: level out of range"); return MLS_ERR_INVALID_ARG; }
+      need = 8 * (int64_t)P->lv[level - 1].g.size;
+      break;
+    default: set_error("mls_plan_copy_stage: unknown stage"); return MLS_ERR_INVALID_ARG;
+  }
+  if (capacity < need) { set_error("mls_plan_copy_stage: destination too small"); return MLS_ERR_INVALID_ARG; }
+  HIP_TRY(launch_copy_stage(P, what, level, dst, (hipStream_t)stream), "copy stage");
+  return MLS_OK;
+}
+
+mls_status mls_plan_status(mls_plan_t P, int* flags) {
+  if (!P || !flags) { set_error("mls_plan_status: null argument"); return MLS_ERR_INVALID_ARG; }
+  HIP_TRY(hipStreamSynchronize(P->last_stream), "synchronise");
+  int h[4] = {0, 0, 0, 0};
+  HIP_TRY(hipMemcpy(h, P->d_flags, sizeof(h), hipMemcpyDeviceToHost), "read flags");
+  HIP_TRY(hipMemset(P->d_flags, 0, sizeof(h)), "clear flags");
+  *flags = h[0];
+  if (h[0]) { set_error("input data contained non-finite positions or non-finite/negative C6"); return MLS_ERR_NONFINITE; }
+  return MLS_OK;
+}
+
+mls_status mls_plan_destroy(mls_plan_t P) {
+  if (!P) return MLS_OK;
+  for (auto& e : P->events) (void)hipEventDestroy(e);
+  P->events.clear();
+  free_plan(P);
+  delete P;
+  return MLS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Internal declarations of the MLS dispersion library: plan layout, device
+// helpers shared by the kernels, and the host-side launchers each kernel file
+// provides.  Not part of the public ABI (see include/mlsdisp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mlsdisp.h"
+
+namespace mls {
+
+// ---------------------------------------------------------------------------
+// Geometry passed by value to kernels
+// ---------------------------------------------------------------------------
+struct CellGeom {
+  double L[3];       // box
+  double invL[3];    // 1 / L (host division, correctly rounded)
+  double inv_w[3];   // nc / L: cell index = trunc(x_w * inv_w)
+  double w[3];       // L / nc
+  int nc[3];         // cells per dimension
+  int noff[3];       // neighbour-cell reach (1 unless the box is narrower than a)
+  int ncell;
+};
+
+struct GridDims {
+  int n[3];
+  int size;          // n0*n1*n2
+};
+
+// One stencil offset of the level-1 table.
+struct Tap {
+  int dx, dy, dz, pad;
+  double w;
+};
+
+// Run of stencil taps sharing |dy|,|dz| (rows folded by the +-dy, +-dz mirror
+// symmetry of the radial kernel) and a half-width in x.
+struct StencilRow {
+  int dy, dz;        // >= 0
+  int hx;            // taps dx in [-hx, hx]
+  int woff;          // offset of the hx+1 weights w[|dx|] in the weight table
+};
+
+// Per-level bookkeeping of the grid hierarchy.
+struct Level {
+  GridDims g;
+  double h[3];
+  double* q = nullptr;   // charges q^k
+  double* e = nullptr;   // evaluation e^k
+  double* E = nullptr;   // prolongated total E^k (aliases e on the coarsest level)
+  float* qf = nullptr;   // mixed precision: q^k - mean, FP32
+  float* ef = nullptr;   // mixed precision: e^k (FP32 stencil output)
+};
+
+}  // namespace mls
+
+struct mls_plan_s {
+  mls_params params{};
+  int levels = 0;
+  int order = 4;
+  int precision = 0;
+  double a = 0, a2 = 0, inv_a2 = 0, inv_a6 = 0, inv_a8 = 0, cself = 0;
+  mls::CellGeom cg{};
+  double invh1[3]{};               // n_1 / L
+  std::vector<mls::Level> lv;      // index k-1 for level k
+  int64_t n_max = 0;
+  int device = 0;
+
+  // stencil tables (levels 1..l-1)
+  std::vector<mls::Tap> taps;
+  std::vector<mls::StencilRow> rows;
+  std::vector<double> row_w;
+  int stencil_R[3]{};              // max |dx|, |dy|, |dz|
+  mls::Tap* d_taps = nullptr;
+  mls::StencilRow* d_rows = nullptr;
+  double* d_row_w = nullptr;
+  float* d_row_wf = nullptr;
+  double taps_wsum = 0;            // sum of level-1 weights (mean term in mixed precision)
+
+  // coarsest kernel K_l, x fastest
+  std::vector<double> Kl;
+  double* d_Kl = nullptr;
+
+  // atom workspace
+  int* d_count = nullptr;          // ncell
+  int* d_cell_start = nullptr;     // ncell + 1
+  int* d_fill = nullptr;           // ncell
+  int* d_cid = nullptr;            // n_max: cell of original atom
+  int* d_perm_tmp = nullptr;       // n_max
+  int* d_perm = nullptr;           // n_max
+  int* d_cell_s = nullptr;         // n_max: cell of sorted atom
+  double4* d_xw = nullptr;         // n_max: wrapped x,y,z + xi, original order
+  double4* d_xs = nullptr;         // n_max: sorted
+  float4* d_xr = nullptr;          // n_max: sorted, cell-relative FP32 (mixed)
+  double* d_e0 = nullptr;          // n_max sorted local potential
+  double* d_floc = nullptr;        // 3 n_max sorted local force / (xi_i)
+  double* d_partial = nullptr;     // energy partial sums
+  int n_partial = 0;
+  double* d_scratch = nullptr;     // small reductions (grid means)
+  int* d_flags = nullptr;
+  int* d_ncell_max = nullptr;
+
+  // per-stage timing (mls_plan_set_timing)
+  bool timing = false;
+  int timing_slots = 0;            // evaluations recorded in the window
+  std::vector<hipEvent_t> events;  // (MLS_NUM_STAGES + 1) per slot
+
+  int64_t bytes = 0;
+  int64_t last_n = -1;
+  hipStream_t last_stream = nullptr;
+  std::vector<void*> allocations;
+};
+
+namespace mls {
+
+// error reporting (api.cpp)
+void set_error(const std::string& msg);
+mls_status hip_fail(hipError_t e, const char* what);
+
+// plan construction (plan.cpp)
+mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* plan);
+void free_plan(mls_plan_s* plan);
+
+// kernel launchers (one per file); all enqueue on `s` and return the launch status
+hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double* c6, hipStream_t s);
+hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s);
+hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s);
+hipError_t launch_restrict(mls_plan_s* P, int k_fine, hipStream_t s);
+hipError_t launch_stencils(mls_plan_s* P, hipStream_t s);
+hipError_t launch_coarsest(mls_plan_s* P, hipStream_t s);
+hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s);
+hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forces,
+                              double* potential, double* dE_dc6, hipStream_t s);
+hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
+hipError_t launch_zero_i(int* p, int64_t count, hipStream_t s);
+hipError_t launch_copy_stage(mls_plan_s* P, int what, int level, void* dst, hipStream_t s);
+
+}  // namespace mls

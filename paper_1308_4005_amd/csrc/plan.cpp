@@ -1,0 +1,332 @@
+// Host-side plan construction: parameter checks, grid hierarchy, linked cells,
+// the level-1 stencil table and the pre-summed coarsest-grid kernel, and the
+// device workspace.  Everything here runs once per plan (the paper notes the
+// g_k tables and operator maps are constant for fixed grids and can be
+// precomputed, Sec. II.A.4, and that the coarsest image sum is
+// time-independent, Sec. II.C).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+
+#include "mls_internal.h"
+
+namespace mls {
+namespace {
+
+// Smoothing function of eq:gamma.
+double gamma_s(double rho) {
+  if (rho < 1.0) {
+    double u = std::pow(rho, 12);
+    return 15.0 / 8.0 + u * (-5.0 / 4.0 + u * (3.0 / 8.0));
+  }
+  return std::pow(rho, -6);
+}
+
+// Level-1 kernel of eq:g_k (k = 1): a^-6 gamma(s/a) - (2a)^-6 gamma(s/2a),
+// zero from 2a on.
+double g_level1(double s, double a) {
+  if (s >= 2.0 * a) return 0.0;
+  return std::pow(a, -6) * gamma_s(s / a) - std::pow(2.0 * a, -6) * gamma_s(s / (2.0 * a));
+}
+
+// Coarsest kernel eq:g_l with A = 2^(l-1) a.
+double g_coarsest(double r, double A) { return std::pow(A, -6) * gamma_s(r / A); }
+
+// ---------------------------------------------------------------------------
+// Periodic r^-6 lattice sum  S(v) = sum_{n: v + nL != 0} |v + n o L|^-6.
+//
+// Screened split of r^-6 = (1/2) int_0^inf t^2 e^{-r^2 t} dt at t = b^2:
+//   near part  r^-6 e^{-y}(1 + y + y^2/2),    y = b^2 r^2
+//   far part   smooth, summed in Fourier space with
+//              F(k) = pi^{3/2} b^3 / 3 * [(1 - 2c^2) e^{-c^2} + 2 sqrt(pi) c^3 erfc(c)],
+//              c = |k| / (2b), and value b^6/6 at r = 0.
+// ---------------------------------------------------------------------------
+class LatticeR6 {
+ public:
+  LatticeR6(const double L[3]) {
+    for (int d = 0; d < 3; ++d) L_[d] = L[d];
+    double Lmin = std::min(L[0], std::min(L[1], L[2]));
+    b_ = 2.5 / Lmin;
+    const double lnTol = 40.0;  // e^-40 ~ 4e-18
+    rcut_ = std::sqrt(lnTol) / b_;
+    double kcut = 2.0 * b_ * std::sqrt(lnTol);
+    vol_ = L[0] * L[1] * L[2];
+    int m[3];
+    for (int d = 0; d < 3; ++d) m[d] = (int)std::ceil(kcut * L[d] / (2.0 * M_PI));
+    // half space of k (k and -k contribute equally to a cosine sum)
+    for (int mz = 0; mz <= m[2]; ++mz)
+      for (int my = (mz == 0 ? 0 : -m[1]); my <= m[1]; ++my)
+        for (int mx = ((mz == 0 && my == 0) ? 0 : -m[0]); mx <= m[0]; ++mx) {
+          double kx = 2.0 * M_PI * mx / L[0], ky = 2.0 * M_PI * my / L[1], kz = 2.0 * M_PI * mz / L[2];
+          double k = std::sqrt(kx * kx + ky * ky + kz * kz);
+          if (k > kcut) continue;
+          double c = k / (2.0 * b_);
+          double F = std::pow(M_PI, 1.5) * b_ * b_ * b_ / 3.0 *
+                     ((1.0 - 2.0 * c * c) * std::exp(-c * c) +
+                      2.0 * std::sqrt(M_PI) * c * c * c * std::erfc(c));
+          double mult = (mx == 0 && my == 0 && mz == 0) ? 1.0 : 2.0;
+          kv_.push_back({kx, ky, kz, mult * F / vol_});
+        }
+  }
+
+  double operator()(const double v[3]) const {
+    double near = 0.0;
+    int nr[3];
+    for (int d = 0; d < 3; ++d) nr[d] = (int)std::ceil((rcut_ + L_[d]) / L_[d]);
+    for (int iz = -nr[2]; iz <= nr[2]; ++iz)
+      for (int iy = -nr[1]; iy <= nr[1]; ++iy)
+        for (int ix = -nr[0]; ix <= nr[0]; ++ix) {
+          double x = v[0] + ix * L_[0], y = v[1] + iy * L_[1], z = v[2] + iz * L_[2];
+          double r2 = x * x + y * y + z * z;
+          if (r2 == 0.0 || r2 > rcut_ * rcut_) continue;
+          double yb = b_ * b_ * r2;
+          near += std::exp(-yb) * (1.0 + yb + 0.5 * yb * yb) / (r2 * r2 * r2);
+        }
+    double far = 0.0;
+    for (const auto& k : kv_) far += k[3] * std::cos(k[0] * v[0] + k[1] * v[1] + k[2] * v[2]);
+    bool on_lattice = true;
+    for (int d = 0; d < 3; ++d) {
+      double f = v[d] / L_[d];
+      if (f != std::round(f)) on_lattice = false;
+    }
+    double self = on_lattice ? std::pow(b_, 6) / 6.0 : 0.0;
+    return near + far - self;
+  }
+
+ private:
+  double L_[3];
+  double b_, rcut_, vol_;
+  std::vector<std::array<double, 4>> kv_;
+};
+
+template <class T>
+mls_status dalloc(mls_plan_s* P, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  size_t bytes = count * sizeof(T);
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    return MLS_ERR_OOM;
+  }
+  P->allocations.push_back((void*)*p);
+  P->bytes += (int64_t)bytes;
+  return MLS_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+}  // namespace
+
+mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
+  // ---------------------------------------------------------------- checks
+  for (int d = 0; d < 3; ++d)
+    if (!finite_pos(p.box[d])) { set_error("box lengths must be finite and > 0"); return MLS_ERR_INVALID_ARG; }
+  if (!finite_pos(p.cutoff)) { set_error("cutoff a must be finite and > 0"); return MLS_ERR_INVALID_ARG; }
+  bool explicit_grid = p.grid[0] > 0 || p.grid[1] > 0 || p.grid[2] > 0;
+  if (!explicit_grid && !finite_pos(p.h)) { set_error("spacing h must be finite and > 0"); return MLS_ERR_INVALID_ARG; }
+  if (p.order != 4 && p.order != 6) { set_error("order must be 4 (cubic) or 6 (quintic)"); return MLS_ERR_INVALID_ARG; }
+  if (p.levels < 0 || p.levels > 16) { set_error("levels must be in [0, 16]"); return MLS_ERR_INVALID_ARG; }
+  if (p.precision != MLS_FP64 && p.precision != MLS_MIXED) { set_error("precision must be MLS_FP64 or MLS_MIXED"); return MLS_ERR_INVALID_ARG; }
+  if (n_max < 0 || n_max > (int64_t)1 << 30) { set_error("n_max must be in [0, 2^30]"); return MLS_ERR_INVALID_ARG; }
+
+  P->params = p;
+  P->order = p.order;
+  P->precision = p.precision;
+  P->n_max = n_max;
+  P->a = p.cutoff;
+  P->a2 = p.cutoff * p.cutoff;
+  P->inv_a2 = 1.0 / P->a2;
+  P->inv_a6 = std::pow(p.cutoff, -6);
+  P->inv_a8 = std::pow(p.cutoff, -8);
+  P->cself = gamma_s(0.0) * P->inv_a6;  // eq:self-interaction-energy
+  hipGetDevice(&P->device);
+
+  // ---------------------------------------------------------------- levels
+  int l = p.levels;
+  if (l == 0) {
+    if (explicit_grid) { set_error("levels = 0 needs a spacing h, not an explicit grid"); return MLS_ERR_INVALID_ARG; }
+    // largest l whose coarsest grid keeps >= p points per dimension
+    int k = 0;
+    while (true) {
+      double mn = 1e300;
+      for (int d = 0; d < 3; ++d) mn = std::min(mn, std::floor(p.box[d] / (std::ldexp(p.h, k + 1)) + 0.5));
+      if (mn >= p.order && k < 15) ++k; else break;
+    }
+    l = k + 1;
+  }
+  P->levels = l;
+  const int m = 1 << (l - 1);
+  int n1[3];
+  for (int d = 0; d < 3; ++d) {
+    if (explicit_grid) {
+      n1[d] = p.grid[d];
+      if (n1[d] <= 0 || n1[d] % m) { set_error("grid dims must be > 0 and divisible by 2^(levels-1)"); return MLS_ERR_INVALID_ARG; }
+    } else {
+      double c = std::floor(p.box[d] / (m * p.h) + 0.5);
+      if (c > 4096.0) { set_error("finest grid too large"); return MLS_ERR_INVALID_ARG; }
+      n1[d] = m * (int)std::max(1.0, c);
+    }
+  }
+  if ((double)n1[0] * n1[1] * n1[2] > 1.0e9) { set_error("finest grid exceeds 1e9 points"); return MLS_ERR_INVALID_ARG; }
+  P->lv.resize(l);
+  for (int k = 1; k <= l; ++k) {
+    Level& L = P->lv[k - 1];
+    for (int d = 0; d < 3; ++d) {
+      L.g.n[d] = n1[d] >> (k - 1);
+      L.h[d] = p.box[d] / L.g.n[d];
+    }
+    L.g.size = L.g.n[0] * L.g.n[1] * L.g.n[2];
+  }
+  for (int d = 0; d < 3; ++d) P->invh1[d] = (double)n1[d] / p.box[d];
+
+  // ---------------------------------------------------------------- cells
+  CellGeom& cg = P->cg;
+  cg.ncell = 1;
+  for (int d = 0; d < 3; ++d) {
+    cg.L[d] = p.box[d];
+    cg.invL[d] = 1.0 / p.box[d];
+    double c = std::floor(p.box[d] / (p.cutoff * (1.0 + 1e-12)));
+    cg.nc[d] = (int)std::max(1.0, std::min(c, 1024.0));
+    cg.inv_w[d] = (double)cg.nc[d] / p.box[d];
+    cg.w[d] = p.box[d] / cg.nc[d];
+    cg.noff[d] = std::max(1, (int)std::ceil(p.cutoff / cg.w[d] - 1e-12));
+    cg.ncell *= cg.nc[d];
+  }
+
+  // ---------------------------------------------------------------- stencil
+  // offsets delta with |delta o h_1| < 2a; g_1 weights (Sec. II.A.4: the same
+  // table serves level k with spacing 2^(k-1) h_1, scaled by 2^(-6(k-1)))
+  const double* h1 = P->lv[0].h;
+  int R[3];
+  for (int d = 0; d < 3; ++d) R[d] = (int)std::ceil(2.0 * p.cutoff / h1[d]);
+  P->taps.clear();
+  P->rows.clear();
+  P->row_w.clear();
+  P->taps_wsum = 0.0;
+  for (int d = 0; d < 3; ++d) P->stencil_R[d] = 0;
+  if (l > 1) {
+    const double lim = 4.0 * p.cutoff * p.cutoff;
+    for (int dz = -R[2]; dz <= R[2]; ++dz)
+      for (int dy = -R[1]; dy <= R[1]; ++dy)
+        for (int dx = -R[0]; dx <= R[0]; ++dx) {
+          double sx = dx * h1[0], sy = dy * h1[1], sz = dz * h1[2];
+          double s2 = sx * sx + sy * sy + sz * sz;
+          if (s2 >= lim) continue;
+          Tap t{dx, dy, dz, 0, g_level1(std::sqrt(s2), p.cutoff)};
+          P->taps.push_back(t);
+          P->taps_wsum += t.w;
+          P->stencil_R[0] = std::max(P->stencil_R[0], std::abs(dx));
+          P->stencil_R[1] = std::max(P->stencil_R[1], std::abs(dy));
+          P->stencil_R[2] = std::max(P->stencil_R[2], std::abs(dz));
+        }
+    for (int dz = 0; dz <= R[2]; ++dz)
+      for (int dy = 0; dy <= R[1]; ++dy) {
+        double base = std::pow(dy * h1[1], 2) + std::pow(dz * h1[2], 2);
+        if (base >= lim) continue;
+        int hx = 0;
+        while (std::pow((hx + 1) * h1[0], 2) + base < lim) ++hx;
+        StencilRow r{dy, dz, hx, (int)P->row_w.size()};
+        for (int dx = 0; dx <= hx; ++dx)
+          P->row_w.push_back(g_level1(std::sqrt(std::pow(dx * h1[0], 2) + base), p.cutoff));
+        P->rows.push_back(r);
+      }
+  }
+
+  // ---------------------------------------------------------------- coarsest kernel
+  {
+    const Level& C = P->lv[l - 1];
+    const double A = std::ldexp(p.cutoff, l - 1);
+    LatticeR6 lat(p.box);
+    P->Kl.assign(C.g.size, 0.0);
+    int nimg[3];
+    for (int d = 0; d < 3; ++d) nimg[d] = (int)std::ceil(A / p.box[d]) + 1;
+    for (int z = 0; z < C.g.n[2]; ++z)
+      for (int y = 0; y < C.g.n[1]; ++y)
+        for (int x = 0; x < C.g.n[0]; ++x) {
+          double v[3] = {x * C.h[0], y * C.h[1], z * C.h[2]};
+          double K = lat(v);
+          // images inside A: replace r^-6 by g_l(r); the r = 0 image carries g_l(0)
+          for (int iz = -nimg[2]; iz <= nimg[2]; ++iz)
+            for (int iy = -nimg[1]; iy <= nimg[1]; ++iy)
+              for (int ix = -nimg[0]; ix <= nimg[0]; ++ix) {
+                double rx = v[0] + ix * p.box[0], ry = v[1] + iy * p.box[1], rz = v[2] + iz * p.box[2];
+                double r = std::sqrt(rx * rx + ry * ry + rz * rz);
+                if (r == 0.0) K += g_coarsest(0.0, A);
+                else if (r < A) K += g_coarsest(r, A) - std::pow(r, -6);
+              }
+          P->Kl[(size_t)(z * C.g.n[1] + y) * C.g.n[0] + x] = K;
+        }
+  }
+
+  // ---------------------------------------------------------------- device memory
+  mls_status st;
+#define ALLOC(ptr, cnt)                                                  \
+  do {                                                                   \
+    if ((st = dalloc(P, &(ptr), (size_t)(cnt))) != MLS_OK) return st;    \
+  } while (0)
+  const size_t N = (size_t)std::max<int64_t>(n_max, 1);
+  ALLOC(P->d_count, cg.ncell);
+  ALLOC(P->d_cell_start, cg.ncell + 1);
+  ALLOC(P->d_fill, cg.ncell);
+  ALLOC(P->d_cid, N);
+  ALLOC(P->d_perm_tmp, N);
+  ALLOC(P->d_perm, N);
+  ALLOC(P->d_cell_s, N);
+  ALLOC(P->d_xw, N);
+  ALLOC(P->d_xs, N);
+  ALLOC(P->d_e0, N);
+  ALLOC(P->d_floc, 3 * N);
+  if (P->precision == MLS_MIXED) ALLOC(P->d_xr, N);
+  P->n_partial = (int)((N + 255) / 256);
+  ALLOC(P->d_partial, 2 * (size_t)P->n_partial + 2);
+  ALLOC(P->d_scratch, 64);
+  ALLOC(P->d_flags, 4);
+  ALLOC(P->d_ncell_max, 4);
+  for (int k = 1; k <= l; ++k) {
+    Level& L = P->lv[k - 1];
+    ALLOC(L.q, L.g.size);
+    ALLOC(L.e, L.g.size);
+    if (k < l) {
+      ALLOC(L.E, L.g.size);
+    } else {
+      L.E = L.e;  // the coarsest level has nothing to prolongate into it
+    }
+    if (P->precision == MLS_MIXED && k < l) {
+      ALLOC(L.qf, L.g.size);
+    }
+  }
+  ALLOC(P->d_taps, P->taps.size());
+  ALLOC(P->d_rows, P->rows.size());
+  ALLOC(P->d_row_w, P->row_w.size());
+  ALLOC(P->d_row_wf, P->row_w.size());
+  ALLOC(P->d_Kl, P->Kl.size());
+#undef ALLOC
+  hipError_t e;
+  if (!P->taps.empty()) {
+    if ((e = hipMemcpy(P->d_taps, P->taps.data(), P->taps.size() * sizeof(Tap), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "copy stencil taps");
+    if ((e = hipMemcpy(P->d_rows, P->rows.data(), P->rows.size() * sizeof(StencilRow), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "copy stencil rows");
+    if ((e = hipMemcpy(P->d_row_w, P->row_w.data(), P->row_w.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "copy stencil weights");
+    std::vector<float> wf(P->row_w.begin(), P->row_w.end());
+    if ((e = hipMemcpy(P->d_row_wf, wf.data(), wf.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "copy stencil weights (fp32)");
+  }
+  if ((e = hipMemcpy(P->d_Kl, P->Kl.data(), P->Kl.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "copy coarsest kernel");
+  if ((e = hipMemset(P->d_flags, 0, 4 * sizeof(int))) != hipSuccess) return hip_fail(e, "clear flags");
+  return MLS_OK;
+}
+
+void free_plan(mls_plan_s* P) {
+  for (void* p : P->allocations) (void)hipFree(p);
+  P->allocations.clear();
+}
+
+}  // namespace mls

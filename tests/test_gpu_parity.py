@@ -1,0 +1,148 @@
+"""GPU parity through the C ABI: every stage of the HIP path against the FP64
+oracle on the same seeded inputs (FP64 path: rel. 1e-10 end to end, 1e-12 per
+stage; binning bit-exact)."""
+import numpy as np
+import pytest
+
+from oracle import exact, mls as M
+from paper_1308_4005_amd import workloads as W
+
+from gpu_common import force_errors, gpu_eval, rel_err, say, stages
+
+pytestmark = pytest.mark.gpu
+
+TOL_STAGE = 1e-12
+TOL_E = 1e-10
+
+
+def _cases():
+    c1 = W.named("cube1k")
+    slab = W.slab(2000, (12.0, 12.0, 48.0), 0.3, 0.7, rho_liquid=0.8, rho_vapour=0.02, seed=21)
+    aniso = W.cube(600, 0.5, seed=22)
+    aniso.box = np.array([11.0, 9.0, 13.5])
+    aniso.pos = np.mod(aniso.pos * aniso.box / aniso.box.max(), aniso.box)
+    rng = np.random.default_rng(23)
+    tiny = W.Workload("tiny", rng.random((30, 3)) * np.array([2.4, 3.1, 2.9]),
+                      rng.uniform(1.0, 9.0, 30), np.array([2.4, 3.1, 2.9]), {})
+    mix = W.cube(700, 0.8, seed=24)
+    mix.c6 = np.where(np.arange(700) % 3 == 0, 9.0, 4.0)
+    return [
+        ("cube1k_p4_l2", c1, dict(a=3.0, h=1.0, order=4, levels=2)),
+        ("cube1k_p6_l2", c1, dict(a=3.0, h=1.0, order=6, levels=2)),
+        ("slab2k_p4_l3", slab, dict(a=3.0, h=1.0, order=4, levels=3)),
+        ("aniso_p6_l3", aniso, dict(a=2.5, h=0.9, order=6, levels=3)),
+        ("tiny_images_l1", tiny, dict(a=2.6, h=0.5, order=4, levels=1)),
+        ("mix_p4_l4", mix, dict(a=2.2, h=0.7, order=4, levels=4)),
+    ]
+
+
+CASES = _cases()
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
+def case(request):
+    name, w, prm = request.param
+    say(f"[parity] case {name}: n={w.n} box={w.box} {prm}")
+    ref = M.mls(w.pos, w.c6, w.box, prm["a"], prm["h"], prm["order"], prm["levels"])
+    plan, out = gpu_eval(w.pos, w.c6, w.box, prm["a"], prm["h"], prm["order"], prm["levels"])
+    st = stages(plan, w.n)
+    return name, w, prm, ref, plan, out, st
+
+
+def test_plan_geometry(case):
+    name, w, prm, ref, plan, out, st = case
+    assert plan.info["levels"] == ref["levels"]
+    assert tuple(plan.info["grid"]) == tuple(int(x) for x in ref["n1"])
+    nc = M.cells_per_dim(w.box, prm["a"])
+    assert tuple(plan.info["cells"]) == tuple(int(x) for x in nc)
+
+
+def test_binning_bit_exact(case):
+    name, w, prm, ref, plan, out, st = case
+    nc, cid, start, perm = M.bin_cells(M.wrap(w.pos, w.box), w.box, prm["a"])
+    np.testing.assert_array_equal(st["cell_start"], start)
+    np.testing.assert_array_equal(st["perm"], perm)
+
+
+def test_local_part(case):
+    name, w, prm, ref, plan, out, st = case
+    assert rel_err(st["e0"], ref["e0"]) < TOL_STAGE
+    assert rel_err(st["Floc"], ref["Floc"]) < TOL_STAGE
+
+
+def test_grid_stages(case):
+    name, w, prm, ref, plan, out, st = case
+    for k in range(ref["levels"]):
+        assert rel_err(st["q"][k], ref["q"][k]) < TOL_STAGE, f"q level {k + 1}"
+        assert rel_err(st["e"][k], ref["e"][k]) < TOL_STAGE, f"e level {k + 1}"
+        assert rel_err(st["E"][k], ref["E"][k]) < TOL_STAGE, f"E level {k + 1}"
+
+
+def test_end_to_end(case):
+    name, w, prm, ref, plan, out, st = case
+    assert out["energy"] == pytest.approx(ref["energy"], rel=TOL_E)
+    rms = np.sqrt(np.mean(np.sum(ref["F"] ** 2, axis=1)))
+    assert np.max(np.abs(out["F"] - ref["F"])) < TOL_E * rms
+    assert rel_err(out["u"], ref["u"]) < TOL_E
+    assert rel_err(out["dE_dc6"], ref["dE_dc6"]) < TOL_E
+    say(f"[parity] {name}: E={out['energy']:.12e} ref={ref['energy']:.12e} "
+        f"force err (rms,dF,max)={force_errors(out['F'], ref['F'])}")
+
+
+def test_atoms_on_coarsest_nodes_are_exact():
+    box = np.array([8.0, 8.0, 16.0])
+    n1, h1 = M.resolve_grid(box, 1.0, 3)
+    hl = h1 * 4
+    nodes = np.array([[0, 0, 0], [1, 0, 1], [1, 1, 3], [0, 1, 2]], dtype=float) * hl
+    c6 = np.array([4.0, 9.0, 1.0, 2.5])
+    say("[parity] coarsest-node exactness")
+    plan, out = gpu_eval(nodes, c6, box, 1.0, 1.0, 4, 3)
+    E, F, u = exact.exact_ewald(nodes, c6, box)
+    assert out["energy"] == pytest.approx(E, rel=1e-12)
+
+
+def test_single_atom_and_empty():
+    box = np.array([9.0, 9.0, 9.0])
+    say("[parity] single atom")
+    pos = np.array([[1.3, 4.4, 8.9]])
+    c6 = np.array([4.0])
+    ref = M.mls(pos, c6, box, 3.0, 1.0, 4, 2)
+    plan, out = gpu_eval(pos, c6, box, 3.0, 1.0, 4, 2)
+    assert out["energy"] == pytest.approx(ref["energy"], rel=TOL_E)
+    np.testing.assert_allclose(out["F"], ref["F"], atol=1e-12)
+    say("[parity] empty input")
+    import torch
+    from paper_1308_4005_amd import Plan
+    p = Plan(box, 3.0, 1.0, 4, 2, n_max=10)
+    e = torch.zeros(0, 3, dtype=torch.float64, device="cuda")
+    r = p.evaluate(e, torch.zeros(0, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    assert float(r.energy.cpu()[0]) == 0.0
+
+
+def test_plan_reuse_with_smaller_input():
+    # one plan, two evaluations; the second with fewer atoms
+    w = W.named("cube1k")
+    say("[parity] plan reuse")
+    import torch
+    from paper_1308_4005_amd import Plan
+    plan = Plan(w.box, 3.0, 1.0, 4, 2, n_max=w.n)
+    for n in (w.n, 337):
+        ref = M.mls(w.pos[:n], w.c6[:n], w.box, 3.0, 1.0, 4, 2)
+        r = plan.evaluate(torch.tensor(w.pos[:n], device="cuda"), torch.tensor(w.c6[:n], device="cuda"))
+        torch.cuda.synchronize()
+        assert float(r.energy.cpu()[0]) == pytest.approx(ref["energy"], rel=TOL_E)
+
+
+def test_input_flags():
+    import torch
+    from paper_1308_4005_amd import Plan
+    box = np.array([9.0, 9.0, 9.0])
+    say("[parity] input flags")
+    plan = Plan(box, 3.0, 1.0, 4, 2, n_max=8)
+    pos = torch.tensor([[1.0, 2.0, 3.0], [float("nan"), 1.0, 1.0], [4.0, 4.0, 4.0]], dtype=torch.float64,
+                       device="cuda")
+    c6 = torch.tensor([4.0, 4.0, -1.0], dtype=torch.float64, device="cuda")
+    plan.evaluate(pos, c6)
+    assert plan.status() == 3
+    assert plan.status() == 0
