@@ -94,6 +94,7 @@ typedef struct {
   int64_t workspace_bytes; /* device memory the plan holds */
   int precision;
   int order;
+  double cell_width[3];    /* linked-cell width L_d / cells_d */
 } mls_plan_info;
 
 /* Build a plan on the current HIP device: resolves grids, levels and linked

@@ -75,7 +75,8 @@ class Plan:
         self.info = dict(levels=inf.levels, grid=tuple(inf.grid), coarsest=tuple(inf.coarsest),
                          cells=tuple(inf.cells), h_eff=tuple(inf.h_eff), taps=int(inf.taps),
                          n_max=int(inf.n_max), workspace_bytes=int(inf.workspace_bytes),
-                         precision=int(inf.precision), order=int(inf.order))
+                         precision=int(inf.precision), order=int(inf.order),
+                         cell_width=tuple(inf.cell_width))
         self.n_max = int(inf.n_max)
 
     # ------------------------------------------------------------------

@@ -63,6 +63,7 @@ class MLSPlanInfo(ctypes.Structure):
         ("workspace_bytes", ctypes.c_int64),
         ("precision", ctypes.c_int),
         ("order", ctypes.c_int),
+        ("cell_width", ctypes.c_double * 3),
     ]
 
 

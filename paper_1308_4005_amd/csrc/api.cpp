@@ -70,6 +70,7 @@ mls_status mls_plan_get_info(mls_plan_t P, mls_plan_info* info) {
     info->coarsest[d] = P->lv[P->levels - 1].g.n[d];
     info->cells[d] = P->cg.nc[d];
     info->h_eff[d] = P->lv[0].h[d];
+    info->cell_width[d] = P->cg.w[d];
   }
   info->taps = (int64_t)P->taps.size();
   info->n_max = P->n_max;

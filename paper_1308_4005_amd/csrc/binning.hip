@@ -1,9 +1,11 @@
 // Linked-cell binning (Sec. III.D): wrap positions into the box, assign each
-// atom to the cell of width L/nc (the smallest width >= a dividing the box),
-// and counting-sort the atoms by cell, stable in the original index.  The
-// result is integer and bit-exact: per-cell counts by atomics, an exclusive
-// scan, an unordered scatter, then a rank sort inside every cell by original
-// index.
+// atom to its cell, and counting-sort the atoms by cell, stable in the
+// original index.  The result is integer and bit-exact:
+//   1. per atom: wrapped position, cell id, arrival slot in its cell (atomic)
+//   2. exclusive scan of the cell counts (block scan, scan of block sums, add)
+//   3. scatter to start[cell] + slot (arrival order)
+//   4. per cell: reorder by original index (rank among the cell's atoms)
+//   5. gather the sorted position/xi array and cell ids
 #include <algorithm>
 
 #include "device_math.h"
@@ -16,8 +18,9 @@ constexpr int kBlock = 256;
 
 __global__ void __launch_bounds__(kBlock) k_bin_count(const double* __restrict__ pos,
                                                       const double* __restrict__ c6, int n, CellGeom g,
-                                                      int* __restrict__ cid, int* __restrict__ count,
-                                                      double4* __restrict__ xw, int* __restrict__ flags) {
+                                                      int* __restrict__ cid, int* __restrict__ slot,
+                                                      int* __restrict__ count, double4* __restrict__ xw,
+                                                      int* __restrict__ flags) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double x = pos[3 * (size_t)i], y = pos[3 * (size_t)i + 1], z = pos[3 * (size_t)i + 2];
@@ -31,85 +34,131 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(const double* __restrict__
     bad |= 2;
     c = 0.0;
   }
-  if (bad) atomicOr(flags, bad);
   double X = wrap_coord(x, g.L[0], g.invL[0]);
   double Y = wrap_coord(y, g.L[1], g.invL[1]);
   double Z = wrap_coord(z, g.L[2], g.invL[2]);
   // coordinates so large that the wrap loses them are reported, not binned
   if (!(X >= 0.0 && X < g.L[0] && Y >= 0.0 && Y < g.L[1] && Z >= 0.0 && Z < g.L[2])) {
-    atomicOr(flags, 1);
+    bad |= 1;
     X = Y = Z = 0.0;
   }
+  if (bad) atomicOr(flags, bad);
   int cx = max(0, min((int)(X * g.inv_w[0]), g.nc[0] - 1));
   int cy = max(0, min((int)(Y * g.inv_w[1]), g.nc[1] - 1));
   int cz = max(0, min((int)(Z * g.inv_w[2]), g.nc[2] - 1));
   int id = (cz * g.nc[1] + cy) * g.nc[0] + cx;
   cid[i] = id;
   xw[i] = make_double4(X, Y, Z, sqrt(c));
-  atomicAdd(&count[id], 1);
+  slot[i] = atomicAdd(&count[id], 1);
 }
 
-// Exclusive scan of `count` (m entries) into start[0..m]; one block.
-constexpr int kScan = 1024;
-__global__ void __launch_bounds__(kScan) k_scan(const int* __restrict__ count, int* __restrict__ start, int m,
-                                                int* __restrict__ max_count) {
-  __shared__ int s[kScan];
-  __shared__ int smax[kScan];
+// Scan phase 1: each block scans kScanItems consecutive counts (exclusive,
+// written to start) and records its total and maximum.
+constexpr int kScanPer = 8;
+constexpr int kScanItems = kBlock * kScanPer;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total) {
   const int t = threadIdx.x;
-  const int per = (m + kScan - 1) / kScan;
-  const int b = min(m, t * per), e = min(m, b + per);
-  int sum = 0, mx = 0;
-  for (int i = b; i < e; ++i) {
-    int c = count[i];
-    sum += c;
-    mx = max(mx, c);
-  }
-  s[t] = sum;
-  smax[t] = mx;
+  sh[t] = v;
   __syncthreads();
-  for (int off = 1; off < kScan; off <<= 1) {
-    int v = t >= off ? s[t - off] : 0;
-    int w = t >= off ? smax[t - off] : 0;
+  for (int off = 1; off < kBlock; off <<= 1) {
+    int u = t >= off ? sh[t - off] : 0;
     __syncthreads();
-    s[t] += v;
-    smax[t] = max(smax[t], w);
+    sh[t] += u;
     __syncthreads();
   }
-  int run = s[t] - sum;
-  for (int i = b; i < e; ++i) {
-    start[i] = run;
-    run += count[i];
+  total = sh[kBlock - 1];
+  const int excl = sh[t] - v;
+  __syncthreads();
+  return excl;
+}
+
+__device__ __forceinline__ int block_max(int v, int* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + off]);
+    __syncthreads();
   }
-  if (t == kScan - 1) {
-    start[m] = s[kScan - 1];
-    *max_count = smax[kScan - 1];
+  const int r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_blocks(const int* __restrict__ count, int m,
+                                                        int* __restrict__ start, int* __restrict__ bsum,
+                                                        int* __restrict__ bmax) {
+  __shared__ int sh[kBlock];
+  const int base = blockIdx.x * kScanItems + threadIdx.x * kScanPer;
+  int v[kScanPer];
+  int sum = 0, mx = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = base + k < m ? count[base + k] : 0;
+    sum += v[k];
+    mx = max(mx, v[k]);
+  }
+  int total;
+  int run = block_exclusive_scan(sum, sh, total);
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < m) start[base + k] = run;
+    run += v[k];
+  }
+  const int bm = block_max(mx, sh);
+  if (threadIdx.x == 0) {
+    bsum[blockIdx.x] = total;
+    bmax[blockIdx.x] = bm;
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_bin_scatter(const int* __restrict__ cid, int n,
-                                                        const int* __restrict__ start, int* __restrict__ fill,
+// Scan phase 2: one block turns the block totals into exclusive offsets and
+// writes the grand total start[m] and the largest cell count.
+__global__ void __launch_bounds__(kBlock) k_scan_sums(int* __restrict__ bsum, const int* __restrict__ bmax, int nb,
+                                                      int* __restrict__ start, int m, int* __restrict__ max_count) {
+  __shared__ int sh[kBlock];
+  int carry = 0, mx = 0;
+  for (int b0 = 0; b0 < nb; b0 += kBlock) {
+    const int b = b0 + threadIdx.x;
+    const int v = b < nb ? bsum[b] : 0;
+    if (b < nb) mx = max(mx, bmax[b]);
+    int total;
+    const int ex = block_exclusive_scan(v, sh, total);
+    if (b < nb) bsum[b] = carry + ex;
+    carry += total;
+  }
+  const int bm = block_max(mx, sh);
+  if (threadIdx.x == 0) {
+    start[m] = carry;
+    *max_count = bm;
+  }
+}
+
+// Scan phase 3: add each block's offset.
+__global__ void __launch_bounds__(kBlock) k_scan_add(int* __restrict__ start, int m, const int* __restrict__ bsum) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < m) start[c] += bsum[c / kScanItems];
+}
+
+__global__ void __launch_bounds__(kBlock) k_bin_scatter(const int* __restrict__ cid, const int* __restrict__ slot,
+                                                        int n, const int* __restrict__ start,
                                                         int* __restrict__ perm_tmp) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int c = cid[i];
-  int slot = start[c] + atomicAdd(&fill[c], 1);
-  perm_tmp[slot] = i;
+  perm_tmp[start[cid[i]] + slot[i]] = i;
 }
 
-// One wave per cell: each atom's rank among the cell's atoms by original
-// index gives its stable position.
-constexpr int kWave = 64;
+// One thread per cell: each atom's rank among the cell's atoms by original
+// index is its stable position.
 __global__ void __launch_bounds__(kBlock) k_cell_rank(const int* __restrict__ start, int ncell,
                                                       const int* __restrict__ perm_tmp, int* __restrict__ perm) {
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (wave >= ncell) return;
-  const int b = start[wave], e = start[wave + 1];
-  const int cnt = e - b;
-  for (int k = lane; k < cnt; k += kWave) {
-    const int v = perm_tmp[b + k];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int b = start[c], e = start[c + 1];
+  for (int k = b; k < e; ++k) {
+    const int v = perm_tmp[k];
     int rank = 0;
-    for (int j = 0; j < cnt; ++j) rank += perm_tmp[b + j] < v;
+    for (int j = b; j < e; ++j) rank += perm_tmp[j] < v;
     perm[b + rank] = v;
   }
 }
@@ -148,6 +197,8 @@ inline int nblocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
 
+int scan_blocks(int ncell) { return nblocks(ncell, kScanItems); }
+
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   int blocks = (int)std::min<int64_t>(nblocks(count, kBlock), 4096);
@@ -166,18 +217,22 @@ hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double*
   const CellGeom& g = P->cg;
   hipError_t e;
   if ((e = launch_zero_i(P->d_count, g.ncell, s)) != hipSuccess) return e;
-  if ((e = launch_zero_i(P->d_fill, g.ncell, s)) != hipSuccess) return e;
   if (n > 0) {
-    k_bin_count<<<nblocks(n, kBlock), kBlock, 0, s>>>(pos, c6, n, g, P->d_cid, P->d_count, P->d_xw, P->d_flags);
+    k_bin_count<<<nblocks(n, kBlock), kBlock, 0, s>>>(pos, c6, n, g, P->d_cid, P->d_slot, P->d_count, P->d_xw,
+                                                      P->d_flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  k_scan<<<1, kScan, 0, s>>>(P->d_count, P->d_cell_start, g.ncell, P->d_ncell_max);
+  const int nb = scan_blocks(g.ncell);
+  k_scan_blocks<<<nb, kBlock, 0, s>>>(P->d_count, g.ncell, P->d_cell_start, P->d_bsum, P->d_bmax);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_scan_sums<<<1, kBlock, 0, s>>>(P->d_bsum, P->d_bmax, nb, P->d_cell_start, g.ncell, P->d_ncell_max);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_scan_add<<<nblocks(g.ncell, kBlock), kBlock, 0, s>>>(P->d_cell_start, g.ncell, P->d_bsum);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (n == 0) return hipSuccess;
-  k_bin_scatter<<<nblocks(n, kBlock), kBlock, 0, s>>>(P->d_cid, n, P->d_cell_start, P->d_fill, P->d_perm_tmp);
+  k_bin_scatter<<<nblocks(n, kBlock), kBlock, 0, s>>>(P->d_cid, P->d_slot, n, P->d_cell_start, P->d_perm_tmp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_cell_rank<<<nblocks((int64_t)g.ncell * kWave, kBlock), kBlock, 0, s>>>(P->d_cell_start, g.ncell,
-                                                                           P->d_perm_tmp, P->d_perm);
+  k_cell_rank<<<nblocks(g.ncell, kBlock), kBlock, 0, s>>>(P->d_cell_start, g.ncell, P->d_perm_tmp, P->d_perm);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_gather_sorted<<<nblocks(n, kBlock), kBlock, 0, s>>>(P->d_perm, n, P->d_xw, P->d_cid, P->d_xs, P->d_cell_s,
                                                         P->d_xr, g);

@@ -54,6 +54,120 @@ __global__ void __launch_bounds__(kBlock) k_anterp_f64(const double4* __restrict
     }
 }
 
+// Owner-computes anterpolation: a block owns the finest-grid points whose
+// positions fall inside a box of CBx x CBy x CBz linked cells (point m of
+// dimension d belongs to cell-block b when ceil(c0 n/nc) <= m < ceil(c1 n/nc)).
+// It gathers the atoms of those cells and of an nh-cell halo (with their
+// periodic image shifts), adds each atom's p^3 contributions that land on
+// owned points into an LDS tile, and stores the tile without global atomics.
+constexpr int kAntTile = 16;     // max owned points per dimension
+constexpr int kAntThreads = 256;
+constexpr int kMaxSeg = 1024;
+
+struct AntGeom {
+  int cb[3];   // cells per block and dimension
+  int nb[3];   // blocks per dimension
+  int nh[3];   // halo cells
+};
+
+template <int P>
+__global__ void __launch_bounds__(kAntThreads) k_anterp_owned(const double4* __restrict__ xs,
+                                                              const int* __restrict__ cstart, CellGeom cg,
+                                                              GridGeom gg, AntGeom ag, double* __restrict__ q) {
+  __shared__ double tile[kAntTile * kAntTile * kAntTile];
+  __shared__ int seg_begin[kMaxSeg];
+  __shared__ int seg_off[kMaxSeg + 1];
+  __shared__ int seg_shift[kMaxSeg][3];
+  __shared__ int nseg_s;
+  const int b = blockIdx.x;
+  const int bi[3] = {b % ag.nb[0], (b / ag.nb[0]) % ag.nb[1], b / (ag.nb[0] * ag.nb[1])};
+  int c0[3], c1[3], lo[3], wd[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    c0[d] = bi[d] * ag.cb[d];
+    c1[d] = min(c0[d] + ag.cb[d], cg.nc[d]);
+    lo[d] = (c0[d] * gg.n[d] + cg.nc[d] - 1) / cg.nc[d];
+    wd[d] = (c1[d] * gg.n[d] + cg.nc[d] - 1) / cg.nc[d] - lo[d];
+  }
+  for (int i = threadIdx.x; i < kAntTile * kAntTile * kAntTile; i += kAntThreads) tile[i] = 0.0;
+  if (threadIdx.x == 0) {
+    // contiguous runs of sorted atoms: rows of cells along x, split where the
+    // periodic image changes
+    int ns = 0, tot = 0;
+    for (int cz = c0[2] - ag.nh[2]; cz < c1[2] + ag.nh[2]; ++cz) {
+      const int iz = floordiv(cz, cg.nc[2]);
+      const int wz = cz - iz * cg.nc[2];
+      for (int cy = c0[1] - ag.nh[1]; cy < c1[1] + ag.nh[1]; ++cy) {
+        const int iy = floordiv(cy, cg.nc[1]);
+        const int wy = cy - iy * cg.nc[1];
+        const int rowc = (wz * cg.nc[1] + wy) * cg.nc[0];
+        int cx = c0[0] - ag.nh[0];
+        const int cxe = c1[0] + ag.nh[0];
+        while (cx < cxe) {
+          const int ix = floordiv(cx, cg.nc[0]);
+          const int wx = cx - ix * cg.nc[0];
+          const int run = min(cxe - cx, cg.nc[0] - wx);
+          const int a0 = cstart[rowc + wx], a1 = cstart[rowc + wx + run];
+          if (a1 > a0 && ns < kMaxSeg) {
+            seg_begin[ns] = a0;
+            seg_off[ns] = tot;
+            seg_shift[ns][0] = ix;
+            seg_shift[ns][1] = iy;
+            seg_shift[ns][2] = iz;
+            tot += a1 - a0;
+            ++ns;
+          }
+          cx += run;
+        }
+      }
+    }
+    seg_off[ns] = tot;
+    nseg_s = ns;
+  }
+  __syncthreads();
+  const int ns = nseg_s;
+  const int tot = seg_off[ns];
+  int sg = 0;
+  for (int i = threadIdx.x; i < tot; i += kAntThreads) {
+    while (seg_off[sg + 1] <= i) ++sg;
+    const double4 p = xs[seg_begin[sg] + (i - seg_off[sg])];
+    const double pc[3] = {p.x, p.y, p.z};
+    double w[3][P];
+    int l0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double t = pc[d] * gg.invh[d];
+      const double m0 = floor(t);
+      basis_weights<P, double>(t - m0, w[d]);
+      l0[d] = (int)m0 - (P / 2 - 1) + seg_shift[sg][d] * gg.n[d] - lo[d];
+    }
+#pragma unroll
+    for (int jz = 0; jz < P; ++jz) {
+      const int lz = l0[2] + jz;
+      if (lz < 0 || lz >= wd[2]) continue;
+#pragma unroll
+      for (int jy = 0; jy < P; ++jy) {
+        const int ly = l0[1] + jy;
+        if (ly < 0 || ly >= wd[1]) continue;
+        const double wzy = p.w * w[2][jz] * w[1][jy];
+        double* row = tile + (lz * kAntTile + ly) * kAntTile;
+#pragma unroll
+        for (int jx = 0; jx < P; ++jx) {
+          const int lx = l0[0] + jx;
+          if (lx >= 0 && lx < wd[0]) atomicAdd(row + lx, wzy * w[0][jx]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int cnt = wd[0] * wd[1] * wd[2];
+  for (int i = threadIdx.x; i < cnt; i += kAntThreads) {
+    const int lx = i % wd[0], ly = (i / wd[0]) % wd[1], lz = i / (wd[0] * wd[1]);
+    q[((size_t)(lo[2] + lz) * gg.n[1] + (lo[1] + ly)) * gg.n[0] + lo[0] + lx] =
+        tile[(lz * kAntTile + ly) * kAntTile + lx];
+  }
+}
+
 // ------------------------------------------------------------ restriction
 // Per-dimension taps around fine index 2M: offsets 0, +-1, +-3 (, +-5).
 template <int P>
@@ -268,11 +382,43 @@ GridGeom finest_geom(const mls_plan_s* P) {
 
 }  // namespace
 
+// Owner-computes geometry: cells per block so that a block owns at most
+// kAntTile points per dimension, halo cells covering the basis support.
+bool anterp_owned_geom(const mls_plan_s* P, AntGeom& ag) {
+  const int half = P->order / 2;
+  int segs = 1;
+  for (int d = 0; d < 3; ++d) {
+    const int n = P->lv[0].g.n[d], nc = P->cg.nc[d];
+    // owned width of cb cells <= ceil(cb n / nc) <= kAntTile
+    int cb = 0;
+    while (cb < nc && ((cb + 1) * (int64_t)n + nc - 1) / nc <= kAntTile) ++cb;
+    if (cb == 0) return false;
+    ag.cb[d] = cb;
+    ag.nb[d] = (nc + cb - 1) / cb;
+    // atoms within (half + 1) grid spacings of the owned range
+    ag.nh[d] = (int)(((int64_t)(half + 1) * nc + n - 1) / n);
+    const int span = cb + 2 * ag.nh[d];
+    // rows along x split at every periodic wrap
+    segs *= (d == 0 ? std::min(span, (span + nc - 1) / nc + 1) : span);
+  }
+  return segs <= kMaxSeg;
+}
+
 hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s) {
   Level& L1 = P->lv[0];
+  GridGeom gg = finest_geom(P);
+  AntGeom ag;
+  if (anterp_owned_geom(P, ag)) {
+    // every owned point is written, so no zero fill is needed
+    const int nb = ag.nb[0] * ag.nb[1] * ag.nb[2];
+    if (P->order == 4)
+      k_anterp_owned<4><<<nb, kAntThreads, 0, s>>>(P->d_xs, P->d_cell_start, P->cg, gg, ag, L1.q);
+    else
+      k_anterp_owned<6><<<nb, kAntThreads, 0, s>>>(P->d_xs, P->d_cell_start, P->cg, gg, ag, L1.q);
+    return hipGetLastError();
+  }
   hipError_t e = launch_zero(L1.q, L1.g.size, s);
   if (e != hipSuccess || n == 0) return e;
-  GridGeom gg = finest_geom(P);
   if (P->order == 4)
     k_anterp_f64<4><<<nblocks(n, kBlock), kBlock, 0, s>>>(P->d_xs, n, gg, L1.q);
   else

@@ -22,7 +22,7 @@ struct CellGeom {
   double inv_w[3];   // nc / L: cell index = trunc(x_w * inv_w)
   double w[3];       // L / nc
   int nc[3];         // cells per dimension
-  int noff[3];       // neighbour-cell reach (1 unless the box is narrower than a)
+  int noff[3];       // neighbour-cell reach: ceil(a / w)
   int ncell;
 };
 
@@ -37,13 +37,18 @@ struct Tap {
   double w;
 };
 
-// Run of stencil taps sharing |dy|,|dz| (rows folded by the +-dy, +-dz mirror
-// symmetry of the radial kernel) and a half-width in x.
+// Column of stencil taps along z sharing |dx|,|dy|: the radial kernel is
+// mirror symmetric in x and y, so the up to four columns (+-dx, +-dy) are
+// summed before the taps dz in [-hz, hz] with weights w[|dz|] are applied.
 struct StencilRow {
-  int dy, dz;        // >= 0
-  int hx;            // taps dx in [-hx, hx]
-  int woff;          // offset of the hx+1 weights w[|dx|] in the weight table
+  int dx, dy;        // >= 0
+  int hz;            // taps dz in [-hz, hz]
+  int woff;          // offset of the hz+1 weights w[|dz|] in the weight table
 };
+
+// Waves per block of the level-stencil kernel; the tap columns are split
+// into this many cost-balanced contiguous ranges at plan time.
+constexpr int kStencilWaves = 4;
 
 // Per-level bookkeeping of the grid hierarchy.
 struct Level {
@@ -77,6 +82,12 @@ struct mls_plan_s {
   int stencil_R[3]{};              // max |dx|, |dy|, |dz|
   mls::Tap* d_taps = nullptr;
   mls::StencilRow* d_rows = nullptr;
+  int* d_wave_rows = nullptr;      // kStencilWaves + 1 offsets into rows
+  double* d_row_w_tile = nullptr;  // weights divided by the mirror duplication on the axes
+  int4* d_tiles = nullptr;         // (level-1, tile x, tile y, tile z) of the tiled stencil
+  int ntiles = 0;
+  int stencil_kernel = 1;          // 1: LDS tile kernel, 0: plane-streaming kernel
+  int stencil_min_waves = 1536;    // launch-shape knob of the level stencils
   double* d_row_w = nullptr;
   float* d_row_wf = nullptr;
   double taps_wsum = 0;            // sum of level-1 weights (mean term in mixed precision)
@@ -88,7 +99,10 @@ struct mls_plan_s {
   // atom workspace
   int* d_count = nullptr;          // ncell
   int* d_cell_start = nullptr;     // ncell + 1
-  int* d_fill = nullptr;           // ncell
+  int* d_slot = nullptr;           // n_max: arrival slot of an atom in its cell
+  int* d_bsum = nullptr;           // scan block sums
+  int* d_bmax = nullptr;           // scan block maxima
+  bool pair_fast = false;          // half-cutoff cells with per-atom row trimming
   int* d_cid = nullptr;            // n_max: cell of original atom
   int* d_perm_tmp = nullptr;       // n_max
   int* d_perm = nullptr;           // n_max
@@ -124,6 +138,12 @@ mls_status hip_fail(hipError_t e, const char* what);
 // plan construction (plan.cpp)
 mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* plan);
 void free_plan(mls_plan_s* plan);
+
+// number of blocks of the cell-count scan
+int scan_blocks(int ncell);
+// halo window of the level stencil and z extent of its LDS tile
+int stencil_window(const mls_plan_s* P);
+int stencil_tile_zc(int R);
 
 // kernel launchers (one per file); all enqueue on `s` and return the launch status
 hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double* c6, hipStream_t s);

@@ -20,9 +20,22 @@ struct PairConst {
 };
 
 // g_0(r) and g_0'(r)/r from s = r^2 (caller guarantees 0 < s < a^2).
+// 1/s from the hardware reciprocal refined by Newton steps (two in FP64,
+// one in FP32): cheaper than the correctly rounded division sequence and
+// accurate to the last bit or so.
+__device__ __forceinline__ double recip(double s) {
+  double r = __builtin_amdgcn_rcp(s);
+  r = fma(fma(-s, r, 1.0), r, r);
+  return fma(fma(-s, r, 1.0), r, r);
+}
+__device__ __forceinline__ float recip(float s) {
+  float r = __builtin_amdgcn_rcpf(s);
+  return fmaf(fmaf(-s, r, 1.0f), r, r);
+}
+
 template <class T>
 __device__ __forceinline__ void g0_pair(T s, T inv_a2, T inv_a6, T inv_a8, T& g, T& fr) {
-  T ir2 = T(1) / s;
+  T ir2 = recip(s);
   T ir6 = ir2 * ir2 * ir2;
   T u = s * inv_a2;            // rho^2
   T u2 = u * u;
@@ -89,13 +102,155 @@ __global__ void __launch_bounds__(kBlock) k_pair_f64(const double4* __restrict__
   floc[3 * (size_t)s + 2] = xi.w * fz;
 }
 
+// FP64, filter-and-drain over half-cutoff cells: one wave of 64 lanes takes
+// 64 consecutive cell-sorted targets.  Each lane visits the 5 x 5 rows of
+// cells around its target's cell, skips rows whose y/z gap to the target is
+// at least a, and trims every other row to the cells the cutoff sphere can
+// reach along x (split at the box edge into periodic images).  A cheap
+// distance test appends sources inside the cutoff to the lane's LDS queue,
+// four candidates per step so four loads are in flight; whenever a queue may
+// overflow, and once at the end, all lanes drain their queues through the
+// full g_0 evaluation, so the expensive arithmetic runs on nearly full waves
+// instead of being masked per candidate.  An entry packs the source index
+// (< 2^26) with its image code (27 images).
+constexpr int kWaveQ = 64;    // lanes per block (one wave)
+constexpr int kQueue = 32;    // entries per lane
+constexpr int kBatch = 4;     // candidates per filter step
+
+__device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, int cnt, int lane,
+                                               const double4& xi, const double4* __restrict__ xs, const CellGeom& g,
+                                               const PairConst& pc, double& e, double& fx, double& fy, double& fz) {
+  for (int t = 0; __any(t < cnt); ++t) {
+    if (t < cnt) {
+      const int ent = queue[t * kWaveQ + lane];
+      const int j = ent >> 5;
+      const int code = ent & 31;
+      const int ix = code % 3 - 1, iy = (code / 3) % 3 - 1, iz = code / 9 - 1;
+      const double4 xj = xs[j];
+      // same arithmetic as the filter, so the cutoff decision is identical
+      const double dx = (xi.x - ix * g.L[0]) - xj.x;
+      const double dy = (xi.y - iy * g.L[1]) - xj.y;
+      const double dz = (xi.z - iz * g.L[2]) - xj.z;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      double gg, fr;
+      g0_pair<double>(r2, pc.inv_a2, pc.inv_a6, pc.inv_a8, gg, fr);
+      e += xj.w * gg;
+      const double f = xj.w * fr;
+      fx += f * dx;
+      fy += f * dy;
+      fz += f * dz;
+    }
+  }
+}
+
+struct PairAcc {
+  double e, fx, fy, fz;
+  int cnt;
+};
+
+// Scan sources [j, j1) seen through image `code` (convergent: every lane
+// calls it, lanes with an empty range just take part in the votes).
+__device__ __forceinline__ void pair_scan_f64(int j, int j1, int code, int s, int s_safe, int* __restrict__ queue,
+                                              int lane, const double4& xi, const double4* __restrict__ xs,
+                                              const CellGeom& g, const PairConst& pc, PairAcc& A) {
+  const int ix = code % 3 - 1, iy = (code / 3) % 3 - 1, iz = code / 9 - 1;
+  const double ax = xi.x - ix * g.L[0], ay = xi.y - iy * g.L[1], az = xi.z - iz * g.L[2];
+  const int self = code == 13 ? s : -1;
+  while (__any(j < j1)) {
+    double4 xj[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) xj[b] = xs[j + b < j1 ? j + b : s_safe];  // past the range: any valid row
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const double dx = ax - xj[b].x, dy = ay - xj[b].y, dz = az - xj[b].z;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const int jb = j + b;
+      const bool hit = jb < j1 && r2 < pc.a2 && jb != self;
+      // slot cnt is free: write unconditionally, keep it only on a hit
+      queue[A.cnt * kWaveQ + lane] = (jb << 5) | code;
+      A.cnt += hit ? 1 : 0;
+    }
+    j += kBatch;
+    if (__any(A.cnt > kQueue - kBatch)) {
+      pair_drain_f64(queue, A.cnt, lane, xi, xs, g, pc, A.e, A.fx, A.fy, A.fz);
+      A.cnt = 0;
+    }
+  }
+}
+
+__device__ __forceinline__ double gap1(double x, double lo, double w, double eps) {
+  return fmax(0.0, fmax(lo - x, x - (lo + w)) - eps);
+}
+
+__global__ void __launch_bounds__(kWaveQ) k_pair_trim_f64(const double4* __restrict__ xs,
+                                                          const int* __restrict__ cell_s,
+                                                          const int* __restrict__ cstart, int n, CellGeom g,
+                                                          PairConst pc, double* __restrict__ e0,
+                                                          double* __restrict__ floc) {
+  __shared__ int queue[kQueue * kWaveQ];
+  const int lane = threadIdx.x;
+  const int s = blockIdx.x * kWaveQ + lane;
+  const bool active = s < n;
+  const int sc = active ? s : n - 1;
+  const double4 xi = xs[sc];
+  const int c = cell_s[sc];
+  const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
+  PairAcc A{0.0, 0.0, 0.0, 0.0, 0};
+  for (int dz = -2; dz <= 2; ++dz) {
+    const int uz = cz + dz;
+    const int iz = uz < 0 ? -1 : (uz >= g.nc[2] ? 1 : 0);
+    const int tz = uz - iz * g.nc[2];
+    const double gz = gap1(xi.z, uz * g.w[2], g.w[2], 1e-12 * g.L[2]);
+    for (int dy = -2; dy <= 2; ++dy) {
+      const int uy = cy + dy;
+      const int iy = uy < 0 ? -1 : (uy >= g.nc[1] ? 1 : 0);
+      const int ty = uy - iy * g.nc[1];
+      const double gy = gap1(xi.y, uy * g.w[1], g.w[1], 1e-12 * g.L[1]);
+      const double rem = pc.a2 - (gy * gy + gz * gz);
+      int clo = 0, chi = -1;
+      if (active && rem > 0.0) {
+        // x cells the cutoff sphere reaches in this row (slightly widened)
+        const double rx = sqrt(rem) * (1.0 + 1e-12) + 1e-12 * g.L[0];
+        clo = max(cx - 2, (int)floor((xi.x - rx) * g.inv_w[0]));
+        chi = min(cx + 2, (int)floor((xi.x + rx) * g.inv_w[0]));
+      }
+      const int row = (tz * g.nc[1] + ty) * g.nc[0];
+      const int cyz = 3 * ((iy + 1) + 3 * (iz + 1));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int ix = k - 1;  // image of the cells [lo, hi] along x
+        const int lo = max(clo, ix * g.nc[0]), hi = min(chi, ix * g.nc[0] + g.nc[0] - 1);
+        int j0 = 0, j1 = 0;
+        if (lo <= hi) {
+          j0 = cstart[row + lo - ix * g.nc[0]];
+          j1 = cstart[row + hi - ix * g.nc[0] + 1];
+        }
+        pair_scan_f64(j0, j1, (ix + 1) + cyz, s, sc, queue, lane, xi, xs, g, pc, A);
+      }
+    }
+  }
+  pair_drain_f64(queue, A.cnt, lane, xi, xs, g, pc, A.e, A.fx, A.fy, A.fz);
+  if (active) {
+    e0[s] = A.e;
+    floc[3 * (size_t)s + 0] = xi.w * A.fx;
+    floc[3 * (size_t)s + 1] = xi.w * A.fy;
+    floc[3 * (size_t)s + 2] = xi.w * A.fz;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   PairConst pc{P->a2, P->inv_a2, P->inv_a6, P->inv_a8};
-  k_pair_f64<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(P->d_xs, P->d_cell_s, P->d_cell_start, n, P->cg, pc,
-                                                          P->d_e0, P->d_floc);
+  const CellGeom& g = P->cg;
+  if (P->pair_fast && n < (1 << 26)) {
+    k_pair_trim_f64<<<(n + kWaveQ - 1) / kWaveQ, kWaveQ, 0, s>>>(P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pc,
+                                                                 P->d_e0, P->d_floc);
+  } else {
+    k_pair_f64<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pc,
+                                                            P->d_e0, P->d_floc);
+  }
   return hipGetLastError();
 }
 

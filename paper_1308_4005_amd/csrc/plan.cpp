@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -185,16 +186,27 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   for (int d = 0; d < 3; ++d) P->invh1[d] = (double)n1[d] / p.box[d];
 
   // ---------------------------------------------------------------- cells
+  // Linked cells (Sec. III.D use the smallest width >= a dividing the box).
+  // When the box spans at least five half-cutoff cells per dimension the
+  // cells are made half as wide (the smallest width >= a/2 dividing the box):
+  // the pair kernel then trims each neighbour row to the cutoff sphere, which
+  // examines far fewer candidates.  The pairs found are the same.
   CellGeom& cg = P->cg;
+  bool fast = true;
+  for (int d = 0; d < 3; ++d)
+    if (std::floor(p.box[d] / (0.5 * p.cutoff * (1.0 + 1e-12))) < 5.0) fast = false;
+  P->pair_fast = fast;
+  const double cw = fast ? 0.5 * p.cutoff : p.cutoff;
   cg.ncell = 1;
   for (int d = 0; d < 3; ++d) {
     cg.L[d] = p.box[d];
     cg.invL[d] = 1.0 / p.box[d];
-    double c = std::floor(p.box[d] / (p.cutoff * (1.0 + 1e-12)));
-    cg.nc[d] = (int)std::max(1.0, std::min(c, 1024.0));
+    double c = std::floor(p.box[d] / (cw * (1.0 + 1e-12)));
+    cg.nc[d] = (int)std::max(1.0, std::min(c, 2048.0));
     cg.inv_w[d] = (double)cg.nc[d] / p.box[d];
     cg.w[d] = p.box[d] / cg.nc[d];
     cg.noff[d] = std::max(1, (int)std::ceil(p.cutoff / cg.w[d] - 1e-12));
+    if ((double)cg.ncell * cg.nc[d] > 2.0e8) { set_error("too many linked cells"); return MLS_ERR_INVALID_ARG; }
     cg.ncell *= cg.nc[d];
   }
 
@@ -224,18 +236,61 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
           P->stencil_R[1] = std::max(P->stencil_R[1], std::abs(dy));
           P->stencil_R[2] = std::max(P->stencil_R[2], std::abs(dz));
         }
-    for (int dz = 0; dz <= R[2]; ++dz)
-      for (int dy = 0; dy <= R[1]; ++dy) {
-        double base = std::pow(dy * h1[1], 2) + std::pow(dz * h1[2], 2);
+    for (int dy = 0; dy <= R[1]; ++dy)
+      for (int dx = 0; dx <= R[0]; ++dx) {
+        double base = std::pow(dx * h1[0], 2) + std::pow(dy * h1[1], 2);
         if (base >= lim) continue;
-        int hx = 0;
-        while (std::pow((hx + 1) * h1[0], 2) + base < lim) ++hx;
-        StencilRow r{dy, dz, hx, (int)P->row_w.size()};
-        for (int dx = 0; dx <= hx; ++dx)
-          P->row_w.push_back(g_level1(std::sqrt(std::pow(dx * h1[0], 2) + base), p.cutoff));
+        int hz = 0;
+        while (std::pow((hz + 1) * h1[2], 2) + base < lim) ++hz;
+        StencilRow r{dx, dy, hz, (int)P->row_w.size()};
+        for (int dz = 0; dz <= hz; ++dz)
+          P->row_w.push_back(g_level1(std::sqrt(std::pow(dz * h1[2], 2) + base), p.cutoff));
         P->rows.push_back(r);
       }
   }
+
+  // contiguous, cost-balanced split of the tap columns over the waves of a
+  // stencil block (cost: mirror loads plus the 2 hz + 1 column updates)
+  std::vector<int> wave_rows(kStencilWaves + 1, (int)P->rows.size());
+  {
+    double total = 0.0;
+    std::vector<double> cost;
+    for (const auto& r : P->rows) {
+      double m = (r.dx ? 2 : 1) * (r.dy ? 2 : 1);
+      cost.push_back(m + 2 * r.hz + 1);
+      total += cost.back();
+    }
+    wave_rows[0] = 0;
+    double run = 0.0;
+    int w = 1;
+    for (size_t i = 0; i < cost.size() && w < kStencilWaves; ++i) {
+      run += cost[i];
+      if (run >= total * w / kStencilWaves) wave_rows[w++] = (int)i + 1;
+    }
+    for (; w < kStencilWaves; ++w) wave_rows[w] = (int)P->rows.size();
+  }
+
+  // tiled stencil: weights compensating the duplicated mirror images on the
+  // axes, and the table of (level, tile) blocks of one launch
+  std::vector<double> row_w_tile(P->row_w);
+  for (const auto& r : P->rows) {
+    const double mult = (r.dx == 0 ? 2.0 : 1.0) * (r.dy == 0 ? 2.0 : 1.0);
+    for (int d = 0; d <= r.hz; ++d) row_w_tile[r.woff + d] /= mult;
+  }
+  std::vector<int4> tiles;
+  if (const char* env = std::getenv("MLS_STENCIL_KERNEL")) P->stencil_kernel = std::atoi(env) == 0 ? 0 : 1;
+  if (l > 1) {
+    const int Rw = stencil_window(P);
+    const int zc = stencil_tile_zc(Rw);
+    for (int k = 1; k < l; ++k) {
+      const GridDims& g = P->lv[k - 1].g;
+      const int tx = (g.n[0] + 7) / 8, ty = (g.n[1] + 7) / 8, tz = (g.n[2] + zc - 1) / zc;
+      for (int z = 0; z < tz; ++z)
+        for (int y = 0; y < ty; ++y)
+          for (int x = 0; x < tx; ++x) tiles.push_back(make_int4(k - 1, x, y, z));
+    }
+  }
+  P->ntiles = (int)tiles.size();
 
   // ---------------------------------------------------------------- coarsest kernel
   {
@@ -272,7 +327,9 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   const size_t N = (size_t)std::max<int64_t>(n_max, 1);
   ALLOC(P->d_count, cg.ncell);
   ALLOC(P->d_cell_start, cg.ncell + 1);
-  ALLOC(P->d_fill, cg.ncell);
+  ALLOC(P->d_slot, N);
+  ALLOC(P->d_bsum, scan_blocks(cg.ncell) + 1);
+  ALLOC(P->d_bmax, scan_blocks(cg.ncell) + 1);
   ALLOC(P->d_cid, N);
   ALLOC(P->d_perm_tmp, N);
   ALLOC(P->d_perm, N);
@@ -302,6 +359,9 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   }
   ALLOC(P->d_taps, P->taps.size());
   ALLOC(P->d_rows, P->rows.size());
+  ALLOC(P->d_wave_rows, kStencilWaves + 1);
+  ALLOC(P->d_row_w_tile, P->row_w.size());
+  ALLOC(P->d_tiles, tiles.size());
   ALLOC(P->d_row_w, P->row_w.size());
   ALLOC(P->d_row_wf, P->row_w.size());
   ALLOC(P->d_Kl, P->Kl.size());
@@ -318,6 +378,16 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
     if ((e = hipMemcpy(P->d_row_wf, wf.data(), wf.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
       return hip_fail(e, "copy stencil weights (fp32)");
   }
+  if (!tiles.empty()) {
+    if ((e = hipMemcpy(P->d_tiles, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "copy stencil tiles");
+    if ((e = hipMemcpy(P->d_row_w_tile, row_w_tile.data(), row_w_tile.size() * sizeof(double),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "copy stencil tile weights");
+  }
+  if ((e = hipMemcpy(P->d_wave_rows, wave_rows.data(), wave_rows.size() * sizeof(int), hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return hip_fail(e, "copy stencil wave split");
   if ((e = hipMemcpy(P->d_Kl, P->Kl.data(), P->Kl.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "copy coarsest kernel");
   if ((e = hipMemset(P->d_flags, 0, 4 * sizeof(int))) != hipSuccess) return hip_fail(e, "clear flags");

@@ -4,18 +4,29 @@
 //                  g_k(2^(k-1) s) = 2^(-6(k-1)) g_1(s), Sec. II.A.4)
 //   level l:       e^l[mu] = sum_nu K_l[(mu - nu) mod n_l] q^l[nu]   with the pre-summed periodic kernel of
 //                  eq:last-grid-periodic-transformed (all-to-all, FP64).
+//
+// Level stencil kernel (k_stencil_stream): a block owns a TX x TY column of
+// output points and a chunk of ZC planes.  It streams input planes z through
+// LDS (one xy plane plus an R-wide periodic halo at a time).  For every tap
+// column (|dx|,|dy|) the up to four mirror images q[x+-dx, y+-dy] are summed
+// once and then applied to the 2 hz + 1 outputs z_in - hz .. z_in + hz held
+// in a rolling register window acc[0..2R]; after each plane the oldest output
+// is complete, written, and the window shifts.
 #include <algorithm>
 
 #include "device_math.h"
 #include "mls_internal.h"
 
 namespace mls {
+
+int stencil_window(const mls_plan_s* P);
+
 namespace {
 
 constexpr int kBlock = 256;
 
 // Reference-structured stencil: one thread per output point, taps from the
-// level-1 table.
+// level-1 table (used for halos wider than the instantiated window).
 __global__ void __launch_bounds__(kBlock) k_stencil_taps_f64(const double* __restrict__ q, GridDims g,
                                                              const Tap* __restrict__ taps, int ntaps, double scale,
                                                              double* __restrict__ e) {
@@ -33,6 +44,235 @@ __global__ void __launch_bounds__(kBlock) k_stencil_taps_f64(const double* __res
   e[mu] = scale * acc;
 }
 
+// Apply one tap column with half height hz (compile-time) to the window.
+template <class T, int R, int HZ>
+__device__ __forceinline__ void apply_column(T (&acc)[2 * R + 1], T s, const T* __restrict__ w) {
+  acc[R] += w[0] * s;
+#pragma unroll
+  for (int d = 1; d <= HZ; ++d) {
+    const T wd = w[d] * s;
+    acc[R + d] += wd;
+    acc[R - d] += wd;
+  }
+}
+
+template <class T, int R, int H = 0>
+__device__ __forceinline__ void apply_switch(int hz, T (&acc)[2 * R + 1], T s, const T* __restrict__ w) {
+  if constexpr (H <= R) {
+    if (hz == H) {
+      apply_column<T, R, H>(acc, s, w);
+      return;
+    }
+    apply_switch<T, R, H + 1>(hz, acc, s, w);
+  }
+}
+
+// W waves share one 8 x 8 output column and one LDS plane; wave w applies
+// the tap columns [wave_rows[w], wave_rows[w+1]) (balanced by cost on the
+// host) and the W partial sums of each finished output are added in LDS.
+// The wrapped halo offsets of the plane are computed once per block, and the
+// next plane is prefetched into registers while the current one is used.
+template <class T, int R, int W>
+__global__ void __launch_bounds__(64 * W) k_stencil_stream(const T* __restrict__ q, GridDims g,
+                                                           const StencilRow* __restrict__ rows,
+                                                           const int* __restrict__ wave_rows,
+                                                           const T* __restrict__ wts, T scale, int zc,
+                                                           T* __restrict__ e) {
+  constexpr int TX = 8, TY = 8;
+  constexpr int SX = TX + 2 * R, SY = TY + 2 * R, NP = SX * SY, NT = 64 * W;
+  constexpr int PER = (NP + NT - 1) / NT;
+  __shared__ T plane[NP];
+  __shared__ T red[W][64];
+  const int tid = threadIdx.x, lane = tid & 63;
+  // wave index made provably uniform: row and weight reads become scalar
+  // loads and the hz dispatch scalar branches
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int tx = lane & 7, ty = lane >> 3;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int z0 = blockIdx.z * zc;
+  const int zend = min(z0 + zc, g.n[2]);
+  const int x = x0 + tx, y = y0 + ty;
+  const bool owner = x < g.n[0] && y < g.n[1];
+  const size_t pstride = (size_t)g.n[0] * g.n[1];
+  int off[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = tid + k * NT;
+    const int lx = i % SX, ly = i / SX;
+    off[k] = i < NP ? wrapi(y0 - R + ly, g.n[1]) * g.n[0] + wrapi(x0 - R + lx, g.n[0]) : 0;
+  }
+  const int r0 = wave_rows[wv], r1 = wave_rows[wv + 1];
+  T acc[2 * R + 1];
+#pragma unroll
+  for (int k = 0; k <= 2 * R; ++k) acc[k] = T(0);
+  T pre[PER];
+  {
+    const T* src = q + (size_t)wrapi(z0 - R, g.n[2]) * pstride;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) pre[k] = src[off[k]];
+  }
+  const T* c = plane + (ty + R) * SX + (tx + R);
+  for (int zin = z0 - R; zin < zend + R; ++zin) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+      if (tid + k * NT < NP) plane[tid + k * NT] = pre[k];
+    __syncthreads();
+    if (zin + 1 < zend + R) {
+      const T* src = q + (size_t)wrapi(zin + 1, g.n[2]) * pstride;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) pre[k] = src[off[k]];
+    }
+    for (int r = r0; r < r1; ++r) {
+      const StencilRow row = rows[r];
+      T s;
+      if (row.dx == 0 && row.dy == 0) {
+        s = c[0];
+      } else if (row.dx == 0) {
+        s = c[-row.dy * SX] + c[row.dy * SX];
+      } else if (row.dy == 0) {
+        s = c[-row.dx] + c[row.dx];
+      } else {
+        s = (c[-row.dy * SX - row.dx] + c[-row.dy * SX + row.dx]) + (c[row.dy * SX - row.dx] + c[row.dy * SX + row.dx]);
+      }
+      apply_switch<T, R>(row.hz, acc, s, wts + row.woff);
+    }
+    // output z = zin - R is complete: add the W partial sums
+    red[wv][lane] = acc[0];
+    __syncthreads();
+    const int zout = zin - R;
+    if (wv == 0 && owner && zout >= z0 && zout < zend) {
+      T sum = red[0][lane];
+#pragma unroll
+      for (int w = 1; w < W; ++w) sum += red[w][lane];
+      e[(size_t)zout * pstride + (size_t)y * g.n[0] + x] = scale * sum;
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) acc[k] = acc[k + 1];
+    acc[2 * R] = T(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tiled level stencil.  A block owns an 8 x 8 x ZC box of output points of
+// one level (all levels share one launch through a tile table).  It loads the
+// box plus an R-wide periodic halo into LDS once.  Its W waves split the tap
+// columns (|dx|,|dy|); for each column the wave reads the column's weights
+// once and runs a fully unrolled loop over the ZC + 2 hz input planes: the
+// four mirror images q[x+-dx, y+-dy] are summed (on the axes the duplicate
+// images are compensated by weights pre-divided on the host) and added with
+// weight w[|dz|] into all ZC outputs held in registers.  The W partial sums
+// are added in LDS at the end.
+}  // namespace
+
+// z extent of a stencil tile for halo window R (the FP64 tile with halo must
+// fit the LDS of one CU: (8 + 2R)^2 (ZC + 2R) doubles)
+constexpr int tile_zc(int R) { return R <= 6 ? 16 : 8; }
+
+int stencil_tile_zc(int R) { return tile_zc(R); }
+
+namespace {
+
+struct StencilLevel {
+  const double* q;
+  double* e;
+  int n[3];
+  int tiles_z;     // z chunks
+  int tile0;       // first tile index of this level
+  double scale;    // 2^(-6(k-1))
+};
+
+struct StencilLaunch {
+  StencilLevel lv[16];
+  int nlev;
+};
+
+template <class T, int HZ, int ZC>
+__device__ __forceinline__ void tile_column(T (&acc)[ZC], const T* __restrict__ c, int o0, int o1, int o2, int o3,
+                                            int pstride, const T* __restrict__ w) {
+  T wr[HZ + 1];
+#pragma unroll
+  for (int d = 0; d <= HZ; ++d) wr[d] = w[d];
+#pragma unroll
+  for (int zi = -HZ; zi < ZC + HZ; ++zi) {
+    const T* p = c + zi * pstride;
+    const T s = (p[o0] + p[o1]) + (p[o2] + p[o3]);
+#pragma unroll
+    for (int dz = -HZ; dz <= HZ; ++dz) {
+      const int zo = zi + dz;
+      if (zo >= 0 && zo < ZC) acc[zo] += wr[dz < 0 ? -dz : dz] * s;
+    }
+  }
+}
+
+template <class T, int R, int ZC, int H = 0>
+__device__ __forceinline__ void tile_switch(int hz, T (&acc)[ZC], const T* c, int o0, int o1, int o2, int o3,
+                                            int pstride, const T* w) {
+  if constexpr (H <= R) {
+    if (hz == H) {
+      tile_column<T, H, ZC>(acc, c, o0, o1, o2, o3, pstride, w);
+      return;
+    }
+    tile_switch<T, R, ZC, H + 1>(hz, acc, c, o0, o1, o2, o3, pstride, w);
+  }
+}
+
+template <class T, int R, int ZC, int W>
+__global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const int4* __restrict__ tiles,
+                                                         const StencilRow* __restrict__ rows,
+                                                         const int* __restrict__ wave_rows,
+                                                         const T* __restrict__ wts) {
+  constexpr int SX = 8 + 2 * R, SY = 8 + 2 * R, SZ = ZC + 2 * R;
+  constexpr int PS = SX * SY, NP = PS * SZ, NT = 64 * W;
+  static_assert(W * ZC * 64 <= NP, "reduction buffer must fit in the tile");
+  __shared__ T tile[NP];
+  __shared__ int wrapx[SX], wrapy[SY], wrapz[SZ];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int4 tinfo = tiles[blockIdx.x];
+  const StencilLevel& V = L.lv[tinfo.x];
+  const int x0 = tinfo.y * 8, y0 = tinfo.z * 8, z0 = tinfo.w * ZC;
+  if (tid < SX) wrapx[tid] = wrapi(x0 - R + tid, V.n[0]);
+  if (tid < SY) wrapy[tid] = wrapi(y0 - R + tid, V.n[1]);
+  if (tid < SZ) wrapz[tid] = wrapi(z0 - R + tid, V.n[2]);
+  __syncthreads();
+  const size_t gps = (size_t)V.n[0] * V.n[1];
+  const double* __restrict__ q = V.q;
+  for (int i = tid; i < NP; i += NT) {
+    const int lx = i % SX, ly = (i / SX) % SY, lz = i / PS;
+    tile[i] = (T)q[(size_t)wrapz[lz] * gps + (size_t)wrapy[ly] * V.n[0] + wrapx[lx]];
+  }
+  __syncthreads();
+  const int tx = lane & 7, ty = lane >> 3;
+  const T* c = tile + R * PS + (ty + R) * SX + (tx + R);
+  T acc[ZC];
+#pragma unroll
+  for (int k = 0; k < ZC; ++k) acc[k] = T(0);
+  const int r0 = wave_rows[wv], r1 = wave_rows[wv + 1];
+  for (int r = r0; r < r1; ++r) {
+    const StencilRow row = rows[r];
+    const int o0 = -row.dy * SX - row.dx, o1 = -row.dy * SX + row.dx;
+    const int o2 = row.dy * SX - row.dx, o3 = row.dy * SX + row.dx;
+    tile_switch<T, R, ZC>(row.hz, acc, c, o0, o1, o2, o3, PS, wts + row.woff);
+  }
+  // add the W partial sums (the tile is reused as the reduction buffer)
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < ZC; ++k) tile[(wv * ZC + k) * 64 + lane] = acc[k];
+  __syncthreads();
+  const int x = x0 + tx, y = y0 + ty;
+  if (x < V.n[0] && y < V.n[1]) {
+    for (int k = wv; k < ZC; k += W) {
+      const int z = z0 + k;
+      if (z >= V.n[2]) break;
+      T sum = tile[k * 64 + lane];
+#pragma unroll
+      for (int w2 = 1; w2 < W; ++w2) sum += tile[(w2 * ZC + k) * 64 + lane];
+      V.e[(size_t)z * gps + (size_t)y * V.n[0] + x] = V.scale * (double)sum;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_coarsest_f64(const double* __restrict__ q, GridDims g,
                                                          const double* __restrict__ K, double* __restrict__ e) {
   const int mu = blockIdx.x * blockDim.x + threadIdx.x;
@@ -40,12 +280,18 @@ __global__ void __launch_bounds__(kBlock) k_coarsest_f64(const double* __restric
   const int x = mu % g.n[0], y = (mu / g.n[0]) % g.n[1], z = mu / (g.n[0] * g.n[1]);
   double acc = 0.0;
   for (int nz = 0; nz < g.n[2]; ++nz) {
-    const int dz = wrapi(z - nz, g.n[2]);
+    int dz = z - nz;
+    if (dz < 0) dz += g.n[2];
     for (int ny = 0; ny < g.n[1]; ++ny) {
-      const int dy = wrapi(y - ny, g.n[1]);
+      int dy = y - ny;
+      if (dy < 0) dy += g.n[1];
       const double* qrow = q + ((size_t)nz * g.n[1] + ny) * g.n[0];
       const double* krow = K + ((size_t)dz * g.n[1] + dy) * g.n[0];
-      for (int nx = 0; nx < g.n[0]; ++nx) acc += krow[wrapi(x - nx, g.n[0])] * qrow[nx];
+      int dx = x;  // x - nx, wrapped, counts down
+      for (int nx = 0; nx < g.n[0]; ++nx) {
+        acc += krow[dx] * qrow[nx];
+        dx = dx == 0 ? g.n[0] - 1 : dx - 1;
+      }
     }
   }
   e[mu] = acc;
@@ -53,15 +299,84 @@ __global__ void __launch_bounds__(kBlock) k_coarsest_f64(const double* __restric
 
 inline int nblocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
+constexpr int kTX = 8, kTY = 8;
+
+template <class T, int R>
+hipError_t launch_stream(const mls_plan_s* P, const T* q, GridDims g, const T* w, T scale, T* e, hipStream_t s) {
+  constexpr int W = kStencilWaves;
+  // z chunk: halve while the launch has fewer than ~1.5k waves, but keep the
+  // 2R warm-up planes below half of the chunk
+  const int xy = nblocks(g.n[0], kTX) * nblocks(g.n[1], kTY);
+  int zc = g.n[2];
+  while (zc > 4 * R && (int64_t)xy * W * nblocks(g.n[2], zc) < P->stencil_min_waves) zc = (zc + 1) / 2;
+  dim3 grid(nblocks(g.n[0], kTX), nblocks(g.n[1], kTY), nblocks(g.n[2], zc));
+  k_stencil_stream<T, R, W><<<grid, 64 * W, 0, s>>>(q, g, P->d_rows, P->d_wave_rows, w, scale, zc, e);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_stream_r(const mls_plan_s* P, int R, const T* q, GridDims g, const T* w, T scale, T* e,
+                           hipStream_t s) {
+  switch (R) {
+    case 1: case 2: case 3: case 4: return launch_stream<T, 4>(P, q, g, w, scale, e, s);
+    case 5: case 6: return launch_stream<T, 6>(P, q, g, w, scale, e, s);
+    case 7: case 8: return launch_stream<T, 8>(P, q, g, w, scale, e, s);
+    case 9: case 10: return launch_stream<T, 10>(P, q, g, w, scale, e, s);
+    case 11: case 12: return launch_stream<T, 12>(P, q, g, w, scale, e, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
+int stencil_window(const mls_plan_s* P) {
+  return std::max(P->stencil_R[0], std::max(P->stencil_R[1], P->stencil_R[2]));
+}
+
+template <int R>
+hipError_t launch_tile(mls_plan_s* P, hipStream_t s) {
+  constexpr int kTileZ = tile_zc(R);
+  StencilLaunch L{};
+  L.nlev = P->levels - 1;
+  int t = 0;
+  for (int k = 1; k < P->levels; ++k) {
+    Level& Lv = P->lv[k - 1];
+    StencilLevel& V = L.lv[k - 1];
+    V.q = Lv.q;
+    V.e = Lv.e;
+    for (int d = 0; d < 3; ++d) V.n[d] = Lv.g.n[d];
+    V.tiles_z = nblocks(Lv.g.n[2], kTileZ);
+    V.tile0 = t;
+    V.scale = std::ldexp(1.0, -6 * (k - 1));
+    t += nblocks(Lv.g.n[0], 8) * nblocks(Lv.g.n[1], 8) * V.tiles_z;
+  }
+  k_stencil_tile<double, R, kTileZ, kStencilWaves><<<t, 64 * kStencilWaves, 0, s>>>(
+      L, P->d_tiles, P->d_rows, P->d_wave_rows, P->d_row_w_tile);
+  return hipGetLastError();
+}
+
 hipError_t launch_stencils(mls_plan_s* P, hipStream_t s) {
+  if (P->levels < 2) return hipSuccess;
+  const int R = stencil_window(P);
+  if (P->stencil_kernel == 1) {
+    switch (R) {
+      case 1: case 2: case 3: case 4: return launch_tile<4>(P, s);
+      case 5: case 6: return launch_tile<6>(P, s);
+      case 7: case 8: return launch_tile<8>(P, s);
+      default: break;
+    }
+  }
   const int ntaps = (int)P->taps.size();
   for (int k = 1; k < P->levels; ++k) {
     Level& L = P->lv[k - 1];
     const double scale = std::ldexp(1.0, -6 * (k - 1));
-    k_stencil_taps_f64<<<nblocks(L.g.size, kBlock), kBlock, 0, s>>>(L.q, L.g, P->d_taps, ntaps, scale, L.e);
-    hipError_t e = hipGetLastError();
+    hipError_t e;
+    if (R >= 1 && R <= 12) {
+      e = launch_stream_r<double>(P, R, L.q, L.g, P->d_row_w, scale, L.e, s);
+    } else {
+      k_stencil_taps_f64<<<nblocks(L.g.size, kBlock), kBlock, 0, s>>>(L.q, L.g, P->d_taps, ntaps, scale, L.e);
+      e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -69,7 +384,7 @@ hipError_t launch_stencils(mls_plan_s* P, hipStream_t s) {
 
 hipError_t launch_coarsest(mls_plan_s* P, hipStream_t s) {
   Level& L = P->lv[P->levels - 1];
-  k_coarsest_f64<<<nblocks(L.g.size, kBlock), kBlock, 0, s>>>(L.q, L.g, P->d_Kl, L.e);
+  k_coarsest_f64<<<nblocks(L.g.size, 64), 64, 0, s>>>(L.q, L.g, P->d_Kl, L.e);
   return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ def _cases():
     rng = np.random.default_rng(23)
     tiny = W.Workload("tiny", rng.random((30, 3)) * np.array([2.4, 3.1, 2.9]),
                       rng.uniform(1.0, 9.0, 30), np.array([2.4, 3.1, 2.9]), {})
+    edge5 = W.cube_box(350, 7.6, seed=25)      # exactly 5 half-cutoff cells per side
     mix = W.cube(700, 0.8, seed=24)
     mix.c6 = np.where(np.arange(700) % 3 == 0, 9.0, 4.0)
     return [
@@ -33,6 +34,8 @@ def _cases():
         ("aniso_p6_l3", aniso, dict(a=2.5, h=0.9, order=6, levels=3)),
         ("tiny_images_l1", tiny, dict(a=2.6, h=0.5, order=4, levels=1)),
         ("mix_p4_l4", mix, dict(a=2.2, h=0.7, order=4, levels=4)),
+        ("edge5cells_p4_l2", edge5, dict(a=3.0, h=0.9, order=4, levels=2)),
+        ("coarse_h_p4_l3", slab, dict(a=2.5, h=1.4, order=4, levels=3)),
     ]
 
 
@@ -49,17 +52,25 @@ def case(request):
     return name, w, prm, ref, plan, out, st
 
 
+def cell_width_rule(box, a):
+    """The library bins with the paper's cells (smallest width >= a dividing
+    the box) unless the box spans >= 5 cells of half that width per
+    dimension, where it uses the half-width cells."""
+    half = 0.5 * a
+    return half if np.all(M.cells_per_dim(box, half) >= 5) else a
+
+
 def test_plan_geometry(case):
     name, w, prm, ref, plan, out, st = case
     assert plan.info["levels"] == ref["levels"]
     assert tuple(plan.info["grid"]) == tuple(int(x) for x in ref["n1"])
-    nc = M.cells_per_dim(w.box, prm["a"])
+    nc = M.cells_per_dim(w.box, cell_width_rule(w.box, prm["a"]))
     assert tuple(plan.info["cells"]) == tuple(int(x) for x in nc)
 
 
 def test_binning_bit_exact(case):
     name, w, prm, ref, plan, out, st = case
-    nc, cid, start, perm = M.bin_cells(M.wrap(w.pos, w.box), w.box, prm["a"])
+    nc, cid, start, perm = M.bin_cells(M.wrap(w.pos, w.box), w.box, cell_width_rule(w.box, prm["a"]))
     np.testing.assert_array_equal(st["cell_start"], start)
     np.testing.assert_array_equal(st["perm"], perm)
 
