@@ -169,7 +169,12 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const int* __restrict_
                                                           double4* __restrict__ xs, int* __restrict__ cell_s,
                                                           float4* __restrict__ xr, CellGeom g) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
+  if (s >= n + kSortedPad) return;
+  if (s >= n) {
+    // padding rows: far outside any cutoff, zero weight
+    xs[s] = make_double4(1e300, 1e300, 1e300, 0.0);
+    return;
+  }
   int i = perm[s];
   double4 p = xw[i];
   int c = cid[i];
@@ -181,6 +186,26 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const int* __restrict_
     xr[s] = make_float4((float)(p.x - cx * g.w[0]), (float)(p.y - cy * g.w[1]), (float)(p.z - cz * g.w[2]),
                         (float)p.w);
   }
+}
+
+// Pair-kernel target order: atoms of the cells taken in brick order.
+__global__ void __launch_bounds__(kBlock) k_brick_counts(const int* __restrict__ order, const int* __restrict__ start,
+                                                         int ncell, int* __restrict__ bcount) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ncell) return;
+  const int c = order[k];
+  bcount[k] = start[c + 1] - start[c];
+}
+
+__global__ void __launch_bounds__(kBlock) k_brick_targets(const int* __restrict__ order,
+                                                          const int* __restrict__ start,
+                                                          const int* __restrict__ bstart, int ncell,
+                                                          int* __restrict__ tgt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ncell) return;
+  const int c = order[k];
+  const int b = start[c], e = start[c + 1], o = bstart[k];
+  for (int i = b; i < e; ++i) tgt[o + (i - b)] = i;
 }
 
 __global__ void k_zero(double* __restrict__ p, int64_t n) {
@@ -222,20 +247,37 @@ hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double*
                                                       P->d_flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  const int nb = scan_blocks(g.ncell);
-  k_scan_blocks<<<nb, kBlock, 0, s>>>(P->d_count, g.ncell, P->d_cell_start, P->d_bsum, P->d_bmax);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_scan_sums<<<1, kBlock, 0, s>>>(P->d_bsum, P->d_bmax, nb, P->d_cell_start, g.ncell, P->d_ncell_max);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_scan_add<<<nblocks(g.ncell, kBlock), kBlock, 0, s>>>(P->d_cell_start, g.ncell, P->d_bsum);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_scan(P, P->d_count, g.ncell, P->d_cell_start, s)) != hipSuccess) return e;
   if (n == 0) return hipSuccess;
   k_bin_scatter<<<nblocks(n, kBlock), kBlock, 0, s>>>(P->d_cid, P->d_slot, n, P->d_cell_start, P->d_perm_tmp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_cell_rank<<<nblocks(g.ncell, kBlock), kBlock, 0, s>>>(P->d_cell_start, g.ncell, P->d_perm_tmp, P->d_perm);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_gather_sorted<<<nblocks(n, kBlock), kBlock, 0, s>>>(P->d_perm, n, P->d_xw, P->d_cid, P->d_xs, P->d_cell_s,
+  k_gather_sorted<<<nblocks(n + kSortedPad, kBlock), kBlock, 0, s>>>(P->d_perm, n, P->d_xw, P->d_cid, P->d_xs,
+                                                                     P->d_cell_s,
                                                         P->d_xr, g);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (P->pair_fast) {
+    // the per-cell counts are no longer needed: reuse that array (ncell entries)
+    k_brick_counts<<<nblocks(g.ncell, kBlock), kBlock, 0, s>>>(P->d_cell_order, P->d_cell_start, g.ncell,
+                                                               P->d_count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_scan(P, P->d_count, g.ncell, P->d_bcount, s)) != hipSuccess) return e;
+    k_brick_targets<<<nblocks(g.ncell, kBlock), kBlock, 0, s>>>(P->d_cell_order, P->d_cell_start, P->d_bcount,
+                                                                g.ncell, P->d_tgt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_scan(mls_plan_s* P, const int* count, int m, int* start, hipStream_t s) {
+  const int nb = scan_blocks(m);
+  k_scan_blocks<<<nb, kBlock, 0, s>>>(count, m, start, P->d_bsum, P->d_bmax);
+  hipError_t e;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_scan_sums<<<1, kBlock, 0, s>>>(P->d_bsum, P->d_bmax, nb, start, m, P->d_ncell_max);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_scan_add<<<nblocks(m, kBlock), kBlock, 0, s>>>(start, m, P->d_bsum);
   return hipGetLastError();
 }
 

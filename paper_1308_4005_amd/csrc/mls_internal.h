@@ -46,6 +46,10 @@ struct StencilRow {
   int woff;          // offset of the hz+1 weights w[|dz|] in the weight table
 };
 
+// Rows past the end of the cell-sorted atom array, filled with far-away
+// positions every evaluation so the pair filter may read ahead freely.
+constexpr int kSortedPad = 16;
+
 // Waves per block of the level-stencil kernel; the tap columns are split
 // into this many cost-balanced contiguous ranges at plan time.
 constexpr int kStencilWaves = 4;
@@ -103,6 +107,9 @@ struct mls_plan_s {
   int* d_bsum = nullptr;           // scan block sums
   int* d_bmax = nullptr;           // scan block maxima
   bool pair_fast = false;          // half-cutoff cells with per-atom row trimming
+  int* d_cell_order = nullptr;     // ncell: cells in 4x4x4-brick order (pair target order)
+  int* d_bcount = nullptr;         // ncell + 1: atom counts / offsets in brick order
+  int* d_tgt = nullptr;            // n_max: sorted atom indices in brick order
   int* d_cid = nullptr;            // n_max: cell of original atom
   int* d_perm_tmp = nullptr;       // n_max
   int* d_perm = nullptr;           // n_max
@@ -148,6 +155,7 @@ int stencil_tile_zc(int R);
 // kernel launchers (one per file); all enqueue on `s` and return the launch status
 hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double* c6, hipStream_t s);
 hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s);
+hipError_t launch_scan(mls_plan_s* P, const int* count, int m, int* start, hipStream_t s);
 hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s);
 hipError_t launch_restrict(mls_plan_s* P, int k_fine, hipStream_t s);
 hipError_t launch_stencils(mls_plan_s* P, hipStream_t s);

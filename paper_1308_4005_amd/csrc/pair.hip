@@ -103,77 +103,86 @@ __global__ void __launch_bounds__(kBlock) k_pair_f64(const double4* __restrict__
 }
 
 // FP64, filter-and-drain over half-cutoff cells: one wave of 64 lanes takes
-// 64 consecutive cell-sorted targets.  Each lane visits the 5 x 5 rows of
-// cells around its target's cell, skips rows whose y/z gap to the target is
-// at least a, and trims every other row to the cells the cutoff sphere can
-// reach along x (split at the box edge into periodic images).  A cheap
-// distance test appends sources inside the cutoff to the lane's LDS queue,
-// four candidates per step so four loads are in flight; whenever a queue may
-// overflow, and once at the end, all lanes drain their queues through the
-// full g_0 evaluation, so the expensive arithmetic runs on nearly full waves
-// instead of being masked per candidate.  An entry packs the source index
-// (< 2^26) with its image code (27 images).
+// 64 targets from a compact group of cells.  Each lane visits the 5 x 5 rows
+// of cells around its target's cell, skips rows whose y/z gap to the target
+// is at least a, and trims every other row to the cells the cutoff sphere
+// can reach along x (at most two runs of cells: one per periodic image).  A
+// cheap distance test appends sources inside the cutoff to the lane's LDS
+// queue, four candidates per step so four loads are in flight; whenever a
+// queue may overflow, and once at the end, all lanes drain their queues
+// through the full g_0 evaluation, so the expensive arithmetic runs on
+// nearly full waves instead of being masked per candidate.  An entry packs
+// the source index (< 2^25) with two bits per dimension for its image.
 constexpr int kWaveQ = 64;    // lanes per block (one wave)
 constexpr int kQueue = 32;    // entries per lane
 constexpr int kBatch = 4;     // candidates per filter step
 
-__device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, int cnt, int lane,
-                                               const double4& xi, const double4* __restrict__ xs, const CellGeom& g,
-                                               const PairConst& pc, double& e, double& fx, double& fy, double& fz) {
-  for (int t = 0; __any(t < cnt); ++t) {
-    if (t < cnt) {
-      const int ent = queue[t * kWaveQ + lane];
-      const int j = ent >> 5;
-      const int code = ent & 31;
-      const int ix = code % 3 - 1, iy = (code / 3) % 3 - 1, iz = code / 9 - 1;
-      const double4 xj = xs[j];
-      // same arithmetic as the filter, so the cutoff decision is identical
-      const double dx = (xi.x - ix * g.L[0]) - xj.x;
-      const double dy = (xi.y - iy * g.L[1]) - xj.y;
-      const double dz = (xi.z - iz * g.L[2]) - xj.z;
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      double gg, fr;
-      g0_pair<double>(r2, pc.inv_a2, pc.inv_a6, pc.inv_a8, gg, fr);
-      e += xj.w * gg;
-      const double f = xj.w * fr;
-      fx += f * dx;
-      fy += f * dy;
-      fz += f * dz;
-    }
-  }
-}
+__device__ __forceinline__ int image_bits(int ix, int iy, int iz) { return (ix + 1) | ((iy + 1) << 2) | ((iz + 1) << 4); }
 
 struct PairAcc {
   double e, fx, fy, fz;
   int cnt;
 };
 
-// Scan sources [j, j1) seen through image `code` (convergent: every lane
-// calls it, lanes with an empty range just take part in the votes).
-__device__ __forceinline__ void pair_scan_f64(int j, int j1, int code, int s, int s_safe, int* __restrict__ queue,
-                                              int lane, const double4& xi, const double4* __restrict__ xs,
+__device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, int cnt, int lane, int self_ent,
+                                               const double4& xi, const double4* __restrict__ xs, const CellGeom& g,
+                                               const PairConst& pc, PairAcc& A) {
+  for (int t = 0; __any(t < cnt); ++t) {
+    const int ent = queue[t * kWaveQ + lane];
+    if (t < cnt && ent != self_ent) {
+      const int j = ent >> 6;
+      const double sx = (double)((ent & 3) - 1) * g.L[0];
+      const double sy = (double)(((ent >> 2) & 3) - 1) * g.L[1];
+      const double sz = (double)(((ent >> 4) & 3) - 1) * g.L[2];
+      const double4 xj = xs[j];
+      // same arithmetic as the filter, so the cutoff decision is identical
+      const double dx = (xi.x - sx) - xj.x;
+      const double dy = (xi.y - sy) - xj.y;
+      const double dz = (xi.z - sz) - xj.z;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      double gg, fr;
+      g0_pair<double>(r2, pc.inv_a2, pc.inv_a6, pc.inv_a8, gg, fr);
+      A.e += xj.w * gg;
+      const double f = xj.w * fr;
+      A.fx += f * dx;
+      A.fy += f * dy;
+      A.fz += f * dz;
+    }
+  }
+}
+
+// Scan sources [j, j1) seen through image bits `img` (convergent: every lane
+// calls it; lanes with an empty range just take part in the votes).  Reads
+// may run up to kBatch - 1 rows past j1: the sorted array is padded with
+// far-away rows, and rows past j1 are never kept.
+__device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int* __restrict__ queue, int lane,
+                                              int self_ent, const double4& xi, const double4* __restrict__ xs,
                                               const CellGeom& g, const PairConst& pc, PairAcc& A) {
-  const int ix = code % 3 - 1, iy = (code / 3) % 3 - 1, iz = code / 9 - 1;
-  const double ax = xi.x - ix * g.L[0], ay = xi.y - iy * g.L[1], az = xi.z - iz * g.L[2];
-  const int self = code == 13 ? s : -1;
+  const double ax = xi.x - (double)((img & 3) - 1) * g.L[0];
+  const double ay = xi.y - (double)(((img >> 2) & 3) - 1) * g.L[1];
+  const double az = xi.z - (double)(((img >> 4) & 3) - 1) * g.L[2];
+  int* slot = queue + A.cnt * kWaveQ + lane;
   while (__any(j < j1)) {
     double4 xj[kBatch];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) xj[b] = xs[j + b < j1 ? j + b : s_safe];  // past the range: any valid row
+    for (int b = 0; b < kBatch; ++b) xj[b] = xs[j + b];
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
       const double dx = ax - xj[b].x, dy = ay - xj[b].y, dz = az - xj[b].z;
       const double r2 = dx * dx + dy * dy + dz * dz;
-      const int jb = j + b;
-      const bool hit = jb < j1 && r2 < pc.a2 && jb != self;
-      // slot cnt is free: write unconditionally, keep it only on a hit
-      queue[A.cnt * kWaveQ + lane] = (jb << 5) | code;
-      A.cnt += hit ? 1 : 0;
+      const bool hit = (j + b < j1) & (r2 < pc.a2);
+      // the slot at the queue's end is free: write unconditionally, keep on a hit
+      *slot = ((j + b) << 6) | img;
+      slot += hit ? kWaveQ : 0;
     }
-    j += kBatch;
+    // lanes past their range stay put (j <= j1 + kBatch - 1): reads stay
+    // within the padding however long other lanes keep scanning
+    j += j < j1 ? kBatch : 0;
+    A.cnt = (int)(slot - queue - lane) / kWaveQ;
     if (__any(A.cnt > kQueue - kBatch)) {
-      pair_drain_f64(queue, A.cnt, lane, xi, xs, g, pc, A.e, A.fx, A.fy, A.fz);
+      pair_drain_f64(queue, A.cnt, lane, self_ent, xi, xs, g, pc, A);
       A.cnt = 0;
+      slot = queue + lane;
     }
   }
 }
@@ -184,18 +193,23 @@ __device__ __forceinline__ double gap1(double x, double lo, double w, double eps
 
 __global__ void __launch_bounds__(kWaveQ) k_pair_trim_f64(const double4* __restrict__ xs,
                                                           const int* __restrict__ cell_s,
-                                                          const int* __restrict__ cstart, int n, CellGeom g,
+                                                          const int* __restrict__ cstart,
+                                                          const int* __restrict__ tgt, int n, CellGeom g,
                                                           PairConst pc, double* __restrict__ e0,
                                                           double* __restrict__ floc) {
   __shared__ int queue[kQueue * kWaveQ];
   const int lane = threadIdx.x;
-  const int s = blockIdx.x * kWaveQ + lane;
-  const bool active = s < n;
-  const int sc = active ? s : n - 1;
+  // targets in brick order: the 64 lanes of a wave sit in a compact group of cells
+  const int k = blockIdx.x * kWaveQ + lane;
+  const bool active = k < n;
+  const int sc = tgt[active ? k : n - 1];
   const double4 xi = xs[sc];
   const int c = cell_s[sc];
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
+  // the target itself, seen in the home image, is skipped in the drain
+  const int self_ent = active ? ((sc << 6) | image_bits(0, 0, 0)) : -1;
   PairAcc A{0.0, 0.0, 0.0, 0.0, 0};
+  const float reach = (float)(1.0 + 1e-5);
   for (int dz = -2; dz <= 2; ++dz) {
     const int uz = cz + dz;
     const int iz = uz < 0 ? -1 : (uz >= g.nc[2] ? 1 : 0);
@@ -209,32 +223,41 @@ __global__ void __launch_bounds__(kWaveQ) k_pair_trim_f64(const double4* __restr
       const double rem = pc.a2 - (gy * gy + gz * gz);
       int clo = 0, chi = -1;
       if (active && rem > 0.0) {
-        // x cells the cutoff sphere reaches in this row (slightly widened)
-        const double rx = sqrt(rem) * (1.0 + 1e-12) + 1e-12 * g.L[0];
+        // x cells the cutoff sphere reaches in this row (conservatively widened)
+        const double rx = (double)(sqrtf((float)rem) * reach) + 1e-6 * g.w[0];
         clo = max(cx - 2, (int)floor((xi.x - rx) * g.inv_w[0]));
         chi = min(cx + 2, (int)floor((xi.x + rx) * g.inv_w[0]));
       }
-      const int row = (tz * g.nc[1] + ty) * g.nc[0];
-      const int cyz = 3 * ((iy + 1) + 3 * (iz + 1));
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int ix = k - 1;  // image of the cells [lo, hi] along x
-        const int lo = max(clo, ix * g.nc[0]), hi = min(chi, ix * g.nc[0] + g.nc[0] - 1);
-        int j0 = 0, j1 = 0;
-        if (lo <= hi) {
-          j0 = cstart[row + lo - ix * g.nc[0]];
-          j1 = cstart[row + hi - ix * g.nc[0] + 1];
-        }
-        pair_scan_f64(j0, j1, (ix + 1) + cyz, s, sc, queue, lane, xi, xs, g, pc, A);
+      // at most one box edge inside [clo, chi] (nc >= 5): two runs of cells
+      int lo1 = clo, hi1 = chi, ix1 = 0, lo2 = 0, hi2 = -1, ix2 = 0;
+      if (clo < 0) {
+        lo1 = clo + g.nc[0]; hi1 = g.nc[0] - 1; ix1 = -1;
+        lo2 = 0; hi2 = chi; ix2 = 0;
+      } else if (chi >= g.nc[0]) {
+        lo1 = clo; hi1 = g.nc[0] - 1; ix1 = 0;
+        lo2 = 0; hi2 = chi - g.nc[0]; ix2 = 1;
       }
+      const int row = (tz * g.nc[1] + ty) * g.nc[0];
+      int j0 = 0, j1 = 0;
+      if (lo1 <= hi1) {
+        j0 = cstart[row + lo1];
+        j1 = cstart[row + hi1 + 1];
+      }
+      int k0 = 0, k1 = 0;
+      if (lo2 <= hi2) {
+        k0 = cstart[row + lo2];
+        k1 = cstart[row + hi2 + 1];
+      }
+      pair_scan_f64(j0, j1, image_bits(ix1, iy, iz), queue, lane, self_ent, xi, xs, g, pc, A);
+      pair_scan_f64(k0, k1, image_bits(ix2, iy, iz), queue, lane, self_ent, xi, xs, g, pc, A);
     }
   }
-  pair_drain_f64(queue, A.cnt, lane, xi, xs, g, pc, A.e, A.fx, A.fy, A.fz);
+  pair_drain_f64(queue, A.cnt, lane, self_ent, xi, xs, g, pc, A);
   if (active) {
-    e0[s] = A.e;
-    floc[3 * (size_t)s + 0] = xi.w * A.fx;
-    floc[3 * (size_t)s + 1] = xi.w * A.fy;
-    floc[3 * (size_t)s + 2] = xi.w * A.fz;
+    e0[sc] = A.e;
+    floc[3 * (size_t)sc + 0] = xi.w * A.fx;
+    floc[3 * (size_t)sc + 1] = xi.w * A.fy;
+    floc[3 * (size_t)sc + 2] = xi.w * A.fz;
   }
 }
 
@@ -244,9 +267,9 @@ hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   PairConst pc{P->a2, P->inv_a2, P->inv_a6, P->inv_a8};
   const CellGeom& g = P->cg;
-  if (P->pair_fast && n < (1 << 26)) {
-    k_pair_trim_f64<<<(n + kWaveQ - 1) / kWaveQ, kWaveQ, 0, s>>>(P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pc,
-                                                                 P->d_e0, P->d_floc);
+  if (P->pair_fast && n < (1 << 25)) {
+    k_pair_trim_f64<<<(n + kWaveQ - 1) / kWaveQ, kWaveQ, 0, s>>>(P->d_xs, P->d_cell_s, P->d_cell_start, P->d_tgt,
+                                                                 n, g, pc, P->d_e0, P->d_floc);
   } else {
     k_pair_f64<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pc,
                                                             P->d_e0, P->d_floc);

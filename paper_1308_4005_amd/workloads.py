@@ -289,8 +289,27 @@ def _c5():
 
 
 NAMED = {"cube1k": _c1, "slab32k": _c2, "cube1M": _c3, "mixture100k": _c5}
+NAMED_PARAMS = {"cube1k": dict(a=3.0, h=1.0, order=4, levels=2),
+                "slab32k": dict(a=3.0, h=1.0, order=4, levels=4),
+                "cube1M": dict(a=3.0, h=1.0, order=4, levels=5),
+                "mixture100k": dict(a=3.0, h=1.0, order=4, levels=0)}
 
 
 def named(name: str) -> Workload:
-    """Build one of the named workloads (see ``NAMED``)."""
-    return NAMED[name]()
+    """Build one of the named workloads (see ``NAMED``).
+
+    If the environment variable MLS_WORKLOAD_CACHE names a directory, the
+    generated arrays are stored there and reused by later calls.
+    """
+    import os
+    cache = os.environ.get("MLS_WORKLOAD_CACHE")
+    if cache:
+        path = os.path.join(cache, f"{name}.npz")
+        if os.path.exists(path):
+            z = np.load(path, allow_pickle=False)
+            return Workload(name, z["pos"], z["c6"], z["box"], NAMED_PARAMS.get(name, {}))
+    w = NAMED[name]()
+    if cache:
+        os.makedirs(cache, exist_ok=True)
+        np.savez(os.path.join(cache, f"{name}.npz"), pos=w.pos, c6=w.c6, box=w.box)
+    return w
