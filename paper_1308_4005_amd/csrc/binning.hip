@@ -167,12 +167,17 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const int* __restrict_
                                                           const double4* __restrict__ xw,
                                                           const int* __restrict__ cid,
                                                           double4* __restrict__ xs, int* __restrict__ cell_s,
-                                                          float4* __restrict__ xr, CellGeom g) {
+                                                          float4* __restrict__ xr, float* __restrict__ xif,
+                                                          CellGeom g) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n + kSortedPad) return;
   if (s >= n) {
     // padding rows: far outside any cutoff, zero weight
     xs[s] = make_double4(1e300, 1e300, 1e300, 0.0);
+    if (xr) {
+      xr[s] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+      xif[s] = 0.0f;
+    }
     return;
   }
   int i = perm[s];
@@ -181,10 +186,12 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const int* __restrict_
   xs[s] = p;
   cell_s[s] = c;
   if (xr) {
-    // cell-relative FP32 coordinates for the mixed-precision pair kernel
+    // cell-relative FP32 coordinates and the cell x index (exact in FP32)
+    // for the mixed-precision pair kernel
     int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
     xr[s] = make_float4((float)(p.x - cx * g.w[0]), (float)(p.y - cy * g.w[1]), (float)(p.z - cz * g.w[2]),
-                        (float)p.w);
+                        (float)cx);
+    xif[s] = (float)p.w;
   }
 }
 
@@ -206,6 +213,34 @@ __global__ void __launch_bounds__(kBlock) k_brick_targets(const int* __restrict_
   const int c = order[k];
   const int b = start[c], e = start[c + 1], o = bstart[k];
   for (int i = b; i < e; ++i) tgt[o + (i - b)] = i;
+}
+
+// Sum of xi over the atoms (fixed order: per-block partials, then one block).
+__global__ void __launch_bounds__(kBlock) k_sum_xi_blocks(const double4* __restrict__ xs, int n,
+                                                          double* __restrict__ partial) {
+  __shared__ double sh[kBlock];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  sh[threadIdx.x] = s < n ? xs[s].w : 0.0;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_sum_final(const double* __restrict__ partial, int nb,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[kBlock];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) a += partial[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
 }
 
 __global__ void k_zero(double* __restrict__ p, int64_t n) {
@@ -254,9 +289,16 @@ hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double*
   k_cell_rank<<<nblocks(g.ncell, kBlock), kBlock, 0, s>>>(P->d_cell_start, g.ncell, P->d_perm_tmp, P->d_perm);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_gather_sorted<<<nblocks(n + kSortedPad, kBlock), kBlock, 0, s>>>(P->d_perm, n, P->d_xw, P->d_cid, P->d_xs,
-                                                                     P->d_cell_s,
-                                                        P->d_xr, g);
+                                                                     P->d_cell_s, P->d_xr, P->d_xif, g);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (P->precision == MLS_MIXED) {
+    // sum of xi: the mean of every grid level's charges (partition of unity)
+    const int nb = nblocks(n, kBlock);
+    k_sum_xi_blocks<<<nb, kBlock, 0, s>>>(P->d_xs, n, P->d_partial);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_sum_final<<<1, kBlock, 0, s>>>(P->d_partial, nb, P->d_scratch);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (P->pair_fast) {
     // the per-cell counts are no longer needed: reuse that array (ncell entries)
     k_brick_counts<<<nblocks(g.ncell, kBlock), kBlock, 0, s>>>(P->d_cell_order, P->d_cell_start, g.ncell,

@@ -70,7 +70,7 @@ struct AntGeom {
   int nh[3];   // halo cells
 };
 
-template <int P>
+template <int P, class W>
 __global__ void __launch_bounds__(kAntThreads) k_anterp_owned(const double4* __restrict__ xs,
                                                               const int* __restrict__ cstart, CellGeom cg,
                                                               GridGeom gg, AntGeom ag, double* __restrict__ q) {
@@ -132,15 +132,16 @@ __global__ void __launch_bounds__(kAntThreads) k_anterp_owned(const double4* __r
     while (seg_off[sg + 1] <= i) ++sg;
     const double4 p = xs[seg_begin[sg] + (i - seg_off[sg])];
     const double pc[3] = {p.x, p.y, p.z};
-    double w[3][P];
+    W w[3][P];
     int l0[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double t = pc[d] * gg.invh[d];
       const double m0 = floor(t);
-      basis_weights<P, double>(t - m0, w[d]);
+      basis_weights<P, W>((W)(t - m0), w[d]);
       l0[d] = (int)m0 - (P / 2 - 1) + seg_shift[sg][d] * gg.n[d] - lo[d];
     }
+    const W xiw = (W)p.w;
 #pragma unroll
     for (int jz = 0; jz < P; ++jz) {
       const int lz = l0[2] + jz;
@@ -149,12 +150,13 @@ __global__ void __launch_bounds__(kAntThreads) k_anterp_owned(const double4* __r
       for (int jy = 0; jy < P; ++jy) {
         const int ly = l0[1] + jy;
         if (ly < 0 || ly >= wd[1]) continue;
-        const double wzy = p.w * w[2][jz] * w[1][jy];
+        const W wzy = xiw * w[2][jz] * w[1][jy];
         double* row = tile + (lz * kAntTile + ly) * kAntTile;
 #pragma unroll
         for (int jx = 0; jx < P; ++jx) {
           const int lx = l0[0] + jx;
-          if (lx >= 0 && lx < wd[0]) atomicAdd(row + lx, wzy * w[0][jx]);
+          // charges accumulate in FP64 whatever the weight precision
+          if (lx >= 0 && lx < wd[0]) atomicAdd(row + lx, (double)(wzy * w[0][jx]));
         }
       }
     }
@@ -264,7 +266,7 @@ struct OutPtrs {
   double* dE_dc6;
 };
 
-template <int P>
+template <int P, class W>
 __global__ void __launch_bounds__(kBlock) k_interp_f64(const double4* __restrict__ xs, const int* __restrict__ perm,
                                                        int n, GridGeom gg, const double* __restrict__ E1,
                                                        const double* __restrict__ e0, const double* __restrict__ floc,
@@ -274,13 +276,13 @@ __global__ void __launch_bounds__(kBlock) k_interp_f64(const double4* __restrict
   if (s < n) {
     const double4 p = xs[s];
     const double pc[3] = {p.x, p.y, p.z};
-    double w[3][P], dw[3][P];
+    W w[3][P], dw[3][P];
     int idx[3][P];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double t = pc[d] * gg.invh[d];
       const double m0 = floor(t);
-      basis_weights_d<P, double>(t - m0, w[d], dw[d]);
+      basis_weights_d<P, W>((W)(t - m0), w[d], dw[d]);
       const int base = (int)m0 - (P / 2 - 1);
 #pragma unroll
       for (int j = 0; j < P; ++j) idx[d][j] = wrapi(base + j, gg.n[d]);
@@ -296,17 +298,17 @@ __global__ void __launch_bounds__(kBlock) k_interp_f64(const double4* __restrict
 #pragma unroll
         for (int jx = 0; jx < P; ++jx) {
           const double e = row[idx[0][jx]];
-          v += w[0][jx] * e;
-          vd += dw[0][jx] * e;
+          v += (double)w[0][jx] * e;
+          vd += (double)dw[0][jx] * e;
         }
-        ru += w[1][jy] * v;
-        rgx += w[1][jy] * vd;
-        rgy += dw[1][jy] * v;
+        ru += (double)w[1][jy] * v;
+        rgx += (double)w[1][jy] * vd;
+        rgy += (double)dw[1][jy] * v;
       }
-      u += w[2][jz] * ru;
-      gx += w[2][jz] * rgx;
-      gy += w[2][jz] * rgy;
-      gz += dw[2][jz] * ru;
+      u += (double)w[2][jz] * ru;
+      gx += (double)w[2][jz] * rgx;
+      gy += (double)w[2][jz] * rgy;
+      gz += (double)dw[2][jz] * ru;
     }
     const int i = perm[s];
     const double xi = p.w;
@@ -411,10 +413,15 @@ hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s) {
   if (anterp_owned_geom(P, ag)) {
     // every owned point is written, so no zero fill is needed
     const int nb = ag.nb[0] * ag.nb[1] * ag.nb[2];
-    if (P->order == 4)
-      k_anterp_owned<4><<<nb, kAntThreads, 0, s>>>(P->d_xs, P->d_cell_start, P->cg, gg, ag, L1.q);
+    const bool mixed = P->precision == MLS_MIXED;
+    if (P->order == 4 && !mixed)
+      k_anterp_owned<4, double><<<nb, kAntThreads, 0, s>>>(P->d_xs, P->d_cell_start, P->cg, gg, ag, L1.q);
+    else if (P->order == 4)
+      k_anterp_owned<4, float><<<nb, kAntThreads, 0, s>>>(P->d_xs, P->d_cell_start, P->cg, gg, ag, L1.q);
+    else if (!mixed)
+      k_anterp_owned<6, double><<<nb, kAntThreads, 0, s>>>(P->d_xs, P->d_cell_start, P->cg, gg, ag, L1.q);
     else
-      k_anterp_owned<6><<<nb, kAntThreads, 0, s>>>(P->d_xs, P->d_cell_start, P->cg, gg, ag, L1.q);
+      k_anterp_owned<6, float><<<nb, kAntThreads, 0, s>>>(P->d_xs, P->d_cell_start, P->cg, gg, ag, L1.q);
     return hipGetLastError();
   }
   hipError_t e = launch_zero(L1.q, L1.g.size, s);
@@ -452,12 +459,19 @@ hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forc
   if (n > 0) {
     GridGeom gg = finest_geom(P);
     OutPtrs out{forces, potential, dE_dc6};
-    if (P->order == 4)
-      k_interp_f64<4><<<nb, kBlock, 0, s>>>(P->d_xs, P->d_perm, n, gg, P->lv[0].E, P->d_e0, P->d_floc, P->cself, out,
-                                            P->d_partial);
+    const bool mixed = P->precision == MLS_MIXED;
+    if (P->order == 4 && !mixed)
+      k_interp_f64<4, double><<<nb, kBlock, 0, s>>>(P->d_xs, P->d_perm, n, gg, P->lv[0].E, P->d_e0, P->d_floc,
+                                                    P->cself, out, P->d_partial);
+    else if (P->order == 4)
+      k_interp_f64<4, float><<<nb, kBlock, 0, s>>>(P->d_xs, P->d_perm, n, gg, P->lv[0].E, P->d_e0, P->d_floc,
+                                                   P->cself, out, P->d_partial);
+    else if (!mixed)
+      k_interp_f64<6, double><<<nb, kBlock, 0, s>>>(P->d_xs, P->d_perm, n, gg, P->lv[0].E, P->d_e0, P->d_floc,
+                                                    P->cself, out, P->d_partial);
     else
-      k_interp_f64<6><<<nb, kBlock, 0, s>>>(P->d_xs, P->d_perm, n, gg, P->lv[0].E, P->d_e0, P->d_floc, P->cself, out,
-                                            P->d_partial);
+      k_interp_f64<6, float><<<nb, kBlock, 0, s>>>(P->d_xs, P->d_perm, n, gg, P->lv[0].E, P->d_e0, P->d_floc,
+                                                   P->cself, out, P->d_partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   } else {

@@ -88,6 +88,7 @@ struct mls_plan_s {
   mls::StencilRow* d_rows = nullptr;
   int* d_wave_rows = nullptr;      // kStencilWaves + 1 offsets into rows
   double* d_row_w_tile = nullptr;  // weights divided by the mirror duplication on the axes
+  float* d_row_wf_tile = nullptr;  // the same in FP32 (mixed precision)
   int4* d_tiles = nullptr;         // (level-1, tile x, tile y, tile z) of the tiled stencil
   int ntiles = 0;
   int stencil_kernel = 1;          // 1: LDS tile kernel, 0: plane-streaming kernel
@@ -116,7 +117,8 @@ struct mls_plan_s {
   int* d_cell_s = nullptr;         // n_max: cell of sorted atom
   double4* d_xw = nullptr;         // n_max: wrapped x,y,z + xi, original order
   double4* d_xs = nullptr;         // n_max: sorted
-  float4* d_xr = nullptr;          // n_max: sorted, cell-relative FP32 (mixed)
+  float4* d_xr = nullptr;          // n_max + pad: sorted, cell-relative FP32 x,y,z and cell x index (mixed)
+  float* d_xif = nullptr;          // n_max + pad: sorted xi in FP32 (mixed)
   double* d_e0 = nullptr;          // n_max sorted local potential
   double* d_floc = nullptr;        // 3 n_max sorted local force / (xi_i)
   double* d_partial = nullptr;     // energy partial sums

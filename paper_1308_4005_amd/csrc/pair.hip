@@ -261,13 +261,171 @@ __global__ void __launch_bounds__(kWaveQ) k_pair_trim_f64(const double4* __restr
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP32-mixed variant of the same scheme.  Sources carry cell-relative FP32
+// coordinates (x - cx w, y - cy w, z - cz w) and their cell x index (exact in
+// FP32) in the fourth component; xi is a separate FP32 array read only in the
+// drain.  The displacement is rebuilt as
+//   d_x = (cx_i - ix nc - cx_j) w_x + xr_i - xr_j,  d_y = yr_i - dy w_y - yr_j, ...
+// with integer cell offsets, so no large coordinates enter FP32 arithmetic.
+// Queue entries pack the source index (< 2^24), the x image and the row
+// offsets dy, dz.  Pair arithmetic is FP32; e_0 and the forces accumulate in
+// FP64.
+struct PairConstF {
+  float a2, inv_a2, inv_a6, inv_a8;
+  float w[3];
+};
+
+struct PairAccM {
+  double e, fx, fy, fz;
+  int cnt;
+};
+
+__device__ __forceinline__ int entry_bits(int ix, int dy, int dz) { return (ix + 1) | ((dy + 2) << 2) | ((dz + 2) << 5); }
+
+__device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, int cnt, int lane, int self_ent,
+                                               const float4& xi, int cxi, const float4* __restrict__ xr,
+                                               const float* __restrict__ xif, const CellGeom& g,
+                                               const PairConstF& pc, PairAccM& A) {
+  for (int t = 0; __any(t < cnt); ++t) {
+    const int ent = queue[t * kWaveQ + lane];
+    if (t < cnt && ent != self_ent) {
+      const int j = ent >> 8;
+      const int ix = (ent & 3) - 1, dy = ((ent >> 2) & 7) - 2, dz = ((ent >> 5) & 7) - 2;
+      const float4 xj = xr[j];
+      const float bx = (float)(cxi - ix * g.nc[0]);
+      const float dxv = fmaf(bx - xj.w, pc.w[0], xi.x) - xj.x;
+      const float dyv = fmaf((float)-dy, pc.w[1], xi.y) - xj.y;
+      const float dzv = fmaf((float)-dz, pc.w[2], xi.z) - xj.z;
+      const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
+      float gg, fr;
+      g0_pair<float>(r2, pc.inv_a2, pc.inv_a6, pc.inv_a8, gg, fr);
+      const float wj = xif[j];
+      A.e += (double)(wj * gg);
+      const float f = wj * fr;
+      A.fx += (double)(f * dxv);
+      A.fy += (double)(f * dyv);
+      A.fz += (double)(f * dzv);
+    }
+  }
+}
+
+__device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int dz, int* __restrict__ queue,
+                                              int lane, int self_ent, const float4& xi, int cxi,
+                                              const float4* __restrict__ xr, const float* __restrict__ xif,
+                                              const CellGeom& g, const PairConstF& pc, PairAccM& A) {
+  const float bx = (float)(cxi - ix * g.nc[0]);
+  const float ay = fmaf((float)-dy, pc.w[1], xi.y);
+  const float az = fmaf((float)-dz, pc.w[2], xi.z);
+  const int bits = entry_bits(ix, dy, dz);
+  int* slot = queue + A.cnt * kWaveQ + lane;
+  while (__any(j < j1)) {
+    float4 xj[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) xj[b] = xr[j + b];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const float dxv = fmaf(bx - xj[b].w, pc.w[0], xi.x) - xj[b].x;
+      const float dyv = ay - xj[b].y, dzv = az - xj[b].z;
+      const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
+      const bool hit = (j + b < j1) & (r2 < pc.a2);
+      *slot = ((j + b) << 8) | bits;
+      slot += hit ? kWaveQ : 0;
+    }
+    j += j < j1 ? kBatch : 0;
+    A.cnt = (int)(slot - queue - lane) / kWaveQ;
+    if (__any(A.cnt > kQueue - kBatch)) {
+      pair_drain_f32(queue, A.cnt, lane, self_ent, xi, cxi, xr, xif, g, pc, A);
+      A.cnt = 0;
+      slot = queue + lane;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kWaveQ) k_pair_trim_f32(const float4* __restrict__ xr,
+                                                          const float* __restrict__ xif,
+                                                          const double4* __restrict__ xs,
+                                                          const int* __restrict__ cell_s,
+                                                          const int* __restrict__ cstart,
+                                                          const int* __restrict__ tgt, int n, CellGeom g,
+                                                          PairConstF pc, double* __restrict__ e0,
+                                                          double* __restrict__ floc) {
+  __shared__ int queue[kQueue * kWaveQ];
+  const int lane = threadIdx.x;
+  const int k = blockIdx.x * kWaveQ + lane;
+  const bool active = k < n;
+  const int sc = tgt[active ? k : n - 1];
+  const float4 xi = xr[sc];
+  const double4 xd = xs[sc];   // FP64 position: only for choosing rows and cells
+  const int c = cell_s[sc];
+  const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
+  const int self_ent = active ? ((sc << 8) | entry_bits(0, 0, 0)) : -1;
+  PairAccM A{0.0, 0.0, 0.0, 0.0, 0};
+  const double a2 = (double)pc.a2 * (1.0 + 1e-6);
+  const float reach = (float)(1.0 + 1e-5);
+  for (int dz = -2; dz <= 2; ++dz) {
+    const int uz = cz + dz;
+    const int iz = uz < 0 ? -1 : (uz >= g.nc[2] ? 1 : 0);
+    const int tz = uz - iz * g.nc[2];
+    const double gz = gap1(xd.z, uz * g.w[2], g.w[2], 1e-12 * g.L[2]);
+    for (int dy = -2; dy <= 2; ++dy) {
+      const int uy = cy + dy;
+      const int iy = uy < 0 ? -1 : (uy >= g.nc[1] ? 1 : 0);
+      const int ty = uy - iy * g.nc[1];
+      const double gy = gap1(xd.y, uy * g.w[1], g.w[1], 1e-12 * g.L[1]);
+      const double rem = a2 - (gy * gy + gz * gz);
+      int clo = 0, chi = -1;
+      if (active && rem > 0.0) {
+        const double rx = (double)(sqrtf((float)rem) * reach) + 1e-6 * g.w[0];
+        clo = max(cx - 2, (int)floor((xd.x - rx) * g.inv_w[0]));
+        chi = min(cx + 2, (int)floor((xd.x + rx) * g.inv_w[0]));
+      }
+      int lo1 = clo, hi1 = chi, ix1 = 0, lo2 = 0, hi2 = -1, ix2 = 0;
+      if (clo < 0) {
+        lo1 = clo + g.nc[0]; hi1 = g.nc[0] - 1; ix1 = -1;
+        lo2 = 0; hi2 = chi; ix2 = 0;
+      } else if (chi >= g.nc[0]) {
+        lo1 = clo; hi1 = g.nc[0] - 1; ix1 = 0;
+        lo2 = 0; hi2 = chi - g.nc[0]; ix2 = 1;
+      }
+      const int row = (tz * g.nc[1] + ty) * g.nc[0];
+      int j0 = 0, j1 = 0;
+      if (lo1 <= hi1) {
+        j0 = cstart[row + lo1];
+        j1 = cstart[row + hi1 + 1];
+      }
+      int k0 = 0, k1 = 0;
+      if (lo2 <= hi2) {
+        k0 = cstart[row + lo2];
+        k1 = cstart[row + hi2 + 1];
+      }
+      pair_scan_f32(j0, j1, ix1, dy, dz, queue, lane, self_ent, xi, cx, xr, xif, g, pc, A);
+      pair_scan_f32(k0, k1, ix2, dy, dz, queue, lane, self_ent, xi, cx, xr, xif, g, pc, A);
+    }
+  }
+  pair_drain_f32(queue, A.cnt, lane, self_ent, xi, cx, xr, xif, g, pc, A);
+  if (active) {
+    const double wi = (double)xif[sc];
+    e0[sc] = A.e;
+    floc[3 * (size_t)sc + 0] = wi * A.fx;
+    floc[3 * (size_t)sc + 1] = wi * A.fy;
+    floc[3 * (size_t)sc + 2] = wi * A.fz;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   PairConst pc{P->a2, P->inv_a2, P->inv_a6, P->inv_a8};
   const CellGeom& g = P->cg;
-  if (P->pair_fast && n < (1 << 25)) {
+  if (P->precision == MLS_MIXED && P->pair_fast && n < (1 << 24)) {
+    PairConstF pf{(float)P->a2, (float)P->inv_a2, (float)P->inv_a6, (float)P->inv_a8,
+                  {(float)g.w[0], (float)g.w[1], (float)g.w[2]}};
+    k_pair_trim_f32<<<(n + kWaveQ - 1) / kWaveQ, kWaveQ, 0, s>>>(P->d_xr, P->d_xif, P->d_xs, P->d_cell_s,
+                                                                 P->d_cell_start, P->d_tgt, n, g, pf, P->d_e0,
+                                                                 P->d_floc);
+  } else if (P->pair_fast && n < (1 << 25)) {
     k_pair_trim_f64<<<(n + kWaveQ - 1) / kWaveQ, kWaveQ, 0, s>>>(P->d_xs, P->d_cell_s, P->d_cell_start, P->d_tgt,
                                                                  n, g, pc, P->d_e0, P->d_floc);
   } else {

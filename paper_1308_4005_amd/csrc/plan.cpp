@@ -341,7 +341,10 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   ALLOC(P->d_xs, N + kSortedPad);
   ALLOC(P->d_e0, N);
   ALLOC(P->d_floc, 3 * N);
-  if (P->precision == MLS_MIXED) ALLOC(P->d_xr, N);
+  if (P->precision == MLS_MIXED) {
+    ALLOC(P->d_xr, N + kSortedPad);
+    ALLOC(P->d_xif, N + kSortedPad);
+  }
   P->n_partial = (int)((N + 255) / 256);
   ALLOC(P->d_partial, 2 * (size_t)P->n_partial + 2);
   ALLOC(P->d_scratch, 64);
@@ -364,6 +367,7 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   ALLOC(P->d_rows, P->rows.size());
   ALLOC(P->d_wave_rows, kStencilWaves + 1);
   ALLOC(P->d_row_w_tile, P->row_w.size());
+  ALLOC(P->d_row_wf_tile, P->row_w.size());
   ALLOC(P->d_tiles, tiles.size());
   ALLOC(P->d_row_w, P->row_w.size());
   ALLOC(P->d_row_wf, P->row_w.size());
@@ -387,6 +391,10 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
     if ((e = hipMemcpy(P->d_row_w_tile, row_w_tile.data(), row_w_tile.size() * sizeof(double),
                        hipMemcpyHostToDevice)) != hipSuccess)
       return hip_fail(e, "copy stencil tile weights");
+    std::vector<float> wtf(row_w_tile.begin(), row_w_tile.end());
+    if ((e = hipMemcpy(P->d_row_wf_tile, wtf.data(), wtf.size() * sizeof(float), hipMemcpyHostToDevice)) !=
+        hipSuccess)
+      return hip_fail(e, "copy stencil tile weights (fp32)");
   }
   {
     // cells grouped in 4 x 4 x 4 bricks (x fastest inside a brick and across
@@ -410,6 +418,7 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   if ((e = hipMemcpy(P->d_Kl, P->Kl.data(), P->Kl.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "copy coarsest kernel");
   if ((e = hipMemset(P->d_flags, 0, 4 * sizeof(int))) != hipSuccess) return hip_fail(e, "clear flags");
+  if ((e = hipMemset(P->d_scratch, 0, 64 * sizeof(double))) != hipSuccess) return hip_fail(e, "clear scratch");
   return MLS_OK;
 }
 

@@ -180,6 +180,7 @@ struct StencilLevel {
   int tiles_z;     // z chunks
   int tile0;       // first tile index of this level
   double scale;    // 2^(-6(k-1))
+  double inv_size; // 1 / points of the level
 };
 
 struct StencilLaunch {
@@ -217,11 +218,15 @@ __device__ __forceinline__ void tile_switch(int hz, T (&acc)[ZC], const T* c, in
   }
 }
 
+// FP32 tiles hold q - mean (mean = sum_i xi / points, the exact mean by the
+// partition of unity); the constant part adds back as mean * sum of weights,
+// since a periodic convolution maps a constant c to c times the weight sum.
 template <class T, int R, int ZC, int W>
 __global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const int4* __restrict__ tiles,
                                                          const StencilRow* __restrict__ rows,
                                                          const int* __restrict__ wave_rows,
-                                                         const T* __restrict__ wts) {
+                                                         const T* __restrict__ wts,
+                                                         const double* __restrict__ sum_xi, double wsum) {
   constexpr int SX = 8 + 2 * R, SY = 8 + 2 * R, SZ = ZC + 2 * R;
   constexpr int PS = SX * SY, NP = PS * SZ, NT = 64 * W;
   static_assert(W * ZC * 64 <= NP, "reduction buffer must fit in the tile");
@@ -238,9 +243,10 @@ __global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const 
   __syncthreads();
   const size_t gps = (size_t)V.n[0] * V.n[1];
   const double* __restrict__ q = V.q;
+  const double mean = sizeof(T) < sizeof(double) ? *sum_xi * V.inv_size : 0.0;
   for (int i = tid; i < NP; i += NT) {
     const int lx = i % SX, ly = (i / SX) % SY, lz = i / PS;
-    tile[i] = (T)q[(size_t)wrapz[lz] * gps + (size_t)wrapy[ly] * V.n[0] + wrapx[lx]];
+    tile[i] = (T)(q[(size_t)wrapz[lz] * gps + (size_t)wrapy[ly] * V.n[0] + wrapx[lx]] - mean);
   }
   __syncthreads();
   const int tx = lane & 7, ty = lane >> 3;
@@ -268,7 +274,7 @@ __global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const 
       T sum = tile[k * 64 + lane];
 #pragma unroll
       for (int w2 = 1; w2 < W; ++w2) sum += tile[(w2 * ZC + k) * 64 + lane];
-      V.e[(size_t)z * gps + (size_t)y * V.n[0] + x] = V.scale * (double)sum;
+      V.e[(size_t)z * gps + (size_t)y * V.n[0] + x] = V.scale * ((double)sum + mean * wsum);
     }
   }
 }
@@ -333,8 +339,8 @@ int stencil_window(const mls_plan_s* P) {
   return std::max(P->stencil_R[0], std::max(P->stencil_R[1], P->stencil_R[2]));
 }
 
-template <int R>
-hipError_t launch_tile(mls_plan_s* P, hipStream_t s) {
+template <class T, int R>
+hipError_t launch_tile(mls_plan_s* P, const T* wts, hipStream_t s) {
   constexpr int kTileZ = tile_zc(R);
   StencilLaunch L{};
   L.nlev = P->levels - 1;
@@ -348,23 +354,30 @@ hipError_t launch_tile(mls_plan_s* P, hipStream_t s) {
     V.tiles_z = nblocks(Lv.g.n[2], kTileZ);
     V.tile0 = t;
     V.scale = std::ldexp(1.0, -6 * (k - 1));
+    V.inv_size = 1.0 / (double)Lv.g.size;
     t += nblocks(Lv.g.n[0], 8) * nblocks(Lv.g.n[1], 8) * V.tiles_z;
   }
-  k_stencil_tile<double, R, kTileZ, kStencilWaves><<<t, 64 * kStencilWaves, 0, s>>>(
-      L, P->d_tiles, P->d_rows, P->d_wave_rows, P->d_row_w_tile);
+  k_stencil_tile<T, R, kTileZ, kStencilWaves><<<t, 64 * kStencilWaves, 0, s>>>(
+      L, P->d_tiles, P->d_rows, P->d_wave_rows, wts, P->d_scratch, P->taps_wsum);
   return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_tile_r(mls_plan_s* P, int R, const T* wts, hipStream_t s) {
+  switch (R) {
+    case 1: case 2: case 3: case 4: return launch_tile<T, 4>(P, wts, s);
+    case 5: case 6: return launch_tile<T, 6>(P, wts, s);
+    case 7: case 8: return launch_tile<T, 8>(P, wts, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_stencils(mls_plan_s* P, hipStream_t s) {
   if (P->levels < 2) return hipSuccess;
   const int R = stencil_window(P);
-  if (P->stencil_kernel == 1) {
-    switch (R) {
-      case 1: case 2: case 3: case 4: return launch_tile<4>(P, s);
-      case 5: case 6: return launch_tile<6>(P, s);
-      case 7: case 8: return launch_tile<8>(P, s);
-      default: break;
-    }
+  if (P->stencil_kernel == 1 && R >= 1 && R <= 8) {
+    if (P->precision == MLS_MIXED) return launch_tile_r<float>(P, R, P->d_row_wf_tile, s);
+    return launch_tile_r<double>(P, R, P->d_row_w_tile, s);
   }
   const int ntaps = (int)P->taps.size();
   for (int k = 1; k < P->levels; ++k) {
