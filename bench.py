@@ -62,6 +62,35 @@ def work_model(plan_info, n, pairs, order):
     }
 
 
+# kernel that carries each stage of the 10^6-atom cube (cell width a/2 there)
+STAGE_KERNEL = {("pair", "mixed"): "k_pair_trim_f32", ("pair", "fp64"): "k_pair_trim_f64",
+                ("stencil", "mixed"): "void k_stencil_tile<float, 6, 16, 4>",
+                ("stencil", "fp64"): "void k_stencil_tile<double, 6, 16, 4>",
+                ("anterpolation", "mixed"): "void k_anterp_owned<4, float>",
+                ("anterpolation", "fp64"): "void k_anterp_owned<4, double>",
+                ("interpolation", "mixed"): "void k_interp_f64<4, float>",
+                ("interpolation", "fp64"): "void k_interp_f64<4, double>"}
+
+
+def measured_traffic(stage, precision):
+    """HBM bytes per launch of the stage's kernel, from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE record (calibrated on a plain copy); None
+    when no record exists or any kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    name = STAGE_KERNEL.get((stage, precision))
+    if name is None or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_1308_4005_amd", "csrc")
+    for f, h in rec["sources_sha1"].items():
+        fp = os.path.join(csrc, f)
+        if not os.path.exists(fp) or hashlib.sha1(open(fp, "rb").read()).hexdigest() != h:
+            return None
+    k = rec["kernels"].get(name)
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
+
+
 def time_precision(w, prm, precision, steps, warmup, dev):
     import torch
     from paper_1308_4005_amd import Plan, Result
@@ -120,14 +149,17 @@ def cpu_baseline(prm, target_n):
     from oracle import mls as oracle_mls
     from paper_1308_4005_amd import workloads as W
     w = W.cube(32000, 0.8, seed=31)
+    times = []
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        oracle_mls.mls(w.pos, w.c6, w.box, prm["a"], prm["h"], prm["order"], 3)
-        dt = time.perf_counter() - t0
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle_mls.mls(w.pos, w.c6, w.box, prm["a"], prm["h"], prm["order"], 3)
+            times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     return {"value": (1.0 / dt) * (w.n / target_n), "unit": "evals/s (1M-atom equivalent)",
             "cores": 1, "kind": "oracle",
             "sample": f"oracle.mls FP64 on a {w.n}-atom cube (rho 0.8, a={prm['a']}, h={prm['h']}, "
-                      f"p={prm['order']}, 3 levels): {dt:.2f} s per evaluation, scaled by "
+                      f"p={prm['order']}, 3 levels): median of 3 runs {dt:.2f} s per evaluation, scaled by "
                       f"{w.n}/{target_n} atoms; numpy single thread (BLAS limited to 1)"}
 
 
@@ -188,7 +220,7 @@ def main():
         peak = PEAK["fp32" if head == "mixed" else "fp64"]
         unit = "TFLOP/s"
     roofline = {"bound": m["bound"], "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak, "traffic": measured_traffic(dom, head), "traffic_unit": "bytes",
                 "work_per_launch": m.get("flops", m.get("bytes")),
                 "avg_launch_ms": sm[dom]}
 
