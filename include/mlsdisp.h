@@ -182,24 +182,53 @@ mls_status mls_plan_read_timing(mls_plan_t plan, double* ms, int* count);
 mls_status mls_plan_destroy(mls_plan_t plan);
 
 /* ---------------------------------------------------------------------------
- * Batched form: many independent periodic boxes, each with its own plan
- * parameters, evaluated by one sequence of persistent launches that walk a
- * (box, tile) work list built at creation.  The list and launch shapes are
- * chosen by an autotuner run in mls_batch_create; mls_batch_evaluate can be
- * captured into a hipGraph by the caller.
- *   per_box   host (nbox) parameter sets (precision must agree)
- *   n_per_box host (nbox) atom counts
- * Atoms of box b occupy rows offsets[b]..offsets[b+1]-1 of pos/c6/forces,
- * offsets being the exclusive prefix sum of n_per_box (computed by the
- * library).  energies: device (nbox).
+ * Batched form: many independent periodic boxes of uneven size, each with its
+ * own parameter set (grids, levels and cells are resolved per box exactly as
+ * mls_plan_create does; the method is that of Sec. II applied to every box).
+ * One evaluation of the batch is a fixed sequence of launches, one per phase
+ * of Sec. II.B (binning, local part, anterpolation, each restriction, the
+ * level stencils, the coarsest level, each prolongation, interpolation);
+ * each launch covers every box with work in that phase by walking a
+ * (box, block) work list with a persistent grid.  The sequence is captured
+ * into a hipGraph on first use and replayed.
+ *
+ *   nbox       1 .. 2^20 boxes
+ *   per_box    host (nbox) parameter sets; precision and order must agree
+ *   n_per_box  host (nbox) atom counts >= 0 (total < 2^31)
+ *   autotune   nonzero: the first mls_batch_evaluate times every stage over
+ *              a set of persistent grid sizes and stencil tile depths on the
+ *              caller's data, keeps the fastest per stage, then captures.
+ *              That first call synchronises the device.
+ *
+ * Layout: atoms of box b are rows off[b] .. off[b+1]-1 of pos (n,3), c6 (n),
+ * forces (n,3) and dE_dc6 (n), off being the exclusive prefix sum of
+ * n_per_box; energies is device (nbox).  All arrays are device FP64 owned by
+ * the caller; forces and dE_dc6 may be NULL.  Outputs are overwritten.
+ * Changing any of the five pointers between calls rebuilds the launch tables
+ * and the graph, which synchronises the device; calls with the same pointers
+ * are enqueue-only.  Errors: as mls_evaluate; mls_batch_create returns
+ * MLS_ERR_UNSUPPORTED for a box whose level-stencil window 2a/h exceeds 8
+ * grid points.  A batch is not thread-safe.
  * ------------------------------------------------------------------------- */
+typedef struct {
+  int blocks[MLS_NUM_STAGES]; /* persistent grid of each MLS_T_* stage in blocks; 0 = one block per item */
+  int stencil_zc;             /* z extent of a level-stencil tile: 16 or 8 (16 applies to windows <= 6) */
+  double tuned_ms;            /* one evaluation with this shape, as timed by the autotuner (0: not timed) */
+} mls_batch_tuning;
+
 mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* n_per_box,
                             int autotune, mls_batch_t* out);
 mls_status mls_batch_evaluate(mls_batch_t batch, const double* pos, const double* c6,
                               double* energies, double* forces, double* dE_dc6, void* stream);
-/* Autotuned launch shape (host out-params), for reporting. */
-mls_status mls_batch_get_tuning(mls_batch_t batch, int* pair_block, int* stencil_block,
-                                double* tuned_ms);
+/* enable (default) or disable graph replay; disabled, every call launches eagerly */
+mls_status mls_batch_set_graph(mls_batch_t batch, int enable);
+/* current launch shape (after autotuning: the tuned one) / force a shape (cancels a pending autotune) */
+mls_status mls_batch_get_tuning(mls_batch_t batch, mls_batch_tuning* tuning);
+mls_status mls_batch_set_tuning(mls_batch_t batch, const mls_batch_tuning* tuning);
+/* resolved grids, levels and cells of box `box` (as mls_plan_get_info) */
+mls_status mls_batch_box_info(mls_batch_t batch, int box, mls_plan_info* info);
+/* synchronises; ORs the data flags of every box (MLS_ERR_NONFINITE if any) and clears them */
+mls_status mls_batch_status(mls_batch_t batch, int* device_flags);
 mls_status mls_batch_destroy(mls_batch_t batch);
 
 /* Static description of a status code. */

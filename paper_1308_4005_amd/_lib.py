@@ -31,7 +31,8 @@ MLS_STAGE_E_TOTAL = 6
 EXPORTS = [
     "mls_plan_create", "mls_plan_get_info", "mls_evaluate", "mls_plan_copy_stage",
     "mls_plan_status", "mls_plan_destroy", "mls_batch_create", "mls_batch_evaluate",
-    "mls_batch_get_tuning", "mls_batch_destroy", "mls_status_string", "mls_last_error",
+    "mls_batch_set_graph", "mls_batch_get_tuning", "mls_batch_set_tuning", "mls_batch_box_info",
+    "mls_batch_status", "mls_batch_destroy", "mls_status_string", "mls_last_error",
     "mls_plan_set_timing", "mls_plan_read_timing",
 ]
 
@@ -67,6 +68,14 @@ class MLSPlanInfo(ctypes.Structure):
     ]
 
 
+class MLSBatchTuning(ctypes.Structure):
+    _fields_ = [
+        ("blocks", ctypes.c_int * 8),
+        ("stencil_zc", ctypes.c_int),
+        ("tuned_ms", ctypes.c_double),
+    ]
+
+
 class MLSError(RuntimeError):
     def __init__(self, status, where, detail):
         super().__init__(f"{where}: status {status}: {detail}")
@@ -99,16 +108,17 @@ def load():
     lib.mls_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(MLSParams), ctypes.POINTER(i64),
                                      ctypes.c_int, ctypes.POINTER(P)]
     lib.mls_batch_evaluate.argtypes = [P, dp, dp, dp, dp, dp, P]
-    lib.mls_batch_get_tuning.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                         ctypes.POINTER(ctypes.c_double)]
+    lib.mls_batch_set_graph.argtypes = [P, ctypes.c_int]
+    lib.mls_batch_get_tuning.argtypes = [P, ctypes.POINTER(MLSBatchTuning)]
+    lib.mls_batch_set_tuning.argtypes = [P, ctypes.POINTER(MLSBatchTuning)]
+    lib.mls_batch_box_info.argtypes = [P, ctypes.c_int, ctypes.POINTER(MLSPlanInfo)]
+    lib.mls_batch_status.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
     lib.mls_batch_destroy.argtypes = [P]
     lib.mls_plan_set_timing.argtypes = [P, ctypes.c_int]
     lib.mls_plan_read_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
-    for fn in ("mls_plan_create", "mls_plan_get_info", "mls_evaluate", "mls_plan_copy_stage",
-               "mls_plan_status", "mls_plan_destroy", "mls_batch_create", "mls_batch_evaluate",
-               "mls_batch_get_tuning", "mls_batch_destroy", "mls_plan_set_timing",
-               "mls_plan_read_timing"):
-        getattr(lib, fn).restype = ctypes.c_int
+    for fn in EXPORTS:
+        if fn not in ("mls_status_string", "mls_last_error"):
+            getattr(lib, fn).restype = ctypes.c_int
     lib.mls_status_string.argtypes = [ctypes.c_int]
     lib.mls_status_string.restype = ctypes.c_char_p
     lib.mls_last_error.argtypes = []

@@ -65,6 +65,145 @@ struct Level {
   float* ef = nullptr;   // mixed precision: e^k (FP32 stencil output)
 };
 
+// ---------------------------------------------------------------------------
+// Kernel argument sets.  Every kernel body is a functor K with
+//   using Args = ...;  static constexpr int kThreads;  static __device__ void run(const Args&, int blk);
+// The single-plan path launches k_one<K> (one block per blk, Args by value);
+// the batched path launches k_batched<K>, whose blocks walk a list of
+// (box, blk) items over a device array of per-box Args.
+// ---------------------------------------------------------------------------
+struct GridGeom {
+  int n[3];
+  double invh[3];
+};
+
+// owner-computes anterpolation blocking (cells per block, blocks, halo cells)
+struct AntGeom {
+  int cb[3];
+  int nb[3];
+  int nh[3];
+};
+
+struct PairConst {
+  double a2, inv_a2, inv_a6, inv_a8;
+};
+
+struct PairConstF {
+  float a2, inv_a2, inv_a6, inv_a8;
+  float w[3];
+};
+
+struct OutPtrs {
+  double* forces;
+  double* potential;
+  double* dE_dc6;
+};
+
+struct FillArgs { int* p; int n; };
+struct FillDArgs { double* p; int n; };
+struct BinCountArgs {
+  const double* pos; const double* c6; int n; CellGeom g;
+  int* cid; int* slot; int* count; double4* xw; int* flags;
+};
+struct ScanArgs { const int* count; int m; int* start; int* bsum; int* bmax; int* max_count; };
+struct ScatterArgs { const int* cid; const int* slot; int n; const int* start; int* perm_tmp; };
+struct RankArgs { const int* start; int ncell; const int* perm_tmp; int* perm; };
+struct GatherArgs {
+  const int* perm; int n; const double4* xw; const int* cid;
+  double4* xs; int* cell_s; float4* xr; float* xif; CellGeom g;
+};
+struct BrickArgs { const int* order; const int* start; const int* bstart; int ncell; int* bcount; int* tgt; };
+struct SumXiArgs { const double4* xs; int n; double* partial; double* out; };
+struct PairArgs {
+  const double4* xs; const int* cell_s; const int* cstart; const int* tgt; int n; CellGeom g; PairConst pc;
+  double* e0; double* floc;
+};
+struct PairArgsF {
+  const float4* xr; const float* xif; const double4* xs; const int* cell_s; const int* cstart; const int* tgt;
+  int n; CellGeom g; PairConstF pc; double* e0; double* floc;
+};
+struct AnterpArgs {
+  const double4* xs; const int* cstart; int n; CellGeom cg; GridGeom gg; AntGeom ag; double* q;
+};
+struct TransferArgs {              // restriction (fine -> coarse) and prolongation (coarse -> fine)
+  const double* src; GridDims gs;  // q^{k-1} (restriction) or E^{k+1} (prolongation)
+  const double* add;               // prolongation: e^k added to the interpolated values
+  double* dst; GridDims gd;
+};
+struct InterpArgs {
+  const double4* xs; const int* perm; int n; GridGeom gg; const double* E1; const double* e0;
+  const double* floc; double cself; OutPtrs out; double* partial;
+};
+struct EnergyArgs { const double* partial; int nb; double cself; double* energy; };
+struct CoarsestArgs { const double* q; GridDims g; const double* K; double* e; };
+
+// One level of the tiled stencil: grids, scale, and the tap tables of its plan.
+struct StencilLevel {
+  const double* q;
+  double* e;
+  int n[3];
+  int tiles_z;                 // z chunks
+  int tile0;                   // first tile index of this level
+  double scale;                // 2^(-6(k-1))
+  double inv_size;             // 1 / points of the level
+  const StencilRow* rows;
+  const int* wave_rows;
+  const void* wts;             // tile weights (double, or float in mixed precision)
+  const double* sum_xi;        // mixed precision: sum of xi (mean of the charges)
+  double wsum;                 // sum of the level-1 weights
+};
+
+// One phase of a batched evaluation: a kernel, per-box Args in device
+// memory, and its (box, blk) work list.  The stencil phase walks int4 tiles
+// (StencilLevel index, tile x, y, z) instead.
+enum BatchKernel {
+  BK_FILL_I, BK_FILL_D, BK_BIN_COUNT, BK_SCAN_BLOCKS, BK_SCAN_SUMS, BK_SCAN_ADD, BK_SCATTER, BK_RANK, BK_GATHER,
+  BK_SUM_XI_BLOCKS, BK_SUM_XI_FINAL, BK_BRICK_COUNTS, BK_BRICK_TARGETS,
+  BK_PAIR_GENERIC, BK_PAIR_TRIM_F64, BK_PAIR_TRIM_F32,
+  BK_ANT_ATOMIC, BK_ANT_OWNED, BK_RESTRICT, BK_PROLONG, BK_INTERP, BK_ENERGY,
+  BK_STENCIL, BK_COARSEST
+};
+
+struct BatchPhase {
+  int kernel = 0;              // BatchKernel
+  int stage = 0;               // MLS_T_* stage it belongs to (timing and tuning)
+  int variant = 0;             // order / precision / stencil window, per kernel
+  void* args = nullptr;        // device array of the kernel's Args (one per box)
+  void* work = nullptr;        // device int2 (box, blk) items, or int4 tiles for BK_STENCIL
+  int nwork = 0;
+  int grid = 0;                // persistent grid in blocks (0: one block per item)
+};
+
+template <class K>
+__global__ void __launch_bounds__(K::kThreads) k_one(typename K::Args a) {
+  K::run(a, blockIdx.x);
+}
+
+template <class K>
+__global__ void __launch_bounds__(K::kThreads) k_batched(const typename K::Args* __restrict__ args,
+                                                         const int2* __restrict__ work, int nwork) {
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const int2 it = work[w];
+    K::run(args[it.x], it.y);
+    __syncthreads();   // LDS of the item is free before the next one
+  }
+}
+
+template <class K>
+hipError_t launch_one(const typename K::Args& a, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  k_one<K><<<blocks, K::kThreads, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <class K>
+hipError_t launch_batched_phase(const BatchPhase& ph, hipStream_t s) {
+  if (ph.nwork == 0) return hipSuccess;
+  const int grid = ph.grid > 0 ? (ph.grid < ph.nwork ? ph.grid : ph.nwork) : ph.nwork;
+  k_batched<K><<<grid, K::kThreads, 0, s>>>((const typename K::Args*)ph.args, (const int2*)ph.work, ph.nwork);
+  return hipGetLastError();
+}
+
 }  // namespace mls
 
 struct mls_plan_s {
@@ -168,5 +307,16 @@ hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forc
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
 hipError_t launch_zero_i(int* p, int64_t count, hipStream_t s);
 hipError_t launch_copy_stage(mls_plan_s* P, int what, int level, void* dst, hipStream_t s);
+
+// owner-computes anterpolation blocking of a plan (false: use the atomic kernel)
+bool anterp_owned_geom(const mls_plan_s* P, AntGeom& ag);
+// z extent candidates of a stencil tile for window R
+bool stencil_tile_ok(int R, int zc);
+
+// batched launchers: one phase of a batched evaluation (per kernel file)
+hipError_t launch_batched_binning(const BatchPhase& ph, hipStream_t s);
+hipError_t launch_batched_pair(const BatchPhase& ph, hipStream_t s);
+hipError_t launch_batched_grid(const BatchPhase& ph, hipStream_t s);
+hipError_t launch_batched_stencil(const BatchPhase& ph, hipStream_t s);
 
 }  // namespace mls

@@ -15,10 +15,6 @@ namespace {
 
 constexpr int kBlock = 128;
 
-struct PairConst {
-  double a2, inv_a2, inv_a6, inv_a8;
-};
-
 // g_0(r) and g_0'(r)/r from s = r^2 (caller guarantees 0 < s < a^2).
 // 1/s from the hardware reciprocal refined by Newton steps (two in FP64,
 // one in FP32): cheaper than the correctly rounded division sequence and
@@ -50,57 +46,62 @@ __device__ __forceinline__ void g0_pair(T s, T inv_a2, T inv_a6, T inv_a8, T& g,
 }
 
 // FP64: one thread per cell-sorted target atom.
-__global__ void __launch_bounds__(kBlock) k_pair_f64(const double4* __restrict__ xs, const int* __restrict__ cell_s,
-                                                     const int* __restrict__ cstart, int n, CellGeom g, PairConst pc,
-                                                     double* __restrict__ e0, double* __restrict__ floc) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const double4 xi = xs[s];
-  const int c = cell_s[s];
-  const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
-  double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-  for (int oz = -g.noff[2]; oz <= g.noff[2]; ++oz) {
-    int tz = cz + oz;
-    const int iz = floordiv(tz, g.nc[2]);
-    tz -= iz * g.nc[2];
-    const double sz = iz * g.L[2];
-    for (int oy = -g.noff[1]; oy <= g.noff[1]; ++oy) {
-      int ty = cy + oy;
-      const int iy = floordiv(ty, g.nc[1]);
-      ty -= iy * g.nc[1];
-      const double sy = iy * g.L[1];
-      for (int ox = -g.noff[0]; ox <= g.noff[0]; ++ox) {
-        int tx = cx + ox;
-        const int ix = floordiv(tx, g.nc[0]);
-        tx -= ix * g.nc[0];
-        const double sx = ix * g.L[0];
-        const bool home = (ix | iy | iz) == 0;
-        const int t = (tz * g.nc[1] + ty) * g.nc[0] + tx;
-        const int j0 = cstart[t], j1 = cstart[t + 1];
-        for (int j = j0; j < j1; ++j) {
-          const double4 xj = xs[j];
-          const double dx = xi.x - (xj.x + sx);
-          const double dy = xi.y - (xj.y + sy);
-          const double dz = xi.z - (xj.z + sz);
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 < pc.a2 && !(home && j == s)) {
-            double gg, fr;
-            g0_pair<double>(r2, pc.inv_a2, pc.inv_a6, pc.inv_a8, gg, fr);
-            e += xj.w * gg;
-            const double f = xj.w * fr;
-            fx += f * dx;
-            fy += f * dy;
-            fz += f * dz;
+struct PairGeneric {
+  using Args = PairArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    const int s = blk * kBlock + threadIdx.x;
+    if (s >= a.n) return;
+    const CellGeom& g = a.g;
+    const PairConst& pc = a.pc;
+    const double4* __restrict__ xs = a.xs;
+    const double4 xi = xs[s];
+    const int c = a.cell_s[s];
+    const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
+    double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int oz = -g.noff[2]; oz <= g.noff[2]; ++oz) {
+      int tz = cz + oz;
+      const int iz = floordiv(tz, g.nc[2]);
+      tz -= iz * g.nc[2];
+      const double sz = iz * g.L[2];
+      for (int oy = -g.noff[1]; oy <= g.noff[1]; ++oy) {
+        int ty = cy + oy;
+        const int iy = floordiv(ty, g.nc[1]);
+        ty -= iy * g.nc[1];
+        const double sy = iy * g.L[1];
+        for (int ox = -g.noff[0]; ox <= g.noff[0]; ++ox) {
+          int tx = cx + ox;
+          const int ix = floordiv(tx, g.nc[0]);
+          tx -= ix * g.nc[0];
+          const double sx = ix * g.L[0];
+          const bool home = (ix | iy | iz) == 0;
+          const int t = (tz * g.nc[1] + ty) * g.nc[0] + tx;
+          const int j0 = a.cstart[t], j1 = a.cstart[t + 1];
+          for (int j = j0; j < j1; ++j) {
+            const double4 xj = xs[j];
+            const double dx = xi.x - (xj.x + sx);
+            const double dy = xi.y - (xj.y + sy);
+            const double dz = xi.z - (xj.z + sz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < pc.a2 && !(home && j == s)) {
+              double gg, fr;
+              g0_pair<double>(r2, pc.inv_a2, pc.inv_a6, pc.inv_a8, gg, fr);
+              e += xj.w * gg;
+              const double f = xj.w * fr;
+              fx += f * dx;
+              fy += f * dy;
+              fz += f * dz;
+            }
           }
         }
       }
     }
+    a.e0[s] = e;
+    a.floc[3 * (size_t)s + 0] = xi.w * fx;
+    a.floc[3 * (size_t)s + 1] = xi.w * fy;
+    a.floc[3 * (size_t)s + 2] = xi.w * fz;
   }
-  e0[s] = e;
-  floc[3 * (size_t)s + 0] = xi.w * fx;
-  floc[3 * (size_t)s + 1] = xi.w * fy;
-  floc[3 * (size_t)s + 2] = xi.w * fz;
-}
+};
 
 // FP64, filter-and-drain over half-cutoff cells: one wave of 64 lanes takes
 // 64 targets from a compact group of cells.  Each lane visits the 5 x 5 rows
@@ -191,20 +192,23 @@ __device__ __forceinline__ double gap1(double x, double lo, double w, double eps
   return fmax(0.0, fmax(lo - x, x - (lo + w)) - eps);
 }
 
-__global__ void __launch_bounds__(kWaveQ) k_pair_trim_f64(const double4* __restrict__ xs,
-                                                          const int* __restrict__ cell_s,
-                                                          const int* __restrict__ cstart,
-                                                          const int* __restrict__ tgt, int n, CellGeom g,
-                                                          PairConst pc, double* __restrict__ e0,
-                                                          double* __restrict__ floc) {
+struct PairTrimF64 {
+  using Args = PairArgs;
+  static constexpr int kThreads = kWaveQ;
+  static __device__ void run(const Args& ar, int blk) {
+  const double4* __restrict__ xs = ar.xs;
+  const int* __restrict__ cstart = ar.cstart;
+  const CellGeom& g = ar.g;
+  const PairConst& pc = ar.pc;
+  const int n = ar.n;
   __shared__ int queue[kQueue * kWaveQ];
   const int lane = threadIdx.x;
   // targets in brick order: the 64 lanes of a wave sit in a compact group of cells
-  const int k = blockIdx.x * kWaveQ + lane;
+  const int k = blk * kWaveQ + lane;
   const bool active = k < n;
-  const int sc = tgt[active ? k : n - 1];
+  const int sc = ar.tgt[active ? k : n - 1];
   const double4 xi = xs[sc];
-  const int c = cell_s[sc];
+  const int c = ar.cell_s[sc];
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
   // the target itself, seen in the home image, is skipped in the drain
   const int self_ent = active ? ((sc << 6) | image_bits(0, 0, 0)) : -1;
@@ -254,12 +258,13 @@ __global__ void __launch_bounds__(kWaveQ) k_pair_trim_f64(const double4* __restr
   }
   pair_drain_f64(queue, A.cnt, lane, self_ent, xi, xs, g, pc, A);
   if (active) {
-    e0[sc] = A.e;
-    floc[3 * (size_t)sc + 0] = xi.w * A.fx;
-    floc[3 * (size_t)sc + 1] = xi.w * A.fy;
-    floc[3 * (size_t)sc + 2] = xi.w * A.fz;
+    ar.e0[sc] = A.e;
+    ar.floc[3 * (size_t)sc + 0] = xi.w * A.fx;
+    ar.floc[3 * (size_t)sc + 1] = xi.w * A.fy;
+    ar.floc[3 * (size_t)sc + 2] = xi.w * A.fz;
   }
-}
+  }
+};
 
 // ---------------------------------------------------------------------------
 // FP32-mixed variant of the same scheme.  Sources carry cell-relative FP32
@@ -271,11 +276,6 @@ __global__ void __launch_bounds__(kWaveQ) k_pair_trim_f64(const double4* __restr
 // Queue entries pack the source index (< 2^24), the x image and the row
 // offsets dy, dz.  Pair arithmetic is FP32; e_0 and the forces accumulate in
 // FP64.
-struct PairConstF {
-  float a2, inv_a2, inv_a6, inv_a8;
-  float w[3];
-};
-
 struct PairAccM {
   double e, fx, fy, fz;
   int cnt;
@@ -342,22 +342,24 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
   }
 }
 
-__global__ void __launch_bounds__(kWaveQ) k_pair_trim_f32(const float4* __restrict__ xr,
-                                                          const float* __restrict__ xif,
-                                                          const double4* __restrict__ xs,
-                                                          const int* __restrict__ cell_s,
-                                                          const int* __restrict__ cstart,
-                                                          const int* __restrict__ tgt, int n, CellGeom g,
-                                                          PairConstF pc, double* __restrict__ e0,
-                                                          double* __restrict__ floc) {
+struct PairTrimF32 {
+  using Args = PairArgsF;
+  static constexpr int kThreads = kWaveQ;
+  static __device__ void run(const Args& ar, int blk) {
+  const float4* __restrict__ xr = ar.xr;
+  const float* __restrict__ xif = ar.xif;
+  const int* __restrict__ cstart = ar.cstart;
+  const CellGeom& g = ar.g;
+  const PairConstF& pc = ar.pc;
+  const int n = ar.n;
   __shared__ int queue[kQueue * kWaveQ];
   const int lane = threadIdx.x;
-  const int k = blockIdx.x * kWaveQ + lane;
+  const int k = blk * kWaveQ + lane;
   const bool active = k < n;
-  const int sc = tgt[active ? k : n - 1];
+  const int sc = ar.tgt[active ? k : n - 1];
   const float4 xi = xr[sc];
-  const double4 xd = xs[sc];   // FP64 position: only for choosing rows and cells
-  const int c = cell_s[sc];
+  const double4 xd = ar.xs[sc];   // FP64 position: only for choosing rows and cells
+  const int c = ar.cell_s[sc];
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
   const int self_ent = active ? ((sc << 8) | entry_bits(0, 0, 0)) : -1;
   PairAccM A{0.0, 0.0, 0.0, 0.0, 0};
@@ -406,12 +408,13 @@ __global__ void __launch_bounds__(kWaveQ) k_pair_trim_f32(const float4* __restri
   pair_drain_f32(queue, A.cnt, lane, self_ent, xi, cx, xr, xif, g, pc, A);
   if (active) {
     const double wi = (double)xif[sc];
-    e0[sc] = A.e;
-    floc[3 * (size_t)sc + 0] = wi * A.fx;
-    floc[3 * (size_t)sc + 1] = wi * A.fy;
-    floc[3 * (size_t)sc + 2] = wi * A.fz;
+    ar.e0[sc] = A.e;
+    ar.floc[3 * (size_t)sc + 0] = wi * A.fx;
+    ar.floc[3 * (size_t)sc + 1] = wi * A.fy;
+    ar.floc[3 * (size_t)sc + 2] = wi * A.fz;
   }
-}
+  }
+};
 
 }  // namespace
 
@@ -422,17 +425,21 @@ hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s) {
   if (P->precision == MLS_MIXED && P->pair_fast && n < (1 << 24)) {
     PairConstF pf{(float)P->a2, (float)P->inv_a2, (float)P->inv_a6, (float)P->inv_a8,
                   {(float)g.w[0], (float)g.w[1], (float)g.w[2]}};
-    k_pair_trim_f32<<<(n + kWaveQ - 1) / kWaveQ, kWaveQ, 0, s>>>(P->d_xr, P->d_xif, P->d_xs, P->d_cell_s,
-                                                                 P->d_cell_start, P->d_tgt, n, g, pf, P->d_e0,
-                                                                 P->d_floc);
-  } else if (P->pair_fast && n < (1 << 25)) {
-    k_pair_trim_f64<<<(n + kWaveQ - 1) / kWaveQ, kWaveQ, 0, s>>>(P->d_xs, P->d_cell_s, P->d_cell_start, P->d_tgt,
-                                                                 n, g, pc, P->d_e0, P->d_floc);
-  } else {
-    k_pair_f64<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pc,
-                                                            P->d_e0, P->d_floc);
+    PairArgsF a{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, P->d_tgt, n, g, pf, P->d_e0, P->d_floc};
+    return launch_one<PairTrimF32>(a, (n + kWaveQ - 1) / kWaveQ, s);
   }
-  return hipGetLastError();
+  PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, P->d_tgt, n, g, pc, P->d_e0, P->d_floc};
+  if (P->pair_fast && n < (1 << 25)) return launch_one<PairTrimF64>(a, (n + kWaveQ - 1) / kWaveQ, s);
+  return launch_one<PairGeneric>(a, (n + kBlock - 1) / kBlock, s);
+}
+
+hipError_t launch_batched_pair(const BatchPhase& ph, hipStream_t s) {
+  switch (ph.kernel) {
+    case BK_PAIR_GENERIC: return launch_batched_phase<PairGeneric>(ph, s);
+    case BK_PAIR_TRIM_F64: return launch_batched_phase<PairTrimF64>(ph, s);
+    case BK_PAIR_TRIM_F32: return launch_batched_phase<PairTrimF32>(ph, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace mls

@@ -173,16 +173,6 @@ int stencil_tile_zc(int R) { return tile_zc(R); }
 
 namespace {
 
-struct StencilLevel {
-  const double* q;
-  double* e;
-  int n[3];
-  int tiles_z;     // z chunks
-  int tile0;       // first tile index of this level
-  double scale;    // 2^(-6(k-1))
-  double inv_size; // 1 / points of the level
-};
-
 struct StencilLaunch {
   StencilLevel lv[16];
   int nlev;
@@ -222,11 +212,7 @@ __device__ __forceinline__ void tile_switch(int hz, T (&acc)[ZC], const T* c, in
 // partition of unity); the constant part adds back as mean * sum of weights,
 // since a periodic convolution maps a constant c to c times the weight sum.
 template <class T, int R, int ZC, int W>
-__global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const int4* __restrict__ tiles,
-                                                         const StencilRow* __restrict__ rows,
-                                                         const int* __restrict__ wave_rows,
-                                                         const T* __restrict__ wts,
-                                                         const double* __restrict__ sum_xi, double wsum) {
+__device__ __forceinline__ void stencil_tile(const StencilLevel& V, const int4 tinfo) {
   constexpr int SX = 8 + 2 * R, SY = 8 + 2 * R, SZ = ZC + 2 * R;
   constexpr int PS = SX * SY, NP = PS * SZ, NT = 64 * W;
   static_assert(W * ZC * 64 <= NP, "reduction buffer must fit in the tile");
@@ -234,8 +220,6 @@ __global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const 
   __shared__ int wrapx[SX], wrapy[SY], wrapz[SZ];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int4 tinfo = tiles[blockIdx.x];
-  const StencilLevel& V = L.lv[tinfo.x];
   const int x0 = tinfo.y * 8, y0 = tinfo.z * 8, z0 = tinfo.w * ZC;
   if (tid < SX) wrapx[tid] = wrapi(x0 - R + tid, V.n[0]);
   if (tid < SY) wrapy[tid] = wrapi(y0 - R + tid, V.n[1]);
@@ -243,7 +227,7 @@ __global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const 
   __syncthreads();
   const size_t gps = (size_t)V.n[0] * V.n[1];
   const double* __restrict__ q = V.q;
-  const double mean = sizeof(T) < sizeof(double) ? *sum_xi * V.inv_size : 0.0;
+  const double mean = sizeof(T) < sizeof(double) ? *V.sum_xi * V.inv_size : 0.0;
   for (int i = tid; i < NP; i += NT) {
     const int lx = i % SX, ly = (i / SX) % SY, lz = i / PS;
     tile[i] = (T)(q[(size_t)wrapz[lz] * gps + (size_t)wrapy[ly] * V.n[0] + wrapx[lx]] - mean);
@@ -254,7 +238,9 @@ __global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const 
   T acc[ZC];
 #pragma unroll
   for (int k = 0; k < ZC; ++k) acc[k] = T(0);
-  const int r0 = wave_rows[wv], r1 = wave_rows[wv + 1];
+  const StencilRow* __restrict__ rows = V.rows;
+  const T* __restrict__ wts = (const T*)V.wts;
+  const int r0 = V.wave_rows[wv], r1 = V.wave_rows[wv + 1];
   for (int r = r0; r < r1; ++r) {
     const StencilRow row = rows[r];
     const int o0 = -row.dy * SX - row.dx, o1 = -row.dy * SX + row.dx;
@@ -274,34 +260,56 @@ __global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const 
       T sum = tile[k * 64 + lane];
 #pragma unroll
       for (int w2 = 1; w2 < W; ++w2) sum += tile[(w2 * ZC + k) * 64 + lane];
-      V.e[(size_t)z * gps + (size_t)y * V.n[0] + x] = V.scale * ((double)sum + mean * wsum);
+      V.e[(size_t)z * gps + (size_t)y * V.n[0] + x] = V.scale * ((double)sum + mean * V.wsum);
     }
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_coarsest_f64(const double* __restrict__ q, GridDims g,
-                                                         const double* __restrict__ K, double* __restrict__ e) {
-  const int mu = blockIdx.x * blockDim.x + threadIdx.x;
-  if (mu >= g.size) return;
-  const int x = mu % g.n[0], y = (mu / g.n[0]) % g.n[1], z = mu / (g.n[0] * g.n[1]);
-  double acc = 0.0;
-  for (int nz = 0; nz < g.n[2]; ++nz) {
-    int dz = z - nz;
-    if (dz < 0) dz += g.n[2];
-    for (int ny = 0; ny < g.n[1]; ++ny) {
-      int dy = y - ny;
-      if (dy < 0) dy += g.n[1];
-      const double* qrow = q + ((size_t)nz * g.n[1] + ny) * g.n[0];
-      const double* krow = K + ((size_t)dz * g.n[1] + dy) * g.n[0];
-      int dx = x;  // x - nx, wrapped, counts down
-      for (int nx = 0; nx < g.n[0]; ++nx) {
-        acc += krow[dx] * qrow[nx];
-        dx = dx == 0 ? g.n[0] - 1 : dx - 1;
+// One plan: all levels of the plan in one launch, level descriptors by value.
+template <class T, int R, int ZC, int W>
+__global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const int4* __restrict__ tiles) {
+  const int4 tinfo = tiles[blockIdx.x];
+  stencil_tile<T, R, ZC, W>(L.lv[tinfo.x], tinfo);
+}
+
+// Batched: tiles of many plans' levels; tinfo.x indexes the descriptor array.
+template <class T, int R, int ZC, int W>
+__global__ void __launch_bounds__(64 * W) k_stencil_tile_batched(const StencilLevel* __restrict__ lv,
+                                                                 const int4* __restrict__ tiles, int ntiles) {
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int4 tinfo = tiles[t];
+    stencil_tile<T, R, ZC, W>(lv[tinfo.x], tinfo);
+    __syncthreads();
+  }
+}
+
+struct Coarsest {
+  using Args = CoarsestArgs;
+  static constexpr int kThreads = 64;
+  static __device__ void run(const Args& a, int blk) {
+    const GridDims& g = a.g;
+    const int mu = blk * kThreads + threadIdx.x;
+    if (mu >= g.size) return;
+    const int x = mu % g.n[0], y = (mu / g.n[0]) % g.n[1], z = mu / (g.n[0] * g.n[1]);
+    double acc = 0.0;
+    for (int nz = 0; nz < g.n[2]; ++nz) {
+      int dz = z - nz;
+      if (dz < 0) dz += g.n[2];
+      for (int ny = 0; ny < g.n[1]; ++ny) {
+        int dy = y - ny;
+        if (dy < 0) dy += g.n[1];
+        const double* qrow = a.q + ((size_t)nz * g.n[1] + ny) * g.n[0];
+        const double* krow = a.K + ((size_t)dz * g.n[1] + dy) * g.n[0];
+        int dx = x;  // x - nx, wrapped, counts down
+        for (int nx = 0; nx < g.n[0]; ++nx) {
+          acc += krow[dx] * qrow[nx];
+          dx = dx == 0 ? g.n[0] - 1 : dx - 1;
+        }
       }
     }
+    a.e[mu] = acc;
   }
-  e[mu] = acc;
-}
+};
 
 inline int nblocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
@@ -355,10 +363,14 @@ hipError_t launch_tile(mls_plan_s* P, const T* wts, hipStream_t s) {
     V.tile0 = t;
     V.scale = std::ldexp(1.0, -6 * (k - 1));
     V.inv_size = 1.0 / (double)Lv.g.size;
+    V.rows = P->d_rows;
+    V.wave_rows = P->d_wave_rows;
+    V.wts = wts;
+    V.sum_xi = P->d_scratch;
+    V.wsum = P->taps_wsum;
     t += nblocks(Lv.g.n[0], 8) * nblocks(Lv.g.n[1], 8) * V.tiles_z;
   }
-  k_stencil_tile<T, R, kTileZ, kStencilWaves><<<t, 64 * kStencilWaves, 0, s>>>(
-      L, P->d_tiles, P->d_rows, P->d_wave_rows, wts, P->d_scratch, P->taps_wsum);
+  k_stencil_tile<T, R, kTileZ, kStencilWaves><<<t, 64 * kStencilWaves, 0, s>>>(L, P->d_tiles);
   return hipGetLastError();
 }
 
@@ -397,8 +409,45 @@ hipError_t launch_stencils(mls_plan_s* P, hipStream_t s) {
 
 hipError_t launch_coarsest(mls_plan_s* P, hipStream_t s) {
   Level& L = P->lv[P->levels - 1];
-  k_coarsest_f64<<<nblocks(L.g.size, 64), 64, 0, s>>>(L.q, L.g, P->d_Kl, L.e);
+  return launch_one<Coarsest>(CoarsestArgs{L.q, L.g, P->d_Kl, L.e}, nblocks(L.g.size, Coarsest::kThreads), s);
+}
+
+bool stencil_tile_ok(int R, int zc) {
+  if (R < 1 || R > 8) return false;
+  if (zc == 8) return true;
+  return zc == 16 && R <= 6;
+}
+
+template <class T, int R, int ZC>
+hipError_t launch_tiles_batched(const BatchPhase& ph, hipStream_t s) {
+  const int grid = ph.grid > 0 ? std::min(ph.grid, ph.nwork) : ph.nwork;
+  k_stencil_tile_batched<T, R, ZC, kStencilWaves><<<grid, 64 * kStencilWaves, 0, s>>>(
+      (const StencilLevel*)ph.args, (const int4*)ph.work, ph.nwork);
   return hipGetLastError();
+}
+
+// Batched phases of this file.  Stencil variant = window template (4, 6, 8)
+// | z extent << 8 | 0x10000 for FP32 tiles.
+hipError_t launch_batched_stencil(const BatchPhase& ph, hipStream_t s) {
+  if (ph.nwork == 0) return hipSuccess;
+  if (ph.kernel == BK_COARSEST) return launch_batched_phase<Coarsest>(ph, s);
+  if (ph.kernel != BK_STENCIL) return hipErrorInvalidValue;
+  const int R = ph.variant & 0xff, zc = (ph.variant >> 8) & 0xff;
+  const bool f32 = (ph.variant & 0x10000) != 0;
+  if (f32) {
+    if (R == 4 && zc == 16) return launch_tiles_batched<float, 4, 16>(ph, s);
+    if (R == 4 && zc == 8) return launch_tiles_batched<float, 4, 8>(ph, s);
+    if (R == 6 && zc == 16) return launch_tiles_batched<float, 6, 16>(ph, s);
+    if (R == 6 && zc == 8) return launch_tiles_batched<float, 6, 8>(ph, s);
+    if (R == 8 && zc == 8) return launch_tiles_batched<float, 8, 8>(ph, s);
+  } else {
+    if (R == 4 && zc == 16) return launch_tiles_batched<double, 4, 16>(ph, s);
+    if (R == 4 && zc == 8) return launch_tiles_batched<double, 4, 8>(ph, s);
+    if (R == 6 && zc == 16) return launch_tiles_batched<double, 6, 16>(ph, s);
+    if (R == 6 && zc == 8) return launch_tiles_batched<double, 6, 8>(ph, s);
+    if (R == 8 && zc == 8) return launch_tiles_batched<double, 8, 8>(ph, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace mls

@@ -186,7 +186,12 @@ def cube(n, density=0.8, seed=0, dmin=0.8, c6=4.0, params=None, name="cube"):
 
 def cube_box(n, L, seed=0, dmin=0.8, c6=4.0, params=None, name="cube"):
     """Homogeneous periodic cube of side ``L`` holding ``n`` atoms."""
-    box = np.array([L, L, L], dtype=np.float64)
+    return fill_box(n, (L, L, L), seed, dmin, c6, params, name)
+
+
+def fill_box(n, box, seed=0, dmin=0.8, c6=4.0, params=None, name="box"):
+    """Homogeneous periodic orthorhombic ``box`` holding ``n`` atoms."""
+    box = np.array(box, dtype=np.float64)
     rng = np.random.Generator(np.random.PCG64(seed))
     occ = _Occupancy(box, dmin, n)
     rsa_fill(rng, occ, n, _uniform_box([0, 0, 0], box))
@@ -293,6 +298,28 @@ NAMED_PARAMS = {"cube1k": dict(a=3.0, h=1.0, order=4, levels=2),
                 "slab32k": dict(a=3.0, h=1.0, order=4, levels=4),
                 "cube1M": dict(a=3.0, h=1.0, order=4, levels=5),
                 "mixture100k": dict(a=3.0, h=1.0, order=4, levels=0)}
+
+
+def named_batch(name: str = "batch256"):
+    """The batched workload (256 boxes of ``batch_boxes`` with seed 4) as a
+    list of Workloads, cached like ``named``."""
+    import os
+    if name != "batch256":
+        raise KeyError(name)
+    cache = os.environ.get("MLS_WORKLOAD_CACHE")
+    path = os.path.join(cache, f"{name}.npz") if cache else None
+    if path and os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        off, boxes = z["off"], z["boxes"]
+        return [Workload(f"batch{b}", z["pos"][off[b]:off[b + 1]], z["c6"][off[b]:off[b + 1]], boxes[b], {})
+                for b in range(len(boxes))]
+    ws = batch_boxes(256, seed=4)
+    if path:
+        os.makedirs(cache, exist_ok=True)
+        off = np.concatenate([[0], np.cumsum([w.n for w in ws])])
+        np.savez(path, pos=np.concatenate([w.pos for w in ws]), c6=np.concatenate([w.c6 for w in ws]),
+                 boxes=np.stack([w.box for w in ws]), off=off)
+    return ws
 
 
 def named(name: str) -> Workload:
