@@ -124,6 +124,64 @@ def time_precision(w, prm, precision, steps, warmup, dev):
     return dict(ms=ms, stage_ms=stage_ms, E=E, F=F, info=info)
 
 
+def time_batched(ws, precision, steps, warmup, dev):
+    """The batched form on the many-box workload: one graph replay per step
+    (all boxes), after autotuning on the first call; beside it the same boxes
+    evaluated one single plan after another on the same stream."""
+    import numpy as np
+    import torch
+    from paper_1308_4005_amd import BatchPlan, Plan, Result
+    bp = BatchPlan([w.box for w in ws], [w.n for w in ws], 3.0, 1.0, 4, 0, precision=precision, autotune=True,
+                   device=dev.index)
+    pos = torch.tensor(np.concatenate([w.pos for w in ws]), dtype=torch.float64, device=dev)
+    c6 = torch.tensor(np.concatenate([w.c6 for w in ws]), dtype=torch.float64, device=dev)
+    out = bp.evaluate(pos, c6)
+    for _ in range(warmup):
+        bp.evaluate(pos, c6, out=out)
+    stream = torch.cuda.current_stream(dev)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(steps):
+        bp.evaluate(pos, c6, out=out)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    tuning = bp.tuning()
+    E_batch = out.energies.cpu().numpy()
+    bp.close()
+    # the same boxes through single plans, one evaluate call per box
+    plans, outs = [], []
+    off = np.concatenate([[0], np.cumsum([w.n for w in ws])])
+    for b, w in enumerate(ws):
+        plans.append(Plan(w.box, 3.0, 1.0, 4, 0, precision=precision, n_max=w.n, device=dev.index))
+        outs.append(Result(torch.empty(1, dtype=torch.float64, device=dev),
+                           torch.empty((w.n, 3), dtype=torch.float64, device=dev)))
+    views = [(pos[off[b]:off[b + 1]], c6[off[b]:off[b + 1]]) for b in range(len(ws))]
+
+    def sweep():
+        for pl, (p, c), o in zip(plans, views, outs):
+            pl.evaluate(p, c, out=o)
+    sweep()
+    seq_steps = max(2, steps // 4)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(seq_steps):
+        sweep()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = t0.elapsed_time(t1) / seq_steps
+    E_seq = np.array([float(o.energy.cpu()[0]) for o in outs])
+    for pl in plans:
+        pl.close()
+    n = int(off[-1])
+    return {"ms_per_step": ms, "batch_evals_per_s": 1000.0 / ms, "particle_evals_per_s": n * 1000.0 / ms,
+            "sequential_single_plans_ms": ms_seq, "speedup_vs_sequential": ms_seq / ms,
+            "max_rel_energy_diff_vs_single": float(np.max(np.abs(E_batch - E_seq) / np.abs(E_seq))),
+            "tuning": tuning}
+
+
 def golden_errors(E, F, gold):
     import numpy as np
     if gold is None:
@@ -175,6 +233,7 @@ def main():
     ap.add_argument("--levels", type=int, default=5)
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="leave out the batched-form measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: MLS here is a single-GPU path "
@@ -234,6 +293,21 @@ def main():
             dE=abs(res["mixed"]["E"] - res["fp64"]["E"]) / abs(res["fp64"]["E"]),
             rms_rel_F=float(np.sqrt(np.sum(dif ** 2) / np.sum(Fd ** 2))))
 
+    batched = None
+    if not args.no_batch:
+        t = time.time()
+        ws = W.named_batch("batch256")
+        log(f"[bench] batch256: {len(ws)} boxes, {sum(w.n for w in ws)} atoms ({time.time() - t:.1f}s)")
+        batched = {"workload": "batch256: 256 periodic boxes, N ~ floor(exp U(ln 500, ln 20000)), box (L, L, aL) "
+                               "with a ~ U(1,4), density ~ U(0.02,0.85), RSA min distance 0.8, C6=4; "
+                               "a=3, h=1, p=4, levels by box size",
+                   "boxes": len(ws), "atoms": int(sum(w.n for w in ws))}
+        for p in precisions:
+            log(f"[bench] batched {p}")
+            batched[p] = time_batched(ws, p, args.steps, args.warmup, dev)
+            log(f"[bench] batched {p}: {batched[p]['ms_per_step']:.3f} ms/step, sequential single plans "
+                f"{batched[p]['sequential_single_plans_ms']:.3f} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
@@ -264,6 +338,7 @@ def main():
         "mixed_over_fp64": (res["fp64"]["ms"] / res["mixed"]["ms"]) if len(res) == 2 else None,
         "accuracy": accuracy,
         "roofline": roofline,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -214,6 +214,7 @@ typedef struct {
   int blocks[MLS_NUM_STAGES]; /* persistent grid of each MLS_T_* stage in blocks; 0 = one block per item */
   int stencil_zc;             /* z extent of a level-stencil tile: 16 or 8 (16 applies to windows <= 6) */
   double tuned_ms;            /* one evaluation with this shape, as timed by the autotuner (0: not timed) */
+  double stage_ms[MLS_NUM_STAGES]; /* its MLS_T_* stages (0: not timed) */
 } mls_batch_tuning;
 
 mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* n_per_box,

@@ -73,6 +73,7 @@ class MLSBatchTuning(ctypes.Structure):
         ("blocks", ctypes.c_int * 8),
         ("stencil_zc", ctypes.c_int),
         ("tuned_ms", ctypes.c_double),
+        ("stage_ms", ctypes.c_double * 8),
     ]
 
 

@@ -86,7 +86,7 @@ class BatchPlan:
         t = _lib.MLSBatchTuning()
         _lib.check(self._lib.mls_batch_get_tuning(self._batch, ctypes.byref(t)), "mls_batch_get_tuning")
         return dict(blocks=dict(zip(_lib.STAGE_NAMES, list(t.blocks))), stencil_zc=int(t.stencil_zc),
-                    tuned_ms=float(t.tuned_ms))
+                    tuned_ms=float(t.tuned_ms), stage_ms=dict(zip(_lib.STAGE_NAMES, list(t.stage_ms))))
 
     def set_tuning(self, blocks, stencil_zc=16):
         """Force a launch shape: ``blocks`` is one grid size for every stage or a
@@ -95,7 +95,6 @@ class BatchPlan:
         for i, k in enumerate(_lib.STAGE_NAMES):
             t.blocks[i] = int(blocks[k] if isinstance(blocks, dict) else blocks)
         t.stencil_zc = int(stencil_zc)
-        t.tuned_ms = 0.0
         _lib.check(self._lib.mls_batch_set_tuning(self._batch, ctypes.byref(t)), "mls_batch_set_tuning")
 
     def status(self):

@@ -166,7 +166,7 @@ mls_status build_phases(mls_batch_s* B) {
       set_box(s2, b, sa, 1);
       set_box(s3, b, sa, nblk(nc, 256));
       set_box(sc, b, ScatterArgs{P->d_cid, P->d_slot, n, P->d_cell_start, P->d_perm_tmp}, nblk(n, 256));
-      set_box(rk, b, RankArgs{P->d_cell_start, nc, P->d_perm_tmp, P->d_perm}, n > 0 ? nblk(nc, 256) : 0);
+      set_box(rk, b, RankArgs{P->d_cell_start, P->d_cid, P->d_perm_tmp, n, P->d_perm}, nblk(n, 256));
       set_box(ga, b, GatherArgs{P->d_perm, n, P->d_xw, P->d_cid, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, P->cg},
               nblk(n + kSortedPad, 256));
       if (mixed) {
@@ -193,6 +193,7 @@ mls_status build_phases(mls_batch_s* B) {
     HostPhase f32 = make_phase<PairArgsF>(BK_PAIR_TRIM_F32, MLS_T_PAIR, 0, nb);
     HostPhase f64 = make_phase<PairArgs>(BK_PAIR_TRIM_F64, MLS_T_PAIR, 0, nb);
     HostPhase gen = make_phase<PairArgs>(BK_PAIR_GENERIC, MLS_T_PAIR, 0, nb);
+    HostPhase wav = make_phase<PairArgs>(BK_PAIR_WAVE, MLS_T_PAIR, 0, nb);
     for (int b : order) {
       mls_plan_s* P = B->plans[b];
       const int n = n_of(b);
@@ -207,12 +208,15 @@ mls_status build_phases(mls_batch_s* B) {
                                   P->d_e0, P->d_floc}, nblk(n, 64));
       } else if (P->pair_fast && n < (1 << 25)) {
         set_box(f64, b, a, nblk(n, 64));
+      } else if (!P->pair_fast) {
+        set_box(wav, b, a, n);
       } else {
         set_box(gen, b, a, nblk(n, 128));
       }
     }
     hp.push_back(std::move(f32));
     hp.push_back(std::move(f64));
+    hp.push_back(std::move(wav));
     hp.push_back(std::move(gen));
   }
 
@@ -298,7 +302,7 @@ mls_status build_phases(mls_batch_s* B) {
     for (int b : order) {
       mls_plan_s* P = B->plans[b];
       Level& L = P->lv[P->levels - 1];
-      set_box(c, b, CoarsestArgs{L.q, L.g, P->d_Kl, L.e}, nblk(L.g.size, 64));
+      set_box(c, b, CoarsestArgs{L.q, L.g, P->d_Kl, L.e}, nblk(L.g.size, kCoarsestThreads));
     }
     hp.push_back(std::move(c));
   }
@@ -384,6 +388,7 @@ mls_status build_phases(mls_batch_s* B) {
 hipError_t launch_phase(const BatchPhase& ph, hipStream_t s) {
   switch (ph.kernel) {
     case BK_PAIR_GENERIC:
+    case BK_PAIR_WAVE:
     case BK_PAIR_TRIM_F64:
     case BK_PAIR_TRIM_F32: return launch_batched_pair(ph, s);
     case BK_ANT_ATOMIC:
@@ -478,6 +483,7 @@ mls_status autotune(mls_batch_s* B, hipStream_t s) {
   double ms[MLS_NUM_STAGES], tot;
   if ((st = time_stages(B, s, kTuneReps, ms, &tot)) != MLS_OK) return st;
   B->tune.tuned_ms = tot;
+  for (int k = 0; k < MLS_NUM_STAGES; ++k) B->tune.stage_ms[k] = ms[k];
   return MLS_OK;
 }
 
@@ -537,6 +543,7 @@ mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* 
   for (int k = 0; k < MLS_NUM_STAGES; ++k) B->tune.blocks[k] = 0;
   B->tune.stencil_zc = 16;
   B->tune.tuned_ms = 0.0;
+  for (int k = 0; k < MLS_NUM_STAGES; ++k) B->tune.stage_ms[k] = 0.0;
   B->tune_pending = autotune_flag != 0;
   hipError_t e = hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return fail(hip_fail(e, "batch: capture stream"));
@@ -614,6 +621,7 @@ mls_status mls_batch_set_tuning(mls_batch_t B, const mls_batch_tuning* t) {
   const bool rebuild = B->built && t->stencil_zc != B->tune.stencil_zc;
   B->tune = *t;
   B->tune.tuned_ms = 0.0;
+  for (int k = 0; k < MLS_NUM_STAGES; ++k) B->tune.stage_ms[k] = 0.0;
   B->tune_pending = false;
   if (rebuild) return build_phases(B);
   apply_grids(B);

@@ -4,7 +4,7 @@
 //   1. per atom: wrapped position, cell id, arrival slot in its cell (atomic)
 //   2. exclusive scan of the cell counts (block scan, scan of block sums, add)
 //   3. scatter to start[cell] + slot (arrival order)
-//   4. per cell: reorder by original index (rank among the cell's atoms)
+//   4. per atom: reorder by original index (rank among its cell's atoms)
 //   5. gather the sorted position/xi array and cell ids
 #include <algorithm>
 
@@ -179,21 +179,20 @@ struct BinScatter {
   }
 };
 
-// One thread per cell: each atom's rank among the cell's atoms by original
-// index is its stable position.
+// One thread per atom: its rank among its cell's atoms by original index is
+// its stable position (work per thread: the size of its cell).
 struct CellRank {
   using Args = RankArgs;
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int blk) {
-    const int c = blk * kBlock + threadIdx.x;
-    if (c >= a.ncell) return;
+    const int s = blk * kBlock + threadIdx.x;
+    if (s >= a.n) return;
+    const int v = a.perm_tmp[s];
+    const int c = a.cid[v];
     const int b = a.start[c], e = a.start[c + 1];
-    for (int k = b; k < e; ++k) {
-      const int v = a.perm_tmp[k];
-      int rank = 0;
-      for (int j = b; j < e; ++j) rank += a.perm_tmp[j] < v;
-      a.perm[b + rank] = v;
-    }
+    int rank = 0;
+    for (int j = b; j < e; ++j) rank += a.perm_tmp[j] < v;
+    a.perm[b + rank] = v;
   }
 };
 
@@ -331,8 +330,8 @@ hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double*
   if ((e = launch_one<BinScatter>(ScatterArgs{P->d_cid, P->d_slot, n, P->d_cell_start, P->d_perm_tmp},
                                   nblocks(n, kBlock), s)) != hipSuccess)
     return e;
-  if ((e = launch_one<CellRank>(RankArgs{P->d_cell_start, g.ncell, P->d_perm_tmp, P->d_perm},
-                                nblocks(g.ncell, kBlock), s)) != hipSuccess)
+  if ((e = launch_one<CellRank>(RankArgs{P->d_cell_start, P->d_cid, P->d_perm_tmp, n, P->d_perm},
+                                nblocks(n, kBlock), s)) != hipSuccess)
     return e;
   GatherArgs ga{P->d_perm, n, P->d_xw, P->d_cid, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, g};
   if ((e = launch_one<GatherSorted>(ga, nblocks(n + kSortedPad, kBlock), s)) != hipSuccess) return e;

@@ -62,6 +62,7 @@ struct AnterpAtomic {
 constexpr int kAntTile = 16;     // max owned points per dimension
 constexpr int kAntThreads = 256;
 constexpr int kMaxSeg = 1024;
+constexpr int kAntScan = kMaxSeg / kAntThreads;   // scan slots per thread
 
 template <int P, class W>
 struct AnterpOwned {
@@ -73,6 +74,7 @@ struct AnterpOwned {
     __shared__ int seg_off[kMaxSeg + 1];
     __shared__ int seg_shift[kMaxSeg][3];
     __shared__ int nseg_s;
+    __shared__ int scan_sh[kAntThreads];
     const CellGeom& cg = a.cg;
     const GridGeom& gg = a.gg;
     const AntGeom& ag = a.ag;
@@ -87,39 +89,66 @@ struct AnterpOwned {
       wd[d] = (c1[d] * gg.n[d] + cg.nc[d] - 1) / cg.nc[d] - lo[d];
     }
     for (int i = threadIdx.x; i < kAntTile * kAntTile * kAntTile; i += kAntThreads) tile[i] = 0.0;
-    if (threadIdx.x == 0) {
-      // contiguous runs of sorted atoms: rows of cells along x, split where the
-      // periodic image changes
-      int ns = 0, tot = 0;
-      for (int cz = c0[2] - ag.nh[2]; cz < c1[2] + ag.nh[2]; ++cz) {
-        const int iz = floordiv(cz, cg.nc[2]);
-        const int wz = cz - iz * cg.nc[2];
-        for (int cy = c0[1] - ag.nh[1]; cy < c1[1] + ag.nh[1]; ++cy) {
-          const int iy = floordiv(cy, cg.nc[1]);
-          const int wy = cy - iy * cg.nc[1];
-          const int rowc = (wz * cg.nc[1] + wy) * cg.nc[0];
-          int cx = c0[0] - ag.nh[0];
-          const int cxe = c1[0] + ag.nh[0];
-          while (cx < cxe) {
-            const int ix = floordiv(cx, cg.nc[0]);
-            const int wx = cx - ix * cg.nc[0];
-            const int run = min(cxe - cx, cg.nc[0] - wx);
-            const int a0 = cstart[rowc + wx], a1 = cstart[rowc + wx + run];
-            if (a1 > a0 && ns < kMaxSeg) {
-              seg_begin[ns] = a0;
-              seg_off[ns] = tot;
-              seg_shift[ns][0] = ix;
-              seg_shift[ns][1] = iy;
-              seg_shift[ns][2] = iz;
-              tot += a1 - a0;
-              ++ns;
-            }
-            cx += run;
-          }
-        }
+    // contiguous runs of sorted atoms: one thread per row of cells along x;
+    // a row splits into at most rx runs where the periodic image changes
+    // (empty slots get length 0)
+    const int span[3] = {c1[0] - c0[0] + 2 * ag.nh[0], c1[1] - c0[1] + 2 * ag.nh[1], c1[2] - c0[2] + 2 * ag.nh[2]};
+    const int rx = min(span[0], (span[0] + cg.nc[0] - 1) / cg.nc[0] + 1);
+    const int nrows = span[1] * span[2];
+    const int nslot = nrows * rx;   // <= kMaxSeg (checked on the host)
+    for (int r = threadIdx.x; r < nrows; r += kAntThreads) {
+      const int cy = c0[1] - ag.nh[1] + r % span[1];
+      const int cz = c0[2] - ag.nh[2] + r / span[1];
+      const int iz = floordiv(cz, cg.nc[2]);
+      const int iy = floordiv(cy, cg.nc[1]);
+      const int rowc = ((cz - iz * cg.nc[2]) * cg.nc[1] + (cy - iy * cg.nc[1])) * cg.nc[0];
+      int k = r * rx;
+      int cx = c0[0] - ag.nh[0];
+      const int cxe = c1[0] + ag.nh[0];
+      while (cx < cxe) {
+        const int ix = floordiv(cx, cg.nc[0]);
+        const int wx = cx - ix * cg.nc[0];
+        const int run = min(cxe - cx, cg.nc[0] - wx);
+        const int a0 = cstart[rowc + wx];
+        seg_begin[k] = a0;
+        seg_off[k] = cstart[rowc + wx + run] - a0;   // length, turned into offsets below
+        seg_shift[k][0] = ix;
+        seg_shift[k][1] = iy;
+        seg_shift[k][2] = iz;
+        ++k;
+        cx += run;
       }
-      seg_off[ns] = tot;
-      nseg_s = ns;
+      for (; k < (r + 1) * rx; ++k) seg_off[k] = 0;
+    }
+    __syncthreads();
+    // exclusive scan of the lengths (kAntScan consecutive slots per thread)
+    {
+      int len[kAntScan];
+      int sum = 0;
+      const int base = threadIdx.x * kAntScan;
+#pragma unroll
+      for (int k = 0; k < kAntScan; ++k) {
+        len[k] = base + k < nslot ? seg_off[base + k] : 0;
+        sum += len[k];
+      }
+      scan_sh[threadIdx.x] = sum;
+      __syncthreads();
+      for (int off = 1; off < kAntThreads; off <<= 1) {
+        const int u = threadIdx.x >= off ? scan_sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        scan_sh[threadIdx.x] += u;
+        __syncthreads();
+      }
+      int run = scan_sh[threadIdx.x] - sum;
+#pragma unroll
+      for (int k = 0; k < kAntScan; ++k) {
+        if (base + k < nslot) seg_off[base + k] = run;
+        run += len[k];
+      }
+      if (threadIdx.x == kAntThreads - 1) {
+        seg_off[nslot] = run;
+        nseg_s = nslot;
+      }
     }
     __syncthreads();
     const int ns = nseg_s;

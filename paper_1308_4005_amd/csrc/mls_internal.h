@@ -107,7 +107,7 @@ struct BinCountArgs {
 };
 struct ScanArgs { const int* count; int m; int* start; int* bsum; int* bmax; int* max_count; };
 struct ScatterArgs { const int* cid; const int* slot; int n; const int* start; int* perm_tmp; };
-struct RankArgs { const int* start; int ncell; const int* perm_tmp; int* perm; };
+struct RankArgs { const int* start; const int* cid; const int* perm_tmp; int n; int* perm; };
 struct GatherArgs {
   const int* perm; int n; const double4* xw; const int* cid;
   double4* xs; int* cell_s; float4* xr; float* xif; CellGeom g;
@@ -136,6 +136,7 @@ struct InterpArgs {
 };
 struct EnergyArgs { const double* partial; int nb; double cself; double* energy; };
 struct CoarsestArgs { const double* q; GridDims g; const double* K; double* e; };
+constexpr int kCoarsestThreads = 256;   // outputs per block of the coarsest-level kernel
 
 // One level of the tiled stencil: grids, scale, and the tap tables of its plan.
 struct StencilLevel {
@@ -159,7 +160,7 @@ struct StencilLevel {
 enum BatchKernel {
   BK_FILL_I, BK_FILL_D, BK_BIN_COUNT, BK_SCAN_BLOCKS, BK_SCAN_SUMS, BK_SCAN_ADD, BK_SCATTER, BK_RANK, BK_GATHER,
   BK_SUM_XI_BLOCKS, BK_SUM_XI_FINAL, BK_BRICK_COUNTS, BK_BRICK_TARGETS,
-  BK_PAIR_GENERIC, BK_PAIR_TRIM_F64, BK_PAIR_TRIM_F32,
+  BK_PAIR_GENERIC, BK_PAIR_WAVE, BK_PAIR_TRIM_F64, BK_PAIR_TRIM_F32,
   BK_ANT_ATOMIC, BK_ANT_OWNED, BK_RESTRICT, BK_PROLONG, BK_INTERP, BK_ENERGY,
   BK_STENCIL, BK_COARSEST
 };

@@ -103,6 +103,84 @@ struct PairGeneric {
   }
 };
 
+// FP64, one wave per target, for boxes too narrow for half-cutoff cells
+// (few, crowded cells, often several images of one atom inside the cutoff).
+// The wave walks the target's neighbour cells as contiguous runs of sorted
+// atoms (a run ends where the periodic image changes) and its 64 lanes split
+// each run; the lane sums are added in LDS.  Same cells, images and pairs as
+// PairGeneric.
+struct PairWave {
+  using Args = PairArgs;
+  static constexpr int kThreads = 64;
+  static __device__ void run(const Args& a, int s) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x;
+    const CellGeom& g = a.g;
+    const PairConst& pc = a.pc;
+    const double4* __restrict__ xs = a.xs;
+    const double4 xi = xs[s];
+    const int c = a.cell_s[s];
+    const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
+    double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int oz = -g.noff[2]; oz <= g.noff[2]; ++oz) {
+      int tz = cz + oz;
+      const int iz = floordiv(tz, g.nc[2]);
+      tz -= iz * g.nc[2];
+      const double sz = iz * g.L[2];
+      for (int oy = -g.noff[1]; oy <= g.noff[1]; ++oy) {
+        int ty = cy + oy;
+        const int iy = floordiv(ty, g.nc[1]);
+        ty -= iy * g.nc[1];
+        const double sy = iy * g.L[1];
+        const int row = (tz * g.nc[1] + ty) * g.nc[0];
+        int u = cx - g.noff[0];
+        const int uend = cx + g.noff[0];
+        while (u <= uend) {
+          const int ix = floordiv(u, g.nc[0]);
+          const int tx = u - ix * g.nc[0];
+          const int run = min(uend - u + 1, g.nc[0] - tx);
+          const int j1 = a.cstart[row + tx + run];
+          const double sx = ix * g.L[0];
+          const bool home = (ix | iy | iz) == 0;
+          for (int j = a.cstart[row + tx] + lane; j < j1; j += 64) {
+            const double4 xj = xs[j];
+            const double dx = xi.x - (xj.x + sx);
+            const double dy = xi.y - (xj.y + sy);
+            const double dz = xi.z - (xj.z + sz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < pc.a2 && !(home && j == s)) {
+              double gg, fr;
+              g0_pair<double>(r2, pc.inv_a2, pc.inv_a6, pc.inv_a8, gg, fr);
+              e += xj.w * gg;
+              const double f = xj.w * fr;
+              fx += f * dx;
+              fy += f * dy;
+              fz += f * dz;
+            }
+          }
+          u += run;
+        }
+      }
+    }
+    red[0][lane] = e;
+    red[1][lane] = fx;
+    red[2][lane] = fy;
+    red[3][lane] = fz;
+    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+      if (lane < off)
+        for (int k = 0; k < 4; ++k) red[k][lane] += red[k][lane + off];
+      __syncthreads();
+    }
+    if (lane == 0) {
+      a.e0[s] = red[0][0];
+      a.floc[3 * (size_t)s + 0] = xi.w * red[1][0];
+      a.floc[3 * (size_t)s + 1] = xi.w * red[2][0];
+      a.floc[3 * (size_t)s + 2] = xi.w * red[3][0];
+    }
+  }
+};
+
 // FP64, filter-and-drain over half-cutoff cells: one wave of 64 lanes takes
 // 64 targets from a compact group of cells.  Each lane visits the 5 x 5 rows
 // of cells around its target's cell, skips rows whose y/z gap to the target
@@ -430,12 +508,14 @@ hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s) {
   }
   PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, P->d_tgt, n, g, pc, P->d_e0, P->d_floc};
   if (P->pair_fast && n < (1 << 25)) return launch_one<PairTrimF64>(a, (n + kWaveQ - 1) / kWaveQ, s);
+  if (!P->pair_fast) return launch_one<PairWave>(a, n, s);
   return launch_one<PairGeneric>(a, (n + kBlock - 1) / kBlock, s);
 }
 
 hipError_t launch_batched_pair(const BatchPhase& ph, hipStream_t s) {
   switch (ph.kernel) {
     case BK_PAIR_GENERIC: return launch_batched_phase<PairGeneric>(ph, s);
+    case BK_PAIR_WAVE: return launch_batched_phase<PairWave>(ph, s);
     case BK_PAIR_TRIM_F64: return launch_batched_phase<PairTrimF64>(ph, s);
     case BK_PAIR_TRIM_F32: return launch_batched_phase<PairTrimF32>(ph, s);
     default: return hipErrorInvalidValue;

@@ -283,11 +283,29 @@ __global__ void __launch_bounds__(64 * W) k_stencil_tile_batched(const StencilLe
   }
 }
 
+// Coarsest level: thread per output point, all-to-all over the level.  Up to
+// kCoarseLds points the charges and the kernel are staged in LDS first, so the
+// inner loop reads LDS (q is the same for every lane: a broadcast).
+constexpr int kCoarseLds = 2048;
+
 struct Coarsest {
   using Args = CoarsestArgs;
-  static constexpr int kThreads = 64;
+  static constexpr int kThreads = kCoarsestThreads;
   static __device__ void run(const Args& a, int blk) {
+    __shared__ double sq[kCoarseLds], sk[kCoarseLds];
     const GridDims& g = a.g;
+    const bool staged = g.size <= kCoarseLds;
+    const double* q = a.q;
+    const double* K = a.K;
+    if (staged) {
+      for (int i = threadIdx.x; i < g.size; i += kThreads) {
+        sq[i] = a.q[i];
+        sk[i] = a.K[i];
+      }
+      __syncthreads();
+      q = sq;
+      K = sk;
+    }
     const int mu = blk * kThreads + threadIdx.x;
     if (mu >= g.size) return;
     const int x = mu % g.n[0], y = (mu / g.n[0]) % g.n[1], z = mu / (g.n[0] * g.n[1]);
@@ -298,8 +316,8 @@ struct Coarsest {
       for (int ny = 0; ny < g.n[1]; ++ny) {
         int dy = y - ny;
         if (dy < 0) dy += g.n[1];
-        const double* qrow = a.q + ((size_t)nz * g.n[1] + ny) * g.n[0];
-        const double* krow = a.K + ((size_t)dz * g.n[1] + dy) * g.n[0];
+        const double* qrow = q + ((size_t)nz * g.n[1] + ny) * g.n[0];
+        const double* krow = K + ((size_t)dz * g.n[1] + dy) * g.n[0];
         int dx = x;  // x - nx, wrapped, counts down
         for (int nx = 0; nx < g.n[0]; ++nx) {
           acc += krow[dx] * qrow[nx];
@@ -310,7 +328,6 @@ struct Coarsest {
     a.e[mu] = acc;
   }
 };
-
 inline int nblocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 constexpr int kTX = 8, kTY = 8;
