@@ -146,13 +146,7 @@ mls_status build_phases(mls_batch_s* B) {
     HostPhase sc = make_phase<ScatterArgs>(BK_SCATTER, MLS_T_BINNING, 0, nb);
     HostPhase rk = make_phase<RankArgs>(BK_RANK, MLS_T_BINNING, 0, nb);
     HostPhase ga = make_phase<GatherArgs>(BK_GATHER, MLS_T_BINNING, 0, nb);
-    HostPhase x1 = make_phase<SumXiArgs>(BK_SUM_XI_BLOCKS, MLS_T_BINNING, 0, nb);
     HostPhase x2 = make_phase<SumXiArgs>(BK_SUM_XI_FINAL, MLS_T_BINNING, 0, nb);
-    HostPhase bc = make_phase<BrickArgs>(BK_BRICK_COUNTS, MLS_T_BINNING, 0, nb);
-    HostPhase t1 = make_phase<ScanArgs>(BK_SCAN_BLOCKS, MLS_T_BINNING, 0, nb);
-    HostPhase t2 = make_phase<ScanArgs>(BK_SCAN_SUMS, MLS_T_BINNING, 0, nb);
-    HostPhase t3 = make_phase<ScanArgs>(BK_SCAN_ADD, MLS_T_BINNING, 0, nb);
-    HostPhase bt = make_phase<BrickArgs>(BK_BRICK_TARGETS, MLS_T_BINNING, 0, nb);
     for (int b : order) {
       mls_plan_s* P = B->plans[b];
       const int n = n_of(b);
@@ -167,24 +161,11 @@ mls_status build_phases(mls_batch_s* B) {
       set_box(s3, b, sa, nblk(nc, 256));
       set_box(sc, b, ScatterArgs{P->d_cid, P->d_slot, n, P->d_cell_start, P->d_perm_tmp}, nblk(n, 256));
       set_box(rk, b, RankArgs{P->d_cell_start, P->d_cid, P->d_perm_tmp, n, P->d_perm}, nblk(n, 256));
-      set_box(ga, b, GatherArgs{P->d_perm, n, P->d_xw, P->d_cid, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, P->cg},
-              nblk(n + kSortedPad, 256));
-      if (mixed) {
-        SumXiArgs xa{P->d_xs, n, P->d_partial, P->d_scratch};
-        set_box(x1, b, xa, nblk(n, 256));
-        set_box(x2, b, xa, 1);
-      }
-      if (P->pair_fast && n > 0) {
-        BrickArgs ba{P->d_cell_order, P->d_cell_start, P->d_bcount, nc, P->d_count, P->d_tgt};
-        set_box(bc, b, ba, nblk(nc, 256));
-        ScanArgs ta{P->d_count, nc, P->d_bcount, P->d_bsum, P->d_bmax, P->d_ncell_max};
-        set_box(t1, b, ta, scan_blocks(nc));
-        set_box(t2, b, ta, 1);
-        set_box(t3, b, ta, nblk(nc, 256));
-        set_box(bt, b, ba, nblk(nc, 256));
-      }
+      set_box(ga, b, GatherArgs{P->d_perm, n, P->d_xw, P->d_cid, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, P->cg,
+                                mixed ? P->d_partial : nullptr}, nblk(n + kSortedPad, 256));
+      if (mixed) set_box(x2, b, SumXiArgs{n + kSortedPad, P->d_partial, P->d_scratch}, 1);
     }
-    for (HostPhase* h : {&fill, &cnt, &s1, &s2, &s3, &sc, &rk, &ga, &x1, &x2, &bc, &t1, &t2, &t3, &bt})
+    for (HostPhase* h : {&fill, &cnt, &s1, &s2, &s3, &sc, &rk, &ga, &x2})
       hp.push_back(std::move(*h));
   }
 
@@ -200,11 +181,11 @@ mls_status build_phases(mls_batch_s* B) {
       if (n == 0) continue;
       const CellGeom& g = P->cg;
       PairConst pc{P->a2, P->inv_a2, P->inv_a6, P->inv_a8};
-      PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, P->d_tgt, n, g, pc, P->d_e0, P->d_floc};
+      PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pc, P->d_e0, P->d_floc};
       if (mixed && P->pair_fast && n < (1 << 24)) {
         PairConstF pf{(float)P->a2, (float)P->inv_a2, (float)P->inv_a6, (float)P->inv_a8,
                       {(float)g.w[0], (float)g.w[1], (float)g.w[2]}};
-        set_box(f32, b, PairArgsF{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, P->d_tgt, n, g, pf,
+        set_box(f32, b, PairArgsF{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pf,
                                   P->d_e0, P->d_floc}, nblk(n, 64));
       } else if (P->pair_fast && n < (1 << 25)) {
         set_box(f64, b, a, nblk(n, 64));
@@ -316,7 +297,7 @@ mls_status build_phases(mls_batch_s* B) {
       if (k < 1) continue;
       Level& F = P->lv[k - 1];
       Level& C = P->lv[k];
-      set_box(p, b, TransferArgs{C.E, C.g, F.e, F.E, F.g}, nblk(F.g.size, 256));
+      set_box(p, b, TransferArgs{C.E, C.g, F.e, F.E, F.g}, nblk(C.g.size, 256));
     }
     hp.push_back(std::move(p));
   }

@@ -5,7 +5,8 @@
 //   2. exclusive scan of the cell counts (block scan, scan of block sums, add)
 //   3. scatter to start[cell] + slot (arrival order)
 //   4. per atom: reorder by original index (rank among its cell's atoms)
-//   5. gather the sorted position/xi array and cell ids
+//   5. gather the sorted position/xi array and cell ids (and, in mixed
+//      precision, the per-block sums of xi)
 #include <algorithm>
 
 #include "device_math.h"
@@ -34,6 +35,33 @@ struct FillD {
   }
 };
 
+// Sanitised, wrapped position and xi of atom i (flags: 1 = position, 2 = C6).
+// Non-finite positions and coordinates too large for the wrap become the
+// origin, non-finite or negative C6 become 0.
+__device__ __forceinline__ double4 wrapped_atom(const double* __restrict__ pos, const double* __restrict__ c6,
+                                                int i, const CellGeom& g, int& bad) {
+  double x = pos[3 * (size_t)i], y = pos[3 * (size_t)i + 1], z = pos[3 * (size_t)i + 2];
+  double c = c6[i];
+  bad = 0;
+  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+    bad |= 1;
+    x = y = z = 0.0;
+  }
+  if (!isfinite(c) || !(c >= 0.0)) {
+    bad |= 2;
+    c = 0.0;
+  }
+  double X = wrap_coord(x, g.L[0], g.invL[0]);
+  double Y = wrap_coord(y, g.L[1], g.invL[1]);
+  double Z = wrap_coord(z, g.L[2], g.invL[2]);
+  // coordinates so large that the wrap loses them are reported, not binned
+  if (!(X >= 0.0 && X < g.L[0] && Y >= 0.0 && Y < g.L[1] && Z >= 0.0 && Z < g.L[2])) {
+    bad |= 1;
+    X = Y = Z = 0.0;
+  }
+  return make_double4(X, Y, Z, sqrt(c));
+}
+
 struct BinCount {
   using Args = BinCountArgs;
   static constexpr int kThreads = kBlock;
@@ -41,32 +69,15 @@ struct BinCount {
     const int i = blk * kBlock + threadIdx.x;
     if (i >= a.n) return;
     const CellGeom& g = a.g;
-    double x = a.pos[3 * (size_t)i], y = a.pos[3 * (size_t)i + 1], z = a.pos[3 * (size_t)i + 2];
-    double c = a.c6[i];
-    int bad = 0;
-    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
-      bad |= 1;
-      x = y = z = 0.0;
-    }
-    if (!isfinite(c) || !(c >= 0.0)) {
-      bad |= 2;
-      c = 0.0;
-    }
-    double X = wrap_coord(x, g.L[0], g.invL[0]);
-    double Y = wrap_coord(y, g.L[1], g.invL[1]);
-    double Z = wrap_coord(z, g.L[2], g.invL[2]);
-    // coordinates so large that the wrap loses them are reported, not binned
-    if (!(X >= 0.0 && X < g.L[0] && Y >= 0.0 && Y < g.L[1] && Z >= 0.0 && Z < g.L[2])) {
-      bad |= 1;
-      X = Y = Z = 0.0;
-    }
+    int bad;
+    const double4 p = wrapped_atom(a.pos, a.c6, i, g, bad);
     if (bad) atomicOr(a.flags, bad);
-    int cx = max(0, min((int)(X * g.inv_w[0]), g.nc[0] - 1));
-    int cy = max(0, min((int)(Y * g.inv_w[1]), g.nc[1] - 1));
-    int cz = max(0, min((int)(Z * g.inv_w[2]), g.nc[2] - 1));
+    int cx = max(0, min((int)(p.x * g.inv_w[0]), g.nc[0] - 1));
+    int cy = max(0, min((int)(p.y * g.inv_w[1]), g.nc[1] - 1));
+    int cz = max(0, min((int)(p.z * g.inv_w[2]), g.nc[2] - 1));
     int id = (cz * g.nc[1] + cy) * g.nc[0] + cx;
     a.cid[i] = id;
-    a.xw[i] = make_double4(X, Y, Z, sqrt(c));
+    a.xw[i] = p;
     a.slot[i] = atomicAdd(&a.count[id], 1);
   }
 };
@@ -200,81 +211,53 @@ struct GatherSorted {
   using Args = GatherArgs;
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int blk) {
+    __shared__ double sh[kBlock];
     const int s = blk * kBlock + threadIdx.x;
-    if (s >= a.n + kSortedPad) return;
-    if (s >= a.n) {
+    double xi = 0.0;
+    if (s < a.n) {
+      const int i = a.perm[s];
+      const double4 p = a.xw[i];
+      const int c = a.cid[i];
+      a.xs[s] = p;
+      a.cell_s[s] = c;
+      xi = p.w;
+      if (a.xr) {
+        // cell-relative FP32 coordinates and the cell x index (exact in FP32)
+        // for the mixed-precision pair kernel
+        const CellGeom& g = a.g;
+        int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
+        a.xr[s] = make_float4((float)(p.x - cx * g.w[0]), (float)(p.y - cy * g.w[1]),
+                              (float)(p.z - cz * g.w[2]), (float)cx);
+        a.xif[s] = (float)p.w;
+      }
+    } else if (s < a.n + kSortedPad) {
       // padding rows: far outside any cutoff, zero weight
       a.xs[s] = make_double4(1e300, 1e300, 1e300, 0.0);
       if (a.xr) {
         a.xr[s] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
         a.xif[s] = 0.0f;
       }
-      return;
     }
-    const int i = a.perm[s];
-    const double4 p = a.xw[i];
-    const int c = a.cid[i];
-    a.xs[s] = p;
-    a.cell_s[s] = c;
-    if (a.xr) {
-      // cell-relative FP32 coordinates and the cell x index (exact in FP32)
-      // for the mixed-precision pair kernel
-      const CellGeom& g = a.g;
-      int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
-      a.xr[s] = make_float4((float)(p.x - cx * g.w[0]), (float)(p.y - cy * g.w[1]), (float)(p.z - cz * g.w[2]),
-                            (float)cx);
-      a.xif[s] = (float)p.w;
-    }
-  }
-};
-
-// Pair-kernel target order: atoms of the cells taken in brick order.
-struct BrickCounts {
-  using Args = BrickArgs;
-  static constexpr int kThreads = kBlock;
-  static __device__ void run(const Args& a, int blk) {
-    const int k = blk * kBlock + threadIdx.x;
-    if (k >= a.ncell) return;
-    const int c = a.order[k];
-    a.bcount[k] = a.start[c + 1] - a.start[c];
-  }
-};
-
-struct BrickTargets {
-  using Args = BrickArgs;
-  static constexpr int kThreads = kBlock;
-  static __device__ void run(const Args& a, int blk) {
-    const int k = blk * kBlock + threadIdx.x;
-    if (k >= a.ncell) return;
-    const int c = a.order[k];
-    const int b = a.start[c], e = a.start[c + 1], o = a.bstart[k];
-    for (int i = b; i < e; ++i) a.tgt[o + (i - b)] = i;
-  }
-};
-
-// Sum of xi over the atoms (fixed order: per-block partials, then one block).
-struct SumXiBlocks {
-  using Args = SumXiArgs;
-  static constexpr int kThreads = kBlock;
-  static __device__ void run(const Args& a, int blk) {
-    __shared__ double sh[kBlock];
-    const int s = blk * kBlock + threadIdx.x;
-    sh[threadIdx.x] = s < a.n ? a.xs[s].w : 0.0;
-    __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    if (a.xi_partial) {
+      // per-block sum of xi (fixed order)
+      sh[threadIdx.x] = xi;
       __syncthreads();
+      for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) a.xi_partial[blk] = sh[0];
     }
-    if (threadIdx.x == 0) a.partial[blk] = sh[0];
   }
 };
 
+// Sum of xi over the atoms from the gather's per-block partials (fixed order).
 struct SumXiFinal {
   using Args = SumXiArgs;
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int) {
     __shared__ double sh[kBlock];
-    const int nb = (a.n + kBlock - 1) / kBlock;
+    const int nb = (a.rows + kBlock - 1) / kBlock;
     double v = 0.0;
     for (int i = threadIdx.x; i < nb; i += kBlock) v += a.partial[i];
     sh[threadIdx.x] = v;
@@ -333,20 +316,14 @@ hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double*
   if ((e = launch_one<CellRank>(RankArgs{P->d_cell_start, P->d_cid, P->d_perm_tmp, n, P->d_perm},
                                 nblocks(n, kBlock), s)) != hipSuccess)
     return e;
-  GatherArgs ga{P->d_perm, n, P->d_xw, P->d_cid, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, g};
+  const bool mixed = P->precision == MLS_MIXED;
+  GatherArgs ga{P->d_perm, n, P->d_xw, P->d_cid, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, g,
+                mixed ? P->d_partial : nullptr};
   if ((e = launch_one<GatherSorted>(ga, nblocks(n + kSortedPad, kBlock), s)) != hipSuccess) return e;
-  if (P->precision == MLS_MIXED) {
+  if (mixed) {
     // sum of xi: the mean of every grid level's charges (partition of unity)
-    SumXiArgs sa{P->d_xs, n, P->d_partial, P->d_scratch};
-    if ((e = launch_one<SumXiBlocks>(sa, nblocks(n, kBlock), s)) != hipSuccess) return e;
+    SumXiArgs sa{n + kSortedPad, P->d_partial, P->d_scratch};
     if ((e = launch_one<SumXiFinal>(sa, 1, s)) != hipSuccess) return e;
-  }
-  if (P->pair_fast) {
-    // the per-cell counts are no longer needed: reuse that array (ncell entries)
-    BrickArgs ba{P->d_cell_order, P->d_cell_start, P->d_bcount, g.ncell, P->d_count, P->d_tgt};
-    if ((e = launch_one<BrickCounts>(ba, nblocks(g.ncell, kBlock), s)) != hipSuccess) return e;
-    if ((e = launch_scan(P, P->d_count, g.ncell, P->d_bcount, s)) != hipSuccess) return e;
-    if ((e = launch_one<BrickTargets>(ba, nblocks(g.ncell, kBlock), s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -370,10 +347,7 @@ hipError_t launch_batched_binning(const BatchPhase& ph, hipStream_t s) {
     case BK_SCATTER: return launch_batched_phase<BinScatter>(ph, s);
     case BK_RANK: return launch_batched_phase<CellRank>(ph, s);
     case BK_GATHER: return launch_batched_phase<GatherSorted>(ph, s);
-    case BK_SUM_XI_BLOCKS: return launch_batched_phase<SumXiBlocks>(ph, s);
     case BK_SUM_XI_FINAL: return launch_batched_phase<SumXiFinal>(ph, s);
-    case BK_BRICK_COUNTS: return launch_batched_phase<BrickCounts>(ph, s);
-    case BK_BRICK_TARGETS: return launch_batched_phase<BrickTargets>(ph, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -247,24 +247,11 @@ struct Restrict {
 
 // ------------------------------------------------------------ prolongation
 // Fine index j receives coarse M with j - 2M in {0} (j even) or the odd
-// offsets +-1, +-3 (, +-5) (j odd).
-template <int P>
-__device__ __forceinline__ int prolong_taps(int j, int nc, int* idx, double* w) {
-  if ((j & 1) == 0) {
-    idx[0] = wrapi(j >> 1, nc);
-    w[0] = 1.0;
-    return 1;
-  }
-#pragma unroll
-  for (int k = 0; k < P / 2; ++k) {
-    const int o = 2 * k + 1;
-    idx[2 * k] = wrapi((j - o) >> 1, nc);
-    idx[2 * k + 1] = wrapi((j + o) >> 1, nc);
-    w[2 * k] = w[2 * k + 1] = rp_weight_odd<P>(k);
-  }
-  return P;
-}
-
+// offsets +-1, +-3 (, +-5) (j odd).  One thread per coarse point M writes the
+// 2 x 2 x 2 fine points 2M + {0,1}: both parities need only the coarse points
+// M - P/2 + 1 .. M + P/2 per dimension (the even one uses M alone), so the
+// thread walks those P z-planes, interpolates each plane in x then y, and
+// adds it into the 8 outputs.
 template <int P>
 struct Prolong {
   using Args = TransferArgs;
@@ -272,26 +259,64 @@ struct Prolong {
   static __device__ void run(const Args& a, int blk) {
     const GridDims& c = a.gs;
     const GridDims& f = a.gd;
-    const int J = blk * kBlock + threadIdx.x;
-    if (J >= f.size) return;
-    const int x = J % f.n[0], y = (J / f.n[0]) % f.n[1], z = J / (f.n[0] * f.n[1]);
+    const int M = blk * kBlock + threadIdx.x;
+    if (M >= c.size) return;
+    const int X = M % c.n[0], Y = (M / c.n[0]) % c.n[1], Z = M / (c.n[0] * c.n[1]);
+    constexpr int H = P / 2;
+    double w[P];   // weight of coarse M - H + 1 + t for the odd fine point 2M + 1
     int ix[P], iy[P], iz[P];
-    double wx[P], wy[P], wz[P];
-    const int nx = prolong_taps<P>(x, c.n[0], ix, wx);
-    const int ny = prolong_taps<P>(y, c.n[1], iy, wy);
-    const int nz = prolong_taps<P>(z, c.n[2], iz, wz);
-    double acc = 0.0;
-    for (int i = 0; i < nz; ++i) {
-      double sy = 0.0;
-      for (int j = 0; j < ny; ++j) {
-        const double* row = a.src + ((size_t)iz[i] * c.n[1] + iy[j]) * c.n[0];
-        double sx = 0.0;
-        for (int cc = 0; cc < nx; ++cc) sx += wx[cc] * row[ix[cc]];
-        sy += wy[j] * sx;
-      }
-      acc += wz[i] * sy;
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      const int o = 2 * H - 1 - 2 * t;   // (2M + 1) - 2 (M - H + 1 + t)
+      w[t] = rp_weight_odd<P>(((o < 0 ? -o : o) - 1) / 2);
+      ix[t] = wrapi(X - H + 1 + t, c.n[0]);
+      iy[t] = wrapi(Y - H + 1 + t, c.n[1]);
+      iz[t] = wrapi(Z - H + 1 + t, c.n[2]);
     }
-    a.dst[J] = a.add[J] + acc;
+    double acc[2][2][2];   // [z parity][y parity][x parity]
+#pragma unroll
+    for (int tz = 0; tz < P; ++tz) {
+      double ye[2] = {0.0, 0.0}, yo[2] = {0.0, 0.0};   // y even / odd, [x parity]
+#pragma unroll
+      for (int ty = 0; ty < P; ++ty) {
+        const double* row = a.src + ((size_t)iz[tz] * c.n[1] + iy[ty]) * c.n[0];
+        double v[P];
+#pragma unroll
+        for (int tx = 0; tx < P; ++tx) v[tx] = row[ix[tx]];
+        double xo = 0.0;
+#pragma unroll
+        for (int tx = 0; tx < P; ++tx) xo += w[tx] * v[tx];
+        const double xe = v[H - 1];
+        if (ty == H - 1) {
+          ye[0] = xe;
+          ye[1] = xo;
+        }
+        yo[0] += w[ty] * xe;
+        yo[1] += w[ty] * xo;
+      }
+      if (tz == 0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[1][0][q] = acc[1][1][q] = 0.0;
+      }
+      if (tz == H - 1) {
+        acc[0][0][0] = ye[0];
+        acc[0][0][1] = ye[1];
+        acc[0][1][0] = yo[0];
+        acc[0][1][1] = yo[1];
+      }
+      acc[1][0][0] += w[tz] * ye[0];
+      acc[1][0][1] += w[tz] * ye[1];
+      acc[1][1][0] += w[tz] * yo[0];
+      acc[1][1][1] += w[tz] * yo[1];
+    }
+#pragma unroll
+    for (int pz = 0; pz < 2; ++pz)
+#pragma unroll
+      for (int py = 0; py < 2; ++py) {
+        const size_t J = ((size_t)(2 * Z + pz) * f.n[1] + (2 * Y + py)) * f.n[0] + 2 * X;
+        a.dst[J] = a.add[J] + acc[pz][py][0];
+        a.dst[J + 1] = a.add[J + 1] + acc[pz][py][1];
+      }
   }
 };
 
@@ -318,13 +343,20 @@ struct Interp {
 #pragma unroll
         for (int j = 0; j < P; ++j) idx[d][j] = wrapi(base + j, gg.n[d]);
       }
+      // one z-plane at a time (not unrolled: few registers, more waves); the
+      // plane's z weight and row offset sit in slot 0, rotated after each plane
       double u = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+      size_t yrow[P];
 #pragma unroll
+      for (int jy = 0; jy < P; ++jy) yrow[jy] = (size_t)idx[1][jy] * gg.n[0];
+      const size_t plane = (size_t)gg.n[0] * gg.n[1];
+#pragma unroll 1
       for (int jz = 0; jz < P; ++jz) {
+        const double* E1z = a.E1 + (size_t)idx[2][0] * plane;
         double ru = 0.0, rgx = 0.0, rgy = 0.0;
 #pragma unroll
         for (int jy = 0; jy < P; ++jy) {
-          const double* row = a.E1 + ((size_t)idx[2][jz] * gg.n[1] + idx[1][jy]) * gg.n[0];
+          const double* row = E1z + yrow[jy];
           double v = 0.0, vd = 0.0;
 #pragma unroll
           for (int jx = 0; jx < P; ++jx) {
@@ -336,10 +368,16 @@ struct Interp {
           rgx += (double)w[1][jy] * vd;
           rgy += (double)dw[1][jy] * v;
         }
-        u += (double)w[2][jz] * ru;
-        gx += (double)w[2][jz] * rgx;
-        gy += (double)w[2][jz] * rgy;
-        gz += (double)dw[2][jz] * ru;
+        u += (double)w[2][0] * ru;
+        gx += (double)w[2][0] * rgx;
+        gy += (double)w[2][0] * rgy;
+        gz += (double)dw[2][0] * ru;
+#pragma unroll
+        for (int t = 0; t + 1 < P; ++t) {
+          w[2][t] = w[2][t + 1];
+          dw[2][t] = dw[2][t + 1];
+          idx[2][t] = idx[2][t + 1];
+        }
       }
       const int i = a.perm[s];
       const double xi = p.w;
@@ -471,8 +509,8 @@ hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s) {
   Level& F = P->lv[k_fine - 1];
   Level& C = P->lv[k_fine];
   TransferArgs a{C.E, C.g, F.e, F.E, F.g};
-  if (P->order == 4) return launch_one<Prolong<4>>(a, nblocks(F.g.size, kBlock), s);
-  return launch_one<Prolong<6>>(a, nblocks(F.g.size, kBlock), s);
+  if (P->order == 4) return launch_one<Prolong<4>>(a, nblocks(C.g.size, kBlock), s);
+  return launch_one<Prolong<6>>(a, nblocks(C.g.size, kBlock), s);
 }
 
 hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forces, double* potential,

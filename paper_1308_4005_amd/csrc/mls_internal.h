@@ -111,15 +111,15 @@ struct RankArgs { const int* start; const int* cid; const int* perm_tmp; int n; 
 struct GatherArgs {
   const int* perm; int n; const double4* xw; const int* cid;
   double4* xs; int* cell_s; float4* xr; float* xif; CellGeom g;
+  double* xi_partial;   // mixed precision: per-block sums of xi (else null)
 };
-struct BrickArgs { const int* order; const int* start; const int* bstart; int ncell; int* bcount; int* tgt; };
-struct SumXiArgs { const double4* xs; int n; double* partial; double* out; };
+struct SumXiArgs { int rows; const double* partial; double* out; };   // partials of ceil(rows / 256) gather blocks
 struct PairArgs {
-  const double4* xs; const int* cell_s; const int* cstart; const int* tgt; int n; CellGeom g; PairConst pc;
+  const double4* xs; const int* cell_s; const int* cstart; int n; CellGeom g; PairConst pc;
   double* e0; double* floc;
 };
 struct PairArgsF {
-  const float4* xr; const float* xif; const double4* xs; const int* cell_s; const int* cstart; const int* tgt;
+  const float4* xr; const float* xif; const double4* xs; const int* cell_s; const int* cstart;
   int n; CellGeom g; PairConstF pc; double* e0; double* floc;
 };
 struct AnterpArgs {
@@ -159,7 +159,7 @@ struct StencilLevel {
 // (StencilLevel index, tile x, y, z) instead.
 enum BatchKernel {
   BK_FILL_I, BK_FILL_D, BK_BIN_COUNT, BK_SCAN_BLOCKS, BK_SCAN_SUMS, BK_SCAN_ADD, BK_SCATTER, BK_RANK, BK_GATHER,
-  BK_SUM_XI_BLOCKS, BK_SUM_XI_FINAL, BK_BRICK_COUNTS, BK_BRICK_TARGETS,
+  BK_SUM_XI_FINAL,
   BK_PAIR_GENERIC, BK_PAIR_WAVE, BK_PAIR_TRIM_F64, BK_PAIR_TRIM_F32,
   BK_ANT_ATOMIC, BK_ANT_OWNED, BK_RESTRICT, BK_PROLONG, BK_INTERP, BK_ENERGY,
   BK_STENCIL, BK_COARSEST
@@ -245,17 +245,14 @@ struct mls_plan_s {
   int* d_count = nullptr;          // ncell
   int* d_cell_start = nullptr;     // ncell + 1
   int* d_slot = nullptr;           // n_max: arrival slot of an atom in its cell
+  double4* d_xw = nullptr;         // n_max: wrapped x,y,z + xi, original order
   int* d_bsum = nullptr;           // scan block sums
   int* d_bmax = nullptr;           // scan block maxima
   bool pair_fast = false;          // half-cutoff cells with per-atom row trimming
-  int* d_cell_order = nullptr;     // ncell: cells in 4x4x4-brick order (pair target order)
-  int* d_bcount = nullptr;         // ncell + 1: atom counts / offsets in brick order
-  int* d_tgt = nullptr;            // n_max: sorted atom indices in brick order
   int* d_cid = nullptr;            // n_max: cell of original atom
   int* d_perm_tmp = nullptr;       // n_max
   int* d_perm = nullptr;           // n_max
   int* d_cell_s = nullptr;         // n_max: cell of sorted atom
-  double4* d_xw = nullptr;         // n_max: wrapped x,y,z + xi, original order
   double4* d_xs = nullptr;         // n_max: sorted
   float4* d_xr = nullptr;          // n_max + pad: sorted, cell-relative FP32 x,y,z and cell x index (mixed)
   float* d_xif = nullptr;          // n_max + pad: sorted xi in FP32 (mixed)

@@ -182,7 +182,7 @@ struct PairWave {
 };
 
 // FP64, filter-and-drain over half-cutoff cells: one wave of 64 lanes takes
-// 64 targets from a compact group of cells.  Each lane visits the 5 x 5 rows
+// 64 consecutive cell-sorted targets.  Each lane visits the 5 x 5 rows
 // of cells around its target's cell, skips rows whose y/z gap to the target
 // is at least a, and trims every other row to the cells the cutoff sphere
 // can reach along x (at most two runs of cells: one per periodic image).  A
@@ -240,7 +240,7 @@ __device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int* __res
   const double ax = xi.x - (double)((img & 3) - 1) * g.L[0];
   const double ay = xi.y - (double)(((img >> 2) & 3) - 1) * g.L[1];
   const double az = xi.z - (double)(((img >> 4) & 3) - 1) * g.L[2];
-  int* slot = queue + A.cnt * kWaveQ + lane;
+  int* const qlane = queue + lane;
   while (__any(j < j1)) {
     double4 xj[kBatch];
 #pragma unroll
@@ -251,17 +251,15 @@ __device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int* __res
       const double r2 = dx * dx + dy * dy + dz * dz;
       const bool hit = (j + b < j1) & (r2 < pc.a2);
       // the slot at the queue's end is free: write unconditionally, keep on a hit
-      *slot = ((j + b) << 6) | img;
-      slot += hit ? kWaveQ : 0;
+      qlane[kWaveQ * A.cnt] = ((j + b) << 6) | img;
+      A.cnt += hit ? 1 : 0;
     }
     // lanes past their range stay put (j <= j1 + kBatch - 1): reads stay
     // within the padding however long other lanes keep scanning
     j += j < j1 ? kBatch : 0;
-    A.cnt = (int)(slot - queue - lane) / kWaveQ;
     if (__any(A.cnt > kQueue - kBatch)) {
       pair_drain_f64(queue, A.cnt, lane, self_ent, xi, xs, g, pc, A);
       A.cnt = 0;
-      slot = queue + lane;
     }
   }
 }
@@ -281,10 +279,9 @@ struct PairTrimF64 {
   const int n = ar.n;
   __shared__ int queue[kQueue * kWaveQ];
   const int lane = threadIdx.x;
-  // targets in brick order: the 64 lanes of a wave sit in a compact group of cells
   const int k = blk * kWaveQ + lane;
   const bool active = k < n;
-  const int sc = ar.tgt[active ? k : n - 1];
+  const int sc = active ? k : n - 1;
   const double4 xi = xs[sc];
   const int c = ar.cell_s[sc];
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
@@ -396,7 +393,7 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
   const float ay = fmaf((float)-dy, pc.w[1], xi.y);
   const float az = fmaf((float)-dz, pc.w[2], xi.z);
   const int bits = entry_bits(ix, dy, dz);
-  int* slot = queue + A.cnt * kWaveQ + lane;
+  int* const qlane = queue + lane;
   while (__any(j < j1)) {
     float4 xj[kBatch];
 #pragma unroll
@@ -407,15 +404,13 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
       const float dyv = ay - xj[b].y, dzv = az - xj[b].z;
       const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
       const bool hit = (j + b < j1) & (r2 < pc.a2);
-      *slot = ((j + b) << 8) | bits;
-      slot += hit ? kWaveQ : 0;
+      qlane[kWaveQ * A.cnt] = ((j + b) << 8) | bits;
+      A.cnt += hit ? 1 : 0;
     }
     j += j < j1 ? kBatch : 0;
-    A.cnt = (int)(slot - queue - lane) / kWaveQ;
     if (__any(A.cnt > kQueue - kBatch)) {
       pair_drain_f32(queue, A.cnt, lane, self_ent, xi, cxi, xr, xif, g, pc, A);
       A.cnt = 0;
-      slot = queue + lane;
     }
   }
 }
@@ -434,7 +429,7 @@ struct PairTrimF32 {
   const int lane = threadIdx.x;
   const int k = blk * kWaveQ + lane;
   const bool active = k < n;
-  const int sc = ar.tgt[active ? k : n - 1];
+  const int sc = active ? k : n - 1;
   const float4 xi = xr[sc];
   const double4 xd = ar.xs[sc];   // FP64 position: only for choosing rows and cells
   const int c = ar.cell_s[sc];
@@ -503,10 +498,10 @@ hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s) {
   if (P->precision == MLS_MIXED && P->pair_fast && n < (1 << 24)) {
     PairConstF pf{(float)P->a2, (float)P->inv_a2, (float)P->inv_a6, (float)P->inv_a8,
                   {(float)g.w[0], (float)g.w[1], (float)g.w[2]}};
-    PairArgsF a{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, P->d_tgt, n, g, pf, P->d_e0, P->d_floc};
+    PairArgsF a{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pf, P->d_e0, P->d_floc};
     return launch_one<PairTrimF32>(a, (n + kWaveQ - 1) / kWaveQ, s);
   }
-  PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, P->d_tgt, n, g, pc, P->d_e0, P->d_floc};
+  PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pc, P->d_e0, P->d_floc};
   if (P->pair_fast && n < (1 << 25)) return launch_one<PairTrimF64>(a, (n + kWaveQ - 1) / kWaveQ, s);
   if (!P->pair_fast) return launch_one<PairWave>(a, n, s);
   return launch_one<PairGeneric>(a, (n + kBlock - 1) / kBlock, s);

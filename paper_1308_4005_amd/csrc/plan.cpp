@@ -328,16 +328,13 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   ALLOC(P->d_count, cg.ncell);
   ALLOC(P->d_cell_start, cg.ncell + 1);
   ALLOC(P->d_slot, N);
-  ALLOC(P->d_cell_order, cg.ncell);
-  ALLOC(P->d_bcount, cg.ncell + 1);
-  ALLOC(P->d_tgt, N);
   ALLOC(P->d_bsum, scan_blocks(cg.ncell) + 1);
   ALLOC(P->d_bmax, scan_blocks(cg.ncell) + 1);
   ALLOC(P->d_cid, N);
+  ALLOC(P->d_xw, N);
   ALLOC(P->d_perm_tmp, N);
   ALLOC(P->d_perm, N);
   ALLOC(P->d_cell_s, N);
-  ALLOC(P->d_xw, N);
   ALLOC(P->d_xs, N + kSortedPad);
   ALLOC(P->d_e0, N);
   ALLOC(P->d_floc, 3 * N);
@@ -395,22 +392,6 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
     if ((e = hipMemcpy(P->d_row_wf_tile, wtf.data(), wtf.size() * sizeof(float), hipMemcpyHostToDevice)) !=
         hipSuccess)
       return hip_fail(e, "copy stencil tile weights (fp32)");
-  }
-  {
-    // cells grouped in 4 x 4 x 4 bricks (x fastest inside a brick and across
-    // bricks): pair-kernel waves then take spatially compact target groups
-    std::vector<int> order;
-    order.reserve(cg.ncell);
-    const int B = 4;
-    for (int bz = 0; bz < cg.nc[2]; bz += B)
-      for (int by = 0; by < cg.nc[1]; by += B)
-        for (int bx = 0; bx < cg.nc[0]; bx += B)
-          for (int z = bz; z < std::min(bz + B, cg.nc[2]); ++z)
-            for (int y = by; y < std::min(by + B, cg.nc[1]); ++y)
-              for (int x = bx; x < std::min(bx + B, cg.nc[0]); ++x) order.push_back((z * cg.nc[1] + y) * cg.nc[0] + x);
-    if ((e = hipMemcpy(P->d_cell_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice)) !=
-        hipSuccess)
-      return hip_fail(e, "copy cell order");
   }
   if ((e = hipMemcpy(P->d_wave_rows, wave_rows.data(), wave_rows.size() * sizeof(int), hipMemcpyHostToDevice)) !=
       hipSuccess)
