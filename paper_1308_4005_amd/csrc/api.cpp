@@ -105,21 +105,39 @@ mls_status mls_evaluate(mls_plan_t P, int64_t n, const double* pos, const double
     ++P->timing_slots;
   }
   auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
+  // with per-stage timing every stage runs in order on the caller's stream;
+  // otherwise the grid chain runs on the plan's second stream, concurrently
+  // with the local part
+  const bool fork = !ev;
+  if (fork && !P->side) {
+    HIP_TRY(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    HIP_TRY(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming), "hipEventCreateWithFlags");
+    HIP_TRY(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming), "hipEventCreateWithFlags");
+  }
+  const hipStream_t g = fork ? P->side : s;
   HIP_TRY(mark(0), "timing event");
   HIP_TRY(launch_binning(P, ni, pos, c6, s), "binning");
   HIP_TRY(mark(1 + MLS_T_BINNING), "timing event");
+  if (fork) {
+    HIP_TRY(hipEventRecord(P->ev_fork, s), "fork");
+    HIP_TRY(hipStreamWaitEvent(g, P->ev_fork, 0), "fork");
+  }
   HIP_TRY(launch_pair(P, ni, s), "pair kernel");
   HIP_TRY(mark(1 + MLS_T_PAIR), "timing event");
-  HIP_TRY(launch_anterpolate(P, ni, s), "anterpolation");
+  HIP_TRY(launch_anterpolate(P, ni, g), "anterpolation");
   HIP_TRY(mark(1 + MLS_T_ANTERP), "timing event");
-  for (int k = 2; k <= P->levels; ++k) HIP_TRY(launch_restrict(P, k - 1, s), "restriction");
+  for (int k = 2; k <= P->levels; ++k) HIP_TRY(launch_restrict(P, k - 1, g), "restriction");
   HIP_TRY(mark(1 + MLS_T_RESTRICT), "timing event");
-  HIP_TRY(launch_stencils(P, s), "level stencils");
+  HIP_TRY(launch_stencils(P, g), "level stencils");
   HIP_TRY(mark(1 + MLS_T_STENCIL), "timing event");
-  HIP_TRY(launch_coarsest(P, s), "coarsest grid");
+  HIP_TRY(launch_coarsest(P, g), "coarsest grid");
   HIP_TRY(mark(1 + MLS_T_COARSEST), "timing event");
-  for (int k = P->levels - 1; k >= 1; --k) HIP_TRY(launch_prolong(P, k, s), "prolongation");
+  for (int k = P->levels - 1; k >= 1; --k) HIP_TRY(launch_prolong(P, k, g), "prolongation");
   HIP_TRY(mark(1 + MLS_T_PROLONG), "timing event");
+  if (fork) {
+    HIP_TRY(hipEventRecord(P->ev_join, g), "join");
+    HIP_TRY(hipStreamWaitEvent(s, P->ev_join, 0), "join");
+  }
   HIP_TRY(launch_interpolate(P, ni, energy, forces, potential, dE_dc6, s), "interpolation");
   HIP_TRY(mark(1 + MLS_T_INTERP), "timing event");
   return MLS_OK;
@@ -190,6 +208,12 @@ mls_status mls_plan_destroy(mls_plan_t P) {
   if (!P) return MLS_OK;
   for (auto& e : P->events) (void)hipEventDestroy(e);
   P->events.clear();
+  if (P->side) {
+    (void)hipStreamSynchronize(P->side);
+    (void)hipStreamDestroy(P->side);
+    (void)hipEventDestroy(P->ev_fork);
+    (void)hipEventDestroy(P->ev_join);
+  }
   free_plan(P);
   delete P;
   return MLS_OK;

@@ -54,6 +54,8 @@ struct mls_batch_s {
 
   bool use_graph = true;
   hipStream_t cap_stream = nullptr;
+  hipStream_t side = nullptr;        // grid chain, concurrent with the local part
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t last_stream = nullptr;
@@ -385,12 +387,32 @@ hipError_t launch_phase(const BatchPhase& ph, hipStream_t s) {
 }
 
 // Enqueue every phase; with `ev`, record an event at each stage boundary
-// (ev[k] before stage k, ev[MLS_NUM_STAGES] at the end).
+// (ev[k] before stage k, ev[MLS_NUM_STAGES] at the end) and keep every phase
+// on `s`.  Without, the grid chain (anterpolation .. prolongation) runs on the
+// batch's second stream, forked after binning and joined before
+// interpolation, concurrently with the local part.
 mls_status run_phases(mls_batch_s* B, hipStream_t s, hipEvent_t* ev) {
+  const bool fork = !ev;
+  bool forked = false, joined = false;
   int stage = -1;
   for (const BatchPhase& ph : B->phases) {
     while (ev && stage < ph.stage) HIP_TRY(hipEventRecord(ev[++stage], s), "batch: timing event");
-    HIP_TRY(launch_phase(ph, s), "batch: launch");
+    if (fork && !forked && ph.stage > MLS_T_BINNING) {
+      HIP_TRY(hipEventRecord(B->ev_fork, s), "batch: fork");
+      HIP_TRY(hipStreamWaitEvent(B->side, B->ev_fork, 0), "batch: fork");
+      forked = true;
+    }
+    if (forked && !joined && ph.stage > MLS_T_PROLONG) {
+      HIP_TRY(hipEventRecord(B->ev_join, B->side), "batch: join");
+      HIP_TRY(hipStreamWaitEvent(s, B->ev_join, 0), "batch: join");
+      joined = true;
+    }
+    const bool chain = forked && ph.stage >= MLS_T_ANTERP && ph.stage <= MLS_T_PROLONG;
+    HIP_TRY(launch_phase(ph, chain ? B->side : s), "batch: launch");
+  }
+  if (forked && !joined) {
+    HIP_TRY(hipEventRecord(B->ev_join, B->side), "batch: join");
+    HIP_TRY(hipStreamWaitEvent(s, B->ev_join, 0), "batch: join");
   }
   while (ev && stage < MLS_NUM_STAGES) HIP_TRY(hipEventRecord(ev[++stage], s), "batch: timing event");
   return MLS_OK;
@@ -527,7 +549,10 @@ mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* 
   for (int k = 0; k < MLS_NUM_STAGES; ++k) B->tune.stage_ms[k] = 0.0;
   B->tune_pending = autotune_flag != 0;
   hipError_t e = hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking);
-  if (e != hipSuccess) return fail(hip_fail(e, "batch: capture stream"));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming);
+  if (e != hipSuccess) return fail(hip_fail(e, "batch: streams and events"));
   *out = B;
   return MLS_OK;
 }
@@ -635,6 +660,12 @@ mls_status mls_batch_destroy(mls_batch_t B) {
   drop_phases(B);
   for (auto& e : B->events) (void)hipEventDestroy(e);
   if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+  if (B->side) {
+    (void)hipStreamSynchronize(B->side);
+    (void)hipStreamDestroy(B->side);
+  }
+  if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
+  if (B->ev_join) (void)hipEventDestroy(B->ev_join);
   for (auto* P : B->plans) {
     if (!P) continue;
     free_plan(P);

@@ -153,8 +153,25 @@ struct AnterpOwned {
     __syncthreads();
     const int ns = nseg_s;
     const int tot = seg_off[ns];
+    // the block's atom list is cut into 64 contiguous chunks, one per lane
+    // position; the waves take turns within a chunk.  The 64 lanes of a wave
+    // then work on atoms far apart in the list (different cells), so their
+    // LDS additions rarely land on the same grid points.
+    const int lanepos = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int kWaves = kAntThreads / 64;
+    const int chunk = (tot + 63) / 64;
+    const int i0 = lanepos * chunk, i1 = min(i0 + chunk, tot);
     int sg = 0;
-    for (int i = threadIdx.x; i < tot; i += kAntThreads) {
+    {
+      // first segment holding i0 (binary search over the run offsets)
+      int lo = 0, hi = ns;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg_off[mid] <= i0) lo = mid; else hi = mid;
+      }
+      sg = lo;
+    }
+    for (int i = i0 + wave; i < i1; i += kWaves) {
       while (seg_off[sg + 1] <= i) ++sg;
       const double4 p = a.xs[seg_begin[sg] + (i - seg_off[sg])];
       const double pc[3] = {p.x, p.y, p.z};

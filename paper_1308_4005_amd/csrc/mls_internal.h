@@ -264,6 +264,12 @@ struct mls_plan_s {
   int* d_flags = nullptr;
   int* d_ncell_max = nullptr;
 
+  // the grid chain (anterpolation .. prolongation) runs on a second stream,
+  // concurrently with the local part: fork after binning, join before
+  // interpolation
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
   // per-stage timing (mls_plan_set_timing)
   bool timing = false;
   int timing_slots = 0;            // evaluations recorded in the window
