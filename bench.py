@@ -63,13 +63,13 @@ def work_model(plan_info, n, pairs, order):
 
 
 # kernel that carries each stage of the 10^6-atom cube (cell width a/2 there)
-STAGE_KERNEL = {("pair", "mixed"): "k_pair_trim_f32", ("pair", "fp64"): "k_pair_trim_f64",
+STAGE_KERNEL = {("pair", "mixed"): "void k_one<PairTrimF32>", ("pair", "fp64"): "void k_one<PairTrimF64>",
                 ("stencil", "mixed"): "void k_stencil_tile<float, 6, 16, 4>",
                 ("stencil", "fp64"): "void k_stencil_tile<double, 6, 16, 4>",
-                ("anterpolation", "mixed"): "void k_anterp_owned<4, float>",
-                ("anterpolation", "fp64"): "void k_anterp_owned<4, double>",
-                ("interpolation", "mixed"): "void k_interp_f64<4, float>",
-                ("interpolation", "fp64"): "void k_interp_f64<4, double>"}
+                ("anterpolation", "mixed"): "void k_one<AnterpOwned<4, float> >",
+                ("anterpolation", "fp64"): "void k_one<AnterpOwned<4, double> >",
+                ("interpolation", "mixed"): "void k_one<Interp<4, float> >",
+                ("interpolation", "fp64"): "void k_one<Interp<4, double> >"}
 
 
 def measured_traffic(stage, precision):
