@@ -53,56 +53,77 @@ __all__ = [
 # --------------------------------------------------------------------------
 
 
-def gamma(rho):
-    """Smoothing function of eq:gamma: 15/8 - 5/4 rho^12 + 3/8 rho^24 inside
-    the unit ball, rho^-6 outside."""
+def _binom_half(m):
+    """binom(-1/2, m), the m-th coefficient of the series of (1+u)^(-1/2)."""
+    c = 1.0
+    for j in range(m):
+        c *= (-0.5 - j) / (j + 1)
+    return c
+
+
+def gamma(rho, cont=2):
+    """Smoothing function.  cont = 2 is eq:gamma as printed,
+    15/8 - 5/4 rho^12 + 3/8 rho^24 inside the unit ball, rho^-6 outside.
+    The family studied in Sec. III.B (continuity C^1 .. C^4) is read as the
+    order-``cont`` Taylor polynomial of rho^-6 = (1 + u)^(-1/2) in
+    u = rho^12 - 1, i.e. sum_{m<=cont} binom(-1/2, m) u^m, which joins rho^-6
+    at rho = 1 with ``cont`` continuous derivatives; cont = 2 reproduces
+    eq:gamma."""
     rho = np.asarray(rho, dtype=np.float64)
     out = np.empty_like(rho)
     inside = rho < 1.0
     r = rho[inside]
-    out[inside] = 15.0 / 8.0 - 5.0 / 4.0 * r ** 12 + 3.0 / 8.0 * r ** 24
+    if cont == 2:
+        out[inside] = 15.0 / 8.0 - 5.0 / 4.0 * r ** 12 + 3.0 / 8.0 * r ** 24
+    else:
+        u = r ** 12 - 1.0
+        out[inside] = sum(_binom_half(m) * u ** m for m in range(cont + 1))
     out[~inside] = rho[~inside] ** -6.0
     return out
 
 
-def dgamma(rho):
-    """d gamma / d rho (derivative of eq:gamma, piece by piece)."""
+def dgamma(rho, cont=2):
+    """d gamma / d rho (piece by piece; chain rule du/drho = 12 rho^11)."""
     rho = np.asarray(rho, dtype=np.float64)
     out = np.empty_like(rho)
     inside = rho < 1.0
     r = rho[inside]
-    out[inside] = -15.0 * r ** 11 + 9.0 * r ** 23
+    if cont == 2:
+        out[inside] = -15.0 * r ** 11 + 9.0 * r ** 23
+    else:
+        u = r ** 12 - 1.0
+        out[inside] = sum(_binom_half(m) * m * u ** (m - 1) for m in range(1, cont + 1)) * 12.0 * r ** 11
     out[~inside] = -6.0 * rho[~inside] ** -7.0
     return out
 
 
-def g0(r, a):
+def g0(r, a, cont=2):
     """Local kernel eq:g_0: r^-6 - a^-6 gamma(r/a); zero for r >= a."""
     r = np.asarray(r, dtype=np.float64)
     # the two terms cancel identically for r >= a (Sec. II.A.3)
-    return np.where(r < a, r ** -6.0 - a ** -6.0 * gamma(r / a), 0.0)
+    return np.where(r < a, r ** -6.0 - a ** -6.0 * gamma(r / a, cont), 0.0)
 
 
-def dg0(r, a):
+def dg0(r, a, cont=2):
     """d g_0 / d r."""
     r = np.asarray(r, dtype=np.float64)
-    return np.where(r < a, -6.0 * r ** -7.0 - a ** -7.0 * dgamma(r / a), 0.0)
+    return np.where(r < a, -6.0 * r ** -7.0 - a ** -7.0 * dgamma(r / a, cont), 0.0)
 
 
-def gk(r, a, k):
+def gk(r, a, k, cont=2):
     """Intermediate-level kernel eq:g_k for 1 <= k <= l-1 (cutoff 2^k a)."""
     r = np.asarray(r, dtype=np.float64)
     A1 = 2.0 ** (k - 1) * a
     A2 = 2.0 ** k * a
     # zero beyond the level cutoff 2^k a, where both terms equal r^-6
-    return np.where(r < A2, A1 ** -6.0 * gamma(r / A1) - A2 ** -6.0 * gamma(r / A2), 0.0)
+    return np.where(r < A2, A1 ** -6.0 * gamma(r / A1, cont) - A2 ** -6.0 * gamma(r / A2, cont), 0.0)
 
 
-def g_last(r, a, l):
+def g_last(r, a, l, cont=2):
     """Coarsest-level kernel eq:g_l: (2^(l-1) a)^-6 gamma(r / 2^(l-1) a)."""
     r = np.asarray(r, dtype=np.float64)
     A = 2.0 ** (l - 1) * a
-    return A ** -6.0 * gamma(r / A)
+    return A ** -6.0 * gamma(r / A, cont)
 
 
 # --------------------------------------------------------------------------
@@ -275,7 +296,7 @@ def bin_cells(xw, box, a):
 # --------------------------------------------------------------------------
 
 
-def local_part(xw, xi, box, a):
+def local_part(xw, xi, box, a, cont=2):
     """e0_i = sum_{(j,n) != (i,0), r<a} xi_j g_0(r) and
     F_i = sum xi_i xi_j g_0'(r)/r d,  d = x_i - x_j - n*L, over all images.
 
@@ -316,14 +337,14 @@ def local_part(xw, xi, box, a):
                 keep = (r2 < a2) & ~self_pair
                 i_idx, j_idx, d, r2 = i_idx[keep], j_idx[keep], d[keep], r2[keep]
                 r = np.sqrt(r2)
-                e0 += np.bincount(i_idx, weights=xi[j_idx] * g0(r, a), minlength=n)
-                coef = xi[i_idx] * xi[j_idx] * dg0(r, a) / r
+                e0 += np.bincount(i_idx, weights=xi[j_idx] * g0(r, a, cont), minlength=n)
+                coef = xi[i_idx] * xi[j_idx] * dg0(r, a, cont) / r
                 for dim in range(3):
                     F[:, dim] += np.bincount(i_idx, weights=coef * d[:, dim], minlength=n)
     return e0, F
 
 
-def local_part_bruteforce(xw, xi, box, a):
+def local_part_bruteforce(xw, xi, box, a, cont=2):
     """Same sums as ``local_part`` by direct enumeration of every pair and every
     image shift that can come within a (tiny inputs only)."""
     box = np.asarray(box, dtype=np.float64)
@@ -343,8 +364,8 @@ def local_part_bruteforce(xw, xi, box, a):
                         m[i] = False
                     if not m.any():
                         continue
-                    e0[i] += np.sum(xi[m] * g0(r[m], a))
-                    F[i] += np.sum((xi[i] * xi[m] * dg0(r[m], a) / r[m])[:, None] * d[m], axis=0)
+                    e0[i] += np.sum(xi[m] * g0(r[m], a, cont))
+                    F[i] += np.sum((xi[i] * xi[m] * dg0(r[m], a, cont) / r[m])[:, None] * d[m], axis=0)
     return e0, F
 
 
@@ -445,7 +466,7 @@ def interpolate(xw, E1, box, n1, order=4):
 # --------------------------------------------------------------------------
 
 
-def stencil_taps(h1, a):
+def stencil_taps(h1, a, cont=2):
     """Offsets delta (integer, (T,3) as x,y,z) with |delta o h_1| < 2a and the
     level-1 weights g_1(|delta o h_1|).  On level k the same offsets reach
     2^k a (spacing 2^(k-1) h_1) and g_k(2^(k-1) s) = 2^(-6(k-1)) g_1(s)."""
@@ -457,13 +478,13 @@ def stencil_taps(h1, a):
     s = np.sqrt(np.sum((off * h1) ** 2, axis=1))
     keep = s < 2.0 * a
     off, s = off[keep], s[keep]
-    return off, gk(s, a, 1)
+    return off, gk(s, a, 1, cont)
 
 
-def level_eval(q, k, h1, a):
+def level_eval(q, k, h1, a, cont=2):
     """e^k[mu] = sum_nu g_k(|x_mu - x_nu| over images) q^k[nu]; the cutoff 2^k a
     makes it a periodic stencil sum over the taps of ``stencil_taps``."""
-    off, wts = stencil_taps(h1, a)
+    off, wts = stencil_taps(h1, a, cont)
     scale = 2.0 ** (-6 * (k - 1))
     e = np.zeros_like(q)
     for (dx, dy, dz), wgt in zip(off, wts):
@@ -472,7 +493,7 @@ def level_eval(q, k, h1, a):
     return e
 
 
-def coarsest_kernel(box, n_l, a, l, beta=None):
+def coarsest_kernel(box, n_l, a, l, beta=None, cont=2):
     """Pre-summed coarsest-grid kernel of eq:last-grid-periodic-transformed:
     K_l[delta] = sum_{n in Z^3} g_l(|delta o h_l + n o L|), one entry per grid
     offset (translation invariance, Sec. II.C).  Returned indexed [z, y, x].
@@ -498,8 +519,8 @@ def coarsest_kernel(box, n_l, a, l, beta=None):
                 r = np.sqrt(np.sum(rv * rv, axis=1))
                 zero = r == 0.0
                 inside = (r < A) & ~zero
-                corr[inside] += g_last(r[inside], a, l) - r[inside] ** -6.0
-                corr[zero] += A ** -6.0 * gamma(np.zeros(1))[0]
+                corr[inside] += g_last(r[inside], a, l, cont) - r[inside] ** -6.0
+                corr[zero] += A ** -6.0 * gamma(np.zeros(1), cont)[0]
     K = (Z + corr).reshape(n_l[0], n_l[1], n_l[2])   # [x, y, z]
     return np.transpose(K, (2, 1, 0)).copy()
 
@@ -522,8 +543,9 @@ def coarsest_eval(q, K):
 # --------------------------------------------------------------------------
 
 
-def mls(pos, c6, box, a, h, order=4, levels=0, grid=None, beta=None):
-    """One MLS energy-and-force evaluation (Sec. II.B).
+def mls(pos, c6, box, a, h, order=4, levels=0, grid=None, beta=None, continuity=2):
+    """One MLS energy-and-force evaluation (Sec. II.B), with the smoothing
+    function of continuity C^``continuity`` (``gamma``; 2 = eq:gamma).
 
     Returns a dict with the energy E, forces F (N,3), per-atom potential u
     (e^{0,tot} including the grid self-term), dE/dC6, and the intermediates:
@@ -539,7 +561,8 @@ def mls(pos, c6, box, a, h, order=4, levels=0, grid=None, beta=None):
     xi = np.sqrt(c6)                                   # eq:xi-general
     xw = wrap(pos, box)
     # k = 0
-    e0, Floc = local_part(xw, xi, box, a)
+    cont = int(continuity)
+    e0, Floc = local_part(xw, xi, box, a, cont)
     # anterpolation and restriction
     q = [anterpolate(xw, xi, box, n1, order)]
     for k in range(2, l + 1):
@@ -547,9 +570,9 @@ def mls(pos, c6, box, a, h, order=4, levels=0, grid=None, beta=None):
     # evaluation on every grid
     e = []
     for k in range(1, l):
-        e.append(level_eval(q[k - 1], k, h1, a))
+        e.append(level_eval(q[k - 1], k, h1, a, cont))
     n_l = n1 // 2 ** (l - 1)
-    K = coarsest_kernel(box, n_l, a, l, beta=beta)
+    K = coarsest_kernel(box, n_l, a, l, beta=beta, cont=cont)
     e.append(coarsest_eval(q[l - 1], K))
     # prolongation
     E = [None] * l
@@ -560,7 +583,7 @@ def mls(pos, c6, box, a, h, order=4, levels=0, grid=None, beta=None):
     ug, grad = interpolate(xw, E[0], box, n1, order)
     u = e0 + ug
     F = Floc + xi[:, None] * grad
-    cself = gamma(np.zeros(1))[0] / a ** 6             # eq:self-interaction-energy
+    cself = gamma(np.zeros(1), cont)[0] / a ** 6       # eq:self-interaction-energy
     energy = -0.5 * (np.dot(xi, u) - cself * np.dot(xi, xi))
     dE_dxi = -(u - cself * xi)
     with np.errstate(divide="ignore", invalid="ignore"):
