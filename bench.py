@@ -91,11 +91,11 @@ def measured_traffic(stage, precision):
     return None if k is None else k["read_bytes"] + k["write_bytes"]
 
 
-def time_precision(w, prm, precision, steps, warmup, dev):
+def time_precision(w, prm, precision, steps, warmup, dev, continuity=2, stages=True):
     import torch
     from paper_1308_4005_amd import Plan, Result
     plan = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], precision=precision,
-                n_max=w.n, device=dev.index)
+                n_max=w.n, device=dev.index, continuity=continuity)
     pos = torch.tensor(w.pos, dtype=torch.float64, device=dev)
     c6 = torch.tensor(w.c6, dtype=torch.float64, device=dev)
     out = Result(torch.empty(1, dtype=torch.float64, device=dev),
@@ -114,13 +114,15 @@ def time_precision(w, prm, precision, steps, warmup, dev):
     ms = t0.elapsed_time(t1) / steps
     # stage breakdown: library hipEvents at every stage boundary (in this mode
     # the stages run one after another on one stream)
-    plan.set_timing(True)
-    for _ in range(steps):
-        plan.evaluate(pos, c6, out=out)
-    torch.cuda.synchronize()
-    stage_ms, cnt = plan.read_timing()
-    plan.set_timing(False)
-    stage_ms = {k: v / max(cnt, 1) for k, v in stage_ms.items()}
+    stage_ms = {}
+    if stages:
+        plan.set_timing(True)
+        for _ in range(steps):
+            plan.evaluate(pos, c6, out=out)
+        torch.cuda.synchronize()
+        stage_ms, cnt = plan.read_timing()
+        plan.set_timing(False)
+        stage_ms = {k: v / max(cnt, 1) for k, v in stage_ms.items()}
     E = float(out.energy.cpu()[0])
     F = out.forces.cpu().numpy()
     info = plan.info
@@ -238,6 +240,7 @@ def main():
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="leave out the batched-form measurement")
+    ap.add_argument("--no-family", action="store_true", help="leave out the smoothing-family measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: MLS here is a single-GPU path "
@@ -297,6 +300,20 @@ def main():
             dE=abs(res["mixed"]["E"] - res["fp64"]["E"]) / abs(res["fp64"]["E"]),
             rms_rel_F=float(np.sqrt(np.sum(dif ** 2) / np.sum(Fd ** 2))))
 
+    # the smoothing-function family (continuity C^1..C^4, Sec. III.B) at the
+    # headline precision; k = 2 is the headline itself
+    family = None
+    if not args.no_family:
+        family = {"precision": head, "ms_per_step": {}, "energy": {}}
+        for k in (1, 2, 3, 4):
+            if k == 2:
+                r = res[head]
+            else:
+                log(f"[bench] continuity C^{k}")
+                r = time_precision(w, prm, head, max(5, args.steps // 2), 2, dev, continuity=k, stages=False)
+            family["ms_per_step"][f"C{k}"] = r["ms"]
+            family["energy"][f"C{k}"] = r["E"]
+
     batched = None
     if not args.no_batch:
         t = time.time()
@@ -343,6 +360,7 @@ def main():
         "mixed_over_fp64": (res["fp64"]["ms"] / res["mixed"]["ms"]) if len(res) == 2 else None,
         "accuracy": accuracy,
         "roofline": roofline,
+        "continuity_family": family,
         "batched": batched,
         "cpu_baseline": cpu,
     }

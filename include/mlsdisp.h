@@ -80,6 +80,10 @@ typedef struct {
                      arithmetic in FP32 with FP64 accumulation of energy,
                      forces and grid charges, and keeps the coarsest level
                      and the energy reduction in FP64 */
+  int continuity; /* k = 1..4: smoothing function gamma_k, the order-k Taylor
+                     polynomial of rho^-6 = (1 + u)^(-1/2) in u = rho^12 - 1
+                     for rho < 1 (C^k at rho = 1; the family of Sec. III.B).
+                     2 is eq:gamma; 0 means 2 */
 } mls_params;
 
 /* Resolved plan geometry (host struct filled by mls_plan_get_info). */
@@ -95,6 +99,7 @@ typedef struct {
   int precision;
   int order;
   double cell_width[3];    /* linked-cell width L_d / cells_d */
+  int continuity;          /* k of gamma_k */
 } mls_plan_info;
 
 /* Build a plan on the current HIP device: resolves grids, levels and linked
@@ -193,7 +198,8 @@ mls_status mls_plan_destroy(mls_plan_t plan);
  * into a hipGraph on first use and replayed.
  *
  *   nbox       1 .. 2^20 boxes
- *   per_box    host (nbox) parameter sets; precision and order must agree
+ *   per_box    host (nbox) parameter sets; precision, order and continuity
+ *              must agree
  *   n_per_box  host (nbox) atom counts >= 0 (total < 2^31)
  *   autotune   nonzero: the first mls_batch_evaluate times every stage over
  *              a set of persistent grid sizes and stencil tile depths on the

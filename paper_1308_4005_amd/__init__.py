@@ -32,7 +32,7 @@ def precision_code(precision) -> int:
     raise ValueError(f"unknown precision {precision!r}")
 
 
-def _params(box, cutoff, h, order, levels, grid, precision):
+def _params(box, cutoff, h, order, levels, grid, precision, continuity=2):
     p = _lib.MLSParams()
     for d in range(3):
         p.box[d] = float(box[d])
@@ -42,6 +42,7 @@ def _params(box, cutoff, h, order, levels, grid, precision):
     p.order = int(order)
     p.levels = int(levels)
     p.precision = precision_code(precision)
+    p.continuity = int(continuity)
     return p
 
 
@@ -61,11 +62,11 @@ class Plan:
     """A resolved MLS setup for one periodic box (``mls_plan_create``)."""
 
     def __init__(self, box, cutoff, h=1.0, order=4, levels=0, grid=None, precision="fp64",
-                 n_max=0, device=None):
+                 n_max=0, device=None, continuity=2):
         import torch
         self._lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        self.params = _params(box, cutoff, h, order, levels, grid, precision)
+        self.params = _params(box, cutoff, h, order, levels, grid, precision, continuity)
         self._plan = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(self._lib.mls_plan_create(ctypes.byref(self.params), int(n_max),
@@ -76,7 +77,7 @@ class Plan:
                          cells=tuple(inf.cells), h_eff=tuple(inf.h_eff), taps=int(inf.taps),
                          n_max=int(inf.n_max), workspace_bytes=int(inf.workspace_bytes),
                          precision=int(inf.precision), order=int(inf.order),
-                         cell_width=tuple(inf.cell_width))
+                         cell_width=tuple(inf.cell_width), continuity=int(inf.continuity))
         self.n_max = int(inf.n_max)
 
     # ------------------------------------------------------------------

@@ -49,6 +49,7 @@ class MLSParams(ctypes.Structure):
         ("levels", ctypes.c_int),
         ("grid", ctypes.c_int * 3),
         ("precision", ctypes.c_int),
+        ("continuity", ctypes.c_int),
     ]
 
 
@@ -65,6 +66,7 @@ class MLSPlanInfo(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("order", ctypes.c_int),
         ("cell_width", ctypes.c_double * 3),
+        ("continuity", ctypes.c_int),
     ]
 
 

@@ -77,6 +77,7 @@ mls_status mls_plan_get_info(mls_plan_t P, mls_plan_info* info) {
   info->workspace_bytes = P->bytes;
   info->precision = P->precision;
   info->order = P->order;
+  info->continuity = P->continuity;
   return MLS_OK;
 }
 

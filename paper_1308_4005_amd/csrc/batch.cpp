@@ -173,21 +173,19 @@ mls_status build_phases(mls_batch_s* B) {
 
   // ------------------------------------------------ local part (eq:g_0)
   {
-    HostPhase f32 = make_phase<PairArgsF>(BK_PAIR_TRIM_F32, MLS_T_PAIR, 0, nb);
-    HostPhase f64 = make_phase<PairArgs>(BK_PAIR_TRIM_F64, MLS_T_PAIR, 0, nb);
-    HostPhase gen = make_phase<PairArgs>(BK_PAIR_GENERIC, MLS_T_PAIR, 0, nb);
-    HostPhase wav = make_phase<PairArgs>(BK_PAIR_WAVE, MLS_T_PAIR, 0, nb);
+    const int pv = pair_variant(B->plans[0]);   // boxes share the smoothing function
+    HostPhase f32 = make_phase<PairArgsF>(BK_PAIR_TRIM_F32, MLS_T_PAIR, pv, nb);
+    HostPhase f64 = make_phase<PairArgs>(BK_PAIR_TRIM_F64, MLS_T_PAIR, pv, nb);
+    HostPhase gen = make_phase<PairArgs>(BK_PAIR_GENERIC, MLS_T_PAIR, pv, nb);
+    HostPhase wav = make_phase<PairArgs>(BK_PAIR_WAVE, MLS_T_PAIR, pv, nb);
     for (int b : order) {
       mls_plan_s* P = B->plans[b];
       const int n = n_of(b);
       if (n == 0) continue;
       const CellGeom& g = P->cg;
-      PairConst pc{P->a2, P->inv_a2, P->inv_a6, P->inv_a8};
-      PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pc, P->d_e0, P->d_floc};
+      PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const(P), P->d_e0, P->d_floc};
       if (mixed && P->pair_fast && n < (1 << 24)) {
-        PairConstF pf{(float)P->a2, (float)P->inv_a2, (float)P->inv_a6, (float)P->inv_a8,
-                      {(float)g.w[0], (float)g.w[1], (float)g.w[2]}};
-        set_box(f32, b, PairArgsF{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pf,
+        set_box(f32, b, PairArgsF{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const_f(P),
                                   P->d_e0, P->d_floc}, nblk(n, 64));
       } else if (P->pair_fast && n < (1 << 25)) {
         set_box(f64, b, a, nblk(n, 64));
@@ -508,8 +506,10 @@ mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* 
       set_error("mls_batch_create: box " + std::to_string(b) + " atom count outside [0, 2^30]");
       return MLS_ERR_INVALID_ARG;
     }
-    if (per_box[b].precision != per_box[0].precision || per_box[b].order != per_box[0].order) {
-      set_error("mls_batch_create: all boxes must share precision and order");
+    if (per_box[b].precision != per_box[0].precision || per_box[b].order != per_box[0].order ||
+        (per_box[b].continuity == 0 ? 2 : per_box[b].continuity) !=
+            (per_box[0].continuity == 0 ? 2 : per_box[0].continuity)) {
+      set_error("mls_batch_create: all boxes must share precision, order and continuity");
       return MLS_ERR_INVALID_ARG;
     }
     total += n_per_box[b];

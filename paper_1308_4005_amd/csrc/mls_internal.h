@@ -84,13 +84,17 @@ struct AntGeom {
   int nh[3];
 };
 
+// gc[j]: gamma_k = sum_j gc[j] v^j with v = rho^12 (zero beyond k);
+// gq[j] = 12 (j + 1) gc[j + 1]: gamma_k'(rho) / rho = rho^10 sum_j gq[j] v^j.
 struct PairConst {
   double a2, inv_a2, inv_a6, inv_a8;
+  double gc[5], gq[4];
 };
 
 struct PairConstF {
   float a2, inv_a2, inv_a6, inv_a8;
   float w[3];
+  float gc[5], gq[4];
 };
 
 struct OutPtrs {
@@ -213,6 +217,8 @@ struct mls_plan_s {
   int order = 4;
   int precision = 0;
   double a = 0, a2 = 0, inv_a2 = 0, inv_a6 = 0, inv_a8 = 0, cself = 0;
+  int continuity = 2;              // k of the smoothing function gamma_k
+  double gamma_c[5]{};             // gamma_k inside the unit ball: sum_j gamma_c[j] rho^(12 j)
   mls::CellGeom cg{};
   double invh1[3]{};               // n_1 / L
   std::vector<mls::Level> lv;      // index k-1 for level k
@@ -316,6 +322,12 @@ hipError_t launch_copy_stage(mls_plan_s* P, int what, int level, void* dst, hipS
 bool anterp_owned_geom(const mls_plan_s* P, AntGeom& ag);
 // z extent candidates of a stencil tile for window R
 bool stencil_tile_ok(int R, int zc);
+
+// constants of the pair kernels (pair.hip) and their template variant (2:
+// eq:gamma folded in, 0: any member of the smoothing family)
+PairConst pair_const(const mls_plan_s* P);
+PairConstF pair_const_f(const mls_plan_s* P);
+int pair_variant(const mls_plan_s* P);
 
 // batched launchers: one phase of a batched evaluation (per kernel file)
 hipError_t launch_batched_binning(const BatchPhase& ph, hipStream_t s);

@@ -29,23 +29,42 @@ __device__ __forceinline__ float recip(float s) {
   return fmaf(fmaf(-s, r, 1.0f), r, r);
 }
 
-template <class T>
-__device__ __forceinline__ void g0_pair(T s, T inv_a2, T inv_a6, T inv_a8, T& g, T& fr) {
+// g_0(r) and g_0'(r)/r from s = r^2 (caller guarantees 0 < s < a^2), with
+// rho = r/a and v = rho^12:
+//   g_0     = r^-6 - a^-6 gamma_k(rho),            gamma_k = sum_j gc[j] v^j
+//   g_0'/r  = -6 r^-8 - a^-8 rho^10 sum_j gq[j] v^j
+// K = 2 is eq:gamma with its constants folded in; K = 0 takes any member of
+// the family (k <= 4) from the plan's coefficients, zero-padded to degree 4.
+template <class T, int K, class C>
+__device__ __forceinline__ void g0_pair(T s, const C& pc, T& g, T& fr) {
   T ir2 = recip(s);
   T ir6 = ir2 * ir2 * ir2;
-  T u = s * inv_a2;            // rho^2
+  T u = s * pc.inv_a2;         // rho^2
   T u2 = u * u;
   T u4 = u2 * u2;
   T u5 = u4 * u;
   T u6 = u4 * u2;
-  T u11 = u6 * u5;
-  T u12 = u6 * u6;
-  g = ir6 - inv_a6 * (T(15.0 / 8.0) + u6 * (T(-5.0 / 4.0) + T(3.0 / 8.0) * u6));
-  fr = T(-6) * ir6 * ir2 + inv_a8 * (T(15) * u5 - T(9) * u11);
-  (void)u12;
+  if constexpr (K == 2) {
+    T u11 = u6 * u5;
+    g = ir6 - pc.inv_a6 * (T(15.0 / 8.0) + u6 * (T(-5.0 / 4.0) + T(3.0 / 8.0) * u6));
+    fr = T(-6) * ir6 * ir2 + pc.inv_a8 * (T(15) * u5 - T(9) * u11);
+  } else {
+    T P = pc.gc[4];
+    P = fma(P, u6, pc.gc[3]);
+    P = fma(P, u6, pc.gc[2]);
+    P = fma(P, u6, pc.gc[1]);
+    P = fma(P, u6, pc.gc[0]);
+    T Q = pc.gq[3];
+    Q = fma(Q, u6, pc.gq[2]);
+    Q = fma(Q, u6, pc.gq[1]);
+    Q = fma(Q, u6, pc.gq[0]);
+    g = ir6 - pc.inv_a6 * P;
+    fr = T(-6) * ir6 * ir2 - pc.inv_a8 * u5 * Q;
+  }
 }
 
 // FP64: one thread per cell-sorted target atom.
+template <int K>
 struct PairGeneric {
   using Args = PairArgs;
   static constexpr int kThreads = kBlock;
@@ -85,7 +104,7 @@ struct PairGeneric {
             const double r2 = dx * dx + dy * dy + dz * dz;
             if (r2 < pc.a2 && !(home && j == s)) {
               double gg, fr;
-              g0_pair<double>(r2, pc.inv_a2, pc.inv_a6, pc.inv_a8, gg, fr);
+              g0_pair<double, K>(r2, pc, gg, fr);
               e += xj.w * gg;
               const double f = xj.w * fr;
               fx += f * dx;
@@ -109,6 +128,7 @@ struct PairGeneric {
 // atoms (a run ends where the periodic image changes) and its 64 lanes split
 // each run; the lane sums are added in LDS.  Same cells, images and pairs as
 // PairGeneric.
+template <int K>
 struct PairWave {
   using Args = PairArgs;
   static constexpr int kThreads = 64;
@@ -150,7 +170,7 @@ struct PairWave {
             const double r2 = dx * dx + dy * dy + dz * dz;
             if (r2 < pc.a2 && !(home && j == s)) {
               double gg, fr;
-              g0_pair<double>(r2, pc.inv_a2, pc.inv_a6, pc.inv_a8, gg, fr);
+              g0_pair<double, K>(r2, pc, gg, fr);
               e += xj.w * gg;
               const double f = xj.w * fr;
               fx += f * dx;
@@ -203,6 +223,7 @@ struct PairAcc {
   int cnt;
 };
 
+template <int K>
 __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, int cnt, int lane, int self_ent,
                                                const double4& xi, const double4* __restrict__ xs, const CellGeom& g,
                                                const PairConst& pc, PairAcc& A) {
@@ -220,7 +241,7 @@ __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, in
       const double dz = (xi.z - sz) - xj.z;
       const double r2 = dx * dx + dy * dy + dz * dz;
       double gg, fr;
-      g0_pair<double>(r2, pc.inv_a2, pc.inv_a6, pc.inv_a8, gg, fr);
+      g0_pair<double, K>(r2, pc, gg, fr);
       A.e += xj.w * gg;
       const double f = xj.w * fr;
       A.fx += f * dx;
@@ -234,6 +255,7 @@ __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, in
 // calls it; lanes with an empty range just take part in the votes).  Reads
 // may run up to kBatch - 1 rows past j1: the sorted array is padded with
 // far-away rows, and rows past j1 are never kept.
+template <int K>
 __device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int* __restrict__ queue, int lane,
                                               int self_ent, const double4& xi, const double4* __restrict__ xs,
                                               const CellGeom& g, const PairConst& pc, PairAcc& A) {
@@ -258,7 +280,7 @@ __device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int* __res
     // within the padding however long other lanes keep scanning
     j += j < j1 ? kBatch : 0;
     if (__any(A.cnt > kQueue - kBatch)) {
-      pair_drain_f64(queue, A.cnt, lane, self_ent, xi, xs, g, pc, A);
+      pair_drain_f64<K>(queue, A.cnt, lane, self_ent, xi, xs, g, pc, A);
       A.cnt = 0;
     }
   }
@@ -268,6 +290,7 @@ __device__ __forceinline__ double gap1(double x, double lo, double w, double eps
   return fmax(0.0, fmax(lo - x, x - (lo + w)) - eps);
 }
 
+template <int K>
 struct PairTrimF64 {
   using Args = PairArgs;
   static constexpr int kThreads = kWaveQ;
@@ -327,11 +350,11 @@ struct PairTrimF64 {
         k0 = cstart[row + lo2];
         k1 = cstart[row + hi2 + 1];
       }
-      pair_scan_f64(j0, j1, image_bits(ix1, iy, iz), queue, lane, self_ent, xi, xs, g, pc, A);
-      pair_scan_f64(k0, k1, image_bits(ix2, iy, iz), queue, lane, self_ent, xi, xs, g, pc, A);
+      pair_scan_f64<K>(j0, j1, image_bits(ix1, iy, iz), queue, lane, self_ent, xi, xs, g, pc, A);
+      pair_scan_f64<K>(k0, k1, image_bits(ix2, iy, iz), queue, lane, self_ent, xi, xs, g, pc, A);
     }
   }
-  pair_drain_f64(queue, A.cnt, lane, self_ent, xi, xs, g, pc, A);
+  pair_drain_f64<K>(queue, A.cnt, lane, self_ent, xi, xs, g, pc, A);
   if (active) {
     ar.e0[sc] = A.e;
     ar.floc[3 * (size_t)sc + 0] = xi.w * A.fx;
@@ -358,6 +381,7 @@ struct PairAccM {
 
 __device__ __forceinline__ int entry_bits(int ix, int dy, int dz) { return (ix + 1) | ((dy + 2) << 2) | ((dz + 2) << 5); }
 
+template <int K>
 __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, int cnt, int lane, int self_ent,
                                                const float4& xi, int cxi, const float4* __restrict__ xr,
                                                const float* __restrict__ xif, const CellGeom& g,
@@ -374,7 +398,7 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
       const float dzv = fmaf((float)-dz, pc.w[2], xi.z) - xj.z;
       const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
       float gg, fr;
-      g0_pair<float>(r2, pc.inv_a2, pc.inv_a6, pc.inv_a8, gg, fr);
+      g0_pair<float, K>(r2, pc, gg, fr);
       const float wj = xif[j];
       A.e += (double)(wj * gg);
       const float f = wj * fr;
@@ -385,6 +409,7 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
   }
 }
 
+template <int K>
 __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int dz, int* __restrict__ queue,
                                               int lane, int self_ent, const float4& xi, int cxi,
                                               const float4* __restrict__ xr, const float* __restrict__ xif,
@@ -409,12 +434,13 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
     }
     j += j < j1 ? kBatch : 0;
     if (__any(A.cnt > kQueue - kBatch)) {
-      pair_drain_f32(queue, A.cnt, lane, self_ent, xi, cxi, xr, xif, g, pc, A);
+      pair_drain_f32<K>(queue, A.cnt, lane, self_ent, xi, cxi, xr, xif, g, pc, A);
       A.cnt = 0;
     }
   }
 }
 
+template <int K>
 struct PairTrimF32 {
   using Args = PairArgsF;
   static constexpr int kThreads = kWaveQ;
@@ -474,11 +500,11 @@ struct PairTrimF32 {
         k0 = cstart[row + lo2];
         k1 = cstart[row + hi2 + 1];
       }
-      pair_scan_f32(j0, j1, ix1, dy, dz, queue, lane, self_ent, xi, cx, xr, xif, g, pc, A);
-      pair_scan_f32(k0, k1, ix2, dy, dz, queue, lane, self_ent, xi, cx, xr, xif, g, pc, A);
+      pair_scan_f32<K>(j0, j1, ix1, dy, dz, queue, lane, self_ent, xi, cx, xr, xif, g, pc, A);
+      pair_scan_f32<K>(k0, k1, ix2, dy, dz, queue, lane, self_ent, xi, cx, xr, xif, g, pc, A);
     }
   }
-  pair_drain_f32(queue, A.cnt, lane, self_ent, xi, cx, xr, xif, g, pc, A);
+  pair_drain_f32<K>(queue, A.cnt, lane, self_ent, xi, cx, xr, xif, g, pc, A);
   if (active) {
     const double wi = (double)xif[sc];
     ar.e0[sc] = A.e;
@@ -491,30 +517,57 @@ struct PairTrimF32 {
 
 }  // namespace
 
-hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  PairConst pc{P->a2, P->inv_a2, P->inv_a6, P->inv_a8};
-  const CellGeom& g = P->cg;
-  if (P->precision == MLS_MIXED && P->pair_fast && n < (1 << 24)) {
-    PairConstF pf{(float)P->a2, (float)P->inv_a2, (float)P->inv_a6, (float)P->inv_a8,
-                  {(float)g.w[0], (float)g.w[1], (float)g.w[2]}};
-    PairArgsF a{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pf, P->d_e0, P->d_floc};
-    return launch_one<PairTrimF32>(a, (n + kWaveQ - 1) / kWaveQ, s);
-  }
-  PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pc, P->d_e0, P->d_floc};
-  if (P->pair_fast && n < (1 << 25)) return launch_one<PairTrimF64>(a, (n + kWaveQ - 1) / kWaveQ, s);
-  if (!P->pair_fast) return launch_one<PairWave>(a, n, s);
-  return launch_one<PairGeneric>(a, (n + kBlock - 1) / kBlock, s);
+PairConst pair_const(const mls_plan_s* P) {
+  PairConst pc{P->a2, P->inv_a2, P->inv_a6, P->inv_a8, {}, {}};
+  for (int j = 0; j < 5; ++j) pc.gc[j] = P->gamma_c[j];
+  for (int j = 0; j < 4; ++j) pc.gq[j] = 12.0 * (j + 1) * P->gamma_c[j + 1];
+  return pc;
 }
 
-hipError_t launch_batched_pair(const BatchPhase& ph, hipStream_t s) {
+PairConstF pair_const_f(const mls_plan_s* P) {
+  const PairConst pc = pair_const(P);
+  PairConstF pf{(float)pc.a2, (float)pc.inv_a2, (float)pc.inv_a6, (float)pc.inv_a8,
+                {(float)P->cg.w[0], (float)P->cg.w[1], (float)P->cg.w[2]}, {}, {}};
+  for (int j = 0; j < 5; ++j) pf.gc[j] = (float)pc.gc[j];
+  for (int j = 0; j < 4; ++j) pf.gq[j] = (float)pc.gq[j];
+  return pf;
+}
+
+int pair_variant(const mls_plan_s* P) { return P->continuity == 2 ? 2 : 0; }
+
+template <int K>
+hipError_t launch_pair_k(mls_plan_s* P, int n, hipStream_t s) {
+  const CellGeom& g = P->cg;
+  if (P->precision == MLS_MIXED && P->pair_fast && n < (1 << 24)) {
+    PairArgsF a{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const_f(P), P->d_e0,
+                P->d_floc};
+    return launch_one<PairTrimF32<K>>(a, (n + kWaveQ - 1) / kWaveQ, s);
+  }
+  PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const(P), P->d_e0, P->d_floc};
+  if (P->pair_fast && n < (1 << 25)) return launch_one<PairTrimF64<K>>(a, (n + kWaveQ - 1) / kWaveQ, s);
+  if (!P->pair_fast) return launch_one<PairWave<K>>(a, n, s);
+  return launch_one<PairGeneric<K>>(a, (n + kBlock - 1) / kBlock, s);
+}
+
+hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  return pair_variant(P) == 2 ? launch_pair_k<2>(P, n, s) : launch_pair_k<0>(P, n, s);
+}
+
+template <int K>
+hipError_t launch_batched_pair_k(const BatchPhase& ph, hipStream_t s) {
   switch (ph.kernel) {
-    case BK_PAIR_GENERIC: return launch_batched_phase<PairGeneric>(ph, s);
-    case BK_PAIR_WAVE: return launch_batched_phase<PairWave>(ph, s);
-    case BK_PAIR_TRIM_F64: return launch_batched_phase<PairTrimF64>(ph, s);
-    case BK_PAIR_TRIM_F32: return launch_batched_phase<PairTrimF32>(ph, s);
+    case BK_PAIR_GENERIC: return launch_batched_phase<PairGeneric<K>>(ph, s);
+    case BK_PAIR_WAVE: return launch_batched_phase<PairWave<K>>(ph, s);
+    case BK_PAIR_TRIM_F64: return launch_batched_phase<PairTrimF64<K>>(ph, s);
+    case BK_PAIR_TRIM_F32: return launch_batched_phase<PairTrimF32<K>>(ph, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Batched phases of this file; variant = the pair_variant of its boxes.
+hipError_t launch_batched_pair(const BatchPhase& ph, hipStream_t s) {
+  return ph.variant == 2 ? launch_batched_pair_k<2>(ph, s) : launch_batched_pair_k<0>(ph, s);
 }
 
 }  // namespace mls

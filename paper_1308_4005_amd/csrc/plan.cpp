@@ -17,24 +17,47 @@
 namespace mls {
 namespace {
 
-// Smoothing function of eq:gamma.
-double gamma_s(double rho) {
-  if (rho < 1.0) {
-    double u = std::pow(rho, 12);
-    return 15.0 / 8.0 + u * (-5.0 / 4.0 + u * (3.0 / 8.0));
+// binom(-1/2, m): coefficient m of the series of (1 + u)^(-1/2).
+double binom_half(int m) {
+  double c = 1.0;
+  for (int j = 0; j < m; ++j) c *= (-0.5 - j) / (j + 1);
+  return c;
+}
+
+// Smoothing function gamma_k: rho^-6 from rho = 1 on; inside, the order-k
+// Taylor polynomial of (1 + u)^(-1/2) in u = rho^12 - 1 (C^k at rho = 1, the
+// family of Sec. III.B); k = 2 is eq:gamma, evaluated as printed.
+double gamma_s(double rho, int k) {
+  if (rho >= 1.0) return std::pow(rho, -6);
+  const double v = std::pow(rho, 12);
+  if (k == 2) return 15.0 / 8.0 + v * (-5.0 / 4.0 + v * (3.0 / 8.0));
+  double sum = 0.0, um = 1.0;
+  for (int m = 0; m <= k; ++m, um *= v - 1.0) sum += binom_half(m) * um;
+  return sum;
+}
+
+// gamma_k inside the unit ball as a polynomial in v = rho^12:
+// c_j = sum_{m >= j} binom(-1/2, m) C(m, j) (-1)^(m - j).
+void gamma_coeffs(int k, double* c) {
+  for (int j = 0; j <= 4; ++j) c[j] = 0.0;
+  for (int m = 0; m <= k; ++m) {
+    double cmj = 1.0;   // C(m, j)
+    for (int j = 0; j <= m; ++j) {
+      c[j] += binom_half(m) * cmj * (((m - j) & 1) ? -1.0 : 1.0);
+      cmj = cmj * (m - j) / (j + 1);
+    }
   }
-  return std::pow(rho, -6);
 }
 
 // Level-1 kernel of eq:g_k (k = 1): a^-6 gamma(s/a) - (2a)^-6 gamma(s/2a),
 // zero from 2a on.
-double g_level1(double s, double a) {
+double g_level1(double s, double a, int k) {
   if (s >= 2.0 * a) return 0.0;
-  return std::pow(a, -6) * gamma_s(s / a) - std::pow(2.0 * a, -6) * gamma_s(s / (2.0 * a));
+  return std::pow(a, -6) * gamma_s(s / a, k) - std::pow(2.0 * a, -6) * gamma_s(s / (2.0 * a), k);
 }
 
 // Coarsest kernel eq:g_l with A = 2^(l-1) a.
-double g_coarsest(double r, double A) { return std::pow(A, -6) * gamma_s(r / A); }
+double g_coarsest(double r, double A, int k) { return std::pow(A, -6) * gamma_s(r / A, k); }
 
 // ---------------------------------------------------------------------------
 // Periodic r^-6 lattice sum  S(v) = sum_{n: v + nL != 0} |v + n o L|^-6.
@@ -134,6 +157,8 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   if (p.levels < 0 || p.levels > 16) { set_error("levels must be in [0, 16]"); return MLS_ERR_INVALID_ARG; }
   if (p.precision != MLS_FP64 && p.precision != MLS_MIXED) { set_error("precision must be MLS_FP64 or MLS_MIXED"); return MLS_ERR_INVALID_ARG; }
   if (n_max < 0 || n_max > (int64_t)1 << 30) { set_error("n_max must be in [0, 2^30]"); return MLS_ERR_INVALID_ARG; }
+  const int cont = p.continuity == 0 ? 2 : p.continuity;
+  if (cont < 1 || cont > 4) { set_error("continuity must be 1..4 (0 means 2)"); return MLS_ERR_INVALID_ARG; }
 
   P->params = p;
   P->order = p.order;
@@ -144,7 +169,9 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   P->inv_a2 = 1.0 / P->a2;
   P->inv_a6 = std::pow(p.cutoff, -6);
   P->inv_a8 = std::pow(p.cutoff, -8);
-  P->cself = gamma_s(0.0) * P->inv_a6;  // eq:self-interaction-energy
+  P->continuity = cont;
+  gamma_coeffs(cont, P->gamma_c);
+  P->cself = gamma_s(0.0, cont) * P->inv_a6;  // eq:self-interaction-energy
   hipGetDevice(&P->device);
 
   // ---------------------------------------------------------------- levels
@@ -229,7 +256,7 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
           double sx = dx * h1[0], sy = dy * h1[1], sz = dz * h1[2];
           double s2 = sx * sx + sy * sy + sz * sz;
           if (s2 >= lim) continue;
-          Tap t{dx, dy, dz, 0, g_level1(std::sqrt(s2), p.cutoff)};
+          Tap t{dx, dy, dz, 0, g_level1(std::sqrt(s2), p.cutoff, cont)};
           P->taps.push_back(t);
           P->taps_wsum += t.w;
           P->stencil_R[0] = std::max(P->stencil_R[0], std::abs(dx));
@@ -244,7 +271,7 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
         while (std::pow((hz + 1) * h1[2], 2) + base < lim) ++hz;
         StencilRow r{dx, dy, hz, (int)P->row_w.size()};
         for (int dz = 0; dz <= hz; ++dz)
-          P->row_w.push_back(g_level1(std::sqrt(std::pow(dz * h1[2], 2) + base), p.cutoff));
+          P->row_w.push_back(g_level1(std::sqrt(std::pow(dz * h1[2], 2) + base), p.cutoff, cont));
         P->rows.push_back(r);
       }
   }
@@ -311,8 +338,8 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
               for (int ix = -nimg[0]; ix <= nimg[0]; ++ix) {
                 double rx = v[0] + ix * p.box[0], ry = v[1] + iy * p.box[1], rz = v[2] + iz * p.box[2];
                 double r = std::sqrt(rx * rx + ry * ry + rz * rz);
-                if (r == 0.0) K += g_coarsest(0.0, A);
-                else if (r < A) K += g_coarsest(r, A) - std::pow(r, -6);
+                if (r == 0.0) K += g_coarsest(0.0, A, cont);
+                else if (r < A) K += g_coarsest(r, A, cont) - std::pow(r, -6);
               }
           P->Kl[(size_t)(z * C.g.n[1] + y) * C.g.n[0] + x] = K;
         }

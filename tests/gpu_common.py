@@ -12,12 +12,12 @@ def say(msg):
     sys.stdout.flush()
 
 
-def gpu_eval(pos, c6, box, a, h, order, levels, precision="fp64", grid=None, n_max=None):
+def gpu_eval(pos, c6, box, a, h, order, levels, precision="fp64", grid=None, n_max=None, continuity=2):
     import torch
     from paper_1308_4005_amd import Plan
     n = len(pos)
     plan = Plan(box, a, h, order, levels, grid=grid, precision=precision,
-                n_max=n if n_max is None else n_max)
+                n_max=n if n_max is None else n_max, continuity=continuity)
     tp = torch.tensor(np.ascontiguousarray(pos), dtype=torch.float64, device="cuda")
     tc = torch.tensor(np.ascontiguousarray(c6), dtype=torch.float64, device="cuda")
     res = plan.evaluate(tp, tc, forces=True, potential=True, dE_dc6=True)
