@@ -18,14 +18,16 @@ import numpy as np
 
 from .lattice import ewald_fhat
 
-__all__ = ["exact_ewald", "exact_direct"]
+__all__ = ["ewald_field", "exact_ewald", "exact_ewald_lb", "exact_direct"]
 
 
-def exact_ewald(pos, c6, box, beta=None, tol=1e-16, chunk=2048):
-    """E*, F*, and the per-atom potential u*_i = sum' xi_j r^-6 by Ewald."""
+def ewald_field(pos, w, box, beta=None, tol=1e-16, chunk=2048):
+    """Potential u_i = sum'_{(j,n)} w_j |x_i - x_j - n o L|^-6 of source
+    weights w at every atom, and g_i = sum' w_j (dphi/dr / r)(x_i - x_j - n o L),
+    so that an atom of weight v_i feels the force v_i g_i.  Ewald split."""
     pos = np.asarray(pos, dtype=np.float64)
     box = np.asarray(box, dtype=np.float64)
-    xi = np.sqrt(np.asarray(c6, dtype=np.float64))
+    w = np.asarray(w, dtype=np.float64)
     n = len(pos)
     V = float(np.prod(box))
     if beta is None:
@@ -34,7 +36,7 @@ def exact_ewald(pos, c6, box, beta=None, tol=1e-16, chunk=2048):
     rc = math.sqrt(-math.log(tol)) / beta
     nr = np.ceil(rc / box).astype(int) + 1
     u = np.zeros(n)
-    F = np.zeros((n, 3))
+    g = np.zeros((n, 3))
     for i0 in range(0, n, chunk):
         i1 = min(n, i0 + chunk)
         for nx in range(-nr[0], nr[0] + 1):
@@ -56,9 +58,9 @@ def exact_ewald(pos, c6, box, beta=None, tol=1e-16, chunk=2048):
                     r = np.sqrt(r2m)
                     dphi = np.where(m, -6.0 * ex * (1.0 + x + 0.5 * x * x) / r ** 7
                                     - beta ** 6 * ex / r, 0.0)
-                    u[i0:i1] += phi @ xi
-                    coef = dphi / r * xi[None, :]
-                    F[i0:i1] += xi[i0:i1, None] * np.einsum("ij,ijk->ik", coef, d)
+                    u[i0:i1] += phi @ w
+                    coef = dphi / r * w[None, :]
+                    g[i0:i1] += np.einsum("ij,ijk->ik", coef, d)
     # ---- reciprocal space
     kc = 2.0 * beta * math.sqrt(-math.log(tol))
     nk = np.ceil(kc * box / (2.0 * math.pi)).astype(int)
@@ -74,17 +76,42 @@ def exact_ewald(pos, c6, box, beta=None, tol=1e-16, chunk=2048):
         f = fh[k0:k0 + 512]
         ph = pos @ kv.T                                # (n, K)
         c, s = np.cos(ph), np.sin(ph)
-        Sc = xi @ c                                    # Re S(k)
-        Ss = xi @ s                                    # Im S(k)
+        Sc = w @ c                                     # Re S(k)
+        Ss = w @ s                                     # Im S(k)
         # u_i gets (1/V) sum_k fhat Re(e^{-ik x_i} S(k))
         u += (c * Sc + s * Ss) @ f / V
-        # F_i = -(xi_i / V) sum_k fhat k sum_j xi_j sin(k.(x_i - x_j))
-        sinterm = s * Sc - c * Ss                       # sum_j xi_j sin(k.(x_i-x_j))
-        F -= xi[:, None] * ((sinterm * f) @ kv) / V
+        # g_i = -(1/V) sum_k fhat k sum_j w_j sin(k.(x_i - x_j))
+        sinterm = s * Sc - c * Ss                       # sum_j w_j sin(k.(x_i-x_j))
+        g -= ((sinterm * f) @ kv) / V
     # remove the r = 0 term of the smooth part
-    u -= beta ** 6 / 6.0 * xi
+    u -= beta ** 6 / 6.0 * w
+    return u, g
+
+
+def exact_ewald(pos, c6, box, beta=None, tol=1e-16, chunk=2048):
+    """E*, F*, and the per-atom potential u*_i = sum' xi_j r^-6 by Ewald."""
+    xi = np.sqrt(np.asarray(c6, dtype=np.float64))
+    u, g = ewald_field(pos, xi, box, beta, tol, chunk)
     E = -0.5 * float(np.dot(xi, u))
-    return E, F, u
+    return E, xi[:, None] * g, u
+
+
+def exact_ewald_lb(pos, eps, sigma, box, beta=None, tol=1e-16):
+    """E* and F* under Lorentz-Berthelot mixing (Sec. II.D): pair coefficient
+    C_ij = 2 sqrt(eps_i eps_j) ((sigma_i + sigma_j) / 2)^6, written as the
+    bilinear sum over the seven charge vectors
+    xi_{i,k} = sigma_i^k sqrt(binom(6, k) 2 eps_i) / 8 paired k with 6 - k."""
+    eps = np.asarray(eps, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    xi = [sigma ** k * np.sqrt(math.comb(6, k) * 2.0 * eps) / 8.0 for k in range(7)]
+    fields = [ewald_field(pos, xi[m], box, beta, tol) for m in range(7)]
+    E = 0.0
+    F = np.zeros((len(eps), 3))
+    for k in range(7):
+        u, g = fields[6 - k]
+        E += -0.5 * float(np.dot(xi[k], u))
+        F += xi[k][:, None] * g
+    return E, F
 
 
 def exact_direct(pos, c6, box, R):

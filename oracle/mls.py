@@ -46,6 +46,7 @@ __all__ = [
     "local_part", "local_part_bruteforce", "anterpolate", "restrict",
     "prolong", "restriction_weights", "stencil_taps", "level_eval",
     "coarsest_kernel", "coarsest_eval", "interpolate", "mls",
+    "lb_charges", "lb_pair_coefficient", "local_part_lb", "mls_lb",
 ]
 
 # --------------------------------------------------------------------------
@@ -590,3 +591,112 @@ def mls(pos, c6, box, a, h, order=4, levels=0, grid=None, beta=None, continuity=
         dE_dc6 = dE_dxi / (2.0 * xi)
     return dict(energy=float(energy), F=F, u=u, dE_dc6=dE_dc6, e0=e0, Floc=Floc,
                 q=q, e=e, E=E, K=K, n1=n1, h1=h1, levels=l, xw=xw)
+
+
+# --------------------------------------------------------------------------
+# Lorentz-Berthelot mixing (Sec. II.D)
+# --------------------------------------------------------------------------
+
+
+def lb_pair_coefficient(eps_i, eps_j, sig_i, sig_j):
+    """C_ij = 2 eps_ij sigma_ij^6 (eq:xi-lj) with eps_ij = sqrt(eps_i eps_j)
+    and sigma_ij = (sigma_i + sigma_j) / 2."""
+    return 2.0 * np.sqrt(eps_i * eps_j) * ((sig_i + sig_j) / 2.0) ** 6
+
+
+def lb_charges(eps, sigma):
+    """The seven charge vectors of eq:disp-pair-pot-multilevel-LorentzBerthelot,
+    xi_{i,k} = sigma_i^k sqrt(binom(6, k) 2 eps_i) / 8, k = 0..6 (row k); the
+    energy pairs vector k with vector 6 - k (the printed index k - 6 read as
+    6 - k: only then does sum_k xi_{i,k} xi_{j,6-k} equal C_ij)."""
+    eps = np.asarray(eps, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    return np.stack([sigma ** k * np.sqrt(math.comb(6, k) * 2.0 * eps) / 8.0 for k in range(7)])
+
+
+def local_part_lb(xw, eps, sigma, box, a, cont=2):
+    """l_i = sum_{(j,n) != (i,0), r<a} C_ij g_0(r) and
+    F_i = sum C_ij g_0'(r)/r d over all images, with the Lorentz-Berthelot
+    pair coefficient (same cells and images as ``local_part``)."""
+    box = np.asarray(box, dtype=np.float64)
+    n = len(xw)
+    nc, cid, cell_start, perm = bin_cells(xw, box, a)
+    w = box / nc
+    noff = np.maximum(np.ceil(a / w - 1e-12).astype(np.int64), 1)
+    c3 = np.stack([cid % nc[0], (cid // nc[0]) % nc[1], cid // (nc[0] * nc[1])], axis=1)
+    counts = np.diff(cell_start)
+    ell = np.zeros(n)
+    F = np.zeros((n, 3))
+    a2 = a * a
+    for ox in range(-noff[0], noff[0] + 1):
+        for oy in range(-noff[1], noff[1] + 1):
+            for oz in range(-noff[2], noff[2] + 1):
+                t3 = c3 + np.array([ox, oy, oz])
+                img = np.floor_divide(t3, nc)
+                t3 = t3 - img * nc
+                tcell = (t3[:, 2] * nc[1] + t3[:, 1]) * nc[0] + t3[:, 0]
+                shift = img * box
+                cnt = counts[tcell]
+                tot = int(cnt.sum())
+                if tot == 0:
+                    continue
+                i_idx = np.repeat(np.arange(n), cnt)
+                rel = np.arange(tot) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+                j_idx = perm[np.repeat(cell_start[tcell], cnt) + rel]
+                d = xw[i_idx] - (xw[j_idx] + shift[i_idx])
+                r2 = np.einsum("ij,ij->i", d, d)
+                self_pair = (i_idx == j_idx) & np.all(img[i_idx] == 0, axis=1)
+                keep = (r2 < a2) & ~self_pair
+                i_idx, j_idx, d, r2 = i_idx[keep], j_idx[keep], d[keep], r2[keep]
+                r = np.sqrt(r2)
+                C = lb_pair_coefficient(eps[i_idx], eps[j_idx], sigma[i_idx], sigma[j_idx])
+                ell += np.bincount(i_idx, weights=C * g0(r, a, cont), minlength=n)
+                coef = C * dg0(r, a, cont) / r
+                for dim in range(3):
+                    F[:, dim] += np.bincount(i_idx, weights=coef * d[:, dim], minlength=n)
+    return ell, F
+
+
+def mls_lb(pos, eps, sigma, box, a, h, order=4, levels=0, grid=None, beta=None, continuity=2):
+    """One MLS evaluation under Lorentz-Berthelot mixing (Sec. II.D): the
+    local part with the exact pair coefficient C_ij, and the grid part run
+    once per charge vector xi_k (seven instances of the same linear grid
+    operations), the potential of vector 6 - k interpolated at the atoms and
+    weighted with xi_k:
+        E = -1/2 [ sum_i l_i + sum_k sum_i xi_{i,k} u^(6-k)_i - gamma(0) a^-6 sum_i C_ii ],
+        F_i = F^loc_i + sum_k xi_{i,k} grad u^(6-k)(x_i).
+    """
+    pos = np.asarray(pos, dtype=np.float64)
+    eps = np.asarray(eps, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    if levels in (0, None):
+        levels = resolve_levels(box, h, order)
+    l = int(levels)
+    cont = int(continuity)
+    n1, h1 = resolve_grid(box, h, l, grid)
+    xw = wrap(pos, box)
+    xi = lb_charges(eps, sigma)
+    ell, Floc = local_part_lb(xw, eps, sigma, box, a, cont)
+    n_l = n1 // 2 ** (l - 1)
+    K = coarsest_kernel(box, n_l, a, l, beta=beta, cont=cont)
+    ug, grad = [], []
+    for k in range(7):
+        q = [anterpolate(xw, xi[k], box, n1, order)]
+        for j in range(2, l + 1):
+            q.append(restrict(q[-1], order))
+        e = [level_eval(q[j - 1], j, h1, a, cont) for j in range(1, l)]
+        e.append(coarsest_eval(q[l - 1], K))
+        E = e[l - 1]
+        for j in range(l - 1, 0, -1):
+            E = prolong(E, e[j - 1], order)
+        u_k, g_k = interpolate(xw, E, box, n1, order)
+        ug.append(u_k)
+        grad.append(g_k)
+    phi = sum(xi[k] * ug[6 - k] for k in range(7))
+    F = Floc + sum(xi[k][:, None] * grad[6 - k] for k in range(7))
+    Cii = 2.0 * eps * sigma ** 6
+    cself = gamma(np.zeros(1), cont)[0] / a ** 6
+    energy = -0.5 * (np.sum(ell) + np.sum(phi) - cself * np.sum(Cii))
+    return dict(energy=float(energy), F=F, ell=ell, Floc=Floc, phi=phi, xi=xi, levels=l, n1=n1)
+
