@@ -188,6 +188,41 @@ def time_batched(ws, precision, steps, warmup, dev):
             "tuning": tuning}
 
 
+def time_lb(w, prm, steps, warmup, dev):
+    """Lorentz-Berthelot mixing (mls_evaluate_lb, FP64) on the same positions
+    with two species drawn 50/50 (seed 17): epsilon in {1.0, 0.6}, sigma in
+    {1.0, 1.25}."""
+    import numpy as np
+    import torch
+    from paper_1308_4005_amd import Plan, Result
+    rng = np.random.default_rng(17)
+    eps = np.where(rng.uniform(size=w.n) < 0.5, 1.0, 0.6)
+    sig = np.where(rng.uniform(size=w.n) < 0.5, 1.0, 1.25)
+    plan = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], n_max=w.n, device=dev.index,
+                mixing="lorentz-berthelot")
+    pos = torch.tensor(w.pos, dtype=torch.float64, device=dev)
+    te = torch.tensor(eps, dtype=torch.float64, device=dev)
+    ts = torch.tensor(sig, dtype=torch.float64, device=dev)
+    out = Result(torch.empty(1, dtype=torch.float64, device=dev),
+                 torch.empty((w.n, 3), dtype=torch.float64, device=dev))
+    for _ in range(warmup):
+        plan.evaluate_lb(pos, te, ts, out=out)
+    stream = torch.cuda.current_stream(dev)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(steps):
+        plan.evaluate_lb(pos, te, ts, out=out)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    E = float(out.energy.cpu()[0])
+    plan.close()
+    return {"workload": f"{w.name} positions, two species 50/50: eps {{1.0, 0.6}}, sigma {{1.0, 1.25}} (seed 17)",
+            "precision": "fp64", "ms_per_step": ms, "evals_per_s": 1000.0 / ms, "energy": E}
+
+
 def golden_errors(E, F, gold):
     import numpy as np
     if gold is None:
@@ -241,6 +276,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="leave out the batched-form measurement")
     ap.add_argument("--no-family", action="store_true", help="leave out the smoothing-family measurement")
+    ap.add_argument("--no-lb", action="store_true", help="leave out the Lorentz-Berthelot measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: MLS here is a single-GPU path "
@@ -314,6 +350,12 @@ def main():
             family["ms_per_step"][f"C{k}"] = r["ms"]
             family["energy"][f"C{k}"] = r["E"]
 
+    lb = None
+    if not args.no_lb:
+        log("[bench] Lorentz-Berthelot mixing")
+        lb = time_lb(w, prm, max(5, args.steps // 2), 2, dev)
+        log(f"[bench] Lorentz-Berthelot: {lb['ms_per_step']:.3f} ms/eval")
+
     batched = None
     if not args.no_batch:
         t = time.time()
@@ -361,6 +403,7 @@ def main():
         "accuracy": accuracy,
         "roofline": roofline,
         "continuity_family": family,
+        "lorentz_berthelot": lb,
         "batched": batched,
         "cpu_baseline": cpu,
     }

@@ -61,6 +61,9 @@ typedef enum {
 
 typedef enum { MLS_FP64 = 0, MLS_MIXED = 1 } mls_precision;
 
+/* Mixing rule of the pair coefficients (Sec. II.D). */
+typedef enum { MLS_GEOMETRIC = 0, MLS_LORENTZ_BERTHELOT = 1 } mls_mixing;
+
 /* Method parameters (Sec. III.D lists a, h, p, l as the knobs). */
 typedef struct {
   double box[3];  /* L_x, L_y, L_z > 0: orthorhombic, periodic in all three
@@ -84,6 +87,9 @@ typedef struct {
                      polynomial of rho^-6 = (1 + u)^(-1/2) in u = rho^12 - 1
                      for rho < 1 (C^k at rho = 1; the family of Sec. III.B).
                      2 is eq:gamma; 0 means 2 */
+  int mixing;     /* mls_mixing: MLS_GEOMETRIC (per-atom C6, mls_evaluate) or
+                     MLS_LORENTZ_BERTHELOT (per-atom epsilon and sigma,
+                     mls_evaluate_lb; FP64 plans only) */
 } mls_params;
 
 /* Resolved plan geometry (host struct filled by mls_plan_get_info). */
@@ -100,6 +106,7 @@ typedef struct {
   int order;
   double cell_width[3];    /* linked-cell width L_d / cells_d */
   int continuity;          /* k of gamma_k */
+  int mixing;              /* mls_mixing */
 } mls_plan_info;
 
 /* Build a plan on the current HIP device: resolves grids, levels and linked
@@ -132,6 +139,21 @@ mls_status mls_plan_get_info(mls_plan_t plan, mls_plan_info* info);
 mls_status mls_evaluate(mls_plan_t plan, int64_t n, const double* pos, const double* c6,
                         double* energy, double* forces, double* potential, double* dE_dc6,
                         void* stream);
+
+/* One evaluation under Lorentz-Berthelot mixing (Sec. II.D,
+ * eq:disp-pair-pot-multilevel-LorentzBerthelot): pair coefficient
+ * C_ij = 2 sqrt(eps_i eps_j) ((sigma_i + sigma_j)/2)^6 (eq:xi-lj), so
+ * E = -1/2 sum_{i,j,n}' C_ij r^-6 (LJ dispersion sign) and F = -grad E.  The
+ * local part uses C_ij directly; the grid part runs the steps of Sec. II.B
+ * once per charge vector xi_{i,k} = sigma_i^k sqrt(binom(6,k) 2 eps_i) / 8,
+ * k = 0..6, pairing vector k with vector 6 - k (seven instances, as the paper
+ * states).  The plan must have mixing = MLS_LORENTZ_BERTHELOT and precision
+ * MLS_FP64.
+ *   eps, sigma  device (n) FP64, finite and >= 0 (else a device flag, as C6)
+ *   energy      device, 1 FP64 (overwritten); forces device (n,3) or NULL
+ * Same ordering, threading and error behaviour as mls_evaluate. */
+mls_status mls_evaluate_lb(mls_plan_t plan, int64_t n, const double* pos, const double* eps, const double* sigma,
+                           double* energy, double* forces, void* stream);
 
 /* Intermediate results of the last evaluation, for per-stage checks.
  * `what` selects the array, written to device memory `dst` of `capacity`

@@ -32,7 +32,7 @@ def precision_code(precision) -> int:
     raise ValueError(f"unknown precision {precision!r}")
 
 
-def _params(box, cutoff, h, order, levels, grid, precision, continuity=2):
+def _params(box, cutoff, h, order, levels, grid, precision, continuity=2, mixing=0):
     p = _lib.MLSParams()
     for d in range(3):
         p.box[d] = float(box[d])
@@ -43,6 +43,8 @@ def _params(box, cutoff, h, order, levels, grid, precision, continuity=2):
     p.levels = int(levels)
     p.precision = precision_code(precision)
     p.continuity = int(continuity)
+    p.mixing = {"geometric": 0, "lorentz-berthelot": 1, "lb": 1}.get(mixing, mixing) if isinstance(mixing, str) \
+        else int(mixing)
     return p
 
 
@@ -62,11 +64,11 @@ class Plan:
     """A resolved MLS setup for one periodic box (``mls_plan_create``)."""
 
     def __init__(self, box, cutoff, h=1.0, order=4, levels=0, grid=None, precision="fp64",
-                 n_max=0, device=None, continuity=2):
+                 n_max=0, device=None, continuity=2, mixing="geometric"):
         import torch
         self._lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        self.params = _params(box, cutoff, h, order, levels, grid, precision, continuity)
+        self.params = _params(box, cutoff, h, order, levels, grid, precision, continuity, mixing)
         self._plan = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(self._lib.mls_plan_create(ctypes.byref(self.params), int(n_max),
@@ -77,7 +79,8 @@ class Plan:
                          cells=tuple(inf.cells), h_eff=tuple(inf.h_eff), taps=int(inf.taps),
                          n_max=int(inf.n_max), workspace_bytes=int(inf.workspace_bytes),
                          precision=int(inf.precision), order=int(inf.order),
-                         cell_width=tuple(inf.cell_width), continuity=int(inf.continuity))
+                         cell_width=tuple(inf.cell_width), continuity=int(inf.continuity),
+                         mixing=int(inf.mixing))
         self.n_max = int(inf.n_max)
 
     # ------------------------------------------------------------------
@@ -107,6 +110,22 @@ class Plan:
             _lib.check(self._lib.mls_evaluate(self._plan, n, _ptr(pos), _ptr(c6), _ptr(out.energy),
                                               _ptr(out.forces), _ptr(out.potential), _ptr(out.dE_dc6),
                                               ctypes.c_void_p(s)), "mls_evaluate")
+        return out
+
+    def evaluate_lb(self, pos, eps, sigma, forces=True, out=None, stream=None):
+        """Enqueue one Lorentz-Berthelot evaluation (``mls_evaluate_lb``):
+        per-atom epsilon and sigma instead of C6; returns energy and forces."""
+        import torch
+        self._check_inputs(pos, eps)
+        self._check_inputs(pos, sigma)
+        n = pos.shape[0]
+        if out is None:
+            out = Result(torch.empty(1, dtype=torch.float64, device=self.device),
+                         torch.empty((n, 3), dtype=torch.float64, device=self.device) if forces else None)
+        s = (stream if stream is not None else torch.cuda.current_stream(self.device)).cuda_stream
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.mls_evaluate_lb(self._plan, n, _ptr(pos), _ptr(eps), _ptr(sigma), _ptr(out.energy),
+                                                 _ptr(out.forces), ctypes.c_void_p(s)), "mls_evaluate_lb")
         return out
 
     def copy_stage(self, what, level=1, n=None):

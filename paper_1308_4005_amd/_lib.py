@@ -19,6 +19,8 @@ MLS_ERR_OOM = -4
 MLS_ERR_NONFINITE = -5
 MLS_FP64 = 0
 MLS_MIXED = 1
+MLS_GEOMETRIC = 0
+MLS_LORENTZ_BERTHELOT = 1
 
 MLS_STAGE_PERM = 0
 MLS_STAGE_CELL_START = 1
@@ -29,7 +31,7 @@ MLS_STAGE_E_LEVEL = 5
 MLS_STAGE_E_TOTAL = 6
 
 EXPORTS = [
-    "mls_plan_create", "mls_plan_get_info", "mls_evaluate", "mls_plan_copy_stage",
+    "mls_plan_create", "mls_plan_get_info", "mls_evaluate", "mls_evaluate_lb", "mls_plan_copy_stage",
     "mls_plan_status", "mls_plan_destroy", "mls_batch_create", "mls_batch_evaluate",
     "mls_batch_set_graph", "mls_batch_get_tuning", "mls_batch_set_tuning", "mls_batch_box_info",
     "mls_batch_status", "mls_batch_destroy", "mls_status_string", "mls_last_error",
@@ -50,6 +52,7 @@ class MLSParams(ctypes.Structure):
         ("grid", ctypes.c_int * 3),
         ("precision", ctypes.c_int),
         ("continuity", ctypes.c_int),
+        ("mixing", ctypes.c_int),
     ]
 
 
@@ -67,6 +70,7 @@ class MLSPlanInfo(ctypes.Structure):
         ("order", ctypes.c_int),
         ("cell_width", ctypes.c_double * 3),
         ("continuity", ctypes.c_int),
+        ("mixing", ctypes.c_int),
     ]
 
 
@@ -105,6 +109,7 @@ def load():
     lib.mls_plan_create.argtypes = [ctypes.POINTER(MLSParams), i64, ctypes.POINTER(P)]
     lib.mls_plan_get_info.argtypes = [P, ctypes.POINTER(MLSPlanInfo)]
     lib.mls_evaluate.argtypes = [P, i64, dp, dp, dp, dp, dp, dp, P]
+    lib.mls_evaluate_lb.argtypes = [P, i64, dp, dp, dp, dp, dp, P]
     lib.mls_plan_copy_stage.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, i64, P]
     lib.mls_plan_status.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
     lib.mls_plan_destroy.argtypes = [P]

@@ -27,7 +27,7 @@ class BatchResult:
 
 class BatchPlan:
     def __init__(self, boxes, n_per_box, cutoff, h=1.0, order=4, levels=0, precision="fp64",
-                 autotune=False, device=None, continuity=2):
+                 autotune=False, device=None, continuity=2, mixing="geometric"):
         import numpy as np
         import torch
         self._lib = _lib.load()
@@ -40,7 +40,7 @@ class BatchPlan:
         lv = np.broadcast_to(np.asarray(levels, dtype=np.int64), (self.nbox,))
         params = (_lib.MLSParams * self.nbox)()
         for b in range(self.nbox):
-            params[b] = _params(boxes[b], cutoff, h, order, int(lv[b]), None, precision, continuity)
+            params[b] = _params(boxes[b], cutoff, h, order, int(lv[b]), None, precision, continuity, mixing)
         counts = (ctypes.c_int64 * self.nbox)(*[int(x) for x in self.n_per_box])
         self.offsets = np.concatenate([[0], np.cumsum(self.n_per_box)]).astype(np.int64)
         self.n_total = int(self.offsets[-1])

@@ -3,6 +3,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 
 #include "mls_internal.h"
 
@@ -78,6 +79,7 @@ mls_status mls_plan_get_info(mls_plan_t P, mls_plan_info* info) {
   info->precision = P->precision;
   info->order = P->order;
   info->continuity = P->continuity;
+  info->mixing = P->mixing;
   return MLS_OK;
 }
 
@@ -94,6 +96,10 @@ mls_status mls_evaluate(mls_plan_t P, int64_t n, const double* pos, const double
   HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
   if (dev != P->device) {
     set_error("mls_evaluate: current device differs from the plan's device");
+    return MLS_ERR_INVALID_ARG;
+  }
+  if (P->mixing != MLS_GEOMETRIC) {
+    set_error("mls_evaluate: the plan uses Lorentz-Berthelot mixing (call mls_evaluate_lb)");
     return MLS_ERR_INVALID_ARG;
   }
   hipStream_t s = (hipStream_t)stream;
@@ -141,6 +147,53 @@ mls_status mls_evaluate(mls_plan_t P, int64_t n, const double* pos, const double
   }
   HIP_TRY(launch_interpolate(P, ni, energy, forces, potential, dE_dc6, s), "interpolation");
   HIP_TRY(mark(1 + MLS_T_INTERP), "timing event");
+  return MLS_OK;
+}
+
+mls_status mls_evaluate_lb(mls_plan_t P, int64_t n, const double* pos, const double* eps, const double* sigma,
+                           double* energy, double* forces, void* stream) {
+  if (!P) { set_error("mls_evaluate_lb: null plan"); return MLS_ERR_INVALID_ARG; }
+  if (P->mixing != MLS_LORENTZ_BERTHELOT) {
+    set_error("mls_evaluate_lb: the plan was not created with Lorentz-Berthelot mixing");
+    return MLS_ERR_INVALID_ARG;
+  }
+  if (n < 0 || n > P->n_max) {
+    set_error("mls_evaluate_lb: n = " + std::to_string(n) + " outside [0, n_max = " + std::to_string(P->n_max) + "]");
+    return MLS_ERR_INVALID_ARG;
+  }
+  if (!energy) { set_error("mls_evaluate_lb: energy pointer is required"); return MLS_ERR_INVALID_ARG; }
+  if (n > 0 && (!pos || !eps || !sigma)) { set_error("mls_evaluate_lb: null pos, eps or sigma"); return MLS_ERR_INVALID_ARG; }
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != P->device) {
+    set_error("mls_evaluate_lb: current device differs from the plan's device");
+    return MLS_ERR_INVALID_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  P->last_stream = s;
+  P->last_n = n;
+  const int ni = (int)n;
+  // binning with xi = sqrt(2 eps) (the e_i of the pair coefficient) and the
+  // sorted sigma
+  HIP_TRY(launch_binning_scaled(P, ni, pos, eps, 2.0, s), "binning");
+  HIP_TRY(launch_lb_gather(P, ni, sigma, s), "sigma gather");
+  HIP_TRY(launch_pair_lb(P, ni, s), "pair kernel");
+  // grid part once per charge vector (their grids in turn become the plan's
+  // working levels)
+  for (int k = 0; k < 7; ++k) {
+    HIP_TRY(launch_lb_charge(P, ni, k, s), "charges");
+    std::swap(P->lv, P->lb_lv[k]);
+    P->charge = P->d_charge;
+    hipError_t e = launch_anterpolate(P, ni, s);
+    for (int j = 2; e == hipSuccess && j <= P->levels; ++j) e = launch_restrict(P, j - 1, s);
+    if (e == hipSuccess) e = launch_stencils(P, s);
+    if (e == hipSuccess) e = launch_coarsest(P, s);
+    for (int j = P->levels - 1; e == hipSuccess && j >= 1; --j) e = launch_prolong(P, j, s);
+    P->charge = nullptr;
+    std::swap(P->lv, P->lb_lv[k]);
+    if (e != hipSuccess) return hip_fail(e, "grid part");
+  }
+  HIP_TRY(launch_interpolate_lb(P, ni, energy, forces, s), "interpolation");
   return MLS_OK;
 }
 

@@ -156,7 +156,7 @@ mls_status build_phases(mls_batch_s* B) {
       const int64_t o = B->off[b];
       set_box(fill, b, FillArgs{P->d_count, nc}, nblk(nc, 256));
       set_box(cnt, b, BinCountArgs{B->pos + 3 * o, B->c6 + o, n, P->cg, P->d_cid, P->d_slot, P->d_count, P->d_xw,
-                                   P->d_flags}, nblk(n, 256));
+                                   P->d_flags, 1.0}, nblk(n, 256));
       ScanArgs sa{P->d_count, nc, P->d_cell_start, P->d_bsum, P->d_bmax, P->d_ncell_max};
       set_box(s1, b, sa, scan_blocks(nc));
       set_box(s2, b, sa, 1);
@@ -183,7 +183,7 @@ mls_status build_phases(mls_batch_s* B) {
       const int n = n_of(b);
       if (n == 0) continue;
       const CellGeom& g = P->cg;
-      PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const(P), P->d_e0, P->d_floc};
+      PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const(P), P->d_e0, P->d_floc, nullptr};
       if (mixed && P->pair_fast && n < (1 << 24)) {
         set_box(f32, b, PairArgsF{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const_f(P),
                                   P->d_e0, P->d_floc}, nblk(n, 64));
@@ -210,7 +210,7 @@ mls_status build_phases(mls_batch_s* B) {
     for (int b : order) {
       mls_plan_s* P = B->plans[b];
       const int n = n_of(b);
-      AnterpArgs a{P->d_xs, P->d_cell_start, n, P->cg, finest(P), AntGeom{}, P->lv[0].q};
+      AnterpArgs a{P->d_xs, P->d_cell_start, n, P->cg, finest(P), AntGeom{}, P->lv[0].q, nullptr};
       if (anterp_owned_geom(P, a.ag)) {
         set_box(own, b, a, a.ag.nb[0] * a.ag.nb[1] * a.ag.nb[2]);
       } else {
@@ -511,6 +511,10 @@ mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* 
             (per_box[0].continuity == 0 ? 2 : per_box[0].continuity)) {
       set_error("mls_batch_create: all boxes must share precision, order and continuity");
       return MLS_ERR_INVALID_ARG;
+    }
+    if (per_box[b].mixing != MLS_GEOMETRIC) {
+      set_error("mls_batch_create: the batched form takes geometric mixing only");
+      return MLS_ERR_UNSUPPORTED;
     }
     total += n_per_box[b];
   }

@@ -39,7 +39,7 @@ struct FillD {
 // Non-finite positions and coordinates too large for the wrap become the
 // origin, non-finite or negative C6 become 0.
 __device__ __forceinline__ double4 wrapped_atom(const double* __restrict__ pos, const double* __restrict__ c6,
-                                                int i, const CellGeom& g, int& bad) {
+                                                int i, const CellGeom& g, double scale, int& bad) {
   double x = pos[3 * (size_t)i], y = pos[3 * (size_t)i + 1], z = pos[3 * (size_t)i + 2];
   double c = c6[i];
   bad = 0;
@@ -59,7 +59,7 @@ __device__ __forceinline__ double4 wrapped_atom(const double* __restrict__ pos, 
     bad |= 1;
     X = Y = Z = 0.0;
   }
-  return make_double4(X, Y, Z, sqrt(c));
+  return make_double4(X, Y, Z, sqrt(scale * c));
 }
 
 struct BinCount {
@@ -70,7 +70,7 @@ struct BinCount {
     if (i >= a.n) return;
     const CellGeom& g = a.g;
     int bad;
-    const double4 p = wrapped_atom(a.pos, a.c6, i, g, bad);
+    const double4 p = wrapped_atom(a.pos, a.c6, i, g, a.c6_scale, bad);
     if (bad) atomicOr(a.flags, bad);
     int cx = max(0, min((int)(p.x * g.inv_w[0]), g.nc[0] - 1));
     int cy = max(0, min((int)(p.y * g.inv_w[1]), g.nc[1] - 1));
@@ -251,6 +251,46 @@ struct GatherSorted {
   }
 };
 
+// Lorentz-Berthelot: sigma in sorted order (padding rows 0) and its flag.
+struct LbGather {
+  using Args = LbGatherArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    const int s = blk * kBlock + threadIdx.x;
+    if (s >= a.n + kSortedPad) return;
+    double v = 0.0;
+    if (s < a.n) {
+      v = a.sigma[a.perm[s]];
+      if (!isfinite(v) || !(v >= 0.0)) {
+        atomicOr(a.flags, 2);
+        v = 0.0;
+      }
+    }
+    a.sig_s[s] = v;
+  }
+};
+
+// Lorentz-Berthelot charge vector k in sorted order:
+// xi_{i,k} = sigma_i^k sqrt(binom(6,k) 2 eps_i) / 8 = sigma_i^k sqrt(binom(6,k)) e_i / 8,
+// e_i = sqrt(2 eps_i) being the xi of the binning.
+struct LbCharge {
+  using Args = LbChargeArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    const int s = blk * kBlock + threadIdx.x;
+    if (s >= a.n + kSortedPad) return;
+    double q = 0.0;
+    if (s < a.n) {
+      const double sg = a.sig_s[s];
+      double sk = 1.0;
+      for (int j = 0; j < a.k; ++j) sk *= sg;
+      const int binom = a.k == 0 || a.k == 6 ? 1 : (a.k == 1 || a.k == 5 ? 6 : (a.k == 2 || a.k == 4 ? 15 : 20));
+      q = sk * sqrt((double)binom) * a.xs[s].w * 0.125;
+    }
+    a.charge[s] = q;
+  }
+};
+
 // Sum of xi over the atoms from the gather's per-block partials (fixed order).
 struct SumXiFinal {
   using Args = SumXiArgs;
@@ -301,11 +341,27 @@ hipError_t launch_zero_i(int* p, int64_t count, hipStream_t s) {
 }
 
 hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double* c6, hipStream_t s) {
+  return launch_binning_scaled(P, n, pos, c6, 1.0, s);
+}
+
+hipError_t launch_lb_gather(mls_plan_s* P, int n, const double* sigma, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  return launch_one<LbGather>(LbGatherArgs{P->d_perm, n, sigma, P->d_sig, P->d_flags}, nblocks(n + kSortedPad, kBlock),
+                              s);
+}
+
+hipError_t launch_lb_charge(mls_plan_s* P, int n, int k, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  return launch_one<LbCharge>(LbChargeArgs{P->d_xs, P->d_sig, n, k, P->d_charge}, nblocks(n + kSortedPad, kBlock), s);
+}
+
+hipError_t launch_binning_scaled(mls_plan_s* P, int n, const double* pos, const double* c6, double scale,
+                                 hipStream_t s) {
   const CellGeom& g = P->cg;
   hipError_t e;
   if ((e = launch_zero_i(P->d_count, g.ncell, s)) != hipSuccess) return e;
   if (n > 0) {
-    BinCountArgs a{pos, c6, n, g, P->d_cid, P->d_slot, P->d_count, P->d_xw, P->d_flags};
+    BinCountArgs a{pos, c6, n, g, P->d_cid, P->d_slot, P->d_count, P->d_xw, P->d_flags, scale};
     if ((e = launch_one<BinCount>(a, nblocks(n, kBlock), s)) != hipSuccess) return e;
   }
   if ((e = launch_scan(P, P->d_count, g.ncell, P->d_cell_start, s)) != hipSuccess) return e;

@@ -29,6 +29,7 @@ struct AnterpAtomic {
     if (s >= a.n) return;
     const GridGeom& gg = a.gg;
     const double4 p = a.xs[s];
+    const double qi = a.charge ? a.charge[s] : p.w;
     const double pc[3] = {p.x, p.y, p.z};
     double w[3][P];
     int idx[3][P];
@@ -45,7 +46,7 @@ struct AnterpAtomic {
     for (int jz = 0; jz < P; ++jz)
 #pragma unroll
       for (int jy = 0; jy < P; ++jy) {
-        const double wzy = p.w * w[2][jz] * w[1][jy];
+        const double wzy = qi * w[2][jz] * w[1][jy];
         double* row = a.q + ((size_t)idx[2][jz] * gg.n[1] + idx[1][jy]) * gg.n[0];
 #pragma unroll
         for (int jx = 0; jx < P; ++jx) unsafeAtomicAdd(row + idx[0][jx], wzy * w[0][jx]);
@@ -173,7 +174,8 @@ struct AnterpOwned {
     }
     for (int i = i0 + wave; i < i1; i += kWaves) {
       while (seg_off[sg + 1] <= i) ++sg;
-      const double4 p = a.xs[seg_begin[sg] + (i - seg_off[sg])];
+      const int ia = seg_begin[sg] + (i - seg_off[sg]);
+      const double4 p = a.xs[ia];
       const double pc[3] = {p.x, p.y, p.z};
       W w[3][P];
       int l0[3];
@@ -184,7 +186,7 @@ struct AnterpOwned {
         basis_weights<P, W>((W)(t - m0), w[d]);
         l0[d] = (int)m0 - (P / 2 - 1) + seg_shift[sg][d] * gg.n[d] - lo[d];
       }
-      const W xiw = (W)p.w;
+      const W xiw = (W)(a.charge ? a.charge[ia] : p.w);
 #pragma unroll
       for (int jz = 0; jz < P; ++jz) {
         const int lz = l0[2] + jz;
@@ -338,6 +340,91 @@ struct Prolong {
 };
 
 // ------------------------------------------------------------ interpolation + assembly
+// Interpolated value and gradient (in grid units) of one grid at an atom with
+// weights w, dw and wrapped indices idx.  The p z-planes are walked in a loop
+// that is not unrolled (few registers, more waves); the plane's z weight and
+// offset sit in slot 0 of local copies rotated after each plane.
+template <int P, class W>
+__device__ __forceinline__ void interp_grid(const double* __restrict__ E1, const GridGeom& gg,
+                                            const W (&w)[3][P], const W (&dw)[3][P], const int (&idx)[3][P],
+                                            double& u, double& gx, double& gy, double& gz) {
+  W wz[P], dwz[P];
+  int iz[P];
+  size_t yrow[P];
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    wz[t] = w[2][t];
+    dwz[t] = dw[2][t];
+    iz[t] = idx[2][t];
+    yrow[t] = (size_t)idx[1][t] * gg.n[0];
+  }
+  const size_t plane = (size_t)gg.n[0] * gg.n[1];
+  u = gx = gy = gz = 0.0;
+#pragma unroll 1
+  for (int jz = 0; jz < P; ++jz) {
+    const double* E1z = E1 + (size_t)iz[0] * plane;
+    double ru = 0.0, rgx = 0.0, rgy = 0.0;
+#pragma unroll
+    for (int jy = 0; jy < P; ++jy) {
+      const double* row = E1z + yrow[jy];
+      double v = 0.0, vd = 0.0;
+#pragma unroll
+      for (int jx = 0; jx < P; ++jx) {
+        const double e = row[idx[0][jx]];
+        v += (double)w[0][jx] * e;
+        vd += (double)dw[0][jx] * e;
+      }
+      ru += (double)w[1][jy] * v;
+      rgx += (double)w[1][jy] * vd;
+      rgy += (double)dw[1][jy] * v;
+    }
+    u += (double)wz[0] * ru;
+    gx += (double)wz[0] * rgx;
+    gy += (double)wz[0] * rgy;
+    gz += (double)dwz[0] * ru;
+#pragma unroll
+    for (int t = 0; t + 1 < P; ++t) {
+      wz[t] = wz[t + 1];
+      dwz[t] = dwz[t + 1];
+      iz[t] = iz[t + 1];
+    }
+  }
+}
+
+template <int P, class W>
+__device__ __forceinline__ void interp_setup(const double4& p, const GridGeom& gg, W (&w)[3][P], W (&dw)[3][P],
+                                             int (&idx)[3][P]) {
+  const double pc[3] = {p.x, p.y, p.z};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double t = pc[d] * gg.invh[d];
+    const double m0 = floor(t);
+    basis_weights_d<P, W>((W)(t - m0), w[d], dw[d]);
+    const int base = (int)m0 - (P / 2 - 1);
+#pragma unroll
+    for (int j = 0; j < P; ++j) idx[d][j] = wrapi(base + j, gg.n[d]);
+  }
+}
+
+// block reduction of the two energy sums (fixed order: deterministic)
+__device__ __forceinline__ void energy_partials(double su, double sxx, double* __restrict__ partial, int blk) {
+  __shared__ double r1[kBlock], r2[kBlock];
+  r1[threadIdx.x] = su;
+  r2[threadIdx.x] = sxx;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      r1[threadIdx.x] += r1[threadIdx.x + off];
+      r2[threadIdx.x] += r2[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blk] = r1[0];
+    partial[2 * blk + 1] = r2[0];
+  }
+}
+
 template <int P, class W>
 struct Interp {
   using Args = InterpArgs;
@@ -348,54 +435,11 @@ struct Interp {
     double su = 0.0, sxx = 0.0;
     if (s < a.n) {
       const double4 p = a.xs[s];
-      const double pc[3] = {p.x, p.y, p.z};
       W w[3][P], dw[3][P];
       int idx[3][P];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double t = pc[d] * gg.invh[d];
-        const double m0 = floor(t);
-        basis_weights_d<P, W>((W)(t - m0), w[d], dw[d]);
-        const int base = (int)m0 - (P / 2 - 1);
-#pragma unroll
-        for (int j = 0; j < P; ++j) idx[d][j] = wrapi(base + j, gg.n[d]);
-      }
-      // one z-plane at a time (not unrolled: few registers, more waves); the
-      // plane's z weight and row offset sit in slot 0, rotated after each plane
-      double u = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-      size_t yrow[P];
-#pragma unroll
-      for (int jy = 0; jy < P; ++jy) yrow[jy] = (size_t)idx[1][jy] * gg.n[0];
-      const size_t plane = (size_t)gg.n[0] * gg.n[1];
-#pragma unroll 1
-      for (int jz = 0; jz < P; ++jz) {
-        const double* E1z = a.E1 + (size_t)idx[2][0] * plane;
-        double ru = 0.0, rgx = 0.0, rgy = 0.0;
-#pragma unroll
-        for (int jy = 0; jy < P; ++jy) {
-          const double* row = E1z + yrow[jy];
-          double v = 0.0, vd = 0.0;
-#pragma unroll
-          for (int jx = 0; jx < P; ++jx) {
-            const double e = row[idx[0][jx]];
-            v += (double)w[0][jx] * e;
-            vd += (double)dw[0][jx] * e;
-          }
-          ru += (double)w[1][jy] * v;
-          rgx += (double)w[1][jy] * vd;
-          rgy += (double)dw[1][jy] * v;
-        }
-        u += (double)w[2][0] * ru;
-        gx += (double)w[2][0] * rgx;
-        gy += (double)w[2][0] * rgy;
-        gz += (double)dw[2][0] * ru;
-#pragma unroll
-        for (int t = 0; t + 1 < P; ++t) {
-          w[2][t] = w[2][t + 1];
-          dw[2][t] = dw[2][t + 1];
-          idx[2][t] = idx[2][t + 1];
-        }
-      }
+      interp_setup<P, W>(p, gg, w, dw, idx);
+      double u, gx, gy, gz;
+      interp_grid<P, W>(a.E1, gg, w, dw, idx, u, gx, gy, gz);
       const int i = a.perm[s];
       const double xi = p.w;
       const double utot = a.e0[s] + u;
@@ -409,22 +453,51 @@ struct Interp {
       su = xi * utot;
       sxx = xi * xi;
     }
-    // block reduction of sum xi u and sum xi^2 (fixed order: deterministic)
-    __shared__ double r1[kBlock], r2[kBlock];
-    r1[threadIdx.x] = su;
-    r2[threadIdx.x] = sxx;
-    __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) {
-        r1[threadIdx.x] += r1[threadIdx.x + off];
-        r2[threadIdx.x] += r2[threadIdx.x + off];
+    energy_partials(su, sxx, a.partial, blk);
+  }
+};
+
+// Lorentz-Berthelot: the grid potential of vector 6 - k weighted with
+// xi_{i,k} = sigma_i^k sqrt(binom(6,k)) e_i / 8 (e_i = sqrt(2 eps_i) = xs.w),
+// summed over k; the local part is e_i e0_i with e0 from the pair kernel; the
+// self term is C_ii = e_i^2 sigma_i^6.
+template <int P>
+struct InterpLb {
+  using Args = InterpLbArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    const GridGeom& gg = a.gg;
+    const int s = blk * kBlock + threadIdx.x;
+    double su = 0.0, sxx = 0.0;
+    if (s < a.n) {
+      const double4 p = a.xs[s];
+      double w[3][P], dw[3][P];
+      int idx[3][P];
+      interp_setup<P, double>(p, gg, w, dw, idx);
+      const double sg = a.sig[s];
+      double phi = 0.0, fx = 0.0, fy = 0.0, fz = 0.0, sk = 1.0;
+      for (int k = 0; k <= 6; ++k) {
+        const int binom = k == 0 || k == 6 ? 1 : (k == 1 || k == 5 ? 6 : (k == 2 || k == 4 ? 15 : 20));
+        const double xik = sk * sqrt((double)binom) * p.w * 0.125;
+        double u, gx, gy, gz;
+        interp_grid<P, double>(a.E1[6 - k], gg, w, dw, idx, u, gx, gy, gz);
+        phi += xik * u;
+        fx += xik * gx;
+        fy += xik * gy;
+        fz += xik * gz;
+        sk *= sg;
       }
-      __syncthreads();
+      const int i = a.perm[s];
+      if (a.forces) {
+        a.forces[3 * (size_t)i + 0] = a.floc[3 * (size_t)s + 0] + fx * gg.invh[0];
+        a.forces[3 * (size_t)i + 1] = a.floc[3 * (size_t)s + 1] + fy * gg.invh[1];
+        a.forces[3 * (size_t)i + 2] = a.floc[3 * (size_t)s + 2] + fz * gg.invh[2];
+      }
+      su = p.w * a.e0[s] + phi;
+      const double s3 = sg * sg * sg;
+      sxx = p.w * p.w * s3 * s3;
     }
-    if (threadIdx.x == 0) {
-      a.partial[2 * blk] = r1[0];
-      a.partial[2 * blk + 1] = r2[0];
-    }
+    energy_partials(su, sxx, a.partial, blk);
   }
 };
 
@@ -498,7 +571,7 @@ bool anterp_owned_geom(const mls_plan_s* P, AntGeom& ag) {
 
 hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s) {
   Level& L1 = P->lv[0];
-  AnterpArgs a{P->d_xs, P->d_cell_start, n, P->cg, finest_geom(P), AntGeom{}, L1.q};
+  AnterpArgs a{P->d_xs, P->d_cell_start, n, P->cg, finest_geom(P), AntGeom{}, L1.q, P->charge};
   if (anterp_owned_geom(P, a.ag)) {
     // every owned point is written, so no zero fill is needed
     const int nb = a.ag.nb[0] * a.ag.nb[1] * a.ag.nb[2];
@@ -545,6 +618,17 @@ hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forc
     if (e != hipSuccess) return e;
   }
   // no atoms: an empty sum, E = 0
+  return launch_one<EnergyFinal>(EnergyArgs{P->d_partial, nb, P->cself, energy}, 1, s);
+}
+
+hipError_t launch_interpolate_lb(mls_plan_s* P, int n, double* energy, double* forces, hipStream_t s) {
+  const int nb = nblocks(n, kBlock);
+  if (n > 0) {
+    InterpLbArgs a{P->d_xs, P->d_sig, P->d_perm, n, finest_geom(P), {}, P->d_e0, P->d_floc, forces, P->d_partial};
+    for (int k = 0; k < 7; ++k) a.E1[k] = P->lb_lv[k][0].E;
+    hipError_t e = P->order == 4 ? launch_one<InterpLb<4>>(a, nb, s) : launch_one<InterpLb<6>>(a, nb, s);
+    if (e != hipSuccess) return e;
+  }
   return launch_one<EnergyFinal>(EnergyArgs{P->d_partial, nb, P->cself, energy}, 1, s);
 }
 

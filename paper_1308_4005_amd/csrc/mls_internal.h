@@ -108,7 +108,10 @@ struct FillDArgs { double* p; int n; };
 struct BinCountArgs {
   const double* pos; const double* c6; int n; CellGeom g;
   int* cid; int* slot; int* count; double4* xw; int* flags;
+  double c6_scale;   // xi = sqrt(c6_scale * c6): 1 for C6, 2 for Lorentz-Berthelot epsilon
 };
+struct LbGatherArgs { const int* perm; int n; const double* sigma; double* sig_s; int* flags; };
+struct LbChargeArgs { const double4* xs; const double* sig_s; int n; int k; double* charge; };
 struct ScanArgs { const int* count; int m; int* start; int* bsum; int* bmax; int* max_count; };
 struct ScatterArgs { const int* cid; const int* slot; int n; const int* start; int* perm_tmp; };
 struct RankArgs { const int* start; const int* cid; const int* perm_tmp; int n; int* perm; };
@@ -121,6 +124,7 @@ struct SumXiArgs { int rows; const double* partial; double* out; };   // partial
 struct PairArgs {
   const double4* xs; const int* cell_s; const int* cstart; int n; CellGeom g; PairConst pc;
   double* e0; double* floc;
+  const double* sig;      // Lorentz-Berthelot: sorted sigma (source weight e_j s_ij^6)
 };
 struct PairArgsF {
   const float4* xr; const float* xif; const double4* xs; const int* cell_s; const int* cstart;
@@ -128,6 +132,7 @@ struct PairArgsF {
 };
 struct AnterpArgs {
   const double4* xs; const int* cstart; int n; CellGeom cg; GridGeom gg; AntGeom ag; double* q;
+  const double* charge;   // sorted charges (else the xi in xs.w)
 };
 struct TransferArgs {              // restriction (fine -> coarse) and prolongation (coarse -> fine)
   const double* src; GridDims gs;  // q^{k-1} (restriction) or E^{k+1} (prolongation)
@@ -139,6 +144,10 @@ struct InterpArgs {
   const double* floc; double cself; OutPtrs out; double* partial;
 };
 struct EnergyArgs { const double* partial; int nb; double cself; double* energy; };
+struct InterpLbArgs {
+  const double4* xs; const double* sig; const int* perm; int n; GridGeom gg; const double* E1[7];
+  const double* e0; const double* floc; double* forces; double* partial;
+};
 struct CoarsestArgs { const double* q; GridDims g; const double* K; double* e; };
 constexpr int kCoarsestThreads = 256;   // outputs per block of the coarsest-level kernel
 
@@ -218,6 +227,11 @@ struct mls_plan_s {
   int precision = 0;
   double a = 0, a2 = 0, inv_a2 = 0, inv_a6 = 0, inv_a8 = 0, cself = 0;
   int continuity = 2;              // k of the smoothing function gamma_k
+  int mixing = 0;                  // mls_mixing
+  std::vector<mls::Level> lb_lv[7];  // Lorentz-Berthelot: grids of charge vector k
+  double* d_sig = nullptr;         // Lorentz-Berthelot: sorted sigma (n_max + pad)
+  double* d_charge = nullptr;      // Lorentz-Berthelot: sorted charges of one vector (n_max + pad)
+  const double* charge = nullptr;  // charges the anterpolation reads (null: xi)
   double gamma_c[5]{};             // gamma_k inside the unit ball: sum_j gamma_c[j] rho^(12 j)
   mls::CellGeom cg{};
   double invh1[3]{};               // n_1 / L
@@ -314,6 +328,14 @@ hipError_t launch_coarsest(mls_plan_s* P, hipStream_t s);
 hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s);
 hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forces,
                               double* potential, double* dE_dc6, hipStream_t s);
+// Lorentz-Berthelot pieces: sorted sigma and flags, the sorted charges of
+// vector k, and the interpolation of all seven vectors with the energy
+hipError_t launch_lb_gather(mls_plan_s* P, int n, const double* sigma, hipStream_t s);
+hipError_t launch_pair_lb(mls_plan_s* P, int n, hipStream_t s);
+hipError_t launch_lb_charge(mls_plan_s* P, int n, int k, hipStream_t s);
+hipError_t launch_interpolate_lb(mls_plan_s* P, int n, double* energy, double* forces, hipStream_t s);
+hipError_t launch_binning_scaled(mls_plan_s* P, int n, const double* pos, const double* c6, double scale,
+                                 hipStream_t s);
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
 hipError_t launch_zero_i(int* p, int64_t count, hipStream_t s);
 hipError_t launch_copy_stage(mls_plan_s* P, int what, int level, void* dst, hipStream_t s);

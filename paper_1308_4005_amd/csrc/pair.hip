@@ -63,8 +63,22 @@ __device__ __forceinline__ void g0_pair(T s, const C& pc, T& g, T& fr) {
   }
 }
 
+// Source weight of a pair: xi_j (geometric mixing), or under Lorentz-Berthelot
+// e_j ((sigma_i + sigma_j) / 2)^6 with e_j = sqrt(2 eps_j) = xs.w, so that the
+// target's factor e_i times it is C_ij of eq:xi-lj.
+template <bool LB>
+__device__ __forceinline__ double src_weight(double wj, const double* __restrict__ sig, double sig_i, int j) {
+  if constexpr (LB) {
+    const double m = 0.5 * (sig_i + sig[j]);
+    const double m3 = m * m * m;
+    return wj * (m3 * m3);
+  } else {
+    return wj;
+  }
+}
+
 // FP64: one thread per cell-sorted target atom.
-template <int K>
+template <int K, bool LB = false>
 struct PairGeneric {
   using Args = PairArgs;
   static constexpr int kThreads = kBlock;
@@ -75,6 +89,7 @@ struct PairGeneric {
     const PairConst& pc = a.pc;
     const double4* __restrict__ xs = a.xs;
     const double4 xi = xs[s];
+    const double sig_i = LB ? a.sig[s] : 0.0;
     const int c = a.cell_s[s];
     const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
     double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
@@ -105,8 +120,9 @@ struct PairGeneric {
             if (r2 < pc.a2 && !(home && j == s)) {
               double gg, fr;
               g0_pair<double, K>(r2, pc, gg, fr);
-              e += xj.w * gg;
-              const double f = xj.w * fr;
+              const double wj = src_weight<LB>(xj.w, a.sig, sig_i, j);
+              e += wj * gg;
+              const double f = wj * fr;
               fx += f * dx;
               fy += f * dy;
               fz += f * dz;
@@ -128,7 +144,7 @@ struct PairGeneric {
 // atoms (a run ends where the periodic image changes) and its 64 lanes split
 // each run; the lane sums are added in LDS.  Same cells, images and pairs as
 // PairGeneric.
-template <int K>
+template <int K, bool LB = false>
 struct PairWave {
   using Args = PairArgs;
   static constexpr int kThreads = 64;
@@ -139,6 +155,7 @@ struct PairWave {
     const PairConst& pc = a.pc;
     const double4* __restrict__ xs = a.xs;
     const double4 xi = xs[s];
+    const double sig_i = LB ? a.sig[s] : 0.0;
     const int c = a.cell_s[s];
     const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
     double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
@@ -171,8 +188,9 @@ struct PairWave {
             if (r2 < pc.a2 && !(home && j == s)) {
               double gg, fr;
               g0_pair<double, K>(r2, pc, gg, fr);
-              e += xj.w * gg;
-              const double f = xj.w * fr;
+              const double wj = src_weight<LB>(xj.w, a.sig, sig_i, j);
+              e += wj * gg;
+              const double f = wj * fr;
               fx += f * dx;
               fy += f * dy;
               fz += f * dz;
@@ -223,10 +241,11 @@ struct PairAcc {
   int cnt;
 };
 
-template <int K>
+template <int K, bool LB>
 __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, int cnt, int lane, int self_ent,
                                                const double4& xi, const double4* __restrict__ xs, const CellGeom& g,
-                                               const PairConst& pc, PairAcc& A) {
+                                               const PairConst& pc, const double* __restrict__ sig, double sig_i,
+                                               PairAcc& A) {
   for (int t = 0; __any(t < cnt); ++t) {
     const int ent = queue[t * kWaveQ + lane];
     if (t < cnt && ent != self_ent) {
@@ -242,8 +261,9 @@ __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, in
       const double r2 = dx * dx + dy * dy + dz * dz;
       double gg, fr;
       g0_pair<double, K>(r2, pc, gg, fr);
-      A.e += xj.w * gg;
-      const double f = xj.w * fr;
+      const double wj = src_weight<LB>(xj.w, sig, sig_i, j);
+      A.e += wj * gg;
+      const double f = wj * fr;
       A.fx += f * dx;
       A.fy += f * dy;
       A.fz += f * dz;
@@ -255,10 +275,11 @@ __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, in
 // calls it; lanes with an empty range just take part in the votes).  Reads
 // may run up to kBatch - 1 rows past j1: the sorted array is padded with
 // far-away rows, and rows past j1 are never kept.
-template <int K>
+template <int K, bool LB>
 __device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int* __restrict__ queue, int lane,
                                               int self_ent, const double4& xi, const double4* __restrict__ xs,
-                                              const CellGeom& g, const PairConst& pc, PairAcc& A) {
+                                              const CellGeom& g, const PairConst& pc, const double* __restrict__ sig,
+                                              double sig_i, PairAcc& A) {
   const double ax = xi.x - (double)((img & 3) - 1) * g.L[0];
   const double ay = xi.y - (double)(((img >> 2) & 3) - 1) * g.L[1];
   const double az = xi.z - (double)(((img >> 4) & 3) - 1) * g.L[2];
@@ -280,7 +301,7 @@ __device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int* __res
     // within the padding however long other lanes keep scanning
     j += j < j1 ? kBatch : 0;
     if (__any(A.cnt > kQueue - kBatch)) {
-      pair_drain_f64<K>(queue, A.cnt, lane, self_ent, xi, xs, g, pc, A);
+      pair_drain_f64<K, LB>(queue, A.cnt, lane, self_ent, xi, xs, g, pc, sig, sig_i, A);
       A.cnt = 0;
     }
   }
@@ -290,7 +311,7 @@ __device__ __forceinline__ double gap1(double x, double lo, double w, double eps
   return fmax(0.0, fmax(lo - x, x - (lo + w)) - eps);
 }
 
-template <int K>
+template <int K, bool LB = false>
 struct PairTrimF64 {
   using Args = PairArgs;
   static constexpr int kThreads = kWaveQ;
@@ -306,6 +327,7 @@ struct PairTrimF64 {
   const bool active = k < n;
   const int sc = active ? k : n - 1;
   const double4 xi = xs[sc];
+  const double sig_i = LB ? ar.sig[sc] : 0.0;
   const int c = ar.cell_s[sc];
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
   // the target itself, seen in the home image, is skipped in the drain
@@ -350,11 +372,11 @@ struct PairTrimF64 {
         k0 = cstart[row + lo2];
         k1 = cstart[row + hi2 + 1];
       }
-      pair_scan_f64<K>(j0, j1, image_bits(ix1, iy, iz), queue, lane, self_ent, xi, xs, g, pc, A);
-      pair_scan_f64<K>(k0, k1, image_bits(ix2, iy, iz), queue, lane, self_ent, xi, xs, g, pc, A);
+      pair_scan_f64<K, LB>(j0, j1, image_bits(ix1, iy, iz), queue, lane, self_ent, xi, xs, g, pc, ar.sig, sig_i, A);
+      pair_scan_f64<K, LB>(k0, k1, image_bits(ix2, iy, iz), queue, lane, self_ent, xi, xs, g, pc, ar.sig, sig_i, A);
     }
   }
-  pair_drain_f64<K>(queue, A.cnt, lane, self_ent, xi, xs, g, pc, A);
+  pair_drain_f64<K, LB>(queue, A.cnt, lane, self_ent, xi, xs, g, pc, ar.sig, sig_i, A);
   if (active) {
     ar.e0[sc] = A.e;
     ar.floc[3 * (size_t)sc + 0] = xi.w * A.fx;
@@ -543,10 +565,24 @@ hipError_t launch_pair_k(mls_plan_s* P, int n, hipStream_t s) {
                 P->d_floc};
     return launch_one<PairTrimF32<K>>(a, (n + kWaveQ - 1) / kWaveQ, s);
   }
-  PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const(P), P->d_e0, P->d_floc};
+  PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const(P), P->d_e0, P->d_floc, nullptr};
   if (P->pair_fast && n < (1 << 25)) return launch_one<PairTrimF64<K>>(a, (n + kWaveQ - 1) / kWaveQ, s);
   if (!P->pair_fast) return launch_one<PairWave<K>>(a, n, s);
   return launch_one<PairGeneric<K>>(a, (n + kBlock - 1) / kBlock, s);
+}
+
+// Lorentz-Berthelot (FP64 plans): the same kernels with the LB source weight.
+template <int K>
+hipError_t launch_pair_lb_k(mls_plan_s* P, int n, hipStream_t s) {
+  PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, P->cg, pair_const(P), P->d_e0, P->d_floc, P->d_sig};
+  if (P->pair_fast && n < (1 << 25)) return launch_one<PairTrimF64<K, true>>(a, (n + kWaveQ - 1) / kWaveQ, s);
+  if (!P->pair_fast) return launch_one<PairWave<K, true>>(a, n, s);
+  return launch_one<PairGeneric<K, true>>(a, (n + kBlock - 1) / kBlock, s);
+}
+
+hipError_t launch_pair_lb(mls_plan_s* P, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  return pair_variant(P) == 2 ? launch_pair_lb_k<2>(P, n, s) : launch_pair_lb_k<0>(P, n, s);
 }
 
 hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s) {

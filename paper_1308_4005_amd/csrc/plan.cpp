@@ -159,6 +159,15 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   if (n_max < 0 || n_max > (int64_t)1 << 30) { set_error("n_max must be in [0, 2^30]"); return MLS_ERR_INVALID_ARG; }
   const int cont = p.continuity == 0 ? 2 : p.continuity;
   if (cont < 1 || cont > 4) { set_error("continuity must be 1..4 (0 means 2)"); return MLS_ERR_INVALID_ARG; }
+  if (p.mixing != MLS_GEOMETRIC && p.mixing != MLS_LORENTZ_BERTHELOT) {
+    set_error("mixing must be MLS_GEOMETRIC or MLS_LORENTZ_BERTHELOT");
+    return MLS_ERR_INVALID_ARG;
+  }
+  if (p.mixing == MLS_LORENTZ_BERTHELOT && p.precision != MLS_FP64) {
+    set_error("Lorentz-Berthelot mixing is available in FP64 plans only");
+    return MLS_ERR_UNSUPPORTED;
+  }
+  P->mixing = p.mixing;
 
   P->params = p;
   P->order = p.order;
@@ -385,6 +394,25 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
     }
     if (P->precision == MLS_MIXED && k < l) {
       ALLOC(L.qf, L.g.size);
+    }
+  }
+  if (P->mixing == MLS_LORENTZ_BERTHELOT) {
+    // seven charge vectors: one set of grids each (Sec. II.D)
+    ALLOC(P->d_sig, N + kSortedPad);
+    ALLOC(P->d_charge, N + kSortedPad);
+    for (int r = 0; r < 7; ++r) {
+      P->lb_lv[r] = P->lv;
+      for (int k = 1; k <= l; ++k) {
+        Level& L = P->lb_lv[r][k - 1];
+        L.qf = L.ef = nullptr;
+        ALLOC(L.q, L.g.size);
+        ALLOC(L.e, L.g.size);
+        if (k < l) {
+          ALLOC(L.E, L.g.size);
+        } else {
+          L.E = L.e;
+        }
+      }
     }
   }
   ALLOC(P->d_taps, P->taps.size());

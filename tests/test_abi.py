@@ -64,6 +64,7 @@ def _params(**kw):
     p.levels = kw.get("levels", 2)
     p.precision = kw.get("precision", 0)
     p.continuity = kw.get("continuity", 0)
+    p.mixing = kw.get("mixing", 0)
     return p
 
 
@@ -71,7 +72,7 @@ def _params(**kw):
     dict(box=(10.0, -1.0, 10.0)), dict(box=(10.0, float("nan"), 10.0)), dict(cutoff=0.0),
     dict(cutoff=float("inf")), dict(h=-1.0), dict(order=5), dict(order=3), dict(levels=-1),
     dict(levels=17), dict(precision=7), dict(grid=(10, 10, 9), levels=2),
-    dict(grid=(8, 8, 8), levels=0), dict(continuity=5), dict(continuity=-1),
+    dict(grid=(8, 8, 8), levels=0), dict(continuity=5), dict(continuity=-1), dict(mixing=2),
 ])
 def test_plan_create_rejects_bad_parameters(lib, bad):
     p = _params(**bad)
