@@ -223,6 +223,24 @@ def time_lb(w, prm, steps, warmup, dev):
             "precision": "fp64", "ms_per_step": ms, "evals_per_s": 1000.0 / ms, "energy": E}
 
 
+def run_selection(w, head, steps, dev, target=1e-4):
+    """Accuracy-targeted (a, h) (Sec. III.E) for this workload at the headline
+    precision, then the evaluation rate at the chosen parameters."""
+    import torch
+    from paper_1308_4005_amd.params import select_parameters
+    pos = torch.tensor(w.pos, dtype=torch.float64, device=dev)
+    c6 = torch.tensor(w.c6, dtype=torch.float64, device=dev)
+    t = time.time()
+    s = select_parameters(pos, c6, w.box, target, precision=head, device=dev.index)
+    wall = time.time() - t
+    prm = dict(a=s.a, h=s.h, order=4, levels=0)
+    r = time_precision(w, prm, head, max(5, steps // 2), 2, dev, stages=False)
+    return {"target_rms_rel_F": target, "a": s.a, "h": s.h, "levels": s.levels, "measured_rms_rel_F": s.error,
+            "C_local_s": s.C_local, "C_grids_s": s.C_grids, "C_accuracy": s.C, "iterations": len(s.history),
+            "selection_wall_s": wall, "ms_per_step": r["ms"], "evals_per_s": 1000.0 / r["ms"],
+            "reference": f"error against an evaluation with a cutoff 1.7x larger (same h), {head}"}
+
+
 def golden_errors(E, F, gold):
     import numpy as np
     if gold is None:
@@ -277,6 +295,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="leave out the batched-form measurement")
     ap.add_argument("--no-family", action="store_true", help="leave out the smoothing-family measurement")
     ap.add_argument("--no-lb", action="store_true", help="leave out the Lorentz-Berthelot measurement")
+    ap.add_argument("--no-select", action="store_true", help="leave out the parameter-selection measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: MLS here is a single-GPU path "
@@ -356,6 +375,13 @@ def main():
         lb = time_lb(w, prm, max(5, args.steps // 2), 2, dev)
         log(f"[bench] Lorentz-Berthelot: {lb['ms_per_step']:.3f} ms/eval")
 
+    selection = None
+    if not args.no_select:
+        log("[bench] parameter selection for RMS-relative force error 1e-4")
+        selection = run_selection(w, head, args.steps, dev)
+        log(f"[bench] selected a={selection['a']:.3f} h={selection['h']:.3f}: error "
+            f"{selection['measured_rms_rel_F']:.2e}, {selection['ms_per_step']:.3f} ms/eval")
+
     batched = None
     if not args.no_batch:
         t = time.time()
@@ -404,6 +430,7 @@ def main():
         "roofline": roofline,
         "continuity_family": family,
         "lorentz_berthelot": lb,
+        "parameter_selection": selection,
         "batched": batched,
         "cpu_baseline": cpu,
     }
