@@ -5,10 +5,13 @@ One step = one full evaluation (binning, local pair sum, anterpolation,
 restrictions, level stencils, coarsest all-to-all, prolongations,
 interpolation, energy) of the 1,000,000-atom homogeneous LJ cube at density
 0.8 (a = 3, h = 1 -> 112^3 finest grid, cubic basis, 5 levels), inputs
-resident in HBM.  Both precisions are timed; ``value`` is the FP32-mixed
-rate, with the FP64 rate, their ratio and the accuracy of each beside it.
+resident in HBM.  The evaluation is captured into a graph; after W warm-up
+replays, K replays are timed in equal blocks with events and the median block
+gives the rate.  Both precisions are timed; ``value`` is the FP32-mixed rate,
+with the FP64 rate, their ratio, the accuracy of each against the FP64 oracle
+and the discretisation error against the exact sum beside it.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--blocks B] [--gpus 1]
 
 Prints one JSON line.
 """
@@ -91,7 +94,38 @@ def measured_traffic(stage, precision):
     return None if k is None else k["read_bytes"] + k["write_bytes"]
 
 
-def time_precision(w, prm, precision, steps, warmup, dev, continuity=2, stages=True):
+def time_graph(run, steps, warmup, blocks, dev):
+    """Capture ``run`` (one evaluation) into a graph, replay it ``warmup``
+    times, then time ``steps`` replays in ``blocks`` equal blocks with events;
+    returns (median block ms per replay, every block's ms per replay)."""
+    import statistics
+    import torch
+    run()                                   # eager once: lazily created streams exist before capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    for _ in range(warmup):
+        g.replay()
+    per = max(1, steps // blocks)
+    stream = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(blocks + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for b in range(blocks):
+        for _ in range(per):
+            g.replay()
+        ev[b + 1].record(stream)
+    torch.cuda.synchronize()
+    block_ms = [ev[b].elapsed_time(ev[b + 1]) / per for b in range(blocks)]
+    del g
+    return statistics.median(block_ms), block_ms
+
+
+def time_precision(w, prm, precision, steps, warmup, dev, continuity=2, stages=True, blocks=0):
+    """Evaluations of one plan on the workload.  With ``blocks`` > 0 the
+    evaluation is captured into a graph and ``ms`` is the median block of
+    replays; ``eager_ms`` is always the rate of plain evaluate calls."""
     import torch
     from paper_1308_4005_amd import Plan, Result
     plan = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], precision=precision,
@@ -102,22 +136,26 @@ def time_precision(w, prm, precision, steps, warmup, dev, continuity=2, stages=T
                  torch.empty((w.n, 3), dtype=torch.float64, device=dev))
     for _ in range(warmup):
         plan.evaluate(pos, c6, out=out)
+    eager_steps = steps if blocks == 0 else max(5, steps // 5)
     stream = torch.cuda.current_stream(dev)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record(stream)
-    for _ in range(steps):
+    for _ in range(eager_steps):
         plan.evaluate(pos, c6, out=out)
     t1.record(stream)
     torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / steps
+    eager_ms = t0.elapsed_time(t1) / eager_steps
+    ms, block_ms = eager_ms, None
+    if blocks > 0:
+        ms, block_ms = time_graph(lambda: plan.evaluate(pos, c6, out=out), steps, warmup, blocks, dev)
     # stage breakdown: library hipEvents at every stage boundary (in this mode
     # the stages run one after another on one stream)
     stage_ms = {}
     if stages:
         plan.set_timing(True)
-        for _ in range(steps):
+        for _ in range(min(steps, 200)):
             plan.evaluate(pos, c6, out=out)
         torch.cuda.synchronize()
         stage_ms, cnt = plan.read_timing()
@@ -127,7 +165,7 @@ def time_precision(w, prm, precision, steps, warmup, dev, continuity=2, stages=T
     F = out.forces.cpu().numpy()
     info = plan.info
     plan.close()
-    return dict(ms=ms, stage_ms=stage_ms, E=E, F=F, info=info)
+    return dict(ms=ms, eager_ms=eager_ms, block_ms=block_ms, stage_ms=stage_ms, E=E, F=F, info=info)
 
 
 def time_batched(ws, precision, steps, warmup, dev):
@@ -170,7 +208,7 @@ def time_batched(ws, precision, steps, warmup, dev):
         for pl, (p, c), o in zip(plans, views, outs):
             pl.evaluate(p, c, out=o)
     sweep()
-    seq_steps = max(2, steps // 4)
+    seq_steps = max(2, min(20, steps // 4))
     torch.cuda.synchronize()
     t0.record(stream)
     for _ in range(seq_steps):
@@ -234,7 +272,7 @@ def run_selection(w, head, steps, dev, target=1e-4):
     s = select_parameters(pos, c6, w.box, target, precision=head, device=dev.index)
     wall = time.time() - t
     prm = dict(a=s.a, h=s.h, order=4, levels=0)
-    r = time_precision(w, prm, head, max(5, steps // 2), 2, dev, stages=False)
+    r = time_precision(w, prm, head, max(50, steps // 5), 5, dev, stages=False, blocks=5)
     return {"target_rms_rel_F": target, "a": s.a, "h": s.h, "levels": s.levels, "measured_rms_rel_F": s.error,
             "C_local_s": s.C_local, "C_grids_s": s.C_grids, "C_accuracy": s.C, "iterations": len(s.history),
             "selection_wall_s": wall, "ms_per_step": r["ms"], "evals_per_s": 1000.0 / r["ms"],
@@ -257,6 +295,38 @@ def golden_errors(E, F, gold):
                 sampled_atoms=int(len(idx)))
 
 
+def discretisation(prm, precisions, dev):
+    """Error of the library's output against the exact periodic sum (Ewald,
+    stored for 512 atoms of the 32,000-atom cube at density 0.8) with the
+    headline a, h and order; the error does not depend on the system size."""
+    import numpy as np
+    import torch
+    from paper_1308_4005_amd import Plan
+    from paper_1308_4005_amd import workloads as W
+    path = os.path.join(ROOT, "tests", "golden", "cube32k_exact.json")
+    if not os.path.exists(path):
+        return None
+    gold = json.load(open(path))
+    w = W.cube(gold["n"], gold["density"], seed=gold["seed"])
+    pos = torch.tensor(w.pos, dtype=torch.float64, device=dev)
+    c6 = torch.tensor(w.c6, dtype=torch.float64, device=dev)
+    idx = np.asarray(gold["sample"])
+    Fx = np.asarray(gold["forces"])
+    nref = np.linalg.norm(Fx, axis=1)
+    out = {"workload": f"cube32k: {w.n} atoms, L={w.box[0]:.4f}, density {gold['density']}, seed {gold['seed']}",
+           "reference": "exact periodic sum by Ewald at 512 sampled atoms"}
+    for p in precisions:
+        plan = Plan(w.box, prm["a"], prm["h"], prm["order"], 0, precision=p, n_max=w.n, device=dev.index)
+        r = plan.evaluate(pos, c6)
+        torch.cuda.synchronize()
+        diff = np.linalg.norm(r.forces.cpu().numpy()[idx] - Fx, axis=1)
+        out[p] = {"rms_rel_F": float(np.sqrt(np.sum(diff ** 2) / np.sum(nref ** 2))),
+                  "paper_dF": float(np.mean(diff / nref)), "max_F": float(np.max(diff) / np.sqrt(np.mean(nref ** 2))),
+                  "levels": plan.info["levels"], "h_eff": list(plan.info["h_eff"])}
+        plan.close()
+    return out
+
+
 def cpu_baseline(prm, target_n):
     """The FP64 oracle, timed on a bounded sample: a 32,000-atom cube of the
     same density with the same a, h, p (3 levels), scaled by the atom ratio
@@ -273,18 +343,21 @@ def cpu_baseline(prm, target_n):
             oracle_mls.mls(w.pos, w.c6, w.box, prm["a"], prm["h"], prm["order"], 3)
             times.append(time.perf_counter() - t0)
     dt = float(np.median(times))
+    avail = len(os.sched_getaffinity(0))
     return {"value": (1.0 / dt) * (w.n / target_n), "unit": "evals/s (1M-atom equivalent)",
-            "cores": 1, "kind": "oracle",
+            "cores": 1, "cores_available": avail, "kind": "oracle",
             "sample": f"oracle.mls FP64 on a {w.n}-atom cube (rho 0.8, a={prm['a']}, h={prm['h']}, "
                       f"p={prm['order']}, 3 levels): median of 3 runs {dt:.2f} s per evaluation, scaled by "
-                      f"{w.n}/{target_n} atoms; numpy single thread (BLAS limited to 1)"}
+                      f"{w.n}/{target_n} atoms; numpy single thread (BLAS limited to 1, no process pool) "
+                      f"of {avail} cores available"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=1000, help="timed graph replays (split into --blocks blocks)")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--blocks", type=int, default=5, help="timed blocks; the median block is reported")
     ap.add_argument("--workload", default="cube1M")
     ap.add_argument("--a", type=float, default=3.0)
     ap.add_argument("--h", type=float, default=1.0)
@@ -319,9 +392,9 @@ def main():
     precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     res = {}
     for p in precisions:
-        log(f"[bench] timing {p}: warmup {args.warmup}, steps {args.steps}")
-        res[p] = time_precision(w, prm, p, args.steps, args.warmup, dev)
-        log(f"[bench] {p}: {res[p]['ms']:.3f} ms/eval stages {json.dumps({k: round(v, 4) for k, v in res[p]['stage_ms'].items()})}")
+        log(f"[bench] timing {p}: warmup {args.warmup}, steps {args.steps} in {args.blocks} blocks")
+        res[p] = time_precision(w, prm, p, args.steps, args.warmup, dev, blocks=args.blocks)
+        log(f"[bench] {p}: {res[p]['ms']:.3f} ms/eval (graph, median block), eager {res[p]['eager_ms']:.3f} stages {json.dumps({k: round(v, 4) for k, v in res[p]['stage_ms'].items()})}")
 
     head = "mixed" if "mixed" in res else precisions[0]
     info = res[head]["info"]
@@ -355,6 +428,9 @@ def main():
             dE=abs(res["mixed"]["E"] - res["fp64"]["E"]) / abs(res["fp64"]["E"]),
             rms_rel_F=float(np.sqrt(np.sum(dif ** 2) / np.sum(Fd ** 2))))
 
+    log("[bench] discretisation error against the exact sum (32,000-atom cube)")
+    disc = discretisation(prm, precisions, dev)
+
     # the smoothing-function family (continuity C^1..C^4, Sec. III.B) at the
     # headline precision; k = 2 is the headline itself
     family = None
@@ -365,14 +441,15 @@ def main():
                 r = res[head]
             else:
                 log(f"[bench] continuity C^{k}")
-                r = time_precision(w, prm, head, max(5, args.steps // 2), 2, dev, continuity=k, stages=False)
+                r = time_precision(w, prm, head, max(50, args.steps // 5), 5, dev, continuity=k, stages=False,
+                                   blocks=args.blocks)
             family["ms_per_step"][f"C{k}"] = r["ms"]
             family["energy"][f"C{k}"] = r["E"]
 
     lb = None
     if not args.no_lb:
         log("[bench] Lorentz-Berthelot mixing")
-        lb = time_lb(w, prm, max(5, args.steps // 2), 2, dev)
+        lb = time_lb(w, prm, max(5, args.steps // 20), 2, dev)
         log(f"[bench] Lorentz-Berthelot: {lb['ms_per_step']:.3f} ms/eval")
 
     selection = None
@@ -422,11 +499,14 @@ def main():
                    "order": args.order, "levels": info["levels"], "taps": info["taps"],
                    "in_cutoff_pairs": pairs},
         "particle_evals_per_s": w.n * 1000.0 / ms,
-        "per_precision": {p: {"evals_per_s": 1000.0 / r["ms"], "ms_per_step": r["ms"],
-                              "stage_ms": r["stage_ms"], "serial_ms_per_step": sum(r["stage_ms"].values()),
+        "timing": f"graph replays of one evaluation: {args.warmup} warm-up, then {args.steps} replays in "
+                  f"{args.blocks} blocks timed with events; ms_per_step is the median block",
+        "per_precision": {p: {"evals_per_s": 1000.0 / r["ms"], "ms_per_step": r["ms"], "block_ms": r["block_ms"],
+                              "eager_ms_per_step": r["eager_ms"], "stage_ms": r["stage_ms"], "serial_ms_per_step": sum(r["stage_ms"].values()),
                               "energy": r["E"]} for p, r in res.items()},
         "mixed_over_fp64": (res["fp64"]["ms"] / res["mixed"]["ms"]) if len(res) == 2 else None,
         "accuracy": accuracy,
+        "discretisation_error": disc,
         "roofline": roofline,
         "continuity_family": family,
         "lorentz_berthelot": lb,

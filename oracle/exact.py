@@ -21,14 +21,16 @@ from .lattice import ewald_fhat
 __all__ = ["ewald_field", "exact_ewald", "exact_ewald_lb", "exact_direct"]
 
 
-def ewald_field(pos, w, box, beta=None, tol=1e-16, chunk=2048):
+def ewald_field(pos, w, box, beta=None, tol=1e-16, chunk=2048, targets=None):
     """Potential u_i = sum'_{(j,n)} w_j |x_i - x_j - n o L|^-6 of source
-    weights w at every atom, and g_i = sum' w_j (dphi/dr / r)(x_i - x_j - n o L),
-    so that an atom of weight v_i feels the force v_i g_i.  Ewald split."""
+    weights w at every atom (or at the atoms ``targets`` only), and
+    g_i = sum' w_j (dphi/dr / r)(x_i - x_j - n o L), so that an atom of weight
+    v_i feels the force v_i g_i.  Ewald split."""
     pos = np.asarray(pos, dtype=np.float64)
     box = np.asarray(box, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64)
-    n = len(pos)
+    tidx = np.arange(len(pos)) if targets is None else np.asarray(targets)
+    n = len(tidx)
     V = float(np.prod(box))
     if beta is None:
         beta = 3.0 / float(np.min(box))
@@ -39,15 +41,15 @@ def ewald_field(pos, w, box, beta=None, tol=1e-16, chunk=2048):
     g = np.zeros((n, 3))
     for i0 in range(0, n, chunk):
         i1 = min(n, i0 + chunk)
+        ti = tidx[i0:i1]
         for nx in range(-nr[0], nr[0] + 1):
             for ny in range(-nr[1], nr[1] + 1):
                 for nz in range(-nr[2], nr[2] + 1):
                     s = np.array([nx, ny, nz]) * box
-                    d = pos[i0:i1, None, :] - pos[None, :, :] - s   # (ci, n, 3)
+                    d = pos[ti, None, :] - pos[None, :, :] - s      # (ci, N, 3)
                     r2 = np.sum(d * d, axis=2)
                     if nx == 0 and ny == 0 and nz == 0:
-                        ar = np.arange(i0, i1)
-                        r2[ar - i0, ar] = np.inf
+                        r2[np.arange(i1 - i0), ti] = np.inf
                     m = r2 < rc * rc
                     if not m.any():
                         continue
@@ -74,17 +76,18 @@ def ewald_field(pos, w, box, beta=None, tol=1e-16, chunk=2048):
     for k0 in range(0, len(kvec), 512):
         kv = kvec[k0:k0 + 512]
         f = fh[k0:k0 + 512]
-        ph = pos @ kv.T                                # (n, K)
+        ph = pos @ kv.T                                # (N, K)
         c, s = np.cos(ph), np.sin(ph)
         Sc = w @ c                                     # Re S(k)
         Ss = w @ s                                     # Im S(k)
+        c, s = c[tidx], s[tidx]
         # u_i gets (1/V) sum_k fhat Re(e^{-ik x_i} S(k))
         u += (c * Sc + s * Ss) @ f / V
         # g_i = -(1/V) sum_k fhat k sum_j w_j sin(k.(x_i - x_j))
         sinterm = s * Sc - c * Ss                       # sum_j w_j sin(k.(x_i-x_j))
         g -= ((sinterm * f) @ kv) / V
     # remove the r = 0 term of the smooth part
-    u -= beta ** 6 / 6.0 * w
+    u -= beta ** 6 / 6.0 * w[tidx]
     return u, g
 
 
