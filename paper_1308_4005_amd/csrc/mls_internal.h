@@ -188,9 +188,22 @@ struct BatchPhase {
   int grid = 0;                // persistent grid in blocks (0: one block per item)
 };
 
+// Workgroups of a launch go to the chip's eight XCDs in turn (hardware block
+// b runs on XCD b mod 8), and each XCD has its own L2.  xcd_block maps b to a
+// logical block so that every XCD gets one contiguous range of logical blocks
+// (XCD x: [x q + min(x, r), ...) for nblk = 8 q + r); data shared by
+// neighbouring blocks (nearby atoms, adjacent grid rows) is then fetched into
+// one L2 instead of eight.  A bijection on [0, nblk).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+  const int x = b % kXcds, i = b / kXcds;
+  const int q = nblk / kXcds, r = nblk % kXcds;
+  return x * q + (x < r ? x : r) + i;
+}
+
 template <class K>
 __global__ void __launch_bounds__(K::kThreads) k_one(typename K::Args a) {
-  K::run(a, blockIdx.x);
+  K::run(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 template <class K>

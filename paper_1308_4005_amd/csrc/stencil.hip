@@ -268,7 +268,7 @@ __device__ __forceinline__ void stencil_tile(const StencilLevel& V, const int4 t
 // One plan: all levels of the plan in one launch, level descriptors by value.
 template <class T, int R, int ZC, int W>
 __global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const int4* __restrict__ tiles) {
-  const int4 tinfo = tiles[blockIdx.x];
+  const int4 tinfo = tiles[xcd_block(blockIdx.x, gridDim.x)];
   stencil_tile<T, R, ZC, W>(L.lv[tinfo.x], tinfo);
 }
 
