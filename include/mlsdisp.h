@@ -180,8 +180,10 @@ mls_status mls_plan_copy_stage(mls_plan_t plan, int what, int level, void* dst, 
 
 /* Synchronise the plan's last stream and report the device flags set by
  * evaluations since the previous call (bit 0: non-finite position, bit 1:
- * non-finite or negative C6), then clear them.  *flags: host.  Returns
- * MLS_ERR_NONFINITE when a flag is set, else MLS_OK. */
+ * non-finite or negative C6, bit 2: internal consistency check of the
+ * anterpolation blocking failed, results invalid), then clear them.
+ * *flags: host.  Returns MLS_ERR_NONFINITE when bit 0 or 1 is set,
+ * MLS_ERR_HIP when only bit 2 is, else MLS_OK. */
 mls_status mls_plan_status(mls_plan_t plan, int* flags);
 
 /* Per-stage device timing for measurement: with timing enabled, each

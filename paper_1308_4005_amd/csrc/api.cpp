@@ -254,7 +254,8 @@ mls_status mls_plan_status(mls_plan_t P, int* flags) {
   HIP_TRY(hipMemcpy(h, P->d_flags, sizeof(h), hipMemcpyDeviceToHost), "read flags");
   HIP_TRY(hipMemset(P->d_flags, 0, sizeof(h)), "clear flags");
   *flags = h[0];
-  if (h[0]) { set_error("input data contained non-finite positions or non-finite/negative C6"); return MLS_ERR_NONFINITE; }
+  if (h[0] & 3) { set_error("input data contained non-finite positions or non-finite/negative C6"); return MLS_ERR_NONFINITE; }
+  if (h[0]) { set_error("internal error: an atom fell outside its anterpolation block"); return MLS_ERR_HIP; }
   return MLS_OK;
 }
 

@@ -536,6 +536,7 @@ mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* 
     mls_plan_s* P = new (std::nothrow) mls_plan_s();
     if (!P) { set_error("host allocation failed"); return fail(MLS_ERR_OOM); }
     B->plans[b] = P;
+    P->batch_member = true;
     mls_status st = build_plan(per_box[b], n_per_box[b], P);
     if (st != MLS_OK) {
       set_error("box " + std::to_string(b) + ": " + mls_last_error());

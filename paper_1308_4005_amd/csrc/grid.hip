@@ -216,6 +216,143 @@ struct AnterpOwned {
   }
 };
 
+// Two-phase anterpolation.  Phase 1: a block takes the atoms of one block of
+// linked cells only (no halo), adds their p^3 contributions into an LDS tile
+// spanning every finest point those atoms reach (unwrapped indices), and
+// stores the tile into its own box of the expanded grid.  Phase 2: every
+// finest point sums the (at most 4 x 4 x 4, usually 1 to 8) expanded-grid
+// values that belong to it, periodic images included, in a fixed order.
+// Weights in W (FP32 in mixed precision), charges accumulated in FP64.
+template <int P, class W>
+struct AnterpTile {
+  using Args = AnterpTileArgs;
+  static constexpr int kThreads = kAntThreads;
+  static __device__ void run(const Args& a, int b) {
+    __shared__ double tile[kAntTileMax];
+    __shared__ int seg_begin[kAntTileRows];
+    __shared__ int seg_off[kAntTileRows + 1];
+    const AntTiles& T = a.t;
+    const int* __restrict__ tab = a.tab;
+    const CellGeom& cg = a.cg;
+    const GridGeom& gg = a.gg;
+    const int bi[3] = {b % T.nb[0], (b / T.nb[0]) % T.nb[1], b / (T.nb[0] * T.nb[1])};
+    int c0[3], c1[3], e0[3], len[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      c0[d] = tab[T.off_c[d] + bi[d]];
+      c1[d] = tab[T.off_c[d] + bi[d] + 1];
+      e0[d] = tab[T.off_e[d] + bi[d]];
+      len[d] = tab[T.off_len[d] + bi[d]];
+    }
+    const int vol = len[0] * len[1] * len[2];   // <= kAntTileMax (host-checked)
+    for (int i = threadIdx.x; i < vol; i += kAntThreads) tile[i] = 0.0;
+    // the block's atoms: one contiguous run of sorted atoms per cell row (y, z)
+    const int ny = c1[1] - c0[1];
+    const int nrows = ny * (c1[2] - c0[2]);   // <= kAntTileRows = kAntThreads (host-checked)
+    int len_r = 0;
+    if ((int)threadIdx.x < nrows) {
+      const int cy = c0[1] + threadIdx.x % ny, cz = c0[2] + threadIdx.x / ny;
+      const int row = (cz * cg.nc[1] + cy) * cg.nc[0];
+      const int a0 = a.cstart[row + c0[0]];
+      seg_begin[threadIdx.x] = a0;
+      len_r = a.cstart[row + c1[0]] - a0;
+    }
+    // exclusive scan of the run lengths (one run per thread)
+    seg_off[threadIdx.x] = len_r;
+    __syncthreads();
+    for (int off = 1; off < kAntThreads; off <<= 1) {
+      const int u = (int)threadIdx.x >= off ? seg_off[threadIdx.x - off] : 0;
+      __syncthreads();
+      seg_off[threadIdx.x] += u;
+      __syncthreads();
+    }
+    const int incl = seg_off[threadIdx.x];
+    __syncthreads();
+    seg_off[threadIdx.x + 1] = incl;
+    if (threadIdx.x == 0) seg_off[0] = 0;
+    __syncthreads();
+    const int tot = seg_off[nrows];
+    // atoms far apart in the list go to the 64 lanes of a wave (their LDS
+    // additions rarely meet); the waves take turns within a lane's chunk
+    const int lanepos = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int kWaves = kAntThreads / 64;
+    const int chunk = (tot + 63) / 64;
+    const int i0 = lanepos * chunk, i1 = min(i0 + chunk, tot);
+    int sg = 0;
+    {
+      int lo = 0, hi = nrows;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg_off[mid] <= i0) lo = mid; else hi = mid;
+      }
+      sg = lo;
+    }
+    const int pitch_y = len[0], pitch_z = len[0] * len[1];
+    for (int i = i0 + wave; i < i1; i += kWaves) {
+      while (seg_off[sg + 1] <= i) ++sg;
+      const int ia = seg_begin[sg] + (i - seg_off[sg]);
+      const double4 p = a.xs[ia];
+      const double pc[3] = {p.x, p.y, p.z};
+      W w[3][P];
+      int l0[3];
+      bool inside = true;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double t = pc[d] * gg.invh[d];
+        const double m0 = floor(t);
+        basis_weights<P, W>((W)(t - m0), w[d]);
+        l0[d] = (int)m0 - (P / 2 - 1) - e0[d];
+        inside = inside && l0[d] >= 0 && l0[d] + P <= len[d];
+      }
+      if (!inside) {
+        // cannot happen for atoms of the block's cells (the reached ranges
+        // carry a margin); reported instead of writing outside the tile
+        atomicOr(a.flags, 4);
+        continue;
+      }
+      const W qi = (W)(a.charge ? a.charge[ia] : p.w);
+      double* base = tile + l0[2] * pitch_z + l0[1] * pitch_y + l0[0];
+#pragma unroll
+      for (int jz = 0; jz < P; ++jz)
+#pragma unroll
+        for (int jy = 0; jy < P; ++jy) {
+          const W wzy = qi * w[2][jz] * w[1][jy];
+          double* row = base + jz * pitch_z + jy * pitch_y;
+#pragma unroll
+          for (int jx = 0; jx < P; ++jx) atomicAdd(row + jx, (double)(wzy * w[0][jx]));
+        }
+    }
+    __syncthreads();
+    const int X0 = tab[T.off_x0[0] + bi[0]], Y0 = tab[T.off_x0[1] + bi[1]], Z0 = tab[T.off_x0[2] + bi[2]];
+    for (int i = threadIdx.x; i < vol; i += kAntThreads) {
+      const int lx = i % len[0], ly = (i / len[0]) % len[1], lz = i / pitch_z;
+      a.scratch[((size_t)(Z0 + lz) * T.NX[1] + (Y0 + ly)) * T.NX[0] + (X0 + lx)] = tile[i];
+    }
+  }
+};
+
+struct AnterpCollect {
+  using Args = AnterpCollectArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    const int m = blk * kBlock + threadIdx.x;
+    if (m >= a.g.size) return;
+    const int mx = m % a.g.n[0], my = (m / a.g.n[0]) % a.g.n[1], mz = m / (a.g.n[0] * a.g.n[1]);
+    const AntTiles& T = a.t;
+    const int4 cx = reinterpret_cast<const int4*>(a.tab + T.off_cov[0])[mx];
+    const int4 cy = reinterpret_cast<const int4*>(a.tab + T.off_cov[1])[my];
+    const int4 cz = reinterpret_cast<const int4*>(a.tab + T.off_cov[2])[mz];
+    const int xs[4] = {cx.x, cx.y, cx.z, cx.w}, ys[4] = {cy.x, cy.y, cy.z, cy.w}, zs[4] = {cz.x, cz.y, cz.z, cz.w};
+    double sum = 0.0;
+    for (int kz = 0; kz < 4 && zs[kz] >= 0; ++kz)
+      for (int ky = 0; ky < 4 && ys[ky] >= 0; ++ky) {
+        const double* row = a.scratch + ((size_t)zs[kz] * T.NX[1] + ys[ky]) * T.NX[0];
+        for (int kx = 0; kx < 4 && xs[kx] >= 0; ++kx) sum += row[xs[kx]];
+      }
+    a.q[m] = sum;
+  }
+};
+
 // ------------------------------------------------------------ restriction
 // Per-dimension taps around fine index 2M: offsets 0, +-1, +-3 (, +-5).
 template <int P>
@@ -569,8 +706,86 @@ bool anterp_owned_geom(const mls_plan_s* P, AntGeom& ag) {
   return segs <= kMaxSeg;
 }
 
+bool ant_tiles_build(const mls_plan_s* P, AntTiles& T, std::vector<int>& tab, size_t& scratch) {
+  const GridGeom gg = finest_geom(P);
+  const CellGeom& cg = P->cg;
+  const int half = P->order / 2;
+  int cmax = std::min(cg.nc[0], std::min(cg.nc[1], cg.nc[2]));
+  for (int cb = std::max(cmax, 1); cb >= 1; --cb) {
+    std::vector<int> c[3], e[3], len[3];
+    int maxlen[3] = {0, 0, 0}, maxc[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) {
+      const int nc = cg.nc[d];
+      const int nb = (nc + cb - 1) / cb;
+      for (int b = 0; b <= nb; ++b) c[d].push_back((int)((int64_t)b * nc / nb));
+      for (int b = 0; b < nb; ++b) {
+        // finest points reached by atoms with c0 w <= x < c1 w: floor(x/h) in
+        // [lo, hi], taps floor(x/h) - (p/2 - 1) .. floor(x/h) + p/2
+        const double t0 = c[d][b] * cg.w[d] * gg.invh[d], t1 = c[d][b + 1] * cg.w[d] * gg.invh[d];
+        const int lo = (int)std::floor(t0 - 1e-7), hi = (int)std::floor(t1 + 1e-7);
+        e[d].push_back(lo - (half - 1));
+        len[d].push_back(hi - lo + P->order);
+        maxlen[d] = std::max(maxlen[d], len[d].back());
+        maxc[d] = std::max(maxc[d], c[d][b + 1] - c[d][b]);
+      }
+    }
+    if ((int64_t)maxlen[0] * maxlen[1] * maxlen[2] > kAntTileMax || maxc[1] * maxc[2] > kAntTileRows) continue;
+    // tables
+    tab.clear();
+    for (int d = 0; d < 3; ++d) {
+      const int nb = (int)e[d].size();
+      T.nb[d] = nb;
+      T.off_c[d] = (int)tab.size();
+      tab.insert(tab.end(), c[d].begin(), c[d].end());
+      T.off_e[d] = (int)tab.size();
+      tab.insert(tab.end(), e[d].begin(), e[d].end());
+      T.off_len[d] = (int)tab.size();
+      tab.insert(tab.end(), len[d].begin(), len[d].end());
+      T.off_x0[d] = (int)tab.size();
+      int x0 = 0;
+      for (int b = 0; b < nb; ++b) {
+        tab.push_back(x0);
+        x0 += len[d][b];
+      }
+      T.NX[d] = x0;
+    }
+    for (int d = 0; d < 3; ++d) {
+      while (tab.size() % 4) tab.push_back(0);
+      T.off_cov[d] = (int)tab.size();
+      const int n = gg.n[d];
+      for (int m = 0; m < n; ++m) {
+        int cov[4] = {-1, -1, -1, -1}, k = 0;
+        for (int b = 0; b < T.nb[d]; ++b)
+          for (int img = -2; img <= 2; ++img) {
+            const int l = m + img * n - e[d][b];
+            if (l >= 0 && l < len[d][b]) {
+              if (k == 4) return false;
+              cov[k++] = tab[T.off_x0[d] + b] + l;
+            }
+          }
+        tab.insert(tab.end(), cov, cov + 4);
+      }
+    }
+    scratch = (size_t)T.NX[0] * T.NX[1] * T.NX[2];
+    return true;
+  }
+  return false;
+}
+
 hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s) {
   Level& L1 = P->lv[0];
+  if (P->ant_tiles) {
+    AnterpTileArgs t{P->d_xs, P->d_cell_start, P->cg, finest_geom(P), P->ant, P->d_ant_tab, P->d_ant_scratch,
+                     P->charge, P->d_flags};
+    const int nb = P->ant.nb[0] * P->ant.nb[1] * P->ant.nb[2];
+    const bool mixed = P->precision == MLS_MIXED;
+    hipError_t e;
+    if (P->order == 4) e = mixed ? launch_one<AnterpTile<4, float>>(t, nb, s) : launch_one<AnterpTile<4, double>>(t, nb, s);
+    else e = mixed ? launch_one<AnterpTile<6, float>>(t, nb, s) : launch_one<AnterpTile<6, double>>(t, nb, s);
+    if (e != hipSuccess) return e;
+    AnterpCollectArgs c{P->ant, P->d_ant_tab, P->d_ant_scratch, L1.q, L1.g};
+    return launch_one<AnterpCollect>(c, nblocks(L1.g.size, kBlock), s);
+  }
   AnterpArgs a{P->d_xs, P->d_cell_start, n, P->cg, finest_geom(P), AntGeom{}, L1.q, P->charge};
   if (anterp_owned_geom(P, a.ag)) {
     // every owned point is written, so no zero fill is needed

@@ -134,6 +134,27 @@ struct AnterpArgs {
   const double4* xs; const int* cstart; int n; CellGeom cg; GridGeom gg; AntGeom ag; double* q;
   const double* charge;   // sorted charges (else the xi in xs.w)
 };
+// Two-phase anterpolation of single plans: blocks of linked cells, each with
+// the range of finest points its atoms reach (unwrapped), laid side by side in
+// an expanded grid of NX[0] x NX[1] x NX[2] points; for every finest point the
+// expanded coordinates that hold its contributions (up to four per
+// dimension).  Integer tables at the offsets below.
+constexpr int kAntTileMax = 4096;   // doubles of one block's LDS tile
+constexpr int kAntTileRows = 256;   // cell rows (y, z) of one block
+struct AntTiles {
+  int nb[3];        // blocks per dimension
+  int NX[3];        // expanded grid size per dimension
+  int off_c[3];     // nb + 1 cell boundaries
+  int off_e[3];     // nb first reached points (unwrapped)
+  int off_len[3];   // nb reached lengths
+  int off_x0[3];    // nb offsets into the expanded grid
+  int off_cov[3];   // n int4: covering expanded coordinates (-1: none); 16-byte aligned
+};
+struct AnterpTileArgs {
+  const double4* xs; const int* cstart; CellGeom cg; GridGeom gg; AntTiles t; const int* tab;
+  double* scratch; const double* charge; int* flags;
+};
+struct AnterpCollectArgs { AntTiles t; const int* tab; const double* scratch; double* q; GridDims g; };
 struct TransferArgs {              // restriction (fine -> coarse) and prolongation (coarse -> fine)
   const double* src; GridDims gs;  // q^{k-1} (restriction) or E^{k+1} (prolongation)
   const double* add;               // prolongation: e^k added to the interpolated values
@@ -294,7 +315,12 @@ struct mls_plan_s {
   double* d_partial = nullptr;     // energy partial sums
   int n_partial = 0;
   double* d_scratch = nullptr;     // small reductions (grid means)
-  int* d_flags = nullptr;
+  int* d_flags = nullptr;          // [0]: input flags (1 position, 2 C6, 4 anterpolation tile overrun)
+  bool batch_member = false;       // a box of a batched plan (own kernels and buffers)
+  bool ant_tiles = false;          // two-phase anterpolation tables built
+  mls::AntTiles ant{};
+  int* d_ant_tab = nullptr;
+  double* d_ant_scratch = nullptr; // the expanded grid
   int* d_ncell_max = nullptr;
 
   // the grid chain (anterpolation .. prolongation) runs on a second stream,
@@ -355,6 +381,8 @@ hipError_t launch_copy_stage(mls_plan_s* P, int what, int level, void* dst, hipS
 
 // owner-computes anterpolation blocking of a plan (false: use the atomic kernel)
 bool anterp_owned_geom(const mls_plan_s* P, AntGeom& ag);
+// tables of the two-phase anterpolation; false when no blocking fits
+bool ant_tiles_build(const mls_plan_s* P, AntTiles& t, std::vector<int>& tab, size_t& scratch);
 // z extent candidates of a stencil tile for window R
 bool stencil_tile_ok(int R, int zc);
 

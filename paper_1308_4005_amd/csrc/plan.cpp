@@ -354,6 +354,15 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
         }
   }
 
+  // ---------------------------------------------------------------- two-phase anterpolation tables
+  std::vector<int> ant_tab;
+  size_t ant_scratch = 0;
+  P->ant_tiles = false;
+  if (!P->batch_member) {
+    const char* env = std::getenv("MLS_ANTERP_TILES");
+    if (!(env && std::atoi(env) == 0)) P->ant_tiles = ant_tiles_build(P, P->ant, ant_tab, ant_scratch);
+  }
+
   // ---------------------------------------------------------------- device memory
   mls_status st;
 #define ALLOC(ptr, cnt)                                                  \
@@ -424,6 +433,10 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   ALLOC(P->d_row_w, P->row_w.size());
   ALLOC(P->d_row_wf, P->row_w.size());
   ALLOC(P->d_Kl, P->Kl.size());
+  if (P->ant_tiles) {
+    ALLOC(P->d_ant_tab, ant_tab.size());
+    ALLOC(P->d_ant_scratch, ant_scratch);
+  }
 #undef ALLOC
   hipError_t e;
   if (!P->taps.empty()) {
@@ -453,6 +466,9 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
     return hip_fail(e, "copy stencil wave split");
   if ((e = hipMemcpy(P->d_Kl, P->Kl.data(), P->Kl.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "copy coarsest kernel");
+  if (P->ant_tiles &&
+      (e = hipMemcpy(P->d_ant_tab, ant_tab.data(), ant_tab.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "copy anterpolation tables");
   if ((e = hipMemset(P->d_flags, 0, 4 * sizeof(int))) != hipSuccess) return hip_fail(e, "clear flags");
   if ((e = hipMemset(P->d_scratch, 0, 64 * sizeof(double))) != hipSuccess) return hip_fail(e, "clear scratch");
   return MLS_OK;
