@@ -401,65 +401,89 @@ struct PairAccM {
   int cnt;
 };
 
-__device__ __forceinline__ int entry_bits(int ix, int dy, int dz) { return (ix + 1) | ((dy + 2) << 2) | ((dz + 2) << 5); }
+// Per-lane target data of the FP32 scan.
+struct PairLaneF {
+  float xx, yy, zz;     // target cell-relative coordinates
+  float cxf, ncf;       // target cell x index, cells along x
+  int self_ent;         // the target's own home-row entry (-1 for idle lanes)
+  int safe_j;           // a valid source index for idle drain slots
+};
 
+// Queue entry: source index << 8 | x image ix (2 bits) | dy (3 bits) | dz (3
+// bits), the three as two's-complement fields.
+__device__ __forceinline__ int entry_bits(int ix, int dy, int dz) { return (ix & 3) | ((dy & 7) << 2) | ((dz & 7) << 5); }
+
+// Full g_0 evaluation of the queued sources.  The loop body has no branches:
+// slots past a lane's count (and the target itself) evaluate a harmless pair
+// with zero weight, so every lane adds exactly 0 for them.
 template <int K>
-__device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, int cnt, int lane, int self_ent,
-                                               const float4& xi, int cxi, const float4* __restrict__ xr,
-                                               const float* __restrict__ xif, const CellGeom& g,
+__device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, int cnt, int lane, const PairLaneF& L,
+                                               const float4* __restrict__ xr, const float* __restrict__ xif,
                                                const PairConstF& pc, PairAccM& A) {
+  const float r2_idle = 0.25f * pc.a2;
   for (int t = 0; __any(t < cnt); ++t) {
-    const int ent = queue[t * kWaveQ + lane];
-    if (t < cnt && ent != self_ent) {
-      const int j = ent >> 8;
-      const int ix = (ent & 3) - 1, dy = ((ent >> 2) & 7) - 2, dz = ((ent >> 5) & 7) - 2;
-      const float4 xj = xr[j];
-      const float bx = (float)(cxi - ix * g.nc[0]);
-      const float dxv = fmaf(bx - xj.w, pc.w[0], xi.x) - xj.x;
-      const float dyv = fmaf((float)-dy, pc.w[1], xi.y) - xj.y;
-      const float dzv = fmaf((float)-dz, pc.w[2], xi.z) - xj.z;
-      const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
-      float gg, fr;
-      g0_pair<float, K>(r2, pc, gg, fr);
-      const float wj = xif[j];
-      A.e += (double)(wj * gg);
-      const float f = wj * fr;
-      A.fx += (double)(f * dxv);
-      A.fy += (double)(f * dyv);
-      A.fz += (double)(f * dzv);
-    }
+    const int q = queue[t * kWaveQ + lane];
+    const bool ok = (t < cnt) & (q != L.self_ent);
+    const int ent = ok ? q : 0;
+    const int j = ok ? (int)((unsigned)ent >> 8) : L.safe_j;
+    const float4 xj = xr[j];
+    const int ix = (ent << 30) >> 30, dy = (ent << 27) >> 29, dz = (ent << 24) >> 29;
+    const float bx = fmaf((float)ix, -L.ncf, L.cxf);
+    const float dxv = fmaf(bx - xj.w, pc.w[0], L.xx) - xj.x;
+    const float dyv = fmaf((float)-dy, pc.w[1], L.yy) - xj.y;
+    const float dzv = fmaf((float)-dz, pc.w[2], L.zz) - xj.z;
+    const float r2 = ok ? dxv * dxv + dyv * dyv + dzv * dzv : r2_idle;
+    float gg, fr;
+    g0_pair<float, K>(r2, pc, gg, fr);
+    const float wj = ok ? xif[j] : 0.0f;
+    A.e += (double)(wj * gg);
+    const float f = wj * fr;
+    A.fx += (double)(f * dxv);
+    A.fy += (double)(f * dyv);
+    A.fz += (double)(f * dzv);
   }
 }
 
+// Scan sources [j, j1) of one row run (image ix along x, row offsets dy, dz).
+// The filter loop touches no accumulator: it stops when a queue may
+// overflow, the queues are drained, and the filter resumes.
 template <int K>
 __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int dz, int* __restrict__ queue,
-                                              int lane, int self_ent, const float4& xi, int cxi,
-                                              const float4* __restrict__ xr, const float* __restrict__ xif,
-                                              const CellGeom& g, const PairConstF& pc, PairAccM& A) {
-  const float bx = (float)(cxi - ix * g.nc[0]);
-  const float ay = fmaf((float)-dy, pc.w[1], xi.y);
-  const float az = fmaf((float)-dz, pc.w[2], xi.z);
+                                              int lane, const PairLaneF& L, const float4* __restrict__ xr,
+                                              const float* __restrict__ xif, const PairConstF& pc, PairAccM& A) {
+  // the drain rebuilds these with the same operations
+  const float bx = fmaf((float)ix, -L.ncf, L.cxf);
+  const float ay = fmaf((float)-dy, pc.w[1], L.yy);
+  const float az = fmaf((float)-dz, pc.w[2], L.zz);
   const int bits = entry_bits(ix, dy, dz);
   int* const qlane = queue + lane;
-  while (__any(j < j1)) {
-    float4 xj[kBatch];
+  int cnt = A.cnt;
+  for (;;) {
+    bool full = false;
+    while (__any(j < j1)) {
+      float4 xj[kBatch];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) xj[b] = xr[j + b];
+      for (int b = 0; b < kBatch; ++b) xj[b] = xr[j + b];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      const float dxv = fmaf(bx - xj[b].w, pc.w[0], xi.x) - xj[b].x;
-      const float dyv = ay - xj[b].y, dzv = az - xj[b].z;
-      const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
-      const bool hit = (j + b < j1) & (r2 < pc.a2);
-      qlane[kWaveQ * A.cnt] = ((j + b) << 8) | bits;
-      A.cnt += hit ? 1 : 0;
+      for (int b = 0; b < kBatch; ++b) {
+        const float dxv = fmaf(bx - xj[b].w, pc.w[0], L.xx) - xj[b].x;
+        const float dyv = ay - xj[b].y, dzv = az - xj[b].z;
+        const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
+        const bool hit = (j + b < j1) & (r2 < pc.a2);
+        qlane[kWaveQ * cnt] = ((j + b) << 8) | bits;
+        cnt += hit ? 1 : 0;
+      }
+      j += j < j1 ? kBatch : 0;
+      if (__any(cnt > kQueue - kBatch)) {
+        full = true;
+        break;
+      }
     }
-    j += j < j1 ? kBatch : 0;
-    if (__any(A.cnt > kQueue - kBatch)) {
-      pair_drain_f32<K>(queue, A.cnt, lane, self_ent, xi, cxi, xr, xif, g, pc, A);
-      A.cnt = 0;
-    }
+    if (!full) break;
+    pair_drain_f32<K>(queue, cnt, lane, L, xr, xif, pc, A);
+    cnt = 0;
   }
+  A.cnt = cnt;
 }
 
 template <int K>
@@ -482,7 +506,7 @@ struct PairTrimF32 {
   const double4 xd = ar.xs[sc];   // FP64 position: only for choosing rows and cells
   const int c = ar.cell_s[sc];
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
-  const int self_ent = active ? ((sc << 8) | entry_bits(0, 0, 0)) : -1;
+  const PairLaneF L{xi.x, xi.y, xi.z, (float)cx, (float)g.nc[0], active ? ((sc << 8) | entry_bits(0, 0, 0)) : -1, sc};
   PairAccM A{0.0, 0.0, 0.0, 0.0, 0};
   const double a2 = (double)pc.a2 * (1.0 + 1e-6);
   const float reach = (float)(1.0 + 1e-5);
@@ -522,11 +546,11 @@ struct PairTrimF32 {
         k0 = cstart[row + lo2];
         k1 = cstart[row + hi2 + 1];
       }
-      pair_scan_f32<K>(j0, j1, ix1, dy, dz, queue, lane, self_ent, xi, cx, xr, xif, g, pc, A);
-      pair_scan_f32<K>(k0, k1, ix2, dy, dz, queue, lane, self_ent, xi, cx, xr, xif, g, pc, A);
+      pair_scan_f32<K>(j0, j1, ix1, dy, dz, queue, lane, L, xr, xif, pc, A);
+      pair_scan_f32<K>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xif, pc, A);
     }
   }
-  pair_drain_f32<K>(queue, A.cnt, lane, self_ent, xi, cx, xr, xif, g, pc, A);
+  pair_drain_f32<K>(queue, A.cnt, lane, L, xr, xif, pc, A);
   if (active) {
     const double wi = (double)xif[sc];
     ar.e0[sc] = A.e;
