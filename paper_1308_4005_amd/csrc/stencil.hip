@@ -233,7 +233,9 @@ __device__ __forceinline__ void stencil_tile(const StencilLevel& V, const int4 t
     tile[i] = (T)(q[(size_t)wrapz[lz] * gps + (size_t)wrapy[ly] * V.n[0] + wrapx[lx]] - mean);
   }
   __syncthreads();
-  const int tx = lane & 7, ty = lane >> 3;
+  // lanes 0-31 take the even rows, 32-63 the odd ones: with a row pitch of
+  // 20 words (R = 6) each half-wave's four rows then cover disjoint banks
+  const int tx = lane & 7, ty = ((lane >> 3) & 3) * 2 + (lane >> 5);
   const T* c = tile + R * PS + (ty + R) * SX + (tx + R);
   T acc[ZC];
 #pragma unroll
