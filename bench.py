@@ -65,24 +65,25 @@ def work_model(plan_info, n, pairs, order):
     }
 
 
-# kernel that carries each stage of the 10^6-atom cube (cell width a/2 there)
-STAGE_KERNEL = {("pair", "mixed"): "void k_one<PairTrimF32>", ("pair", "fp64"): "void k_one<PairTrimF64>",
-                ("stencil", "mixed"): "void k_stencil_tile<float, 6, 16, 4>",
-                ("stencil", "fp64"): "void k_stencil_tile<double, 6, 16, 4>",
-                ("anterpolation", "mixed"): "void k_one<AnterpOwned<4, float> >",
-                ("anterpolation", "fp64"): "void k_one<AnterpOwned<4, double> >",
-                ("interpolation", "mixed"): "void k_one<Interp<4, float> >",
-                ("interpolation", "fp64"): "void k_one<Interp<4, double> >"}
+# kernels that carry each stage of the 10^6-atom cube (cell width a/2 there)
+STAGE_KERNEL = {("pair", "mixed"): ["void k_one<PairTrimF32<2> >"],
+                ("pair", "fp64"): ["void k_one<PairTrimF64<2, false> >"],
+                ("stencil", "mixed"): ["void k_stencil_tile<float, 6, 16, 4>"],
+                ("stencil", "fp64"): ["void k_stencil_tile<double, 6, 16, 4>"],
+                ("anterpolation", "mixed"): ["void k_one<AnterpTile<4, float> >", "void k_one<AnterpCollect>"],
+                ("anterpolation", "fp64"): ["void k_one<AnterpTile<4, double> >", "void k_one<AnterpCollect>"],
+                ("interpolation", "mixed"): ["void k_one<Interp<4, float> >"],
+                ("interpolation", "fp64"): ["void k_one<Interp<4, double> >"]}
 
 
 def measured_traffic(stage, precision):
-    """HBM bytes per launch of the stage's kernel, from the committed
+    """HBM bytes per launch of the stage's kernels, from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE record (calibrated on a plain copy); None
     when no record exists or any kernel source changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    name = STAGE_KERNEL.get((stage, precision))
-    if name is None or not os.path.exists(path):
+    names = STAGE_KERNEL.get((stage, precision))
+    if names is None or not os.path.exists(path):
         return None
     rec = json.load(open(path))
     csrc = os.path.join(ROOT, "paper_1308_4005_amd", "csrc")
@@ -90,8 +91,13 @@ def measured_traffic(stage, precision):
         fp = os.path.join(csrc, f)
         if not os.path.exists(fp) or hashlib.sha1(open(fp, "rb").read()).hexdigest() != h:
             return None
-    k = rec["kernels"].get(name)
-    return None if k is None else k["read_bytes"] + k["write_bytes"]
+    total = 0.0
+    for name in names:
+        k = rec["kernels"].get(name)
+        if k is None:
+            return None
+        total += k["read_bytes"] + k["write_bytes"]
+    return total
 
 
 def time_graph(run, steps, warmup, blocks, dev):
