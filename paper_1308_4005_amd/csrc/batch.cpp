@@ -162,8 +162,8 @@ mls_status build_phases(mls_batch_s* B) {
       set_box(s2, b, sa, 1);
       set_box(s3, b, sa, nblk(nc, 256));
       set_box(sc, b, ScatterArgs{P->d_cid, P->d_slot, n, P->d_cell_start, P->d_perm_tmp}, nblk(n, 256));
-      set_box(rk, b, RankArgs{P->d_cell_start, P->d_cid, P->d_perm_tmp, n, P->d_perm}, nblk(n, 256));
-      set_box(ga, b, GatherArgs{P->d_perm, n, P->d_xw, P->d_cid, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, P->cg,
+      set_box(rk, b, RankArgs{P->d_cell_start, P->d_perm_tmp, n, P->d_perm}, nblk(n, 256));
+      set_box(ga, b, GatherArgs{P->d_perm, n, P->d_xw, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, P->cg,
                                 mixed ? P->d_partial : nullptr}, nblk(n + kSortedPad, 256));
       if (mixed) set_box(x2, b, SumXiArgs{n + kSortedPad, P->d_partial, P->d_scratch}, 1);
     }

@@ -3,7 +3,7 @@
 // original index.  The result is integer and bit-exact:
 //   1. per atom: wrapped position, cell id, arrival slot in its cell (atomic)
 //   2. exclusive scan of the cell counts (block scan, scan of block sums, add)
-//   3. scatter to start[cell] + slot (arrival order)
+//   3. scatter (index, cell) to start[cell] + slot (arrival order)
 //   4. per atom: reorder by original index (rank among its cell's atoms)
 //   5. gather the sorted position/xi array and cell ids (and, in mixed
 //      precision, the per-block sums of xi)
@@ -186,7 +186,8 @@ struct BinScatter {
   static __device__ void run(const Args& a, int blk) {
     const int i = blk * kBlock + threadIdx.x;
     if (i >= a.n) return;
-    a.perm_tmp[a.start[a.cid[i]] + a.slot[i]] = i;
+    const int c = a.cid[i];
+    a.perm_tmp[a.start[c] + a.slot[i]] = make_int2(i, c);
   }
 };
 
@@ -198,11 +199,11 @@ struct CellRank {
   static __device__ void run(const Args& a, int blk) {
     const int s = blk * kBlock + threadIdx.x;
     if (s >= a.n) return;
-    const int v = a.perm_tmp[s];
-    const int c = a.cid[v];
+    const int2 vc = a.perm_tmp[s];
+    const int v = vc.x, c = vc.y;
     const int b = a.start[c], e = a.start[c + 1];
     int rank = 0;
-    for (int j = b; j < e; ++j) rank += a.perm_tmp[j] < v;
+    for (int j = b; j < e; ++j) rank += a.perm_tmp[j].x < v;
     a.perm[b + rank] = v;
   }
 };
@@ -217,15 +218,19 @@ struct GatherSorted {
     if (s < a.n) {
       const int i = a.perm[s];
       const double4 p = a.xw[i];
-      const int c = a.cid[i];
+      // the cell of BinCount, recomputed from the same wrapped position (no
+      // second random read)
+      const CellGeom& g = a.g;
+      const int cx = max(0, min((int)(p.x * g.inv_w[0]), g.nc[0] - 1));
+      const int cy = max(0, min((int)(p.y * g.inv_w[1]), g.nc[1] - 1));
+      const int cz = max(0, min((int)(p.z * g.inv_w[2]), g.nc[2] - 1));
+      const int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
       a.xs[s] = p;
       a.cell_s[s] = c;
       xi = p.w;
       if (a.xr) {
         // cell-relative FP32 coordinates and the cell x index (exact in FP32)
         // for the mixed-precision pair kernel
-        const CellGeom& g = a.g;
-        int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
         a.xr[s] = make_float4((float)(p.x - cx * g.w[0]), (float)(p.y - cy * g.w[1]),
                               (float)(p.z - cz * g.w[2]), (float)cx);
         a.xif[s] = (float)p.w;
@@ -369,11 +374,11 @@ hipError_t launch_binning_scaled(mls_plan_s* P, int n, const double* pos, const 
   if ((e = launch_one<BinScatter>(ScatterArgs{P->d_cid, P->d_slot, n, P->d_cell_start, P->d_perm_tmp},
                                   nblocks(n, kBlock), s)) != hipSuccess)
     return e;
-  if ((e = launch_one<CellRank>(RankArgs{P->d_cell_start, P->d_cid, P->d_perm_tmp, n, P->d_perm},
+  if ((e = launch_one<CellRank>(RankArgs{P->d_cell_start, P->d_perm_tmp, n, P->d_perm},
                                 nblocks(n, kBlock), s)) != hipSuccess)
     return e;
   const bool mixed = P->precision == MLS_MIXED;
-  GatherArgs ga{P->d_perm, n, P->d_xw, P->d_cid, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, g,
+  GatherArgs ga{P->d_perm, n, P->d_xw, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, g,
                 mixed ? P->d_partial : nullptr};
   if ((e = launch_one<GatherSorted>(ga, nblocks(n + kSortedPad, kBlock), s)) != hipSuccess) return e;
   if (mixed) {

@@ -113,10 +113,10 @@ struct BinCountArgs {
 struct LbGatherArgs { const int* perm; int n; const double* sigma; double* sig_s; int* flags; };
 struct LbChargeArgs { const double4* xs; const double* sig_s; int n; int k; double* charge; };
 struct ScanArgs { const int* count; int m; int* start; int* bsum; int* bmax; int* max_count; };
-struct ScatterArgs { const int* cid; const int* slot; int n; const int* start; int* perm_tmp; };
-struct RankArgs { const int* start; const int* cid; const int* perm_tmp; int n; int* perm; };
+struct ScatterArgs { const int* cid; const int* slot; int n; const int* start; int2* perm_tmp; };
+struct RankArgs { const int* start; const int2* perm_tmp; int n; int* perm; };
 struct GatherArgs {
-  const int* perm; int n; const double4* xw; const int* cid;
+  const int* perm; int n; const double4* xw;
   double4* xs; int* cell_s; float4* xr; float* xif; CellGeom g;
   double* xi_partial;   // mixed precision: per-block sums of xi (else null)
 };
@@ -304,7 +304,7 @@ struct mls_plan_s {
   int* d_bmax = nullptr;           // scan block maxima
   bool pair_fast = false;          // half-cutoff cells with per-atom row trimming
   int* d_cid = nullptr;            // n_max: cell of original atom
-  int* d_perm_tmp = nullptr;       // n_max
+  int2* d_perm_tmp = nullptr;      // n_max: (original index, cell) in arrival order
   int* d_perm = nullptr;           // n_max
   int* d_cell_s = nullptr;         // n_max: cell of sorted atom
   double4* d_xs = nullptr;         // n_max: sorted
