@@ -399,7 +399,13 @@ struct PairTrimF64 {
 struct PairAccM {
   double e, fx, fy, fz;
   int cnt;
+  int head;   // FP32 kernel: the lane's queue is a ring of kQueue slots
 };
+
+// An FP32 drain consumes at most this many entries per lane: the lane that
+// forced it is then well below the limit, and lanes with few entries idle for
+// fewer steps than in a drain to empty.
+constexpr int kDrainF = 16;
 
 // Per-lane target data of the FP32 scan.
 struct PairLaneF {
@@ -413,16 +419,18 @@ struct PairLaneF {
 // bits), the three as two's-complement fields.
 __device__ __forceinline__ int entry_bits(int ix, int dy, int dz) { return (ix & 3) | ((dy & 7) << 2) | ((dz & 7) << 5); }
 
-// Full g_0 evaluation of the queued sources.  The loop body has no branches:
-// slots past a lane's count (and the target itself) evaluate a harmless pair
-// with zero weight, so every lane adds exactly 0 for them.
+// Full g_0 evaluation of up to `limit` queued sources per lane, oldest first.
+// The loop body has no branches: slots past a lane's count (and the target
+// itself) evaluate a harmless pair with zero weight, so every lane adds
+// exactly 0 for them.
 template <int K>
-__device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, int cnt, int lane, const PairLaneF& L,
-                                               const float4* __restrict__ xr, const float* __restrict__ xif,
-                                               const PairConstF& pc, PairAccM& A) {
+__device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, int limit, int lane,
+                                               const PairLaneF& L, const float4* __restrict__ xr,
+                                               const float* __restrict__ xif, const PairConstF& pc, PairAccM& A) {
   const float r2_idle = 0.25f * pc.a2;
-  for (int t = 0; __any(t < cnt); ++t) {
-    const int q = queue[t * kWaveQ + lane];
+  const int cnt = A.cnt;
+  for (int t = 0; t < limit && __any(t < cnt); ++t) {
+    const int q = queue[((A.head + t) & (kQueue - 1)) * kWaveQ + lane];
     const bool ok = (t < cnt) & (q != L.self_ent);
     const int ent = ok ? q : 0;
     const int j = ok ? (int)((unsigned)ent >> 8) : L.safe_j;
@@ -442,11 +450,14 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
     A.fy += (double)(f * dyv);
     A.fz += (double)(f * dzv);
   }
+  const int done = min(cnt, limit);
+  A.head = (A.head + done) & (kQueue - 1);
+  A.cnt = cnt - done;
 }
 
 // Scan sources [j, j1) of one row run (image ix along x, row offsets dy, dz).
 // The filter loop touches no accumulator: it stops when a queue may
-// overflow, the queues are drained, and the filter resumes.
+// overflow, the queues are partly drained, and the filter resumes.
 template <int K>
 __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int dz, int* __restrict__ queue,
                                               int lane, const PairLaneF& L, const float4* __restrict__ xr,
@@ -457,8 +468,9 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
   const float az = fmaf((float)-dz, pc.w[2], L.zz);
   const int bits = entry_bits(ix, dy, dz);
   int* const qlane = queue + lane;
-  int cnt = A.cnt;
   for (;;) {
+    int cnt = A.cnt;
+    const int head = A.head;
     bool full = false;
     while (__any(j < j1)) {
       float4 xj[kBatch];
@@ -470,7 +482,7 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
         const float dyv = ay - xj[b].y, dzv = az - xj[b].z;
         const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
         const bool hit = (j + b < j1) & (r2 < pc.a2);
-        qlane[kWaveQ * cnt] = ((j + b) << 8) | bits;
+        qlane[kWaveQ * ((head + cnt) & (kQueue - 1))] = ((j + b) << 8) | bits;
         cnt += hit ? 1 : 0;
       }
       j += j < j1 ? kBatch : 0;
@@ -479,11 +491,10 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
         break;
       }
     }
+    A.cnt = cnt;
     if (!full) break;
-    pair_drain_f32<K>(queue, cnt, lane, L, xr, xif, pc, A);
-    cnt = 0;
+    pair_drain_f32<K>(queue, kDrainF, lane, L, xr, xif, pc, A);
   }
-  A.cnt = cnt;
 }
 
 template <int K>
@@ -550,7 +561,7 @@ struct PairTrimF32 {
       pair_scan_f32<K>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xif, pc, A);
     }
   }
-  pair_drain_f32<K>(queue, A.cnt, lane, L, xr, xif, pc, A);
+  pair_drain_f32<K>(queue, kQueue, lane, L, xr, xif, pc, A);
   if (active) {
     const double wi = (double)xif[sc];
     ar.e0[sc] = A.e;
