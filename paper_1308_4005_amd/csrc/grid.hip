@@ -572,18 +572,22 @@ struct Interp {
     double su = 0.0, sxx = 0.0;
     if (s < a.n) {
       const double4 p = a.xs[s];
+      // the per-atom loads that do not depend on the grid go first, so their
+      // latency overlaps the grid gathers
+      const int i = a.perm[s];
+      const double e0 = a.e0[s];
+      const double fl0 = a.floc[3 * (size_t)s + 0], fl1 = a.floc[3 * (size_t)s + 1], fl2 = a.floc[3 * (size_t)s + 2];
       W w[3][P], dw[3][P];
       int idx[3][P];
       interp_setup<P, W>(p, gg, w, dw, idx);
       double u, gx, gy, gz;
       interp_grid<P, W>(a.E1, gg, w, dw, idx, u, gx, gy, gz);
-      const int i = a.perm[s];
       const double xi = p.w;
-      const double utot = a.e0[s] + u;
+      const double utot = e0 + u;
       if (a.out.forces) {
-        a.out.forces[3 * (size_t)i + 0] = a.floc[3 * (size_t)s + 0] + xi * gx * gg.invh[0];
-        a.out.forces[3 * (size_t)i + 1] = a.floc[3 * (size_t)s + 1] + xi * gy * gg.invh[1];
-        a.out.forces[3 * (size_t)i + 2] = a.floc[3 * (size_t)s + 2] + xi * gz * gg.invh[2];
+        a.out.forces[3 * (size_t)i + 0] = fl0 + xi * gx * gg.invh[0];
+        a.out.forces[3 * (size_t)i + 1] = fl1 + xi * gy * gg.invh[1];
+        a.out.forces[3 * (size_t)i + 2] = fl2 + xi * gz * gg.invh[2];
       }
       if (a.out.potential) a.out.potential[i] = utot;
       if (a.out.dE_dc6) a.out.dE_dc6[i] = -(utot - a.cself * xi) / (2.0 * xi);
