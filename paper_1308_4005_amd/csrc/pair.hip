@@ -225,11 +225,12 @@ struct PairWave {
 // is at least a, and trims every other row to the cells the cutoff sphere
 // can reach along x (at most two runs of cells: one per periodic image).  A
 // cheap distance test appends sources inside the cutoff to the lane's LDS
-// queue, four candidates per step so four loads are in flight; whenever a
-// queue may overflow, and once at the end, all lanes drain their queues
-// through the full g_0 evaluation, so the expensive arithmetic runs on
-// nearly full waves instead of being masked per candidate.  An entry packs
-// the source index (< 2^25) with two bits per dimension for its image.
+// queue (a ring), four candidates per step so four loads are in flight;
+// whenever a queue may overflow all lanes drain up to kDrain of their oldest
+// entries through the full g_0 evaluation, and at the end everything left,
+// so the expensive arithmetic runs on nearly full waves instead of being
+// masked per candidate.  An entry packs the source index (< 2^25) with two
+// bits per dimension for its image.
 constexpr int kWaveQ = 64;    // lanes per block (one wave)
 constexpr int kQueue = 32;    // entries per lane
 constexpr int kBatch = 4;     // candidates per filter step
@@ -239,71 +240,95 @@ __device__ __forceinline__ int image_bits(int ix, int iy, int iz) { return (ix +
 struct PairAcc {
   double e, fx, fy, fz;
   int cnt;
+  int head;   // the lane's queue is a ring of kQueue slots
 };
 
+// A drain during the scan consumes at most this many entries per lane: the
+// lane that forced it is then well below the limit, and lanes with few
+// entries idle for fewer steps than in a drain to empty.
+constexpr int kDrain = 16;
+
+// Full g_0 evaluation of up to `limit` queued sources per lane, oldest first.
+// The loop body has no branches: slots past a lane's count (and the target
+// itself) evaluate a harmless pair with zero weight, adding exactly 0.
 template <int K, bool LB>
-__device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, int cnt, int lane, int self_ent,
-                                               const double4& xi, const double4* __restrict__ xs, const CellGeom& g,
-                                               const PairConst& pc, const double* __restrict__ sig, double sig_i,
-                                               PairAcc& A) {
-  for (int t = 0; __any(t < cnt); ++t) {
-    const int ent = queue[t * kWaveQ + lane];
-    if (t < cnt && ent != self_ent) {
-      const int j = ent >> 6;
-      const double sx = (double)((ent & 3) - 1) * g.L[0];
-      const double sy = (double)(((ent >> 2) & 3) - 1) * g.L[1];
-      const double sz = (double)(((ent >> 4) & 3) - 1) * g.L[2];
-      const double4 xj = xs[j];
-      // same arithmetic as the filter, so the cutoff decision is identical
-      const double dx = (xi.x - sx) - xj.x;
-      const double dy = (xi.y - sy) - xj.y;
-      const double dz = (xi.z - sz) - xj.z;
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      double gg, fr;
-      g0_pair<double, K>(r2, pc, gg, fr);
-      const double wj = src_weight<LB>(xj.w, sig, sig_i, j);
-      A.e += wj * gg;
-      const double f = wj * fr;
-      A.fx += f * dx;
-      A.fy += f * dy;
-      A.fz += f * dz;
-    }
+__device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, int limit, int lane, int self_ent,
+                                               int safe_j, const double4& xi, const double4* __restrict__ xs,
+                                               const CellGeom& g, const PairConst& pc, const double* __restrict__ sig,
+                                               double sig_i, PairAcc& A) {
+  const double r2_idle = 0.25 * pc.a2;
+  const int cnt = A.cnt;
+  for (int t = 0; t < limit && __any(t < cnt); ++t) {
+    const int q = queue[((A.head + t) & (kQueue - 1)) * kWaveQ + lane];
+    const bool ok = (t < cnt) & (q != self_ent);
+    const int ent = ok ? q : image_bits(0, 0, 0);
+    const int j = ok ? (ent >> 6) : safe_j;
+    const double sx = (double)((ent & 3) - 1) * g.L[0];
+    const double sy = (double)(((ent >> 2) & 3) - 1) * g.L[1];
+    const double sz = (double)(((ent >> 4) & 3) - 1) * g.L[2];
+    const double4 xj = xs[j];
+    // same arithmetic as the filter
+    const double dx = (xi.x - sx) - xj.x;
+    const double dy = (xi.y - sy) - xj.y;
+    const double dz = (xi.z - sz) - xj.z;
+    const double r2 = ok ? dx * dx + dy * dy + dz * dz : r2_idle;
+    double gg, fr;
+    g0_pair<double, K>(r2, pc, gg, fr);
+    const double wj = ok ? src_weight<LB>(xj.w, sig, sig_i, j) : 0.0;
+    A.e += wj * gg;
+    const double f = wj * fr;
+    A.fx += f * dx;
+    A.fy += f * dy;
+    A.fz += f * dz;
   }
+  const int done = min(cnt, limit);
+  A.head = (A.head + done) & (kQueue - 1);
+  A.cnt = cnt - done;
 }
 
 // Scan sources [j, j1) seen through image bits `img` (convergent: every lane
 // calls it; lanes with an empty range just take part in the votes).  Reads
 // may run up to kBatch - 1 rows past j1: the sorted array is padded with
-// far-away rows, and rows past j1 are never kept.
+// far-away rows, and rows past j1 are never kept.  The filter loop touches no
+// accumulator: it stops when a queue may overflow, the queues are partly
+// drained, and the filter resumes.
 template <int K, bool LB>
 __device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int* __restrict__ queue, int lane,
-                                              int self_ent, const double4& xi, const double4* __restrict__ xs,
-                                              const CellGeom& g, const PairConst& pc, const double* __restrict__ sig,
-                                              double sig_i, PairAcc& A) {
+                                              int self_ent, int safe_j, const double4& xi,
+                                              const double4* __restrict__ xs, const CellGeom& g, const PairConst& pc,
+                                              const double* __restrict__ sig, double sig_i, PairAcc& A) {
   const double ax = xi.x - (double)((img & 3) - 1) * g.L[0];
   const double ay = xi.y - (double)(((img >> 2) & 3) - 1) * g.L[1];
   const double az = xi.z - (double)(((img >> 4) & 3) - 1) * g.L[2];
   int* const qlane = queue + lane;
-  while (__any(j < j1)) {
-    double4 xj[kBatch];
+  for (;;) {
+    int cnt = A.cnt;
+    const int head = A.head;
+    bool full = false;
+    while (__any(j < j1)) {
+      double4 xj[kBatch];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) xj[b] = xs[j + b];
+      for (int b = 0; b < kBatch; ++b) xj[b] = xs[j + b];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      const double dx = ax - xj[b].x, dy = ay - xj[b].y, dz = az - xj[b].z;
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      const bool hit = (j + b < j1) & (r2 < pc.a2);
-      // the slot at the queue's end is free: write unconditionally, keep on a hit
-      qlane[kWaveQ * A.cnt] = ((j + b) << 6) | img;
-      A.cnt += hit ? 1 : 0;
+      for (int b = 0; b < kBatch; ++b) {
+        const double dx = ax - xj[b].x, dy = ay - xj[b].y, dz = az - xj[b].z;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const bool hit = (j + b < j1) & (r2 < pc.a2);
+        // the next free slot: write unconditionally, keep on a hit
+        qlane[kWaveQ * ((head + cnt) & (kQueue - 1))] = ((j + b) << 6) | img;
+        cnt += hit ? 1 : 0;
+      }
+      // lanes past their range stay put (j <= j1 + kBatch - 1): reads stay
+      // within the padding however long other lanes keep scanning
+      j += j < j1 ? kBatch : 0;
+      if (__any(cnt > kQueue - kBatch)) {
+        full = true;
+        break;
+      }
     }
-    // lanes past their range stay put (j <= j1 + kBatch - 1): reads stay
-    // within the padding however long other lanes keep scanning
-    j += j < j1 ? kBatch : 0;
-    if (__any(A.cnt > kQueue - kBatch)) {
-      pair_drain_f64<K, LB>(queue, A.cnt, lane, self_ent, xi, xs, g, pc, sig, sig_i, A);
-      A.cnt = 0;
-    }
+    A.cnt = cnt;
+    if (!full) break;
+    pair_drain_f64<K, LB>(queue, kDrain, lane, self_ent, safe_j, xi, xs, g, pc, sig, sig_i, A);
   }
 }
 
@@ -372,11 +397,13 @@ struct PairTrimF64 {
         k0 = cstart[row + lo2];
         k1 = cstart[row + hi2 + 1];
       }
-      pair_scan_f64<K, LB>(j0, j1, image_bits(ix1, iy, iz), queue, lane, self_ent, xi, xs, g, pc, ar.sig, sig_i, A);
-      pair_scan_f64<K, LB>(k0, k1, image_bits(ix2, iy, iz), queue, lane, self_ent, xi, xs, g, pc, ar.sig, sig_i, A);
+      pair_scan_f64<K, LB>(j0, j1, image_bits(ix1, iy, iz), queue, lane, self_ent, sc, xi, xs, g, pc, ar.sig, sig_i,
+                           A);
+      pair_scan_f64<K, LB>(k0, k1, image_bits(ix2, iy, iz), queue, lane, self_ent, sc, xi, xs, g, pc, ar.sig, sig_i,
+                           A);
     }
   }
-  pair_drain_f64<K, LB>(queue, A.cnt, lane, self_ent, xi, xs, g, pc, ar.sig, sig_i, A);
+  pair_drain_f64<K, LB>(queue, kQueue, lane, self_ent, sc, xi, xs, g, pc, ar.sig, sig_i, A);
   if (active) {
     ar.e0[sc] = A.e;
     ar.floc[3 * (size_t)sc + 0] = xi.w * A.fx;
