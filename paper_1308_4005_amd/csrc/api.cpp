@@ -173,26 +173,38 @@ mls_status mls_evaluate_lb(mls_plan_t P, int64_t n, const double* pos, const dou
   P->last_stream = s;
   P->last_n = n;
   const int ni = (int)n;
+  if (!P->side) {
+    HIP_TRY(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    HIP_TRY(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming), "hipEventCreateWithFlags");
+    HIP_TRY(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming), "hipEventCreateWithFlags");
+  }
+  const hipStream_t g = P->side;
   // binning with xi = sqrt(2 eps) (the e_i of the pair coefficient) and the
   // sorted sigma
   HIP_TRY(launch_binning_scaled(P, ni, pos, eps, 2.0, s), "binning");
   HIP_TRY(launch_lb_gather(P, ni, sigma, s), "sigma gather");
+  // the seven grid chains run on the plan's second stream, concurrently with
+  // the local part, and meet it at interpolation
+  HIP_TRY(hipEventRecord(P->ev_fork, s), "fork");
+  HIP_TRY(hipStreamWaitEvent(g, P->ev_fork, 0), "fork");
   HIP_TRY(launch_pair_lb(P, ni, s), "pair kernel");
   // grid part once per charge vector (their grids in turn become the plan's
-  // working levels)
+  // working levels; the vectors share one charge buffer, in stream order)
   for (int k = 0; k < 7; ++k) {
-    HIP_TRY(launch_lb_charge(P, ni, k, s), "charges");
+    HIP_TRY(launch_lb_charge(P, ni, k, g), "charges");
     std::swap(P->lv, P->lb_lv[k]);
     P->charge = P->d_charge;
-    hipError_t e = launch_anterpolate(P, ni, s);
-    for (int j = 2; e == hipSuccess && j <= P->levels; ++j) e = launch_restrict(P, j - 1, s);
-    if (e == hipSuccess) e = launch_stencils(P, s);
-    if (e == hipSuccess) e = launch_coarsest(P, s);
-    for (int j = P->levels - 1; e == hipSuccess && j >= 1; --j) e = launch_prolong(P, j, s);
+    hipError_t e = launch_anterpolate(P, ni, g);
+    for (int j = 2; e == hipSuccess && j <= P->levels; ++j) e = launch_restrict(P, j - 1, g);
+    if (e == hipSuccess) e = launch_stencils(P, g);
+    if (e == hipSuccess) e = launch_coarsest(P, g);
+    for (int j = P->levels - 1; e == hipSuccess && j >= 1; --j) e = launch_prolong(P, j, g);
     P->charge = nullptr;
     std::swap(P->lv, P->lb_lv[k]);
     if (e != hipSuccess) return hip_fail(e, "grid part");
   }
+  HIP_TRY(hipEventRecord(P->ev_join, g), "join");
+  HIP_TRY(hipStreamWaitEvent(s, P->ev_join, 0), "join");
   HIP_TRY(launch_interpolate_lb(P, ni, energy, forces, s), "interpolation");
   return MLS_OK;
 }

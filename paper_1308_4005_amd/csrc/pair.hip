@@ -541,39 +541,49 @@ struct PairTrimF32 {
   const bool active = k < n;
   const int sc = active ? k : n - 1;
   const float4 xi = xr[sc];
-  const double4 xd = ar.xs[sc];   // FP64 position: only for choosing rows and cells
   const int c = ar.cell_s[sc];
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
   const PairLaneF L{xi.x, xi.y, xi.z, (float)cx, (float)g.nc[0], active ? ((sc << 8) | entry_bits(0, 0, 0)) : -1, sc};
   PairAccM A{0.0, 0.0, 0.0, 0.0, 0};
-  const double a2 = (double)pc.a2 * (1.0 + 1e-6);
-  const float reach = (float)(1.0 + 1e-5);
+  // Rows are chosen and trimmed in the target's cell-relative FP32
+  // coordinates.  The gaps are shrunk and the reach grown by margins (1e-5 of
+  // a cell, 2e-5 of the cutoff) far above their FP32 rounding (~1e-7), so no
+  // cell that holds a source inside the cutoff is ever skipped.
+  const float a2m = pc.a2 * (1.0f + 2e-5f);
+  const float reach = 1.0f + 2e-5f;
+  const float inv_wx = 1.0f / pc.w[0];
+  const int nc0 = g.nc[0], nc1 = g.nc[1], nc2 = g.nc[2];
   for (int dz = -2; dz <= 2; ++dz) {
     const int uz = cz + dz;
-    const int iz = uz < 0 ? -1 : (uz >= g.nc[2] ? 1 : 0);
-    const int tz = uz - iz * g.nc[2];
-    const double gz = gap1(xd.z, uz * g.w[2], g.w[2], 1e-12 * g.L[2]);
+    const int tz = uz < 0 ? uz + nc2 : (uz >= nc2 ? uz - nc2 : uz);
+    const float gz = dz == 0 ? 0.0f
+                             : fmaxf(0.0f, (dz > 0 ? fmaf((float)dz, pc.w[2], -xi.z)
+                                                   : fmaf((float)(-dz - 1), pc.w[2], xi.z)) - 1e-5f * pc.w[2]);
+    const float rem_z = a2m - gz * gz;
+    const int rowz = tz * nc1;
+    int ty = cy - 2 < 0 ? cy - 2 + nc1 : cy - 2;
     for (int dy = -2; dy <= 2; ++dy) {
-      const int uy = cy + dy;
-      const int iy = uy < 0 ? -1 : (uy >= g.nc[1] ? 1 : 0);
-      const int ty = uy - iy * g.nc[1];
-      const double gy = gap1(xd.y, uy * g.w[1], g.w[1], 1e-12 * g.L[1]);
-      const double rem = a2 - (gy * gy + gz * gz);
+      const float gy = dy == 0 ? 0.0f
+                               : fmaxf(0.0f, (dy > 0 ? fmaf((float)dy, pc.w[1], -xi.y)
+                                                     : fmaf((float)(-dy - 1), pc.w[1], xi.y)) - 1e-5f * pc.w[1]);
+      const float rem = rem_z - gy * gy;
       int clo = 0, chi = -1;
-      if (active && rem > 0.0) {
-        const double rx = (double)(sqrtf((float)rem) * reach) + 1e-6 * g.w[0];
-        clo = max(cx - 2, (int)floor((xd.x - rx) * g.inv_w[0]));
-        chi = min(cx + 2, (int)floor((xd.x + rx) * g.inv_w[0]));
+      if (active && rem > 0.0f) {
+        // hardware square root (about 1 ulp): far inside the margin
+        const float rx = fmaf(__builtin_amdgcn_sqrtf(rem), reach, 1e-5f * pc.w[0]);
+        clo = cx + max(-2, (int)floorf((xi.x - rx) * inv_wx));
+        chi = cx + min(2, (int)floorf((xi.x + rx) * inv_wx));
       }
       int lo1 = clo, hi1 = chi, ix1 = 0, lo2 = 0, hi2 = -1, ix2 = 0;
       if (clo < 0) {
-        lo1 = clo + g.nc[0]; hi1 = g.nc[0] - 1; ix1 = -1;
+        lo1 = clo + nc0; hi1 = nc0 - 1; ix1 = -1;
         lo2 = 0; hi2 = chi; ix2 = 0;
-      } else if (chi >= g.nc[0]) {
-        lo1 = clo; hi1 = g.nc[0] - 1; ix1 = 0;
-        lo2 = 0; hi2 = chi - g.nc[0]; ix2 = 1;
+      } else if (chi >= nc0) {
+        lo1 = clo; hi1 = nc0 - 1; ix1 = 0;
+        lo2 = 0; hi2 = chi - nc0; ix2 = 1;
       }
-      const int row = (tz * g.nc[1] + ty) * g.nc[0];
+      const int row = (rowz + ty) * nc0;
+      ty = ty + 1 == nc1 ? 0 : ty + 1;
       int j0 = 0, j1 = 0;
       if (lo1 <= hi1) {
         j0 = cstart[row + lo1];
