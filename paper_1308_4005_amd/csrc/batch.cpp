@@ -204,6 +204,8 @@ mls_status build_phases(mls_batch_s* B) {
   const int gvar = B->order | (mixed ? 0x100 : 0);
   // ------------------------------------------------ anterpolation (eq:anterpolation)
   {
+    HostPhase tile = make_phase<AnterpTileArgs>(BK_ANT_TILE, MLS_T_ANTERP, gvar, nb);
+    HostPhase coll = make_phase<AnterpCollectArgs>(BK_ANT_COLLECT, MLS_T_ANTERP, gvar, nb);
     HostPhase own = make_phase<AnterpArgs>(BK_ANT_OWNED, MLS_T_ANTERP, gvar, nb);
     HostPhase zero = make_phase<FillDArgs>(BK_FILL_D, MLS_T_ANTERP, 0, nb);
     HostPhase atom = make_phase<AnterpArgs>(BK_ANT_ATOMIC, MLS_T_ANTERP, gvar, nb);
@@ -211,13 +213,22 @@ mls_status build_phases(mls_batch_s* B) {
       mls_plan_s* P = B->plans[b];
       const int n = n_of(b);
       AnterpArgs a{P->d_xs, P->d_cell_start, n, P->cg, finest(P), AntGeom{}, P->lv[0].q, nullptr};
-      if (anterp_owned_geom(P, a.ag)) {
+      if (P->ant_tiles) {
+        // two phases: per cell block into the expanded grid, then per point
+        set_box(tile, b, AnterpTileArgs{P->d_xs, P->d_cell_start, P->cg, finest(P), P->ant, P->d_ant_tab,
+                                        P->d_ant_scratch, nullptr, P->d_flags},
+                P->ant.nb[0] * P->ant.nb[1] * P->ant.nb[2]);
+        set_box(coll, b, AnterpCollectArgs{P->ant, P->d_ant_tab, P->d_ant_scratch, P->lv[0].q, P->lv[0].g},
+                nblk(P->lv[0].g.size, 256));
+      } else if (anterp_owned_geom(P, a.ag)) {
         set_box(own, b, a, a.ag.nb[0] * a.ag.nb[1] * a.ag.nb[2]);
       } else {
         set_box(zero, b, FillDArgs{P->lv[0].q, P->lv[0].g.size}, nblk(P->lv[0].g.size, 256));
         set_box(atom, b, a, nblk(n, 256));
       }
     }
+    hp.push_back(std::move(tile));
+    hp.push_back(std::move(coll));
     hp.push_back(std::move(own));
     hp.push_back(std::move(zero));
     hp.push_back(std::move(atom));
@@ -374,6 +385,8 @@ hipError_t launch_phase(const BatchPhase& ph, hipStream_t s) {
     case BK_PAIR_TRIM_F32: return launch_batched_pair(ph, s);
     case BK_ANT_ATOMIC:
     case BK_ANT_OWNED:
+    case BK_ANT_TILE:
+    case BK_ANT_COLLECT:
     case BK_RESTRICT:
     case BK_PROLONG:
     case BK_INTERP:
@@ -536,7 +549,6 @@ mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* 
     mls_plan_s* P = new (std::nothrow) mls_plan_s();
     if (!P) { set_error("host allocation failed"); return fail(MLS_ERR_OOM); }
     B->plans[b] = P;
-    P->batch_member = true;
     mls_status st = build_plan(per_box[b], n_per_box[b], P);
     if (st != MLS_OK) {
       set_error("box " + std::to_string(b) + ": " + mls_last_error());

@@ -862,6 +862,12 @@ hipError_t launch_batched_grid(const BatchPhase& ph, hipStream_t s) {
                            : launch_batched_phase<AnterpOwned<6, double>>(ph, s);
       return mixed ? launch_batched_phase<AnterpOwned<4, float>>(ph, s)
                    : launch_batched_phase<AnterpOwned<4, double>>(ph, s);
+    case BK_ANT_TILE:
+      if (p6) return mixed ? launch_batched_phase<AnterpTile<6, float>>(ph, s)
+                           : launch_batched_phase<AnterpTile<6, double>>(ph, s);
+      return mixed ? launch_batched_phase<AnterpTile<4, float>>(ph, s)
+                   : launch_batched_phase<AnterpTile<4, double>>(ph, s);
+    case BK_ANT_COLLECT: return launch_batched_phase<AnterpCollect>(ph, s);
     case BK_RESTRICT:
       return p6 ? launch_batched_phase<Restrict<6>>(ph, s) : launch_batched_phase<Restrict<4>>(ph, s);
     case BK_PROLONG:

@@ -195,7 +195,7 @@ enum BatchKernel {
   BK_FILL_I, BK_FILL_D, BK_BIN_COUNT, BK_SCAN_BLOCKS, BK_SCAN_SUMS, BK_SCAN_ADD, BK_SCATTER, BK_RANK, BK_GATHER,
   BK_SUM_XI_FINAL,
   BK_PAIR_GENERIC, BK_PAIR_WAVE, BK_PAIR_TRIM_F64, BK_PAIR_TRIM_F32,
-  BK_ANT_ATOMIC, BK_ANT_OWNED, BK_RESTRICT, BK_PROLONG, BK_INTERP, BK_ENERGY,
+  BK_ANT_ATOMIC, BK_ANT_OWNED, BK_ANT_TILE, BK_ANT_COLLECT, BK_RESTRICT, BK_PROLONG, BK_INTERP, BK_ENERGY,
   BK_STENCIL, BK_COARSEST
 };
 
@@ -316,7 +316,6 @@ struct mls_plan_s {
   int n_partial = 0;
   double* d_scratch = nullptr;     // small reductions (grid means)
   int* d_flags = nullptr;          // [0]: input flags (1 position, 2 C6, 4 anterpolation tile overrun)
-  bool batch_member = false;       // a box of a batched plan (own kernels and buffers)
   bool ant_tiles = false;          // two-phase anterpolation tables built
   mls::AntTiles ant{};
   int* d_ant_tab = nullptr;

@@ -358,7 +358,7 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   std::vector<int> ant_tab;
   size_t ant_scratch = 0;
   P->ant_tiles = false;
-  if (!P->batch_member) {
+  {
     const char* env = std::getenv("MLS_ANTERP_TILES");
     if (!(env && std::atoi(env) == 0)) P->ant_tiles = ant_tiles_build(P, P->ant, ant_tab, ant_scratch);
   }
