@@ -230,7 +230,8 @@ __global__ void __launch_bounds__(K::kThreads) k_one(typename K::Args a) {
 template <class K>
 __global__ void __launch_bounds__(K::kThreads) k_batched(const typename K::Args* __restrict__ args,
                                                          const int2* __restrict__ work, int nwork) {
-  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+  // round by round, each XCD takes one contiguous stretch of the work list
+  for (int w = xcd_block(blockIdx.x, gridDim.x); w < nwork; w += gridDim.x) {
     const int2 it = work[w];
     K::run(args[it.x], it.y);
     __syncthreads();   // LDS of the item is free before the next one
@@ -353,7 +354,7 @@ void free_plan(mls_plan_s* plan);
 int scan_blocks(int ncell);
 // halo window of the level stencil and z extent of its LDS tile
 int stencil_window(const mls_plan_s* P);
-int stencil_tile_zc(int R);
+int stencil_tile_zc(int R, bool f64);
 
 // kernel launchers (one per file); all enqueue on `s` and return the launch status
 hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double* c6, hipStream_t s);

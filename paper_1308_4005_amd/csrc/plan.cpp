@@ -317,7 +317,7 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   if (const char* env = std::getenv("MLS_STENCIL_KERNEL")) P->stencil_kernel = std::atoi(env) == 0 ? 0 : 1;
   if (l > 1) {
     const int Rw = stencil_window(P);
-    const int zc = stencil_tile_zc(Rw);
+    const int zc = stencil_tile_zc(Rw, P->precision != MLS_MIXED);
     for (int k = 1; k < l; ++k) {
       const GridDims& g = P->lv[k - 1].g;
       const int tx = (g.n[0] + 7) / 8, ty = (g.n[1] + 7) / 8, tz = (g.n[2] + zc - 1) / zc;

@@ -165,11 +165,12 @@ __global__ void __launch_bounds__(64 * W) k_stencil_stream(const T* __restrict__
 // are added in LDS at the end.
 }  // namespace
 
-// z extent of a stencil tile for halo window R (the FP64 tile with halo must
-// fit the LDS of one CU: (8 + 2R)^2 (ZC + 2R) doubles)
-constexpr int tile_zc(int R) { return R <= 6 ? 16 : 8; }
+// z extent of a single plan's stencil tile for halo window R: 16 for FP32
+// tiles up to R = 6, else 8 (an FP64 tile of depth 16 takes (8 + 2R)^2 (16 +
+// 2R) doubles, 90 KB at R = 6: one block per CU; at depth 8, 64 KB: two)
+constexpr int tile_zc(int R, bool f64) { return R <= 6 && !f64 ? 16 : 8; }
 
-int stencil_tile_zc(int R) { return tile_zc(R); }
+int stencil_tile_zc(int R, bool f64) { return tile_zc(R, f64); }
 
 namespace {
 
@@ -278,7 +279,7 @@ __global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const 
 template <class T, int R, int ZC, int W>
 __global__ void __launch_bounds__(64 * W) k_stencil_tile_batched(const StencilLevel* __restrict__ lv,
                                                                  const int4* __restrict__ tiles, int ntiles) {
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (int t = xcd_block(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
     const int4 tinfo = tiles[t];
     stencil_tile<T, R, ZC, W>(lv[tinfo.x], tinfo);
     __syncthreads();
@@ -368,7 +369,7 @@ int stencil_window(const mls_plan_s* P) {
 
 template <class T, int R>
 hipError_t launch_tile(mls_plan_s* P, const T* wts, hipStream_t s) {
-  constexpr int kTileZ = tile_zc(R);
+  constexpr int kTileZ = tile_zc(R, sizeof(T) == 8);
   StencilLaunch L{};
   L.nlev = P->levels - 1;
   int t = 0;
