@@ -421,8 +421,8 @@ struct PairTrimF64 {
 //   d_x = (cx_i - ix nc - cx_j) w_x + xr_i - xr_j,  d_y = yr_i - dy w_y - yr_j, ...
 // with integer cell offsets, so no large coordinates enter FP32 arithmetic.
 // Queue entries pack the source index (< 2^24), the x image and the row
-// offsets dy, dz.  Pair arithmetic is FP32; e_0 and the forces accumulate in
-// FP64.
+// offsets dy, dz.  Pair arithmetic is FP32; each drain sums its terms in
+// FP32, and e_0 and the forces accumulate the drains' sums in FP64.
 struct PairAccM {
   double e, fx, fy, fz;
   int cnt;
@@ -456,6 +456,9 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
                                                const float* __restrict__ xif, const PairConstF& pc, PairAccM& A) {
   const float r2_idle = 0.25f * pc.a2;
   const int cnt = A.cnt;
+  // the (at most 32) terms of one drain are summed in FP32, the drains' sums
+  // in FP64
+  float e = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
   for (int t = 0; t < limit && __any(t < cnt); ++t) {
     const int q = queue[((A.head + t) & (kQueue - 1)) * kWaveQ + lane];
     const bool ok = (t < cnt) & (q != L.self_ent);
@@ -471,12 +474,16 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
     float gg, fr;
     g0_pair<float, K>(r2, pc, gg, fr);
     const float wj = ok ? xif[j] : 0.0f;
-    A.e += (double)(wj * gg);
+    e = fmaf(wj, gg, e);
     const float f = wj * fr;
-    A.fx += (double)(f * dxv);
-    A.fy += (double)(f * dyv);
-    A.fz += (double)(f * dzv);
+    fx = fmaf(f, dxv, fx);
+    fy = fmaf(f, dyv, fy);
+    fz = fmaf(f, dzv, fz);
   }
+  A.e += (double)e;
+  A.fx += (double)fx;
+  A.fy += (double)fy;
+  A.fz += (double)fz;
   const int done = min(cnt, limit);
   A.head = (A.head + done) & (kQueue - 1);
   A.cnt = cnt - done;
