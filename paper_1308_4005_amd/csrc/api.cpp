@@ -129,22 +129,36 @@ mls_status mls_evaluate(mls_plan_t P, int64_t n, const double* pos, const double
     HIP_TRY(hipEventRecord(P->ev_fork, s), "fork");
     HIP_TRY(hipStreamWaitEvent(g, P->ev_fork, 0), "fork");
   }
-  HIP_TRY(launch_pair(P, ni, s), "pair kernel");
-  HIP_TRY(mark(1 + MLS_T_PAIR), "timing event");
+  // In concurrent mode the local part is submitted after the grid chain's
+  // first `pair_after` stages (default 1: the anterpolation, whose blocks need
+  // 35 KB of LDS each and are otherwise held back until the pair kernel has
+  // filled and drained every CU; measured with graph replays at 10^6 atoms:
+  // 0.835 ms per evaluation against 0.877 ms with the pair kernel first).
+  const int after = fork ? P->pair_after : 0;
+  auto pair = [&]() -> mls_status {
+    HIP_TRY(launch_pair(P, ni, s), "pair kernel");
+    HIP_TRY(mark(1 + MLS_T_PAIR), "timing event");
+    return MLS_OK;
+  };
+  mls_status st;
+  if (after == 0 && (st = pair()) != MLS_OK) return st;
   HIP_TRY(launch_anterpolate(P, ni, g), "anterpolation");
   HIP_TRY(mark(1 + MLS_T_ANTERP), "timing event");
+  if (after == 1 && (st = pair()) != MLS_OK) return st;
   for (int k = 2; k <= P->levels; ++k) HIP_TRY(launch_restrict(P, k - 1, g), "restriction");
   HIP_TRY(mark(1 + MLS_T_RESTRICT), "timing event");
+  if (after == 2 && (st = pair()) != MLS_OK) return st;
   HIP_TRY(launch_stencils(P, g), "level stencils");
   HIP_TRY(mark(1 + MLS_T_STENCIL), "timing event");
+  if (after == 3 && (st = pair()) != MLS_OK) return st;
   HIP_TRY(launch_coarsest(P, g), "coarsest grid");
   HIP_TRY(mark(1 + MLS_T_COARSEST), "timing event");
+  if (after == 4 && (st = pair()) != MLS_OK) return st;
   for (int k = P->levels - 1; k >= 1; --k) HIP_TRY(launch_prolong(P, k, g), "prolongation");
   HIP_TRY(mark(1 + MLS_T_PROLONG), "timing event");
-  if (fork) {
-    HIP_TRY(hipEventRecord(P->ev_join, g), "join");
-    HIP_TRY(hipStreamWaitEvent(s, P->ev_join, 0), "join");
-  }
+  if (fork) HIP_TRY(hipEventRecord(P->ev_join, g), "join");
+  if (after == 5 && (st = pair()) != MLS_OK) return st;
+  if (fork) HIP_TRY(hipStreamWaitEvent(s, P->ev_join, 0), "join");
   HIP_TRY(launch_interpolate(P, ni, energy, forces, potential, dE_dc6, s), "interpolation");
   HIP_TRY(mark(1 + MLS_T_INTERP), "timing event");
   return MLS_OK;

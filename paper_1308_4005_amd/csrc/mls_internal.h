@@ -304,6 +304,7 @@ struct mls_plan_s {
   int* d_bsum = nullptr;           // scan block sums
   int* d_bmax = nullptr;           // scan block maxima
   bool pair_fast = false;          // half-cutoff cells with per-atom row trimming
+  int pair_after = 1;              // concurrent mode: grid-chain stages submitted before the local part
   int* d_cid = nullptr;            // n_max: cell of original atom
   int2* d_perm_tmp = nullptr;      // n_max: (original index, cell) in arrival order
   int* d_perm = nullptr;           // n_max

@@ -182,6 +182,7 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   gamma_coeffs(cont, P->gamma_c);
   P->cself = gamma_s(0.0, cont) * P->inv_a6;  // eq:self-interaction-energy
   hipGetDevice(&P->device);
+  if (const char* env = std::getenv("MLS_PAIR_AFTER")) P->pair_after = std::min(5, std::max(0, std::atoi(env)));
 
   // ---------------------------------------------------------------- levels
   int l = p.levels;
