@@ -406,6 +406,15 @@ mls_status run_phases(mls_batch_s* B, hipStream_t s, hipEvent_t* ev) {
   const bool fork = !ev;
   bool forked = false, joined = false;
   int stage = -1;
+  // concurrent mode: the local part's phases are submitted after the
+  // anterpolation phases, whose LDS-heavy blocks then get their CUs first
+  std::vector<const BatchPhase*> local;
+  auto flush_local = [&]() -> mls_status {
+    for (const BatchPhase* q : local) HIP_TRY(launch_phase(*q, s), "batch: launch");
+    local.clear();
+    return MLS_OK;
+  };
+  mls_status st;
   for (const BatchPhase& ph : B->phases) {
     while (ev && stage < ph.stage) HIP_TRY(hipEventRecord(ev[++stage], s), "batch: timing event");
     if (fork && !forked && ph.stage > MLS_T_BINNING) {
@@ -413,6 +422,11 @@ mls_status run_phases(mls_batch_s* B, hipStream_t s, hipEvent_t* ev) {
       HIP_TRY(hipStreamWaitEvent(B->side, B->ev_fork, 0), "batch: fork");
       forked = true;
     }
+    if (forked && ph.stage == MLS_T_PAIR) {
+      local.push_back(&ph);
+      continue;
+    }
+    if (forked && ph.stage > MLS_T_ANTERP && (st = flush_local()) != MLS_OK) return st;
     if (forked && !joined && ph.stage > MLS_T_PROLONG) {
       HIP_TRY(hipEventRecord(B->ev_join, B->side), "batch: join");
       HIP_TRY(hipStreamWaitEvent(s, B->ev_join, 0), "batch: join");
@@ -421,6 +435,7 @@ mls_status run_phases(mls_batch_s* B, hipStream_t s, hipEvent_t* ev) {
     const bool chain = forked && ph.stage >= MLS_T_ANTERP && ph.stage <= MLS_T_PROLONG;
     HIP_TRY(launch_phase(ph, chain ? B->side : s), "batch: launch");
   }
+  if ((st = flush_local()) != MLS_OK) return st;
   if (forked && !joined) {
     HIP_TRY(hipEventRecord(B->ev_join, B->side), "batch: join");
     HIP_TRY(hipStreamWaitEvent(s, B->ev_join, 0), "batch: join");
