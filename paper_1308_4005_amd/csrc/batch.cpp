@@ -294,7 +294,7 @@ mls_status build_phases(mls_batch_s* B) {
     for (int b : order) {
       mls_plan_s* P = B->plans[b];
       Level& L = P->lv[P->levels - 1];
-      set_box(c, b, CoarsestArgs{L.q, L.g, P->d_Kl, L.e}, nblk(L.g.size, kCoarsestThreads));
+      set_box(c, b, CoarsestArgs{L.q, L.g, P->d_Kl, L.e}, nblk(L.g.size, kCoarsestPerBlock));
     }
     hp.push_back(std::move(c));
   }

@@ -170,7 +170,8 @@ struct InterpLbArgs {
   const double* e0; const double* floc; double* forces; double* partial;
 };
 struct CoarsestArgs { const double* q; GridDims g; const double* K; double* e; };
-constexpr int kCoarsestThreads = 256;   // outputs per block of the coarsest-level kernel
+constexpr int kCoarsestThreads = 256;   // threads per block of the coarsest-level kernel
+constexpr int kCoarsestPerBlock = kCoarsestThreads / 64;   // output points per block (one per wave)
 
 // One level of the tiled stencil: grids, scale, and the tap tables of its plan.
 struct StencilLevel {

@@ -286,9 +286,9 @@ __global__ void __launch_bounds__(64 * W) k_stencil_tile_batched(const StencilLe
   }
 }
 
-// Coarsest level: thread per output point, all-to-all over the level.  Up to
-// kCoarseLds points the charges and the kernel are staged in LDS first, so the
-// inner loop reads LDS (q is the same for every lane: a broadcast).
+// Coarsest level: all-to-all over the level, one wave per output point.  Up
+// to kCoarseLds points the charges and the kernel are staged in LDS first, so
+// the inner loop reads LDS.
 constexpr int kCoarseLds = 2048;
 
 struct Coarsest {
@@ -309,26 +309,25 @@ struct Coarsest {
       q = sq;
       K = sk;
     }
-    const int mu = blk * kThreads + threadIdx.x;
+    // one wave per output point: the lanes split the sum over the level's
+    // points, then add their partial sums across the wave (fixed order)
+    const int lane = threadIdx.x & 63;
+    const int mu = blk * kCoarsestPerBlock + (threadIdx.x >> 6);
     if (mu >= g.size) return;
-    const int x = mu % g.n[0], y = (mu / g.n[0]) % g.n[1], z = mu / (g.n[0] * g.n[1]);
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], n01 = n0 * n1;
+    const int x = mu % n0, y = (mu / n0) % n1, z = mu / n01;
     double acc = 0.0;
-    for (int nz = 0; nz < g.n[2]; ++nz) {
-      int dz = z - nz;
-      if (dz < 0) dz += g.n[2];
-      for (int ny = 0; ny < g.n[1]; ++ny) {
-        int dy = y - ny;
-        if (dy < 0) dy += g.n[1];
-        const double* qrow = q + ((size_t)nz * g.n[1] + ny) * g.n[0];
-        const double* krow = K + ((size_t)dz * g.n[1] + dy) * g.n[0];
-        int dx = x;  // x - nx, wrapped, counts down
-        for (int nx = 0; nx < g.n[0]; ++nx) {
-          acc += krow[dx] * qrow[nx];
-          dx = dx == 0 ? g.n[0] - 1 : dx - 1;
-        }
-      }
+    for (int nu = lane; nu < g.size; nu += 64) {
+      const int nz = nu / n01, r = nu - nz * n01, ny = r / n0, nx = r - ny * n0;
+      int dx = x - nx, dy = y - ny, dz = z - nz;
+      dx += dx < 0 ? n0 : 0;
+      dy += dy < 0 ? n1 : 0;
+      dz += dz < 0 ? n2 : 0;
+      acc = fma(K[((size_t)dz * n1 + dy) * n0 + dx], q[nu], acc);
     }
-    a.e[mu] = acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) a.e[mu] = acc;
   }
 };
 inline int nblocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
@@ -429,7 +428,7 @@ hipError_t launch_stencils(mls_plan_s* P, hipStream_t s) {
 
 hipError_t launch_coarsest(mls_plan_s* P, hipStream_t s) {
   Level& L = P->lv[P->levels - 1];
-  return launch_one<Coarsest>(CoarsestArgs{L.q, L.g, P->d_Kl, L.e}, nblocks(L.g.size, Coarsest::kThreads), s);
+  return launch_one<Coarsest>(CoarsestArgs{L.q, L.g, P->d_Kl, L.e}, nblocks(L.g.size, kCoarsestPerBlock), s);
 }
 
 bool stencil_tile_ok(int R, int zc) {
