@@ -1,0 +1,91 @@
+"""The MD oracle (oracle/md.py): the repulsive term of eq:disp-pair-pot against
+the closed form of one pair and its images, Newton's third law and the
+energy gradient; velocity Verlet against its invariants: time reversibility
+(run forward, flip the velocities, run back: the start is recovered to
+rounding) and energy conservation with second-order drift in dt."""
+import numpy as np
+import pytest
+
+from oracle import md as MD
+from paper_1308_4005_amd import workloads as W
+
+
+def test_one_pair_closed_form():
+    box = np.array([20.0, 20.0, 20.0])
+    pos = np.array([[1.0, 2.0, 3.0], [2.1, 2.4, 2.7]])
+    c12 = np.array([4.0, 9.0])
+    E, F = MD.repulsion(pos, c12, box, 3.0)
+    d = pos[0] - pos[1]
+    r2 = d @ d
+    C = np.sqrt(4.0 * 9.0)
+    assert E == pytest.approx(C * r2 ** -6, rel=1e-14)
+    np.testing.assert_allclose(F[0], 12.0 * C * r2 ** -7 * d, rtol=1e-13)
+    np.testing.assert_allclose(F[1], -F[0], rtol=1e-13)
+
+
+def test_images_in_a_narrow_box():
+    # box 2.5 wide in x, cutoff 3: an atom sees its own images at +-2.5 and the
+    # other atom's images; compare with the explicit image list
+    box = np.array([2.5, 9.0, 9.0])
+    pos = np.array([[0.3, 4.0, 4.0], [1.4, 4.5, 4.2]])
+    c12 = np.array([1.0, 2.0])
+    E, F = MD.repulsion(pos, c12, box, 3.0)
+    Eref = 0.0
+    for i in range(2):
+        for j in range(2):
+            for k in range(-3, 4):
+                if i == j and k == 0:
+                    continue
+                d = pos[i] - pos[j] - np.array([k * 2.5, 0, 0])
+                r = np.sqrt(d @ d)
+                if r < 3.0:
+                    Eref += 0.5 * np.sqrt(c12[i] * c12[j]) * r ** -12
+    assert E == pytest.approx(Eref, rel=1e-13)
+    np.testing.assert_allclose(F.sum(axis=0), 0.0, atol=1e-12 * np.abs(F).max())
+
+
+def test_repulsion_forces_are_the_gradient():
+    w = W.cube(60, 0.8, seed=2)
+    c12 = np.where(np.arange(w.n) % 2 == 0, 4.0, 1.0)
+    E, F = MD.repulsion(w.pos, c12, w.box, 2.5)
+    eps = 1e-6
+    for i in (0, 17):
+        for d in range(3):
+            p = w.pos.copy()
+            p[i, d] += eps
+            Ep, _ = MD.repulsion(p, c12, w.box, 2.5)
+            p[i, d] -= 2 * eps
+            Em, _ = MD.repulsion(p, c12, w.box, 2.5)
+            assert -(Ep - Em) / (2 * eps) == pytest.approx(F[i, d], rel=1e-5, abs=1e-6 * np.abs(F).max())
+
+
+@pytest.fixture(scope="module")
+def system():
+    w = W.cube(120, 0.5, seed=8)
+    rng = np.random.default_rng(4)
+    vel = rng.normal(scale=0.3, size=(w.n, 3))
+    c12 = np.full(w.n, 4.0)
+    inv_m = np.full(w.n, 1.0)
+    return w, vel, c12, inv_m
+
+
+def test_velocity_verlet_is_time_reversible(system):
+    w, vel, c12, inv_m = system
+    prm = (w.box, 2.5, 0.9, 4, 2)
+    x1, v1, _, _, _ = MD.md_run(w.pos, vel, w.c6, c12, inv_m, *prm, 0.002, 8)
+    x0, v0, _, _, _ = MD.md_run(x1, -v1, w.c6, c12, inv_m, *prm, 0.002, 8)
+    np.testing.assert_allclose(x0, w.pos, rtol=0, atol=1e-11 * np.abs(w.pos).max())
+    np.testing.assert_allclose(-v0, vel, rtol=0, atol=1e-9 * np.abs(vel).max())
+
+
+def test_energy_drift_is_second_order(system):
+    w, vel, c12, inv_m = system
+    prm = (w.box, 2.5, 0.9, 4, 2)
+    drift = []
+    for dt in (0.004, 0.002):
+        _, _, _, ep, ek = MD.md_run(w.pos, vel, w.c6, c12, inv_m, *prm, dt, int(round(0.04 / dt)))
+        tot = ep + ek
+        drift.append(np.max(np.abs(tot - tot[0])))
+    assert drift[1] < drift[0]
+    # halving dt divides the energy error by about four (velocity Verlet is second order)
+    assert 2.5 < drift[0] / drift[1] < 6.0
