@@ -267,6 +267,43 @@ def time_lb(w, prm, steps, warmup, dev):
             "precision": "fp64", "ms_per_step": ms, "evals_per_s": 1000.0 / ms, "energy": E}
 
 
+def time_md(w, prm, precision, steps, warmup, dev, blocks, chunk=10, dt=0.001):
+    """Molecular dynamics on the workload (mls_md_run): LJ atoms with
+    C6 = 4, C12 = 4 (epsilon = sigma = 1), unit masses, velocities drawn
+    from N(0, 0.8) (seed 29), repulsion cutoff a.  One graph replay runs
+    ``chunk`` velocity-Verlet steps; ``ms_per_step`` is the median block of
+    replays divided by ``chunk``.  Also times one mls_evaluate_md (dispersion
+    plus repulsion) the same way."""
+    import numpy as np
+    import torch
+    from paper_1308_4005_amd import Plan, Result
+    rng = np.random.default_rng(29)
+    plan = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], precision=precision, n_max=w.n,
+                device=dev.index)
+    x = torch.tensor(w.pos, dtype=torch.float64, device=dev)
+    v = torch.tensor(rng.normal(scale=np.sqrt(0.8), size=(w.n, 3)), dtype=torch.float64, device=dev)
+    c6 = torch.tensor(w.c6, dtype=torch.float64, device=dev)
+    c12 = torch.full((w.n,), 4.0, dtype=torch.float64, device=dev)
+    im = torch.ones(w.n, dtype=torch.float64, device=dev)
+    F = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
+    ep = torch.empty(chunk + 1, dtype=torch.float64, device=dev)
+    ek = torch.empty(chunk + 1, dtype=torch.float64, device=dev)
+    out = Result(torch.empty(1, dtype=torch.float64, device=dev), torch.empty((w.n, 3), dtype=torch.float64, device=dev))
+    ms_ev, _ = time_graph(lambda: plan.evaluate_md(x, c6, c12, out=out), steps, warmup, blocks, dev)
+    ms, block_ms = time_graph(lambda: plan.md_run(x, v, c6, c12, im, dt, chunk, forces=F, epot=ep, ekin=ek),
+                              max(blocks, steps // chunk), max(1, warmup // chunk), blocks, dev)
+    torch.cuda.synchronize()
+    flags = plan.status()
+    tot = (ep + ek).cpu().numpy()
+    plan.close()
+    return {"workload": f"{w.name} positions, LJ C6 = C12 = 4, unit masses, velocities N(0, 0.8) (seed 29), "
+                        f"repulsion cutoff {prm['a']}, dt {dt}",
+            "precision": precision, "ms_per_step": ms / chunk, "steps_per_s": 1000.0 * chunk / ms,
+            "block_ms_per_step": [b / chunk for b in block_ms], "steps_per_replay": chunk,
+            "evaluate_md_ms": ms_ev, "flags": flags,
+            "last_replay_total_energy_spread_rel": float((tot.max() - tot.min()) / abs(tot.mean()))}
+
+
 def run_selection(w, head, steps, dev, target=1e-4):
     """Accuracy-targeted (a, h) (Sec. III.E) for this workload at the headline
     precision, then the evaluation rate at the chosen parameters."""
@@ -375,6 +412,7 @@ def main():
     ap.add_argument("--no-family", action="store_true", help="leave out the smoothing-family measurement")
     ap.add_argument("--no-lb", action="store_true", help="leave out the Lorentz-Berthelot measurement")
     ap.add_argument("--no-select", action="store_true", help="leave out the parameter-selection measurement")
+    ap.add_argument("--no-md", action="store_true", help="leave out the molecular-dynamics measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: MLS here is a single-GPU path "
@@ -458,6 +496,12 @@ def main():
         lb = time_lb(w, prm, max(5, args.steps // 20), 2, dev)
         log(f"[bench] Lorentz-Berthelot: {lb['ms_per_step']:.3f} ms/eval")
 
+    md = None
+    if not args.no_md:
+        log("[bench] molecular dynamics (velocity Verlet, dispersion + repulsion)")
+        md = time_md(w, prm, head, args.steps, args.warmup, dev, args.blocks)
+        log(f"[bench] md: {md['ms_per_step']:.3f} ms/step, evaluate_md {md['evaluate_md_ms']:.3f} ms")
+
     selection = None
     if not args.no_select:
         log("[bench] parameter selection for RMS-relative force error 1e-4")
@@ -516,6 +560,7 @@ def main():
         "roofline": roofline,
         "continuity_family": family,
         "lorentz_berthelot": lb,
+        "molecular_dynamics": md,
         "parameter_selection": selection,
         "batched": batched,
         "cpu_baseline": cpu,

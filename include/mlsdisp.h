@@ -140,6 +140,45 @@ mls_status mls_evaluate(mls_plan_t plan, int64_t n, const double* pos, const dou
                         double* energy, double* forces, double* potential, double* dE_dc6,
                         void* stream);
 
+/* Potential energy and forces of the full pair potential eq:disp-pair-pot,
+ * V_ij = C^rep_ij r^-12 - C^disp_ij r^-6 (Sec. II.D), for molecular dynamics
+ * (Sec. III.A): the dispersion part exactly as mls_evaluate, plus the
+ * repulsive part with geometric mixing C^rep_ij = sqrt(C12_i C12_j), summed
+ * directly over every periodic image closer than rc (no grid part: the
+ * r^-12 term is short-ranged):
+ *   E_rep = 1/2 sum_i sum'_{(j,n), r < rc} C^rep_ij r^-12,  F_rep = -grad E_rep.
+ * The repulsion runs in FP64 in every precision mode, on the atoms binned by
+ * the same evaluation.  Plan: geometric mixing.
+ *   c12     device (n) FP64, finite and >= 0 (else device flag bit 3)
+ *   rc      repulsion cutoff, 0 < rc <= a (host)
+ *   energy  device, 1 FP64: E_disp + E_rep (overwritten)
+ *   forces  device (n,3) FP64, or NULL
+ * Same ordering, threading and error behaviour as mls_evaluate. */
+mls_status mls_evaluate_md(mls_plan_t plan, int64_t n, const double* pos, const double* c6, const double* c12,
+                           double rc, double* energy, double* forces, void* stream);
+
+/* nsteps steps of velocity-Verlet molecular dynamics with the forces of
+ * mls_evaluate_md (the paper's MD runs, Sec. III.A, do not name their
+ * integrator; velocity Verlet is the standard choice):
+ *   v += dt/2 F/m;  x += dt v;  F = F(x);  v += dt/2 F/m.
+ * pos and vel (device (n,3) FP64) are advanced in place; positions are not
+ * wrapped (the evaluation wraps them internally).  Outputs, all device FP64:
+ *   forces  (n,3): forces at the final positions (required when n > 0)
+ *   epot    (nsteps+1): potential energy after each force evaluation
+ *           (index 0: initial positions)
+ *   ekin    (nsteps+1): kinetic energy 1/2 sum_i |v_i|^2 / inv_mass_i at the
+ *           same instants
+ *   inv_mass device (n) FP64: 1/m_i, finite and > 0 (else device flag bit 3,
+ *           as are non-finite velocities)
+ *   dt      time step (host, finite); nsteps >= 0 (0: one evaluation)
+ * Enqueued on `stream` with no host synchronisation and no allocation
+ * (nsteps + 1 evaluations and nsteps + 1 integrator launches).  Errors: as
+ * mls_evaluate_md, plus MLS_ERR_INVALID_ARG for null outputs, nsteps < 0 or
+ * non-finite dt. */
+mls_status mls_md_run(mls_plan_t plan, int64_t n, double* pos, double* vel, const double* c6, const double* c12,
+                      double rc, const double* inv_mass, double dt, int nsteps, double* forces, double* epot,
+                      double* ekin, void* stream);
+
 /* One evaluation under Lorentz-Berthelot mixing (Sec. II.D,
  * eq:disp-pair-pot-multilevel-LorentzBerthelot): pair coefficient
  * C_ij = 2 sqrt(eps_i eps_j) ((sigma_i + sigma_j)/2)^6 (eq:xi-lj), so
@@ -181,8 +220,10 @@ mls_status mls_plan_copy_stage(mls_plan_t plan, int what, int level, void* dst, 
 /* Synchronise the plan's last stream and report the device flags set by
  * evaluations since the previous call (bit 0: non-finite position, bit 1:
  * non-finite or negative C6, bit 2: internal consistency check of the
- * anterpolation blocking failed, results invalid), then clear them.
- * *flags: host.  Returns MLS_ERR_NONFINITE when bit 0 or 1 is set,
+ * anterpolation blocking failed, results invalid, bit 3: non-finite or
+ * negative C12, non-finite velocity or non-positive inverse mass in the MD
+ * entry points), then clear them.
+ * *flags: host.  Returns MLS_ERR_NONFINITE when bit 0, 1 or 3 is set,
  * MLS_ERR_HIP when only bit 2 is, else MLS_OK. */
 mls_status mls_plan_status(mls_plan_t plan, int* flags);
 

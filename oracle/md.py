@@ -7,8 +7,9 @@ The pair potential is eq:disp-pair-pot, V_ij = C^rep_ij r^-12 - C^disp_ij r^-6
 (Sec. II.D).  The dispersion part is the MLS evaluation of ``oracle.mls``
 (geometric mixing, C^disp_ij = sqrt(C6_i C6_j)).  The repulsive part, which
 the paper leaves out of the MLS analysis because it is negligible beyond
-sigma, is a plain cutoff sum over every periodic image closer than the MLS
-cutoff a, with geometric mixing C^rep_ij = sqrt(C12_i C12_j).  The paper's
+sigma, is a plain cutoff sum over every periodic image closer than a
+repulsion cutoff r_c (by default the MLS cutoff a), with geometric mixing
+C^rep_ij = sqrt(C12_i C12_j).  The paper's
 MD runs (Sec. III.A) do not name their integrator; velocity Verlet is used
 here (a reading).
 """
@@ -21,44 +22,48 @@ from . import mls as M
 __all__ = ["repulsion", "forces", "md_run"]
 
 
-def repulsion(pos, c12, box, a):
-    """E_rep = 1/2 sum_i sum'_{(j,n), r < a} sqrt(C12_i C12_j) r^-12 and
-    F_rep = -grad E_rep, over all images (brute force: small systems)."""
-    pos = np.asarray(pos, dtype=np.float64)
+def repulsion(pos, c12, box, rc, targets=None):
+    """E_rep = 1/2 sum_i sum'_{(j,n), r < rc} sqrt(C12_i C12_j) r^-12 and
+    F_rep = -grad E_rep, over all images (brute force: small systems).  With
+    ``targets`` (atom indices) only those atoms' terms: E is 1/2 their
+    per-atom sums and F their forces, in the order given."""
     box = np.asarray(box, dtype=np.float64)
+    # the sum is periodic in every coordinate: wrap first, so that differences
+    # lie in (-L, L) and images |n_d| <= ceil(rc / L_d) cover every r < rc
+    pos = np.mod(np.asarray(pos, dtype=np.float64), box)
     x12 = np.sqrt(np.asarray(c12, dtype=np.float64))
-    n = len(pos)
+    tidx = np.arange(len(pos)) if targets is None else np.asarray(targets)
     E = 0.0
-    F = np.zeros((n, 3))
-    nr = np.ceil(a / box).astype(int) + 1
+    F = np.zeros((len(tidx), 3))
+    nr = np.ceil(rc / box).astype(int)
     for ix in range(-nr[0], nr[0] + 1):
         for iy in range(-nr[1], nr[1] + 1):
             for iz in range(-nr[2], nr[2] + 1):
-                d = pos[:, None, :] - pos[None, :, :] - np.array([ix, iy, iz]) * box
+                d = pos[tidx, None, :] - pos[None, :, :] - np.array([ix, iy, iz]) * box
                 r2 = np.sum(d * d, axis=2)
                 if ix == 0 and iy == 0 and iz == 0:
-                    np.fill_diagonal(r2, np.inf)
-                m = r2 < a * a
-                r2m = np.where(m, r2, 1.0)
-                w = np.where(m, np.outer(x12, x12), 0.0)
-                E += 0.5 * np.sum(w * r2m ** -6)
+                    r2[np.arange(len(tidx)), tidx] = np.inf
+                ti, j = np.nonzero(r2 < rc * rc)
+                r2p = r2[ti, j]
+                C = x12[tidx][ti] * x12[j]
+                E += 0.5 * np.sum(C * r2p ** -6)
                 # -d/dx_i of C r^-12 = 12 C r^-14 (x_i - x_j)
-                F += np.einsum("ij,ijk->ik", 12.0 * w * r2m ** -7, d)
+                np.add.at(F, ti, (12.0 * C * r2p ** -7)[:, None] * d[ti, j])
     return E, F
 
 
-def forces(pos, c6, c12, box, a, h, order, levels, continuity=2):
+def forces(pos, c6, c12, box, a, h, order, levels, continuity=2, rc=None):
     """Potential energy and forces of eq:disp-pair-pot: MLS dispersion plus the
-    cutoff repulsion (c12 None: dispersion only)."""
+    cutoff repulsion (c12 None: dispersion only; rc None: rc = a)."""
     r = M.mls(pos, c6, box, a, h, order, levels, continuity=continuity)
     E, F = r["energy"], r["F"]
     if c12 is not None:
-        Er, Fr = repulsion(pos, c12, box, a)
+        Er, Fr = repulsion(pos, c12, box, a if rc is None else rc)
         E, F = E + Er, F + Fr
     return E, F
 
 
-def md_run(pos, vel, c6, c12, inv_mass, box, a, h, order, levels, dt, nsteps, continuity=2):
+def md_run(pos, vel, c6, c12, inv_mass, box, a, h, order, levels, dt, nsteps, continuity=2, rc=None):
     """Velocity Verlet: v += dt/2 F/m; x += dt v; F = F(x); v += dt/2 F/m.
 
     Returns the final positions and velocities, the forces at the final
@@ -71,12 +76,12 @@ def md_run(pos, vel, c6, c12, inv_mass, box, a, h, order, levels, dt, nsteps, co
     def ekin(v_):
         return 0.5 * float(np.sum(np.sum(v_ * v_, axis=1) / im[:, 0]))
 
-    E, F = forces(x, c6, c12, box, a, h, order, levels, continuity)
+    E, F = forces(x, c6, c12, box, a, h, order, levels, continuity, rc)
     epot, kin = [E], [ekin(v)]
     for _ in range(nsteps):
         v = v + 0.5 * dt * F * im
         x = x + dt * v
-        E, F = forces(x, c6, c12, box, a, h, order, levels, continuity)
+        E, F = forces(x, c6, c12, box, a, h, order, levels, continuity, rc)
         v = v + 0.5 * dt * F * im
         epot.append(E)
         kin.append(ekin(v))

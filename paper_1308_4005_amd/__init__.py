@@ -128,6 +128,60 @@ class Plan:
                                                  _ptr(out.forces), ctypes.c_void_p(s)), "mls_evaluate_lb")
         return out
 
+    def _check_vec(self, t, shape, name):
+        import torch
+        if t.device != self.device or t.dtype != torch.float64 or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor of shape {shape} on the plan's device")
+
+    def evaluate_md(self, pos, c6, c12, rc=None, forces=True, out=None, stream=None):
+        """Enqueue one evaluation of the full pair potential (``mls_evaluate_md``):
+        MLS dispersion plus the cutoff r^-12 repulsion (rc None: the cutoff a)."""
+        import torch
+        self._check_inputs(pos, c6)
+        n = pos.shape[0]
+        self._check_vec(c12, (n,), "c12")
+        rc = self.params.cutoff if rc is None else float(rc)
+        if out is None:
+            out = Result(torch.empty(1, dtype=torch.float64, device=self.device),
+                         torch.empty((n, 3), dtype=torch.float64, device=self.device) if forces else None)
+        s = (stream if stream is not None else torch.cuda.current_stream(self.device)).cuda_stream
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.mls_evaluate_md(self._plan, n, _ptr(pos), _ptr(c6), _ptr(c12), ctypes.c_double(rc),
+                                                 _ptr(out.energy), _ptr(out.forces), ctypes.c_void_p(s)),
+                       "mls_evaluate_md")
+        return out
+
+    def md_run(self, pos, vel, c6, c12, inv_mass, dt, nsteps, rc=None, forces=None, epot=None, ekin=None,
+               stream=None):
+        """Enqueue ``nsteps`` velocity-Verlet steps (``mls_md_run``); ``pos`` and
+        ``vel`` advance in place.  Returns (forces, epot, ekin): forces at the
+        final positions and the potential / kinetic energies after each of the
+        nsteps + 1 force evaluations."""
+        import torch
+        self._check_inputs(pos, c6)
+        n = pos.shape[0]
+        self._check_vec(vel, (n, 3), "vel")
+        self._check_vec(c12, (n,), "c12")
+        self._check_vec(inv_mass, (n,), "inv_mass")
+        rc = self.params.cutoff if rc is None else float(rc)
+        nsteps = int(nsteps)
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        if epot is None:
+            epot = torch.empty(max(nsteps, 0) + 1, dtype=torch.float64, device=self.device)
+        if ekin is None:
+            ekin = torch.empty(max(nsteps, 0) + 1, dtype=torch.float64, device=self.device)
+        self._check_vec(forces, (n, 3), "forces")
+        self._check_vec(epot, (max(nsteps, 0) + 1,), "epot")
+        self._check_vec(ekin, (max(nsteps, 0) + 1,), "ekin")
+        s = (stream if stream is not None else torch.cuda.current_stream(self.device)).cuda_stream
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.mls_md_run(self._plan, n, _ptr(pos), _ptr(vel), _ptr(c6), _ptr(c12),
+                                            ctypes.c_double(rc), _ptr(inv_mass), ctypes.c_double(dt), nsteps,
+                                            _ptr(forces), _ptr(epot), _ptr(ekin), ctypes.c_void_p(s)),
+                       "mls_md_run")
+        return forces, epot, ekin
+
     def copy_stage(self, what, level=1, n=None):
         """Intermediate array of the last evaluation (``mls_plan_copy_stage``)."""
         import torch

@@ -1,4 +1,6 @@
 // extern "C" entry points of the MLS dispersion library (include/mlsdisp.h).
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -83,8 +85,21 @@ mls_status mls_plan_get_info(mls_plan_t P, mls_plan_info* info) {
   return MLS_OK;
 }
 
-mls_status mls_evaluate(mls_plan_t P, int64_t n, const double* pos, const double* c6, double* energy,
-                        double* forces, double* potential, double* dE_dc6, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The repulsive term of the MD entry points: sqrt(C12) per atom and its cutoff.
+struct Repulsion {
+  const double* c12;
+  double rc;
+};
+
+// mls_evaluate, optionally with the repulsion (rep non-null) run after the
+// local part on the caller's stream and combined after the interpolation.
+mls_status evaluate_geometric(mls_plan_t P, int64_t n, const double* pos, const double* c6, double* energy,
+                              double* forces, double* potential, double* dE_dc6, void* stream,
+                              const Repulsion* rep) {
   if (!P) { set_error("mls_evaluate: null plan"); return MLS_ERR_INVALID_ARG; }
   if (n < 0 || n > P->n_max) {
     set_error("mls_evaluate: n = " + std::to_string(n) + " outside [0, n_max = " + std::to_string(P->n_max) + "]");
@@ -137,6 +152,7 @@ mls_status mls_evaluate(mls_plan_t P, int64_t n, const double* pos, const double
   const int after = fork ? P->pair_after : 0;
   auto pair = [&]() -> mls_status {
     HIP_TRY(launch_pair(P, ni, s), "pair kernel");
+    if (rep) HIP_TRY(launch_repulsion(P, ni, rep->c12, rep->rc, s), "repulsion");
     HIP_TRY(mark(1 + MLS_T_PAIR), "timing event");
     return MLS_OK;
   };
@@ -160,7 +176,62 @@ mls_status mls_evaluate(mls_plan_t P, int64_t n, const double* pos, const double
   if (after == 5 && (st = pair()) != MLS_OK) return st;
   if (fork) HIP_TRY(hipStreamWaitEvent(s, P->ev_join, 0), "join");
   HIP_TRY(launch_interpolate(P, ni, energy, forces, potential, dE_dc6, s), "interpolation");
+  if (rep) HIP_TRY(launch_rep_combine(P, ni, energy, forces, s), "repulsion");
   HIP_TRY(mark(1 + MLS_T_INTERP), "timing event");
+  return MLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mls_status mls_evaluate(mls_plan_t P, int64_t n, const double* pos, const double* c6, double* energy,
+                        double* forces, double* potential, double* dE_dc6, void* stream) {
+  return evaluate_geometric(P, n, pos, c6, energy, forces, potential, dE_dc6, stream, nullptr);
+}
+
+static mls_status check_rep(mls_plan_t P, int64_t n, const double* c12, double rc, const char* who) {
+  if (!P) { set_error(std::string(who) + ": null plan"); return MLS_ERR_INVALID_ARG; }
+  if (n > 0 && !c12) { set_error(std::string(who) + ": null c12"); return MLS_ERR_INVALID_ARG; }
+  if (!(rc > 0.0 && rc <= P->a)) {
+    set_error(std::string(who) + ": repulsion cutoff must satisfy 0 < rc <= a");
+    return MLS_ERR_INVALID_ARG;
+  }
+  return MLS_OK;
+}
+
+mls_status mls_evaluate_md(mls_plan_t P, int64_t n, const double* pos, const double* c6, const double* c12,
+                           double rc, double* energy, double* forces, void* stream) {
+  mls_status st = check_rep(P, n, c12, rc, "mls_evaluate_md");
+  if (st != MLS_OK) return st;
+  const Repulsion rep{c12, rc};
+  return evaluate_geometric(P, n, pos, c6, energy, forces, nullptr, nullptr, stream, &rep);
+}
+
+mls_status mls_md_run(mls_plan_t P, int64_t n, double* pos, double* vel, const double* c6, const double* c12,
+                      double rc, const double* inv_mass, double dt, int nsteps, double* forces, double* epot,
+                      double* ekin, void* stream) {
+  mls_status st = check_rep(P, n, c12, rc, "mls_md_run");
+  if (st != MLS_OK) return st;
+  if (nsteps < 0 || !(std::isfinite(dt))) { set_error("mls_md_run: nsteps < 0 or non-finite dt"); return MLS_ERR_INVALID_ARG; }
+  if (!epot || !ekin || (n > 0 && (!pos || !vel || !inv_mass || !forces))) {
+    set_error("mls_md_run: null pos, vel, inv_mass, forces, epot or ekin");
+    return MLS_ERR_INVALID_ARG;
+  }
+  const Repulsion rep{c12, rc};
+  const hipStream_t s = (hipStream_t)stream;
+  const int ni = (int)std::min<int64_t>(std::max<int64_t>(n, 0), P->n_max);
+  if ((st = evaluate_geometric(P, n, pos, c6, epot, forces, nullptr, nullptr, stream, &rep)) != MLS_OK) return st;
+  for (int k = 1; k <= nsteps; ++k) {
+    // end of step k-1 (k > 1): second half-kick, E_kin(k-1); step k: first
+    // half-kick and drift
+    const int mode = (k > 1 ? kMdEnd : 0) | kMdStart;
+    HIP_TRY(launch_md_step(P, ni, pos, vel, forces, inv_mass, dt, mode, ekin + (k - 1), s), "integrator");
+    if ((st = evaluate_geometric(P, n, pos, c6, epot + k, forces, nullptr, nullptr, stream, &rep)) != MLS_OK)
+      return st;
+  }
+  HIP_TRY(launch_md_step(P, ni, pos, vel, forces, inv_mass, dt, nsteps > 0 ? kMdEnd : 0, ekin + nsteps, s),
+          "integrator");
   return MLS_OK;
 }
 
@@ -280,7 +351,11 @@ mls_status mls_plan_status(mls_plan_t P, int* flags) {
   HIP_TRY(hipMemcpy(h, P->d_flags, sizeof(h), hipMemcpyDeviceToHost), "read flags");
   HIP_TRY(hipMemset(P->d_flags, 0, sizeof(h)), "clear flags");
   *flags = h[0];
-  if (h[0] & 3) { set_error("input data contained non-finite positions or non-finite/negative C6"); return MLS_ERR_NONFINITE; }
+  if (h[0] & 11) {
+    set_error("input data contained non-finite positions, non-finite/negative C6 or C12, "
+              "non-finite velocities or non-positive inverse masses");
+    return MLS_ERR_NONFINITE;
+  }
   if (h[0]) { set_error("internal error: an atom fell outside its anterpolation block"); return MLS_ERR_HIP; }
   return MLS_OK;
 }

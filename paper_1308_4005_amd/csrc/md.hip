@@ -1,0 +1,234 @@
+// Molecular dynamics around the MLS dispersion (Sec. II.D, eq:disp-pair-pot;
+// the MD runs of Sec. III.A): the short-ranged repulsive term C^rep_ij r^-12
+// with geometric mixing C^rep_ij = sqrt(C12_i C12_j), summed over every
+// periodic image closer than a cutoff r_c <= a, and the velocity-Verlet
+// integrator.
+//
+// The repulsion reuses the cell-sorted atoms of the evaluation it belongs to
+// (binning's wrapped positions, cell starts and permutation) and runs on the
+// caller's stream right after the local dispersion part, so that it overlaps
+// the grid chain on the plan's second stream.  It writes cell-sorted forces
+// and per-block energy sums; RepCombine adds both into the caller's outputs
+// after the interpolation has written them.
+#include <algorithm>
+#include <cmath>
+
+#include "device_math.h"
+#include "mls_internal.h"
+
+namespace mls {
+namespace {
+
+constexpr int kBlock = 256;
+
+// sorted sqrt(C12): one random read per atom instead of one per neighbour
+struct RepGather {
+  using Args = RepGatherArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    const int s = blk * kBlock + threadIdx.x;
+    if (s >= a.n + kSortedPad) return;
+    double x = 0.0;
+    if (s < a.n) {
+      const double c = a.c12[a.perm[s]];
+      if (isfinite(c) && c >= 0.0) {
+        x = sqrt(c);
+      } else {
+        atomicOr(a.flags, 8);
+      }
+    }
+    a.x12s[s] = x;
+  }
+};
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// One thread per cell-sorted atom.  The neighbour cells of one (dy, dz) pair
+// form a run of consecutive cells in x, hence one contiguous range of sorted
+// atoms per periodic image in x: the loop walks (dz, dy, image in x, atom).
+struct RepPair {
+  using Args = RepPairArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    __shared__ double sh[kBlock];
+    const int s = blk * kBlock + threadIdx.x;
+    const CellGeom& g = a.g;
+    double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    if (s < a.n) {
+      const double4 p = a.xs[s];
+      const double ci = a.x12s[s];
+      const int c = a.cell_s[s];
+      const int cx = c % g.nc[0];
+      const int cy = (c / g.nc[0]) % g.nc[1];
+      const int cz = c / (g.nc[0] * g.nc[1]);
+      for (int dz = -a.nr[2]; dz <= a.nr[2]; ++dz) {
+        const int qz = floor_div(cz + dz, g.nc[2]);
+        const int zc = cz + dz - qz * g.nc[2];
+        const double sz = qz * g.L[2];
+        for (int dy = -a.nr[1]; dy <= a.nr[1]; ++dy) {
+          const int qy = floor_div(cy + dy, g.nc[1]);
+          const int yc = cy + dy - qy * g.nc[1];
+          const double sy = qy * g.L[1];
+          const int row = (zc * g.nc[1] + yc) * g.nc[0];
+          const int q0 = floor_div(cx - a.nr[0], g.nc[0]);
+          const int q1 = floor_div(cx + a.nr[0], g.nc[0]);
+          for (int qx = q0; qx <= q1; ++qx) {
+            const int lo = max(cx - a.nr[0] - qx * g.nc[0], 0);
+            const int hi = min(cx + a.nr[0] - qx * g.nc[0], g.nc[0] - 1);
+            const int j0 = a.cell_start[row + lo], j1 = a.cell_start[row + hi + 1];
+            const double sx = qx * g.L[0];
+            const bool home = qx == 0 && qy == 0 && qz == 0;
+            for (int j = j0; j < j1; ++j) {
+              const double4 pj = a.xs[j];
+              const double dx = p.x - (pj.x + sx);
+              const double dyy = p.y - (pj.y + sy);
+              const double dzz = p.z - (pj.z + sz);
+              const double r2 = dx * dx + dyy * dyy + dzz * dzz;
+              if (r2 < a.rc2 && !(home && j == s)) {
+                const double ir2 = 1.0 / r2;
+                const double ir6 = ir2 * ir2 * ir2;
+                const double v = a.x12s[j] * ir6 * ir6;
+                const double f = 12.0 * v * ir2;
+                e += v;
+                fx += f * dx;
+                fy += f * dyy;
+                fz += f * dzz;
+              }
+            }
+          }
+        }
+      }
+      e *= ci;
+      a.frep[s] = ci * fx;
+      a.frep[a.stride + s] = ci * fy;
+      a.frep[2 * a.stride + s] = ci * fz;
+    }
+    const double t = block_sum(e, sh);
+    if (threadIdx.x == 0) a.partial[blk] = t;
+  }
+};
+
+// forces[perm[s]] += frep[s]; block 0 also adds 1/2 of the energy partial
+// sums (written by RepPair earlier in stream order) to *energy
+struct RepCombine {
+  using Args = RepCombineArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    __shared__ double sh[kBlock];
+    const int s = blk * kBlock + threadIdx.x;
+    if (a.forces && s < a.n) {
+      double* f = a.forces + 3 * (size_t)a.perm[s];
+      f[0] += a.frep[s];
+      f[1] += a.frep[a.stride + s];
+      f[2] += a.frep[2 * a.stride + s];
+    }
+    if (blk == 0) {
+      double v = 0.0;
+      for (int i = threadIdx.x; i < a.npartial; i += kBlock) v += a.partial[i];
+      const double t = block_sum(v, sh);
+      if (threadIdx.x == 0) *a.energy += 0.5 * t;
+    }
+  }
+};
+
+// Velocity Verlet, one thread per atom (original order).  With END the
+// second half-kick of the previous step, v += dt/2 F/m, is applied; the
+// kinetic energy of the resulting v is summed per block; with START the
+// first half-kick of the next step and the drift x += dt v follow.
+struct MdStep {
+  using Args = MdStepArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    __shared__ double sh[kBlock];
+    const int i = blk * kBlock + threadIdx.x;
+    double k = 0.0;
+    if (i < a.n) {
+      const double im = a.inv_mass[i];
+      double v[3], f[3];
+      bool bad = !(isfinite(im) && im > 0.0);
+      for (int d = 0; d < 3; ++d) {
+        v[d] = a.vel[3 * (size_t)i + d];
+        f[d] = a.forces[3 * (size_t)i + d];
+        bad |= !isfinite(v[d]);
+      }
+      if (bad) atomicOr(a.flags, 8);
+      if (a.mode & kMdEnd)
+        for (int d = 0; d < 3; ++d) v[d] = v[d] + a.hdt * f[d] * im;
+      k = (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / im;
+      if (a.mode & kMdStart) {
+        for (int d = 0; d < 3; ++d) {
+          v[d] = v[d] + a.hdt * f[d] * im;
+          a.pos[3 * (size_t)i + d] = a.pos[3 * (size_t)i + d] + a.dt * v[d];
+        }
+      }
+      if (a.mode & (kMdEnd | kMdStart))
+        for (int d = 0; d < 3; ++d) a.vel[3 * (size_t)i + d] = v[d];
+    }
+    const double t = block_sum(k, sh);
+    if (threadIdx.x == 0) a.partial[blk] = t;
+  }
+};
+
+// *out = 1/2 sum of the per-block kinetic sums (fixed order)
+struct MdKinetic {
+  using Args = MdKineticArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int) {
+    __shared__ double sh[kBlock];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < a.npartial; i += kBlock) v += a.partial[i];
+    const double t = block_sum(v, sh);
+    if (threadIdx.x == 0) *a.out = 0.5 * t;
+  }
+};
+
+inline int nblocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_repulsion(mls_plan_s* P, int n, const double* c12, double rc, hipStream_t s) {
+  hipError_t e = launch_one<RepGather>(RepGatherArgs{P->d_perm, c12, n, P->d_x12s, P->d_flags},
+                                       nblocks(n + kSortedPad, kBlock), s);
+  if (e != hipSuccess) return e;
+  RepPairArgs ra{};
+  ra.xs = P->d_xs;
+  ra.x12s = P->d_x12s;
+  ra.cell_s = P->d_cell_s;
+  ra.cell_start = P->d_cell_start;
+  ra.g = P->cg;
+  for (int d = 0; d < 3; ++d) ra.nr[d] = (int)std::ceil(rc * P->cg.inv_w[d]);
+  ra.rc2 = rc * rc;
+  ra.n = n;
+  ra.frep = P->d_frep;
+  ra.stride = (int)P->n_max;
+  ra.partial = P->d_md_partial;
+  return launch_one<RepPair>(ra, nblocks(n, kBlock), s);
+}
+
+hipError_t launch_rep_combine(mls_plan_s* P, int n, double* energy, double* forces, hipStream_t s) {
+  RepCombineArgs ca{P->d_perm, n, P->d_frep, (int)P->n_max, P->d_md_partial, nblocks(n, kBlock), energy, forces};
+  return launch_one<RepCombine>(ca, std::max(1, nblocks(n, kBlock)), s);
+}
+
+hipError_t launch_md_step(mls_plan_s* P, int n, double* pos, double* vel, const double* forces,
+                          const double* inv_mass, double dt, int mode, double* kinetic, hipStream_t s) {
+  double* part = P->d_md_partial + P->n_partial;
+  if (n > 0) {
+    MdStepArgs ma{pos, vel, forces, inv_mass, n, 0.5 * dt, dt, mode, part, P->d_flags};
+    hipError_t e = launch_one<MdStep>(ma, nblocks(n, kBlock), s);
+    if (e != hipSuccess) return e;
+  }
+  return launch_one<MdKinetic>(MdKineticArgs{part, nblocks(n, kBlock), kinetic}, 1, s);
+}
+
+}  // namespace mls

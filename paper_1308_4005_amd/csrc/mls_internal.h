@@ -110,6 +110,22 @@ struct BinCountArgs {
   int* cid; int* slot; int* count; double4* xw; int* flags;
   double c6_scale;   // xi = sqrt(c6_scale * c6): 1 for C6, 2 for Lorentz-Berthelot epsilon
 };
+// molecular dynamics (md.hip): repulsion of eq:disp-pair-pot and velocity Verlet
+struct RepGatherArgs { const int* perm; const double* c12; int n; double* x12s; int* flags; };
+struct RepPairArgs {
+  const double4* xs; const double* x12s; const int* cell_s; const int* cell_start; CellGeom g;
+  int nr[3]; double rc2; int n; double* frep; int stride; double* partial;
+};
+struct RepCombineArgs {
+  const int* perm; int n; const double* frep; int stride; const double* partial; int npartial;
+  double* energy; double* forces;
+};
+constexpr int kMdEnd = 1, kMdStart = 2;
+struct MdStepArgs {
+  double* pos; double* vel; const double* forces; const double* inv_mass; int n;
+  double hdt, dt; int mode; double* partial; int* flags;
+};
+struct MdKineticArgs { const double* partial; int npartial; double* out; };
 struct LbGatherArgs { const int* perm; int n; const double* sigma; double* sig_s; int* flags; };
 struct LbChargeArgs { const double4* xs; const double* sig_s; int n; int k; double* charge; };
 struct ScanArgs { const int* count; int m; int* start; int* bsum; int* bmax; int* max_count; };
@@ -318,7 +334,11 @@ struct mls_plan_s {
   double* d_partial = nullptr;     // energy partial sums
   int n_partial = 0;
   double* d_scratch = nullptr;     // small reductions (grid means)
-  int* d_flags = nullptr;          // [0]: input flags (1 position, 2 C6, 4 anterpolation tile overrun)
+  int* d_flags = nullptr;          // [0]: input flags (1 position, 2 C6, 4 anterpolation tile overrun,
+                                   //      8 C12 / inverse mass / velocity of the MD entry points)
+  double* d_x12s = nullptr;        // geometric mixing: sorted sqrt(C12) (n_max + pad)
+  double* d_frep = nullptr;        // geometric mixing: sorted repulsive forces, 3 rows of n_max
+  double* d_md_partial = nullptr;  // geometric mixing: repulsion energy and kinetic block sums (2 n_partial)
   bool ant_tiles = false;          // two-phase anterpolation tables built
   mls::AntTiles ant{};
   int* d_ant_tab = nullptr;
@@ -380,6 +400,13 @@ hipError_t launch_binning_scaled(mls_plan_s* P, int n, const double* pos, const 
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
 hipError_t launch_zero_i(int* p, int64_t count, hipStream_t s);
 hipError_t launch_copy_stage(mls_plan_s* P, int what, int level, void* dst, hipStream_t s);
+// molecular dynamics (md.hip): repulsion over the sorted atoms of the current
+// evaluation, its combination into the outputs, and one velocity-Verlet
+// kernel (mode kMdEnd / kMdStart) with the kinetic energy written to *kinetic
+hipError_t launch_repulsion(mls_plan_s* P, int n, const double* c12, double rc, hipStream_t s);
+hipError_t launch_rep_combine(mls_plan_s* P, int n, double* energy, double* forces, hipStream_t s);
+hipError_t launch_md_step(mls_plan_s* P, int n, double* pos, double* vel, const double* forces,
+                          const double* inv_mass, double dt, int mode, double* kinetic, hipStream_t s);
 
 // owner-computes anterpolation blocking of a plan (false: use the atomic kernel)
 bool anterp_owned_geom(const mls_plan_s* P, AntGeom& ag);

@@ -406,6 +406,12 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
       ALLOC(L.qf, L.g.size);
     }
   }
+  if (P->mixing == MLS_GEOMETRIC) {
+    // molecular dynamics: repulsive term and integrator (mls_evaluate_md, mls_md_run)
+    ALLOC(P->d_x12s, N + kSortedPad);
+    ALLOC(P->d_frep, 3 * N);
+    ALLOC(P->d_md_partial, 2 * (size_t)P->n_partial);
+  }
   if (P->mixing == MLS_LORENTZ_BERTHELOT) {
     // seven charge vectors: one set of grids each (Sec. II.D)
     ALLOC(P->d_sig, N + kSortedPad);

@@ -1,0 +1,184 @@
+"""GPU parity of the molecular-dynamics entry points (mls_evaluate_md,
+mls_md_run) against the MD oracle: the full pair potential eq:disp-pair-pot
+(MLS dispersion plus the cutoff r^-12 repulsion) and velocity-Verlet
+trajectories, on the same seeded inputs.  FP64 plans: rel. 1e-10 (the
+dispersion part's end-to-end bar); mixed plans: the mixed-precision bars of
+the dispersion part (energy 1e-6, forces RMS 1e-5)."""
+import numpy as np
+import pytest
+
+from oracle import md as MD
+from paper_1308_4005_amd import workloads as W
+
+from gpu_common import force_errors, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _t(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _inputs(w, seed):
+    rng = np.random.default_rng(seed)
+    vel = rng.normal(scale=0.3, size=(w.n, 3))
+    c12 = np.where(rng.uniform(size=w.n) < 0.5, 4.0, 2.5)
+    im = rng.uniform(0.5, 2.0, size=w.n)
+    return vel, c12, im
+
+
+def _cases():
+    rng = np.random.default_rng(23)
+    tiny = W.Workload("tiny", rng.random((30, 3)) * np.array([2.4, 3.1, 2.9]),
+                      rng.uniform(1.0, 9.0, 30), np.array([2.4, 3.1, 2.9]), {})
+    return [
+        ("cube1k_rc3", W.named("cube1k"), dict(a=3.0, h=1.0, order=4, levels=2), 3.0),
+        ("cube1k_rc1.2", W.named("cube1k"), dict(a=3.0, h=1.0, order=4, levels=2), 1.2),
+        ("narrow_box", W.fill_box(120, (5.3, 5.3, 9.0), seed=5), dict(a=3.0, h=1.0, order=4, levels=1), 3.0),
+        ("tiny_images", tiny, dict(a=2.6, h=0.5, order=4, levels=1), 2.6),
+        ("slab_p6_l3", W.slab(1500, (11.0, 11.0, 40.0), 0.3, 0.7, rho_liquid=0.8, rho_vapour=0.02, seed=21),
+         dict(a=2.5, h=0.9, order=6, levels=3), 2.0),
+    ]
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name,w,prm,rc", CASES, ids=[c[0] for c in CASES])
+def test_evaluate_md_matches_oracle(name, w, prm, rc):
+    import torch
+    from paper_1308_4005_amd import Plan
+    say(f"[md] evaluate_md {name}: n={w.n} rc={rc} {prm}")
+    _, c12, _ = _inputs(w, 1)
+    plan = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], n_max=w.n)
+    res = plan.evaluate_md(_t(w.pos), _t(w.c6), _t(c12), rc=rc)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    E, F = MD.forces(w.pos, w.c6, c12, w.box, prm["a"], prm["h"], prm["order"], prm["levels"], rc=rc)
+    assert abs(float(res.energy.cpu()[0]) - E) <= TOL * abs(E)
+    assert rel_err(res.forces.cpu().numpy(), F) < TOL
+
+
+@pytest.mark.parametrize("name,w,prm,rc", CASES[:3], ids=[c[0] for c in CASES[:3]])
+def test_md_run_fp64_matches_oracle(name, w, prm, rc):
+    import torch
+    from paper_1308_4005_amd import Plan
+    say(f"[md] md_run fp64 {name}: n={w.n} rc={rc}")
+    vel, c12, im = _inputs(w, 2)
+    plan = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], n_max=w.n)
+    x, v = _t(w.pos), _t(vel)
+    F, ep, ek = plan.md_run(x, v, _t(w.c6), _t(c12), _t(im), dt=0.002, nsteps=5, rc=rc)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    xo, vo, Fo, epo, eko = MD.md_run(w.pos, vel, w.c6, c12, im, w.box, prm["a"], prm["h"], prm["order"],
+                                     prm["levels"], 0.002, 5, rc=rc)
+    assert rel_err(x.cpu().numpy(), xo) < 1e-13
+    assert rel_err(v.cpu().numpy(), vo) < TOL
+    assert rel_err(F.cpu().numpy(), Fo) < TOL
+    assert rel_err(ep.cpu().numpy(), epo) < TOL
+    assert rel_err(ek.cpu().numpy(), eko) < 1e-12
+
+
+def test_md_run_mixed_matches_oracle():
+    import torch
+    from paper_1308_4005_amd import Plan
+    w = W.named("cube1k")
+    say(f"[md] md_run mixed cube1k: n={w.n}")
+    vel, c12, im = _inputs(w, 3)
+    plan = Plan(w.box, 3.0, 1.0, 4, 2, precision="mixed", n_max=w.n)
+    x, v = _t(w.pos), _t(vel)
+    F, ep, ek = plan.md_run(x, v, _t(w.c6), _t(c12), _t(im), dt=0.002, nsteps=5)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    xo, vo, Fo, epo, eko = MD.md_run(w.pos, vel, w.c6, c12, im, w.box, 3.0, 1.0, 4, 2, 0.002, 5)
+    # the mixed-precision error lives in the dispersion part: measure it against
+    # the dispersion energy's magnitude (the repulsion cancels part of it)
+    e_rep, _ = MD.repulsion(w.pos, c12, w.box, 3.0)
+    scale = abs(epo[0] - e_rep)
+    assert np.abs(ep.cpu().numpy() - epo).max() < 1e-6 * scale
+    assert force_errors(F.cpu().numpy(), Fo)[0] < 1e-5
+    # velocities and positions inherit the force error: with per-atom force
+    # errors below 1e-4 max|F| (the RMS bar 1e-5 with a factor 10 of spread),
+    # 5 steps of dt move v by at most 5 dt max(1/m) 1e-4 max|F| and x by at
+    # most 5 dt times that
+    dv = 5 * 0.002 * im.max() * 1e-4 * np.abs(Fo).max()
+    assert np.abs(v.cpu().numpy() - vo).max() < dv
+    assert np.abs(x.cpu().numpy() - xo).max() < 5 * 0.002 * dv
+    vmax = np.abs(vo).max()
+    assert np.abs(ek.cpu().numpy() - eko).max() < 3 * w.n * vmax * dv / im.min()
+
+
+def test_md_edge_cases():
+    import torch
+    from paper_1308_4005_amd import Plan, _lib
+    w = W.named("cube1k")
+    vel, c12, im = _inputs(w, 4)
+    plan = Plan(w.box, 3.0, 1.0, 4, 2, n_max=w.n)
+    say("[md] edge: n = 0")
+    e0 = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    z = torch.empty(0, dtype=torch.float64, device="cuda")
+    F, ep, ek = plan.md_run(e0, e0.clone(), z, z.clone(), z.clone(), dt=0.002, nsteps=3)
+    torch.cuda.synchronize()
+    assert np.all(ep.cpu().numpy() == 0.0) and np.all(ek.cpu().numpy() == 0.0)
+    say("[md] edge: nsteps = 0 (one evaluation, nothing moves)")
+    x, v = _t(w.pos), _t(vel)
+    F, ep, ek = plan.md_run(x, v, _t(w.c6), _t(c12), _t(im), dt=0.002, nsteps=0)
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), w.pos) and np.array_equal(v.cpu().numpy(), vel)
+    E, Fo = MD.forces(w.pos, w.c6, c12, w.box, 3.0, 1.0, 4, 2)
+    assert abs(float(ep.cpu()[0]) - E) <= TOL * abs(E)
+    assert float(ek.cpu()[0]) == pytest.approx(0.5 * np.sum(np.sum(vel * vel, axis=1) / im), rel=1e-13)
+    say("[md] edge: argument errors")
+    with pytest.raises(_lib.MLSError):
+        plan.evaluate_md(_t(w.pos), _t(w.c6), _t(c12), rc=3.5)      # rc > a
+    with pytest.raises(_lib.MLSError):
+        plan.evaluate_md(_t(w.pos), _t(w.c6), _t(c12), rc=0.0)
+    with pytest.raises(_lib.MLSError):
+        plan.md_run(_t(w.pos), _t(vel), _t(w.c6), _t(c12), _t(im), dt=float("nan"), nsteps=1)
+    say("[md] edge: bad C12 and inverse masses set flag bit 3")
+    bad = c12.copy()
+    bad[5] = -1.0
+    plan.evaluate_md(_t(w.pos), _t(w.c6), _t(bad), rc=3.0)
+    assert plan.status() & 8
+    assert plan.status() == 0
+    imb = im.copy()
+    imb[9] = 0.0
+    plan.md_run(_t(w.pos), _t(vel), _t(w.c6), _t(c12), _t(imb), dt=0.002, nsteps=1)
+    assert plan.status() & 8
+
+
+@pytest.mark.timeout(600)
+def test_full_size_sampled():
+    """cube1M (10^6 atoms, the measured workload): the repulsive forces of
+    mls_evaluate_md (its forces minus mls_evaluate's) at sampled atoms against
+    the oracle evaluated at those atoms; a short mixed-precision run keeps its
+    kinetic-energy output consistent with its own final velocities."""
+    import torch
+    from paper_1308_4005_amd import Plan
+    w = W.named("cube1M")
+    prm = w.params
+    say(f"[md] full size: n={w.n}")
+    vel, c12, im = _inputs(w, 5)
+    plan = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], n_max=w.n)
+    tp, tc, t12 = _t(w.pos), _t(w.c6), _t(c12)
+    r_md = plan.evaluate_md(tp, tc, t12, rc=3.0)
+    F_md = r_md.forces.cpu().numpy()
+    r = plan.evaluate(tp, tc)
+    F_d = r.forces.cpu().numpy()
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    t = np.random.default_rng(12345).choice(w.n, 4, replace=False)
+    _, Fr = MD.repulsion(w.pos, c12, w.box, 3.0, targets=t)
+    assert np.abs((F_md[t] - F_d[t]) - Fr).max() < 1e-9 * np.abs(Fr).max()
+    say("[md] full size: mixed run")
+    pm = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], precision="mixed", n_max=w.n)
+    v = _t(vel)
+    F, ep, ek = pm.md_run(tp.clone(), v, tc, t12, _t(im), dt=0.002, nsteps=4)
+    torch.cuda.synchronize()
+    assert pm.status() == 0
+    vv = v.cpu().numpy()
+    assert float(ek.cpu()[-1]) == pytest.approx(0.5 * np.sum(np.sum(vv * vv, axis=1) / im), rel=1e-12)
+    assert np.all(np.isfinite(ep.cpu().numpy()))

@@ -89,3 +89,29 @@ def test_energy_drift_is_second_order(system):
     assert drift[1] < drift[0]
     # halving dt divides the energy error by about four (velocity Verlet is second order)
     assert 2.5 < drift[0] / drift[1] < 6.0
+
+
+def test_targets_match_the_full_sum():
+    w = W.cube(90, 0.8, seed=5)
+    c12 = np.linspace(1.0, 5.0, w.n)
+    E, F = MD.repulsion(w.pos, c12, w.box, 2.5)
+    t = np.array([3, 40, 7, 88])
+    Et, Ft = MD.repulsion(w.pos, c12, w.box, 2.5, targets=t)
+    np.testing.assert_allclose(Ft, F[t], rtol=1e-13, atol=1e-13 * np.abs(F).max())
+    Ea, _ = MD.repulsion(w.pos, c12, w.box, 2.5, targets=np.arange(w.n))
+    assert Ea == pytest.approx(E, rel=1e-13)
+    # the per-atom halves of all atoms add up to the total; a subset stays below it
+    assert 0 < Et < E
+
+
+def test_shifting_atoms_by_box_vectors_changes_nothing():
+    # positions outside the box (an MD trajectory is not wrapped) give the
+    # energy and forces of the wrapped ones
+    w = W.cube(80, 0.8, seed=6)
+    c12 = np.full(w.n, 4.0)
+    rng = np.random.default_rng(1)
+    shifted = w.pos + rng.integers(-2, 3, size=(w.n, 3)) * w.box
+    E, F = MD.repulsion(w.pos, c12, w.box, 2.5)
+    Es, Fs = MD.repulsion(shifted, c12, w.box, 2.5)
+    assert Es == pytest.approx(E, rel=1e-12)
+    np.testing.assert_allclose(Fs, F, rtol=0, atol=1e-10 * np.abs(F).max())
