@@ -69,7 +69,7 @@ def work_model(plan_info, n, pairs, order):
 STAGE_KERNEL = {("pair", "mixed"): ["void k_one<PairTrimF32<2> >"],
                 ("pair", "fp64"): ["void k_one<PairTrimF64<2, false> >"],
                 ("stencil", "mixed"): ["void k_stencil_tile<float, 6, 16, 4>"],
-                ("stencil", "fp64"): ["void k_stencil_tile<double, 6, 16, 4>"],
+                ("stencil", "fp64"): ["void k_stencil_tile<double, 6, 8, 4>"],
                 ("anterpolation", "mixed"): ["void k_one<AnterpTile<4, float> >", "void k_one<AnterpCollect>"],
                 ("anterpolation", "fp64"): ["void k_one<AnterpTile<4, double> >", "void k_one<AnterpCollect>"],
                 ("interpolation", "mixed"): ["void k_one<Interp<4, float> >"],
@@ -267,13 +267,14 @@ def time_lb(w, prm, steps, warmup, dev):
             "precision": "fp64", "ms_per_step": ms, "evals_per_s": 1000.0 / ms, "energy": E}
 
 
-def time_md(w, prm, precision, steps, warmup, dev, blocks, chunk=10, dt=0.001):
+def time_md(w, prm, precision, steps, warmup, dev, blocks, chunk=50, dt=0.001):
     """Molecular dynamics on the workload (mls_md_run): LJ atoms with
     C6 = 4, C12 = 4 (epsilon = sigma = 1), unit masses, velocities drawn
     from N(0, 0.8) (seed 29), repulsion cutoff a.  One graph replay runs
     ``chunk`` velocity-Verlet steps; ``ms_per_step`` is the median block of
-    replays divided by ``chunk``.  Also times one mls_evaluate_md (dispersion
-    plus repulsion) the same way."""
+    replays divided by ``chunk`` (a call evaluates the forces chunk + 1
+    times: once at its starting positions, then once per step).  Also times
+    one mls_evaluate_md (dispersion plus repulsion) the same way."""
     import numpy as np
     import torch
     from paper_1308_4005_amd import Plan, Result

@@ -96,7 +96,7 @@ struct Repulsion {
 };
 
 // mls_evaluate, optionally with the repulsion (rep non-null) run after the
-// local part on the caller's stream and combined after the interpolation.
+// local part on the caller's stream and added in the interpolation.
 mls_status evaluate_geometric(mls_plan_t P, int64_t n, const double* pos, const double* c6, double* energy,
                               double* forces, double* potential, double* dE_dc6, void* stream,
                               const Repulsion* rep) {
@@ -175,8 +175,7 @@ mls_status evaluate_geometric(mls_plan_t P, int64_t n, const double* pos, const 
   if (fork) HIP_TRY(hipEventRecord(P->ev_join, g), "join");
   if (after == 5 && (st = pair()) != MLS_OK) return st;
   if (fork) HIP_TRY(hipStreamWaitEvent(s, P->ev_join, 0), "join");
-  HIP_TRY(launch_interpolate(P, ni, energy, forces, potential, dE_dc6, s), "interpolation");
-  if (rep) HIP_TRY(launch_rep_combine(P, ni, energy, forces, s), "repulsion");
+  HIP_TRY(launch_interpolate(P, ni, energy, forces, potential, dE_dc6, s, rep != nullptr), "interpolation");
   HIP_TRY(mark(1 + MLS_T_INTERP), "timing event");
   return MLS_OK;
 }

@@ -576,7 +576,12 @@ struct Interp {
       // latency overlaps the grid gathers
       const int i = a.perm[s];
       const double e0 = a.e0[s];
-      const double fl0 = a.floc[3 * (size_t)s + 0], fl1 = a.floc[3 * (size_t)s + 1], fl2 = a.floc[3 * (size_t)s + 2];
+      double fl0 = a.floc[3 * (size_t)s + 0], fl1 = a.floc[3 * (size_t)s + 1], fl2 = a.floc[3 * (size_t)s + 2];
+      if (a.frep) {
+        fl0 += a.frep[3 * (size_t)s + 0];
+        fl1 += a.frep[3 * (size_t)s + 1];
+        fl2 += a.frep[3 * (size_t)s + 2];
+      }
       W w[3][P], dw[3][P];
       int idx[3][P];
       interp_setup<P, W>(p, gg, w, dw, idx);
@@ -646,23 +651,27 @@ struct EnergyFinal {
   using Args = EnergyArgs;
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int) {
-    __shared__ double r1[kBlock], r2[kBlock];
-    double x = 0.0, y = 0.0;
+    __shared__ double r1[kBlock], r2[kBlock], r3[kBlock];
+    double x = 0.0, y = 0.0, z = 0.0;
     for (int i = threadIdx.x; i < a.nb; i += kBlock) {
       x += a.partial[2 * i];
       y += a.partial[2 * i + 1];
     }
+    for (int i = threadIdx.x; i < a.rep_nb; i += kBlock) z += a.rep_partial[i];
     r1[threadIdx.x] = x;
     r2[threadIdx.x] = y;
+    r3[threadIdx.x] = z;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
       if ((int)threadIdx.x < off) {
         r1[threadIdx.x] += r1[threadIdx.x + off];
         r2[threadIdx.x] += r2[threadIdx.x + off];
+        r3[threadIdx.x] += r3[threadIdx.x + off];
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) *a.energy = -0.5 * (r1[0] - a.cself * r2[0]);
+    // dispersion (Sec. II.B) plus, from the MD entry points, the repulsion
+    if (threadIdx.x == 0) *a.energy = -0.5 * (r1[0] - a.cself * r2[0]) + 0.5 * r3[0];
   }
 };
 
@@ -823,11 +832,12 @@ hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s) {
 }
 
 hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forces, double* potential,
-                              double* dE_dc6, hipStream_t s) {
+                              double* dE_dc6, hipStream_t s, bool with_repulsion) {
   const int nb = nblocks(n, kBlock);
   if (n > 0) {
     InterpArgs a{P->d_xs, P->d_perm, n, finest_geom(P), P->lv[0].E, P->d_e0, P->d_floc, P->cself,
                  OutPtrs{forces, potential, dE_dc6}, P->d_partial};
+    if (with_repulsion) a.frep = P->d_frep;
     const bool mixed = P->precision == MLS_MIXED;
     hipError_t e;
     if (P->order == 4 && !mixed) e = launch_one<Interp<4, double>>(a, nb, s);
@@ -837,7 +847,12 @@ hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forc
     if (e != hipSuccess) return e;
   }
   // no atoms: an empty sum, E = 0
-  return launch_one<EnergyFinal>(EnergyArgs{P->d_partial, nb, P->cself, energy}, 1, s);
+  EnergyArgs ea{P->d_partial, nb, P->cself, energy};
+  if (with_repulsion) {
+    ea.rep_partial = P->d_md_partial;
+    ea.rep_nb = nb;
+  }
+  return launch_one<EnergyFinal>(ea, 1, s);
 }
 
 hipError_t launch_interpolate_lb(mls_plan_s* P, int n, double* energy, double* forces, hipStream_t s) {

@@ -8,8 +8,9 @@
 // (binning's wrapped positions, cell starts and permutation) and runs on the
 // caller's stream right after the local dispersion part, so that it overlaps
 // the grid chain on the plan's second stream.  It writes cell-sorted forces
-// and per-block energy sums; RepCombine adds both into the caller's outputs
-// after the interpolation has written them.
+// and per-block energy sums; the interpolation adds the forces to the
+// dispersion forces it writes (no second scatter into the caller's array)
+// and the energy reduction adds the sums.
 #include <algorithm>
 #include <cmath>
 
@@ -56,6 +57,12 @@ __device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b :
 // One thread per cell-sorted atom.  The neighbour cells of one (dy, dz) pair
 // form a run of consecutive cells in x, hence one contiguous range of sorted
 // atoms per periodic image in x: the loop walks (dz, dy, image in x, atom).
+// Each row is trimmed to the cells that the cutoff sphere reaches: rows whose
+// y-z slab lies beyond rc are skipped, and the x run is cut to the chord
+// [x - s, x + s], s = sqrt(rc^2 - gy^2 - gz^2), with gy, gz the distances to
+// the row's slab.  Distances to slabs are shrunk and the chord widened by a
+// margin far above the rounding of the cell assignment, so no pair closer
+// than rc is ever left out; the r^2 < rc^2 test decides the rest.
 struct RepPair {
   using Args = RepPairArgs;
   static constexpr int kThreads = kBlock;
@@ -71,20 +78,32 @@ struct RepPair {
       const int cx = c % g.nc[0];
       const int cy = (c / g.nc[0]) % g.nc[1];
       const int cz = c / (g.nc[0] * g.nc[1]);
+      const double my = 1e-6 * g.w[1], mz = 1e-6 * g.w[2], mx = 1e-6 * g.w[0];
       for (int dz = -a.nr[2]; dz <= a.nr[2]; ++dz) {
-        const int qz = floor_div(cz + dz, g.nc[2]);
-        const int zc = cz + dz - qz * g.nc[2];
+        const int uz = cz + dz;  // unwrapped cell index
+        const double gz = fmax(0.0, fmax(uz * g.w[2] - p.z, p.z - (uz + 1) * g.w[2]) - mz);
+        const double rz = a.rc2 - gz * gz;
+        if (rz <= 0.0) continue;
+        const int qz = floor_div(uz, g.nc[2]);
+        const int zc = uz - qz * g.nc[2];
         const double sz = qz * g.L[2];
         for (int dy = -a.nr[1]; dy <= a.nr[1]; ++dy) {
-          const int qy = floor_div(cy + dy, g.nc[1]);
-          const int yc = cy + dy - qy * g.nc[1];
+          const int uy = cy + dy;
+          const double gy = fmax(0.0, fmax(uy * g.w[1] - p.y, p.y - (uy + 1) * g.w[1]) - my);
+          const double rem = rz - gy * gy;
+          if (rem <= 0.0) continue;
+          const int qy = floor_div(uy, g.nc[1]);
+          const int yc = uy - qy * g.nc[1];
           const double sy = qy * g.L[1];
           const int row = (zc * g.nc[1] + yc) * g.nc[0];
-          const int q0 = floor_div(cx - a.nr[0], g.nc[0]);
-          const int q1 = floor_div(cx + a.nr[0], g.nc[0]);
+          const double chord = sqrt(rem) + mx;
+          const int ulo = max(cx - a.nr[0], (int)floor((p.x - chord) * g.inv_w[0]));
+          const int uhi = min(cx + a.nr[0], (int)floor((p.x + chord) * g.inv_w[0]));
+          const int q0 = floor_div(ulo, g.nc[0]);
+          const int q1 = floor_div(uhi, g.nc[0]);
           for (int qx = q0; qx <= q1; ++qx) {
-            const int lo = max(cx - a.nr[0] - qx * g.nc[0], 0);
-            const int hi = min(cx + a.nr[0] - qx * g.nc[0], g.nc[0] - 1);
+            const int lo = max(ulo - qx * g.nc[0], 0);
+            const int hi = min(uhi - qx * g.nc[0], g.nc[0] - 1);
             const int j0 = a.cell_start[row + lo], j1 = a.cell_start[row + hi + 1];
             const double sx = qx * g.L[0];
             const bool home = qx == 0 && qy == 0 && qz == 0;
@@ -109,35 +128,12 @@ struct RepPair {
         }
       }
       e *= ci;
-      a.frep[s] = ci * fx;
-      a.frep[a.stride + s] = ci * fy;
-      a.frep[2 * a.stride + s] = ci * fz;
+      a.frep[3 * (size_t)s + 0] = ci * fx;
+      a.frep[3 * (size_t)s + 1] = ci * fy;
+      a.frep[3 * (size_t)s + 2] = ci * fz;
     }
     const double t = block_sum(e, sh);
     if (threadIdx.x == 0) a.partial[blk] = t;
-  }
-};
-
-// forces[perm[s]] += frep[s]; block 0 also adds 1/2 of the energy partial
-// sums (written by RepPair earlier in stream order) to *energy
-struct RepCombine {
-  using Args = RepCombineArgs;
-  static constexpr int kThreads = kBlock;
-  static __device__ void run(const Args& a, int blk) {
-    __shared__ double sh[kBlock];
-    const int s = blk * kBlock + threadIdx.x;
-    if (a.forces && s < a.n) {
-      double* f = a.forces + 3 * (size_t)a.perm[s];
-      f[0] += a.frep[s];
-      f[1] += a.frep[a.stride + s];
-      f[2] += a.frep[2 * a.stride + s];
-    }
-    if (blk == 0) {
-      double v = 0.0;
-      for (int i = threadIdx.x; i < a.npartial; i += kBlock) v += a.partial[i];
-      const double t = block_sum(v, sh);
-      if (threadIdx.x == 0) *a.energy += 0.5 * t;
-    }
   }
 };
 
@@ -210,14 +206,8 @@ hipError_t launch_repulsion(mls_plan_s* P, int n, const double* c12, double rc, 
   ra.rc2 = rc * rc;
   ra.n = n;
   ra.frep = P->d_frep;
-  ra.stride = (int)P->n_max;
   ra.partial = P->d_md_partial;
   return launch_one<RepPair>(ra, nblocks(n, kBlock), s);
-}
-
-hipError_t launch_rep_combine(mls_plan_s* P, int n, double* energy, double* forces, hipStream_t s) {
-  RepCombineArgs ca{P->d_perm, n, P->d_frep, (int)P->n_max, P->d_md_partial, nblocks(n, kBlock), energy, forces};
-  return launch_one<RepCombine>(ca, std::max(1, nblocks(n, kBlock)), s);
 }
 
 hipError_t launch_md_step(mls_plan_s* P, int n, double* pos, double* vel, const double* forces,

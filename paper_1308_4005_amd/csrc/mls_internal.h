@@ -114,11 +114,7 @@ struct BinCountArgs {
 struct RepGatherArgs { const int* perm; const double* c12; int n; double* x12s; int* flags; };
 struct RepPairArgs {
   const double4* xs; const double* x12s; const int* cell_s; const int* cell_start; CellGeom g;
-  int nr[3]; double rc2; int n; double* frep; int stride; double* partial;
-};
-struct RepCombineArgs {
-  const int* perm; int n; const double* frep; int stride; const double* partial; int npartial;
-  double* energy; double* forces;
+  int nr[3]; double rc2; int n; double* frep; double* partial;
 };
 constexpr int kMdEnd = 1, kMdStart = 2;
 struct MdStepArgs {
@@ -179,8 +175,13 @@ struct TransferArgs {              // restriction (fine -> coarse) and prolongat
 struct InterpArgs {
   const double4* xs; const int* perm; int n; GridGeom gg; const double* E1; const double* e0;
   const double* floc; double cself; OutPtrs out; double* partial;
+  const double* frep = nullptr;   // sorted (n,3) repulsive forces added to the output, or null
 };
-struct EnergyArgs { const double* partial; int nb; double cself; double* energy; };
+struct EnergyArgs {
+  const double* partial; int nb; double cself; double* energy;
+  const double* rep_partial = nullptr;  // block sums of the repulsive energy (twice E_rep), or null
+  int rep_nb = 0;
+};
 struct InterpLbArgs {
   const double4* xs; const double* sig; const int* perm; int n; GridGeom gg; const double* E1[7];
   const double* e0; const double* floc; double* forces; double* partial;
@@ -337,7 +338,7 @@ struct mls_plan_s {
   int* d_flags = nullptr;          // [0]: input flags (1 position, 2 C6, 4 anterpolation tile overrun,
                                    //      8 C12 / inverse mass / velocity of the MD entry points)
   double* d_x12s = nullptr;        // geometric mixing: sorted sqrt(C12) (n_max + pad)
-  double* d_frep = nullptr;        // geometric mixing: sorted repulsive forces, 3 rows of n_max
+  double* d_frep = nullptr;        // geometric mixing: sorted repulsive forces (n_max,3)
   double* d_md_partial = nullptr;  // geometric mixing: repulsion energy and kinetic block sums (2 n_partial)
   bool ant_tiles = false;          // two-phase anterpolation tables built
   mls::AntTiles ant{};
@@ -388,7 +389,7 @@ hipError_t launch_stencils(mls_plan_s* P, hipStream_t s);
 hipError_t launch_coarsest(mls_plan_s* P, hipStream_t s);
 hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s);
 hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forces,
-                              double* potential, double* dE_dc6, hipStream_t s);
+                              double* potential, double* dE_dc6, hipStream_t s, bool with_repulsion = false);
 // Lorentz-Berthelot pieces: sorted sigma and flags, the sorted charges of
 // vector k, and the interpolation of all seven vectors with the energy
 hipError_t launch_lb_gather(mls_plan_s* P, int n, const double* sigma, hipStream_t s);
@@ -401,10 +402,10 @@ hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
 hipError_t launch_zero_i(int* p, int64_t count, hipStream_t s);
 hipError_t launch_copy_stage(mls_plan_s* P, int what, int level, void* dst, hipStream_t s);
 // molecular dynamics (md.hip): repulsion over the sorted atoms of the current
-// evaluation, its combination into the outputs, and one velocity-Verlet
+// evaluation (its forces and energy join the outputs in the interpolation,
+// launch_interpolate with with_repulsion), and one velocity-Verlet
 // kernel (mode kMdEnd / kMdStart) with the kinetic energy written to *kinetic
 hipError_t launch_repulsion(mls_plan_s* P, int n, const double* c12, double rc, hipStream_t s);
-hipError_t launch_rep_combine(mls_plan_s* P, int n, double* energy, double* forces, hipStream_t s);
 hipError_t launch_md_step(mls_plan_s* P, int n, double* pos, double* vel, const double* forces,
                           const double* inv_mass, double dt, int mode, double* kinetic, hipStream_t s);
 
