@@ -147,8 +147,9 @@ mls_status mls_evaluate(mls_plan_t plan, int64_t n, const double* pos, const dou
  * directly over every periodic image closer than rc (no grid part: the
  * r^-12 term is short-ranged):
  *   E_rep = 1/2 sum_i sum'_{(j,n), r < rc} C^rep_ij r^-12,  F_rep = -grad E_rep.
- * The repulsion runs in FP64 in every precision mode, on the atoms binned by
- * the same evaluation.  Plan: geometric mixing.
+ * The repulsion is evaluated on the atoms binned by the same evaluation, in
+ * the precision of the local part (mixed plans: FP32 pair terms summed in
+ * FP64, as the dispersion).  Plan: geometric mixing.
  *   c12     device (n) FP64, finite and >= 0 (else device flag bit 3)
  *   rc      repulsion cutoff, 0 < rc <= a (host)
  *   energy  device, 1 FP64: E_disp + E_rep (overwritten)

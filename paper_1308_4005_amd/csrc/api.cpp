@@ -150,9 +150,14 @@ mls_status evaluate_geometric(mls_plan_t P, int64_t n, const double* pos, const 
   // filled and drained every CU; measured with graph replays at 10^6 atoms:
   // 0.835 ms per evaluation against 0.877 ms with the pair kernel first).
   const int after = fork ? P->pair_after : 0;
+  // the repulsion rides on the pair kernel where that kernel supports it,
+  // else runs as its own kernel right after it
+  const PairRep prep{P->d_x12s, P->d_x12f, rep ? rep->rc * rep->rc : 0.0, P->d_frep, P->d_md_partial};
   auto pair = [&]() -> mls_status {
-    HIP_TRY(launch_pair(P, ni, s), "pair kernel");
-    if (rep) HIP_TRY(launch_repulsion(P, ni, rep->c12, rep->rc, s), "repulsion");
+    if (rep) HIP_TRY(launch_rep_gather(P, ni, rep->c12, s), "repulsion");
+    bool fused = false;
+    HIP_TRY(launch_pair(P, ni, s, rep ? &prep : nullptr, &fused), "pair kernel");
+    if (rep && !fused) HIP_TRY(launch_repulsion(P, ni, rep->rc, s), "repulsion");
     HIP_TRY(mark(1 + MLS_T_PAIR), "timing event");
     return MLS_OK;
   };

@@ -850,7 +850,7 @@ hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forc
   EnergyArgs ea{P->d_partial, nb, P->cself, energy};
   if (with_repulsion) {
     ea.rep_partial = P->d_md_partial;
-    ea.rep_nb = nb;
+    ea.rep_nb = n > 0 ? P->rep_nb : 0;
   }
   return launch_one<EnergyFinal>(ea, 1, s);
 }

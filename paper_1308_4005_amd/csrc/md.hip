@@ -5,10 +5,12 @@
 // integrator.
 //
 // The repulsion reuses the cell-sorted atoms of the evaluation it belongs to
-// (binning's wrapped positions, cell starts and permutation) and runs on the
-// caller's stream right after the local dispersion part, so that it overlaps
-// the grid chain on the plan's second stream.  It writes cell-sorted forces
-// and per-block energy sums; the interpolation adds the forces to the
+// (binning's wrapped positions, cell starts and permutation).  The half-cell
+// pair kernels (pair.hip) evaluate it on the pairs they already queue for
+// the local dispersion part (rc <= a); for the other cell layouts RepPair
+// below runs on the caller's stream right after the local part, overlapping
+// the grid chain on the plan's second stream.  Either writes cell-sorted
+// forces and per-block energy sums; the interpolation adds the forces to the
 // dispersion forces it writes (no second scatter into the caller's array)
 // and the energy reduction adds the sums.
 #include <algorithm>
@@ -39,6 +41,7 @@ struct RepGather {
       }
     }
     a.x12s[s] = x;
+    if (a.x12f) a.x12f[s] = (float)x;
   }
 };
 
@@ -192,10 +195,12 @@ inline int nblocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
 
-hipError_t launch_repulsion(mls_plan_s* P, int n, const double* c12, double rc, hipStream_t s) {
-  hipError_t e = launch_one<RepGather>(RepGatherArgs{P->d_perm, c12, n, P->d_x12s, P->d_flags},
-                                       nblocks(n + kSortedPad, kBlock), s);
-  if (e != hipSuccess) return e;
+hipError_t launch_rep_gather(mls_plan_s* P, int n, const double* c12, hipStream_t s) {
+  return launch_one<RepGather>(RepGatherArgs{P->d_perm, c12, n, P->d_x12s, P->d_x12f, P->d_flags},
+                               nblocks(n + kSortedPad, kBlock), s);
+}
+
+hipError_t launch_repulsion(mls_plan_s* P, int n, double rc, hipStream_t s) {
   RepPairArgs ra{};
   ra.xs = P->d_xs;
   ra.x12s = P->d_x12s;
@@ -207,12 +212,13 @@ hipError_t launch_repulsion(mls_plan_s* P, int n, const double* c12, double rc, 
   ra.n = n;
   ra.frep = P->d_frep;
   ra.partial = P->d_md_partial;
+  P->rep_nb = nblocks(n, kBlock);
   return launch_one<RepPair>(ra, nblocks(n, kBlock), s);
 }
 
 hipError_t launch_md_step(mls_plan_s* P, int n, double* pos, double* vel, const double* forces,
                           const double* inv_mass, double dt, int mode, double* kinetic, hipStream_t s) {
-  double* part = P->d_md_partial + P->n_partial;
+  double* part = P->d_md_partial + P->rep_cap;
   if (n > 0) {
     MdStepArgs ma{pos, vel, forces, inv_mass, n, 0.5 * dt, dt, mode, part, P->d_flags};
     hipError_t e = launch_one<MdStep>(ma, nblocks(n, kBlock), s);

@@ -111,7 +111,7 @@ struct BinCountArgs {
   double c6_scale;   // xi = sqrt(c6_scale * c6): 1 for C6, 2 for Lorentz-Berthelot epsilon
 };
 // molecular dynamics (md.hip): repulsion of eq:disp-pair-pot and velocity Verlet
-struct RepGatherArgs { const int* perm; const double* c12; int n; double* x12s; int* flags; };
+struct RepGatherArgs { const int* perm; const double* c12; int n; double* x12s; float* x12f; int* flags; };
 struct RepPairArgs {
   const double4* xs; const double* x12s; const int* cell_s; const int* cell_start; CellGeom g;
   int nr[3]; double rc2; int n; double* frep; double* partial;
@@ -133,14 +133,23 @@ struct GatherArgs {
   double* xi_partial;   // mixed precision: per-block sums of xi (else null)
 };
 struct SumXiArgs { int rows; const double* partial; double* out; };   // partials of ceil(rows / 256) gather blocks
+// The repulsive term of the MD entry points, evaluated by the pair kernels on
+// the pairs they already hold (rc <= a): sorted sqrt(C12) in FP64 (and FP32
+// for the mixed kernel), the cutoff, the sorted (n,3) forces and one energy
+// sum per block.
+struct PairRep {
+  const double* x12; const float* x12f; double rc2; double* frep; double* partial;
+};
 struct PairArgs {
   const double4* xs; const int* cell_s; const int* cstart; int n; CellGeom g; PairConst pc;
   double* e0; double* floc;
   const double* sig;      // Lorentz-Berthelot: sorted sigma (source weight e_j s_ij^6)
+  PairRep rep{};
 };
 struct PairArgsF {
   const float4* xr; const float* xif; const double4* xs; const int* cell_s; const int* cstart;
   int n; CellGeom g; PairConstF pc; double* e0; double* floc;
+  PairRep rep{};
 };
 struct AnterpArgs {
   const double4* xs; const int* cstart; int n; CellGeom cg; GridGeom gg; AntGeom ag; double* q;
@@ -338,8 +347,11 @@ struct mls_plan_s {
   int* d_flags = nullptr;          // [0]: input flags (1 position, 2 C6, 4 anterpolation tile overrun,
                                    //      8 C12 / inverse mass / velocity of the MD entry points)
   double* d_x12s = nullptr;        // geometric mixing: sorted sqrt(C12) (n_max + pad)
+  float* d_x12f = nullptr;         // the same in FP32 (mixed precision)
+  int rep_cap = 0;                 // repulsion energy block sums d_md_partial holds before the kinetic ones
+  int rep_nb = 0;                  // block sums written by the last repulsion launch
   double* d_frep = nullptr;        // geometric mixing: sorted repulsive forces (n_max,3)
-  double* d_md_partial = nullptr;  // geometric mixing: repulsion energy and kinetic block sums (2 n_partial)
+  double* d_md_partial = nullptr;  // geometric mixing: repulsion energy (rep_cap) and kinetic (n_partial) block sums
   bool ant_tiles = false;          // two-phase anterpolation tables built
   mls::AntTiles ant{};
   int* d_ant_tab = nullptr;
@@ -381,7 +393,9 @@ int stencil_tile_zc(int R, bool f64);
 
 // kernel launchers (one per file); all enqueue on `s` and return the launch status
 hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double* c6, hipStream_t s);
-hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s);
+// With `rep`, the FP32 and FP64 half-cell kernels also evaluate the repulsion
+// (*fused set); other kernels leave it to launch_repulsion.
+hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s, const PairRep* rep = nullptr, bool* fused = nullptr);
 hipError_t launch_scan(mls_plan_s* P, const int* count, int m, int* start, hipStream_t s);
 hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s);
 hipError_t launch_restrict(mls_plan_s* P, int k_fine, hipStream_t s);
@@ -405,7 +419,8 @@ hipError_t launch_copy_stage(mls_plan_s* P, int what, int level, void* dst, hipS
 // evaluation (its forces and energy join the outputs in the interpolation,
 // launch_interpolate with with_repulsion), and one velocity-Verlet
 // kernel (mode kMdEnd / kMdStart) with the kinetic energy written to *kinetic
-hipError_t launch_repulsion(mls_plan_s* P, int n, const double* c12, double rc, hipStream_t s);
+hipError_t launch_rep_gather(mls_plan_s* P, int n, const double* c12, hipStream_t s);
+hipError_t launch_repulsion(mls_plan_s* P, int n, double rc, hipStream_t s);
 hipError_t launch_md_step(mls_plan_s* P, int n, double* pos, double* vel, const double* forces,
                           const double* inv_mass, double dt, int mode, double* kinetic, hipStream_t s);
 

@@ -243,6 +243,12 @@ struct PairAcc {
   int head;   // the lane's queue is a ring of kQueue slots
 };
 
+// Per-lane sums of the repulsive term (MD entry points): sum_j sqrt(C12_j)
+// r^-12 and sum_j 12 sqrt(C12_j) r^-14 d over the pairs with r < rc.
+struct RepAcc {
+  double e, fx, fy, fz;
+};
+
 // A drain during the scan consumes at most this many entries per lane: the
 // lane that forced it is then well below the limit, and lanes with few
 // entries idle for fewer steps than in a drain to empty.
@@ -251,11 +257,11 @@ constexpr int kDrain = 16;
 // Full g_0 evaluation of up to `limit` queued sources per lane, oldest first.
 // The loop body has no branches: slots past a lane's count (and the target
 // itself) evaluate a harmless pair with zero weight, adding exactly 0.
-template <int K, bool LB>
+template <int K, bool LB, bool R>
 __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, int limit, int lane, int self_ent,
                                                int safe_j, const double4& xi, const double4* __restrict__ xs,
                                                const CellGeom& g, const PairConst& pc, const double* __restrict__ sig,
-                                               double sig_i, PairAcc& A) {
+                                               double sig_i, PairAcc& A, const PairRep& rp, RepAcc& B) {
   const double r2_idle = 0.25 * pc.a2;
   const int cnt = A.cnt;
   for (int t = 0; t < limit && __any(t < cnt); ++t) {
@@ -280,6 +286,16 @@ __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, in
     A.fx += f * dx;
     A.fy += f * dy;
     A.fz += f * dz;
+    if constexpr (R) {
+      const double ir2 = recip(r2);
+      const double ir6 = ir2 * ir2 * ir2;
+      const double v = (ok && r2 < rp.rc2 ? rp.x12[j] : 0.0) * ir6 * ir6;
+      const double fv = 12.0 * v * ir2;
+      B.e += v;
+      B.fx += fv * dx;
+      B.fy += fv * dy;
+      B.fz += fv * dz;
+    }
   }
   const int done = min(cnt, limit);
   A.head = (A.head + done) & (kQueue - 1);
@@ -292,11 +308,12 @@ __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, in
 // far-away rows, and rows past j1 are never kept.  The filter loop touches no
 // accumulator: it stops when a queue may overflow, the queues are partly
 // drained, and the filter resumes.
-template <int K, bool LB>
+template <int K, bool LB, bool R>
 __device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int* __restrict__ queue, int lane,
                                               int self_ent, int safe_j, const double4& xi,
                                               const double4* __restrict__ xs, const CellGeom& g, const PairConst& pc,
-                                              const double* __restrict__ sig, double sig_i, PairAcc& A) {
+                                              const double* __restrict__ sig, double sig_i, PairAcc& A,
+                                              const PairRep& rp, RepAcc& B) {
   const double ax = xi.x - (double)((img & 3) - 1) * g.L[0];
   const double ay = xi.y - (double)(((img >> 2) & 3) - 1) * g.L[1];
   const double az = xi.z - (double)(((img >> 4) & 3) - 1) * g.L[2];
@@ -328,7 +345,7 @@ __device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int* __res
     }
     A.cnt = cnt;
     if (!full) break;
-    pair_drain_f64<K, LB>(queue, kDrain, lane, self_ent, safe_j, xi, xs, g, pc, sig, sig_i, A);
+    pair_drain_f64<K, LB, R>(queue, kDrain, lane, self_ent, safe_j, xi, xs, g, pc, sig, sig_i, A, rp, B);
   }
 }
 
@@ -336,7 +353,29 @@ __device__ __forceinline__ double gap1(double x, double lo, double w, double eps
   return fmax(0.0, fmax(lo - x, x - (lo + w)) - eps);
 }
 
-template <int K, bool LB = false>
+// Per-wave sum of one value (lanes of a 64-wide block).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Repulsive outputs of target sc: its sorted forces and, per block (one
+// wave), the sum of sqrt(C12_i) times the lanes' energy sums.
+__device__ __forceinline__ void store_rep(const PairRep& rp, bool active, int sc, int lane, int blk,
+                                          const RepAcc& B) {
+  double e = 0.0;
+  if (active) {
+    const double ci = rp.x12[sc];
+    e = ci * B.e;
+    rp.frep[3 * (size_t)sc + 0] = ci * B.fx;
+    rp.frep[3 * (size_t)sc + 1] = ci * B.fy;
+    rp.frep[3 * (size_t)sc + 2] = ci * B.fz;
+  }
+  e = wave_sum(e);
+  if (lane == 0) rp.partial[blk] = e;
+}
+
+template <int K, bool LB = false, bool R = false>
 struct PairTrimF64 {
   using Args = PairArgs;
   static constexpr int kThreads = kWaveQ;
@@ -358,6 +397,8 @@ struct PairTrimF64 {
   // the target itself, seen in the home image, is skipped in the drain
   const int self_ent = active ? ((sc << 6) | image_bits(0, 0, 0)) : -1;
   PairAcc A{0.0, 0.0, 0.0, 0.0, 0};
+  RepAcc B{0.0, 0.0, 0.0, 0.0};
+  const PairRep& rp = ar.rep;
   const float reach = (float)(1.0 + 1e-5);
   for (int dz = -2; dz <= 2; ++dz) {
     const int uz = cz + dz;
@@ -397,19 +438,20 @@ struct PairTrimF64 {
         k0 = cstart[row + lo2];
         k1 = cstart[row + hi2 + 1];
       }
-      pair_scan_f64<K, LB>(j0, j1, image_bits(ix1, iy, iz), queue, lane, self_ent, sc, xi, xs, g, pc, ar.sig, sig_i,
-                           A);
-      pair_scan_f64<K, LB>(k0, k1, image_bits(ix2, iy, iz), queue, lane, self_ent, sc, xi, xs, g, pc, ar.sig, sig_i,
-                           A);
+      pair_scan_f64<K, LB, R>(j0, j1, image_bits(ix1, iy, iz), queue, lane, self_ent, sc, xi, xs, g, pc, ar.sig,
+                              sig_i, A, rp, B);
+      pair_scan_f64<K, LB, R>(k0, k1, image_bits(ix2, iy, iz), queue, lane, self_ent, sc, xi, xs, g, pc, ar.sig,
+                              sig_i, A, rp, B);
     }
   }
-  pair_drain_f64<K, LB>(queue, kQueue, lane, self_ent, sc, xi, xs, g, pc, ar.sig, sig_i, A);
+  pair_drain_f64<K, LB, R>(queue, kQueue, lane, self_ent, sc, xi, xs, g, pc, ar.sig, sig_i, A, rp, B);
   if (active) {
     ar.e0[sc] = A.e;
     ar.floc[3 * (size_t)sc + 0] = xi.w * A.fx;
     ar.floc[3 * (size_t)sc + 1] = xi.w * A.fy;
     ar.floc[3 * (size_t)sc + 2] = xi.w * A.fz;
   }
+  if constexpr (R) store_rep(rp, active, sc, lane, blk, B);
   }
 };
 
@@ -450,15 +492,18 @@ __device__ __forceinline__ int entry_bits(int ix, int dy, int dz) { return (ix &
 // The loop body has no branches: slots past a lane's count (and the target
 // itself) evaluate a harmless pair with zero weight, so every lane adds
 // exactly 0 for them.
-template <int K>
+template <int K, bool R>
 __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, int limit, int lane,
                                                const PairLaneF& L, const float4* __restrict__ xr,
-                                               const float* __restrict__ xif, const PairConstF& pc, PairAccM& A) {
+                                               const float* __restrict__ xif, const PairConstF& pc, PairAccM& A,
+                                               const PairRep& rp, RepAcc& B) {
   const float r2_idle = 0.25f * pc.a2;
+  const float rc2 = (float)rp.rc2;
   const int cnt = A.cnt;
   // the (at most 32) terms of one drain are summed in FP32, the drains' sums
   // in FP64
   float e = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
+  float re = 0.0f, rfx = 0.0f, rfy = 0.0f, rfz = 0.0f;
   for (int t = 0; t < limit && __any(t < cnt); ++t) {
     const int q = queue[((A.head + t) & (kQueue - 1)) * kWaveQ + lane];
     const bool ok = (t < cnt) & (q != L.self_ent);
@@ -479,11 +524,27 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
     fx = fmaf(f, dxv, fx);
     fy = fmaf(f, dyv, fy);
     fz = fmaf(f, dzv, fz);
+    if constexpr (R) {
+      const float ir2 = recip(r2);
+      const float ir6 = ir2 * ir2 * ir2;
+      const float v = (ok && r2 < rc2 ? rp.x12f[j] : 0.0f) * ir6 * ir6;
+      const float fv = 12.0f * v * ir2;
+      re += v;
+      rfx = fmaf(fv, dxv, rfx);
+      rfy = fmaf(fv, dyv, rfy);
+      rfz = fmaf(fv, dzv, rfz);
+    }
   }
   A.e += (double)e;
   A.fx += (double)fx;
   A.fy += (double)fy;
   A.fz += (double)fz;
+  if constexpr (R) {
+    B.e += (double)re;
+    B.fx += (double)rfx;
+    B.fy += (double)rfy;
+    B.fz += (double)rfz;
+  }
   const int done = min(cnt, limit);
   A.head = (A.head + done) & (kQueue - 1);
   A.cnt = cnt - done;
@@ -492,10 +553,11 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
 // Scan sources [j, j1) of one row run (image ix along x, row offsets dy, dz).
 // The filter loop touches no accumulator: it stops when a queue may
 // overflow, the queues are partly drained, and the filter resumes.
-template <int K>
+template <int K, bool R>
 __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int dz, int* __restrict__ queue,
                                               int lane, const PairLaneF& L, const float4* __restrict__ xr,
-                                              const float* __restrict__ xif, const PairConstF& pc, PairAccM& A) {
+                                              const float* __restrict__ xif, const PairConstF& pc, PairAccM& A,
+                                              const PairRep& rp, RepAcc& B) {
   // the drain rebuilds these with the same operations
   const float bx = fmaf((float)ix, -L.ncf, L.cxf);
   const float ay = fmaf((float)-dy, pc.w[1], L.yy);
@@ -527,11 +589,11 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
     }
     A.cnt = cnt;
     if (!full) break;
-    pair_drain_f32<K>(queue, kDrainF, lane, L, xr, xif, pc, A);
+    pair_drain_f32<K, R>(queue, kDrainF, lane, L, xr, xif, pc, A, rp, B);
   }
 }
 
-template <int K>
+template <int K, bool R = false>
 struct PairTrimF32 {
   using Args = PairArgsF;
   static constexpr int kThreads = kWaveQ;
@@ -552,6 +614,8 @@ struct PairTrimF32 {
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
   const PairLaneF L{xi.x, xi.y, xi.z, (float)cx, (float)g.nc[0], active ? ((sc << 8) | entry_bits(0, 0, 0)) : -1, sc};
   PairAccM A{0.0, 0.0, 0.0, 0.0, 0};
+  RepAcc B{0.0, 0.0, 0.0, 0.0};
+  const PairRep& rp = ar.rep;
   // Rows are chosen and trimmed in the target's cell-relative FP32
   // coordinates.  The gaps are shrunk and the reach grown by margins (1e-5 of
   // a cell, 2e-5 of the cutoff) far above their FP32 rounding (~1e-7), so no
@@ -601,11 +665,11 @@ struct PairTrimF32 {
         k0 = cstart[row + lo2];
         k1 = cstart[row + hi2 + 1];
       }
-      pair_scan_f32<K>(j0, j1, ix1, dy, dz, queue, lane, L, xr, xif, pc, A);
-      pair_scan_f32<K>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xif, pc, A);
+      pair_scan_f32<K, R>(j0, j1, ix1, dy, dz, queue, lane, L, xr, xif, pc, A, rp, B);
+      pair_scan_f32<K, R>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xif, pc, A, rp, B);
     }
   }
-  pair_drain_f32<K>(queue, kQueue, lane, L, xr, xif, pc, A);
+  pair_drain_f32<K, R>(queue, kQueue, lane, L, xr, xif, pc, A, rp, B);
   if (active) {
     const double wi = (double)xif[sc];
     ar.e0[sc] = A.e;
@@ -613,6 +677,7 @@ struct PairTrimF32 {
     ar.floc[3 * (size_t)sc + 1] = wi * A.fy;
     ar.floc[3 * (size_t)sc + 2] = wi * A.fz;
   }
+  if constexpr (R) store_rep(rp, active, sc, lane, blk, B);
   }
 };
 
@@ -637,15 +702,26 @@ PairConstF pair_const_f(const mls_plan_s* P) {
 int pair_variant(const mls_plan_s* P) { return P->continuity == 2 ? 2 : 0; }
 
 template <int K>
-hipError_t launch_pair_k(mls_plan_s* P, int n, hipStream_t s) {
+hipError_t launch_pair_k(mls_plan_s* P, int n, hipStream_t s, const PairRep* rep, bool* fused) {
   const CellGeom& g = P->cg;
+  const int waves = (n + kWaveQ - 1) / kWaveQ;
   if (P->precision == MLS_MIXED && P->pair_fast && n < (1 << 24)) {
     PairArgsF a{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const_f(P), P->d_e0,
                 P->d_floc};
-    return launch_one<PairTrimF32<K>>(a, (n + kWaveQ - 1) / kWaveQ, s);
+    if (!rep) return launch_one<PairTrimF32<K>>(a, waves, s);
+    a.rep = *rep;
+    *fused = true;
+    P->rep_nb = waves;
+    return launch_one<PairTrimF32<K, true>>(a, waves, s);
   }
   PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const(P), P->d_e0, P->d_floc, nullptr};
-  if (P->pair_fast && n < (1 << 25)) return launch_one<PairTrimF64<K>>(a, (n + kWaveQ - 1) / kWaveQ, s);
+  if (P->pair_fast && n < (1 << 25)) {
+    if (!rep) return launch_one<PairTrimF64<K>>(a, waves, s);
+    a.rep = *rep;
+    *fused = true;
+    P->rep_nb = waves;
+    return launch_one<PairTrimF64<K, false, true>>(a, waves, s);
+  }
   if (!P->pair_fast) return launch_one<PairWave<K>>(a, n, s);
   return launch_one<PairGeneric<K>>(a, (n + kBlock - 1) / kBlock, s);
 }
@@ -664,9 +740,12 @@ hipError_t launch_pair_lb(mls_plan_s* P, int n, hipStream_t s) {
   return pair_variant(P) == 2 ? launch_pair_lb_k<2>(P, n, s) : launch_pair_lb_k<0>(P, n, s);
 }
 
-hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s) {
+hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s, const PairRep* rep, bool* fused) {
+  bool f = false;
+  if (!fused) fused = &f;
+  *fused = false;
   if (n == 0) return hipSuccess;
-  return pair_variant(P) == 2 ? launch_pair_k<2>(P, n, s) : launch_pair_k<0>(P, n, s);
+  return pair_variant(P) == 2 ? launch_pair_k<2>(P, n, s, rep, fused) : launch_pair_k<0>(P, n, s, rep, fused);
 }
 
 template <int K>
