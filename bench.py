@@ -66,8 +66,8 @@ def work_model(plan_info, n, pairs, order):
 
 
 # kernels that carry each stage of the 10^6-atom cube (cell width a/2 there)
-STAGE_KERNEL = {("pair", "mixed"): ["void k_one<PairTrimF32<2> >"],
-                ("pair", "fp64"): ["void k_one<PairTrimF64<2, false> >"],
+STAGE_KERNEL = {("pair", "mixed"): ["void k_one<PairTrimF32<2, false> >"],
+                ("pair", "fp64"): ["void k_one<PairTrimF64<2, false, false> >"],
                 ("stencil", "mixed"): ["void k_stencil_tile<float, 6, 16, 4>"],
                 ("stencil", "fp64"): ["void k_stencil_tile<double, 6, 8, 4>"],
                 ("anterpolation", "mixed"): ["void k_one<AnterpTile<4, float> >", "void k_one<AnterpCollect>"],
