@@ -92,3 +92,12 @@ def test_null_arguments_are_rejected(lib):
     assert lib.mls_plan_destroy(None) == _lib.MLS_OK
     info = _lib.MLSPlanInfo()
     assert lib.mls_plan_get_info(None, ctypes.byref(info)) == _lib.MLS_ERR_INVALID_ARG
+
+
+def test_md_entry_points_reject_bad_arguments(lib):
+    # rejected on the host before any device work: null plan
+    assert lib.mls_evaluate_md(None, 0, None, None, None, ctypes.c_double(1.0), None, None,
+                               None) == _lib.MLS_ERR_INVALID_ARG
+    assert lib.mls_md_run(None, 0, None, None, None, None, ctypes.c_double(1.0), None, ctypes.c_double(0.001), 1,
+                          None, None, None, None) == _lib.MLS_ERR_INVALID_ARG
+    assert "null plan" in lib.mls_last_error().decode()
