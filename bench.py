@@ -274,7 +274,9 @@ def time_md(w, prm, precision, steps, warmup, dev, blocks, chunk=50, dt=0.001):
     ``chunk`` velocity-Verlet steps; ``ms_per_step`` is the median block of
     replays divided by ``chunk`` (a call evaluates the forces chunk + 1
     times: once at its starting positions, then once per step).  Also times
-    one mls_evaluate_md (dispersion plus repulsion) the same way."""
+    one mls_evaluate_md (dispersion plus repulsion) the same way, and
+    multiple time stepping (mls_md_run_mts, grid part every 4 steps) in
+    48-step calls continuing the same trajectory."""
     import numpy as np
     import torch
     from paper_1308_4005_amd import Plan, Result
@@ -296,13 +298,27 @@ def time_md(w, prm, precision, steps, warmup, dev, blocks, chunk=50, dt=0.001):
     torch.cuda.synchronize()
     flags = plan.status()
     tot = (ep + ek).cpu().numpy()
+    # multiple time stepping: the grid part every k_slow = 4 steps
+    k_slow, chunk_m = 4, 48
+    epm = torch.empty(chunk_m // k_slow + 1, dtype=torch.float64, device=dev)
+    ekm = torch.empty(chunk_m // k_slow + 1, dtype=torch.float64, device=dev)
+    ms_m, block_m = time_graph(lambda: plan.md_run_mts(x, v, c6, c12, im, dt, chunk_m, k_slow, forces=F, epot=epm,
+                                                       ekin=ekm),
+                               max(blocks, steps // chunk_m), max(1, warmup // chunk_m), blocks, dev)
+    torch.cuda.synchronize()
+    flags |= plan.status()
+    totm = (epm + ekm).cpu().numpy()
     plan.close()
     return {"workload": f"{w.name} positions, LJ C6 = C12 = 4, unit masses, velocities N(0, 0.8) (seed 29), "
                         f"repulsion cutoff {prm['a']}, dt {dt}",
             "precision": precision, "ms_per_step": ms / chunk, "steps_per_s": 1000.0 * chunk / ms,
             "block_ms_per_step": [b / chunk for b in block_ms], "steps_per_replay": chunk,
             "evaluate_md_ms": ms_ev, "flags": flags,
-            "last_replay_total_energy_spread_rel": float((tot.max() - tot.min()) / abs(tot.mean()))}
+            "last_replay_total_energy_spread_rel": float((tot.max() - tot.min()) / abs(tot.mean())),
+            "multiple_time_stepping": {
+                "k_slow": k_slow, "ms_per_step": ms_m / chunk_m, "steps_per_s": 1000.0 * chunk_m / ms_m,
+                "block_ms_per_step": [b / chunk_m for b in block_m], "steps_per_replay": chunk_m,
+                "last_replay_total_energy_spread_rel": float((totm.max() - totm.min()) / abs(totm.mean()))}}
 
 
 def run_selection(w, head, steps, dev, target=1e-4):
@@ -501,7 +517,8 @@ def main():
     if not args.no_md:
         log("[bench] molecular dynamics (velocity Verlet, dispersion + repulsion)")
         md = time_md(w, prm, head, args.steps, args.warmup, dev, args.blocks)
-        log(f"[bench] md: {md['ms_per_step']:.3f} ms/step, evaluate_md {md['evaluate_md_ms']:.3f} ms")
+        log(f"[bench] md: {md['ms_per_step']:.3f} ms/step, evaluate_md {md['evaluate_md_ms']:.3f} ms, "
+            f"multiple time stepping (k=4) {md['multiple_time_stepping']['ms_per_step']:.3f} ms/step")
 
     selection = None
     if not args.no_select:

@@ -180,6 +180,33 @@ mls_status mls_md_run(mls_plan_t plan, int64_t n, double* pos, double* vel, cons
                       double rc, const double* inv_mass, double dt, int nsteps, double* forces, double* epot,
                       double* ekin, void* stream);
 
+/* Multiple time stepping (r-RESPA) with the MLS splitting itself: the fast
+ * force is the local part of eq:evaluation (k = 0, the g_0 pair sum) plus the
+ * repulsion of mls_evaluate_md; the slow force is the grid part (levels
+ * 1..l, eq:anterpolation to eq:interpolation), the smooth remainder, applied
+ * every k_slow steps: the split of length scales for multiple-time-step
+ * methods that Sec. I credits the method with, here with two time steps
+ * (r-RESPA, Tuckerman, Berne and Martyna 1992).  One outer step of
+ * k_slow * dt:
+ *   v += (k_slow dt / 2) F_slow/m;
+ *   k_slow times: v += dt/2 F_fast/m; x += dt v; F_fast(x); v += dt/2 F_fast/m;
+ *   F_slow(x); v += (k_slow dt / 2) F_slow/m.
+ * k_slow = 1 is velocity Verlet with F_fast + F_slow (mls_md_run up to
+ * rounding order).  nsteps counts inner steps and must be a multiple of
+ * k_slow.  Outputs (device FP64):
+ *   forces  (n,3): F_fast + F_slow at the final positions
+ *   epot    (nsteps/k_slow + 1): E_fast + E_slow after each outer step
+ *           (index 0: initial positions), where E_fast = -1/2 sum_i xi_i e0_i
+ *           + E_rep and E_slow = the rest of the MLS energy
+ *   ekin    (nsteps/k_slow + 1): kinetic energy at the same instants
+ * Arguments, flags, ordering and errors as mls_md_run, plus
+ * MLS_ERR_INVALID_ARG for k_slow < 1 or nsteps not a multiple of k_slow.
+ * Every fast and every slow evaluation bins the atoms itself (no neighbour
+ * structure is reused across steps). */
+mls_status mls_md_run_mts(mls_plan_t plan, int64_t n, double* pos, double* vel, const double* c6,
+                          const double* c12, double rc, const double* inv_mass, double dt, int nsteps, int k_slow,
+                          double* forces, double* epot, double* ekin, void* stream);
+
 /* One evaluation under Lorentz-Berthelot mixing (Sec. II.D,
  * eq:disp-pair-pot-multilevel-LorentzBerthelot): pair coefficient
  * C_ij = 2 sqrt(eps_i eps_j) ((sigma_i + sigma_j)/2)^6 (eq:xi-lj), so

@@ -19,7 +19,7 @@ import numpy as np
 
 from . import mls as M
 
-__all__ = ["repulsion", "forces", "md_run"]
+__all__ = ["repulsion", "forces", "md_run", "split_forces", "md_run_mts"]
 
 
 def repulsion(pos, c12, box, rc, targets=None):
@@ -86,3 +86,51 @@ def md_run(pos, vel, c6, c12, inv_mass, box, a, h, order, levels, dt, nsteps, co
         epot.append(E)
         kin.append(ekin(v))
     return x, v, F, np.array(epot), np.array(kin)
+
+
+def split_forces(pos, c6, c12, box, a, h, order, levels, continuity=2, rc=None):
+    """The fast/slow split of multiple time stepping: fast = the local part of
+    eq:evaluation (k = 0: energy -1/2 sum_i xi_i e0_i and its forces) plus the
+    repulsion; slow = the rest of the MLS result (the grid part, levels 1..l,
+    with the self-energy correction).  Returns (E_fast, F_fast, E_slow, F_slow)."""
+    r = M.mls(pos, c6, box, a, h, order, levels, continuity=continuity)
+    xi = np.sqrt(np.asarray(c6, dtype=np.float64))
+    E_loc = -0.5 * float(np.dot(xi, r["e0"]))
+    E_fast, F_fast = E_loc, np.array(r["Floc"], dtype=np.float64)
+    E_slow, F_slow = r["energy"] - E_loc, r["F"] - F_fast
+    Er, Fr = repulsion(pos, c12, box, a if rc is None else rc)
+    return E_fast + Er, F_fast + Fr, E_slow, F_slow
+
+
+def md_run_mts(pos, vel, c6, c12, inv_mass, box, a, h, order, levels, dt, nsteps, k_slow, continuity=2, rc=None):
+    """Multiple time stepping (r-RESPA) with the split of ``split_forces``: per
+    outer step of k_slow dt,
+        v += (k_slow dt/2) F_slow/m
+        k_slow times: v += dt/2 F_fast/m; x += dt v; F_fast(x); v += dt/2 F_fast/m
+        F_slow(x); v += (k_slow dt/2) F_slow/m.
+    nsteps (inner steps) is a multiple of k_slow.  Returns final x, v, the
+    total force F_fast + F_slow at the final positions, and E_pot, E_kin at
+    the nsteps / k_slow + 1 outer-step boundaries."""
+    assert nsteps % k_slow == 0
+    x = np.array(pos, dtype=np.float64)
+    v = np.array(vel, dtype=np.float64)
+    im = np.asarray(inv_mass, dtype=np.float64)[:, None]
+    hs = 0.5 * k_slow * dt
+
+    def ekin(v_):
+        return 0.5 * float(np.sum(np.sum(v_ * v_, axis=1) / im[:, 0]))
+
+    Ef, Ff, Es, Fs = split_forces(x, c6, c12, box, a, h, order, levels, continuity, rc)
+    epot, kin = [Ef + Es], [ekin(v)]
+    for _ in range(nsteps // k_slow):
+        v = v + hs * Fs * im
+        for _ in range(k_slow):
+            v = v + 0.5 * dt * Ff * im
+            x = x + dt * v
+            Ef, Ff, _, _ = split_forces(x, c6, c12, box, a, h, order, levels, continuity, rc)
+            v = v + 0.5 * dt * Ff * im
+        _, _, Es, Fs = split_forces(x, c6, c12, box, a, h, order, levels, continuity, rc)
+        v = v + hs * Fs * im
+        epot.append(Ef + Es)
+        kin.append(ekin(v))
+    return x, v, Ff + Fs, np.array(epot), np.array(kin)

@@ -180,9 +180,57 @@ mls_status evaluate_geometric(mls_plan_t P, int64_t n, const double* pos, const 
   if (fork) HIP_TRY(hipEventRecord(P->ev_join, g), "join");
   if (after == 5 && (st = pair()) != MLS_OK) return st;
   if (fork) HIP_TRY(hipStreamWaitEvent(s, P->ev_join, 0), "join");
-  HIP_TRY(launch_interpolate(P, ni, energy, forces, potential, dE_dc6, s, rep != nullptr), "interpolation");
+  HIP_TRY(launch_interpolate(P, ni, energy, forces, potential, dE_dc6, s, rep ? kInterpRep : 0), "interpolation");
   HIP_TRY(mark(1 + MLS_T_INTERP), "timing event");
   return MLS_OK;
+}
+
+// Multiple time stepping: the fast force alone (local part of eq:evaluation
+// with k = 0 plus the repulsion), all on stream s.
+hipError_t evaluate_fast(mls_plan_t P, int n, const double* pos, const double* c6, const Repulsion& rep,
+                         double* energy, double* forces, hipStream_t s) {
+  hipError_t e = launch_binning(P, n, pos, c6, s);
+  if (e == hipSuccess) e = launch_rep_gather(P, n, rep.c12, s);
+  const PairRep prep{P->d_x12s, P->d_x12f, rep.rc * rep.rc, P->d_frep, P->d_md_partial};
+  bool fused = false;
+  if (e == hipSuccess) e = launch_pair(P, n, s, &prep, &fused);
+  if (e == hipSuccess && !fused) e = launch_repulsion(P, n, rep.rc, s);
+  if (e == hipSuccess) e = launch_local_out(P, n, energy, forces, s);
+  return e;
+}
+
+// Both forces at the same positions from one binning: the grid chain on the
+// plan's second stream, concurrently with the local part (as in
+// mls_evaluate), then the fast outputs and the grid-only interpolation.
+// *energy = E_fast + E_slow.
+hipError_t evaluate_split(mls_plan_t P, int n, const double* pos, const double* c6, const Repulsion& rep,
+                          double* energy, double* forces, double* fslow, hipStream_t s) {
+  hipError_t e;
+  if (!P->side) {
+    if ((e = hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  const hipStream_t g = P->side;
+  if ((e = launch_binning(P, n, pos, c6, s)) != hipSuccess) return e;
+  if ((e = hipEventRecord(P->ev_fork, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(g, P->ev_fork, 0)) != hipSuccess) return e;
+  if ((e = launch_anterpolate(P, n, g)) != hipSuccess) return e;
+  if ((e = launch_rep_gather(P, n, rep.c12, s)) != hipSuccess) return e;
+  const PairRep prep{P->d_x12s, P->d_x12f, rep.rc * rep.rc, P->d_frep, P->d_md_partial};
+  bool fused = false;
+  if ((e = launch_pair(P, n, s, &prep, &fused)) != hipSuccess) return e;
+  if (!fused && (e = launch_repulsion(P, n, rep.rc, s)) != hipSuccess) return e;
+  for (int k = 2; k <= P->levels; ++k)
+    if ((e = launch_restrict(P, k - 1, g)) != hipSuccess) return e;
+  if ((e = launch_stencils(P, g)) != hipSuccess) return e;
+  if ((e = launch_coarsest(P, g)) != hipSuccess) return e;
+  for (int k = P->levels - 1; k >= 1; --k)
+    if ((e = launch_prolong(P, k, g)) != hipSuccess) return e;
+  if ((e = hipEventRecord(P->ev_join, g)) != hipSuccess) return e;
+  if ((e = launch_local_out(P, n, energy, forces, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(s, P->ev_join, 0)) != hipSuccess) return e;
+  return launch_interpolate(P, n, energy, fslow, nullptr, nullptr, s, kInterpGridOnly);
 }
 
 }  // namespace
@@ -236,6 +284,73 @@ mls_status mls_md_run(mls_plan_t P, int64_t n, double* pos, double* vel, const d
   }
   HIP_TRY(launch_md_step(P, ni, pos, vel, forces, inv_mass, dt, nsteps > 0 ? kMdEnd : 0, ekin + nsteps, s),
           "integrator");
+  return MLS_OK;
+}
+
+mls_status mls_md_run_mts(mls_plan_t P, int64_t n, double* pos, double* vel, const double* c6, const double* c12,
+                          double rc, const double* inv_mass, double dt, int nsteps, int k_slow, double* forces,
+                          double* epot, double* ekin, void* stream) {
+  mls_status st = check_rep(P, n, c12, rc, "mls_md_run_mts");
+  if (st != MLS_OK) return st;
+  if (k_slow < 1 || nsteps < 0 || nsteps % k_slow != 0 || !(std::isfinite(dt))) {
+    set_error("mls_md_run_mts: need k_slow >= 1, nsteps >= 0 a multiple of k_slow, finite dt");
+    return MLS_ERR_INVALID_ARG;
+  }
+  if (!epot || !ekin || (n > 0 && (!pos || !vel || !inv_mass || !forces || !c6))) {
+    set_error("mls_md_run_mts: null pos, vel, c6, inv_mass, forces, epot or ekin");
+    return MLS_ERR_INVALID_ARG;
+  }
+  if (n > P->n_max) {
+    set_error("mls_md_run_mts: n = " + std::to_string(n) + " above n_max = " + std::to_string(P->n_max));
+    return MLS_ERR_INVALID_ARG;
+  }
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != P->device) {
+    set_error("mls_md_run_mts: current device differs from the plan's device");
+    return MLS_ERR_INVALID_ARG;
+  }
+  if (P->mixing != MLS_GEOMETRIC) {
+    set_error("mls_md_run_mts: the plan uses Lorentz-Berthelot mixing");
+    return MLS_ERR_INVALID_ARG;
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  P->last_stream = s;
+  P->last_n = n;
+  const int ni = (int)std::max<int64_t>(n, 0);
+  const Repulsion rep{c12, rc};
+  const double hslow = 0.5 * k_slow * dt;
+  double* fs = P->d_fslow;
+  // outer step o: slow half-kick, k_slow inner velocity-Verlet steps with the
+  // fast force, slow force at the new positions, slow half-kick
+  HIP_TRY(evaluate_split(P, ni, pos, c6, rep, epot, forces, fs, s), "forces");
+  const int nout = nsteps / k_slow;
+  for (int o = 1; o <= nout; ++o) {
+    for (int i = 1; i <= k_slow; ++i) {
+      int mode = kMdStart;
+      double* kin = nullptr;
+      if (i == 1) {
+        // end of outer step o-1 (o > 1): its last fast and slow half-kicks and
+        // E_kin; then the slow half-kick of outer step o
+        mode |= kMdSlowStart;
+        if (o > 1) mode |= kMdEnd | kMdSlowEnd;
+        kin = ekin + (o - 1);
+      } else {
+        mode |= kMdEnd;
+      }
+      HIP_TRY(launch_md_step(P, ni, pos, vel, forces, inv_mass, dt, mode, kin, s, fs, hslow), "integrator");
+      if (i < k_slow) {
+        HIP_TRY(evaluate_fast(P, ni, pos, c6, rep, P->d_efast, forces, s), "fast force");
+      } else {
+        HIP_TRY(evaluate_split(P, ni, pos, c6, rep, epot + o, forces, fs, s), "forces");
+      }
+    }
+  }
+  HIP_TRY(launch_md_step(P, ni, pos, vel, forces, inv_mass, dt, nout > 0 ? (kMdEnd | kMdSlowEnd) : 0, ekin + nout, s,
+                         fs, hslow),
+          "integrator");
+  // the total force at the final positions
+  if (ni > 0) HIP_TRY(launch_add_forces(forces, fs, ni, s), "forces");
   return MLS_OK;
 }
 

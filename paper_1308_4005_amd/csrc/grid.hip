@@ -575,8 +575,13 @@ struct Interp {
       // the per-atom loads that do not depend on the grid go first, so their
       // latency overlaps the grid gathers
       const int i = a.perm[s];
-      const double e0 = a.e0[s];
-      double fl0 = a.floc[3 * (size_t)s + 0], fl1 = a.floc[3 * (size_t)s + 1], fl2 = a.floc[3 * (size_t)s + 2];
+      double e0 = 0.0, fl0 = 0.0, fl1 = 0.0, fl2 = 0.0;
+      if (!a.grid_only) {
+        e0 = a.e0[s];
+        fl0 = a.floc[3 * (size_t)s + 0];
+        fl1 = a.floc[3 * (size_t)s + 1];
+        fl2 = a.floc[3 * (size_t)s + 2];
+      }
       if (a.frep) {
         fl0 += a.frep[3 * (size_t)s + 0];
         fl1 += a.frep[3 * (size_t)s + 1];
@@ -671,7 +676,10 @@ struct EnergyFinal {
       __syncthreads();
     }
     // dispersion (Sec. II.B) plus, from the MD entry points, the repulsion
-    if (threadIdx.x == 0) *a.energy = -0.5 * (r1[0] - a.cself * r2[0]) + 0.5 * r3[0];
+    if (threadIdx.x == 0) {
+      const double E = -0.5 * (r1[0] - a.cself * r2[0]) + 0.5 * r3[0];
+      *a.energy = a.add ? *a.energy + E : E;
+    }
   }
 };
 
@@ -832,12 +840,14 @@ hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s) {
 }
 
 hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forces, double* potential,
-                              double* dE_dc6, hipStream_t s, bool with_repulsion) {
+                              double* dE_dc6, hipStream_t s, int mode) {
+  const bool with_repulsion = (mode & kInterpRep) != 0;
   const int nb = nblocks(n, kBlock);
   if (n > 0) {
     InterpArgs a{P->d_xs, P->d_perm, n, finest_geom(P), P->lv[0].E, P->d_e0, P->d_floc, P->cself,
                  OutPtrs{forces, potential, dE_dc6}, P->d_partial};
     if (with_repulsion) a.frep = P->d_frep;
+    a.grid_only = (mode & kInterpGridOnly) ? 1 : 0;
     const bool mixed = P->precision == MLS_MIXED;
     hipError_t e;
     if (P->order == 4 && !mixed) e = launch_one<Interp<4, double>>(a, nb, s);
@@ -852,6 +862,7 @@ hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forc
     ea.rep_partial = P->d_md_partial;
     ea.rep_nb = n > 0 ? P->rep_nb : 0;
   }
+  ea.add = (mode & kInterpGridOnly) ? 1 : 0;
   return launch_one<EnergyFinal>(ea, 1, s);
 }
 

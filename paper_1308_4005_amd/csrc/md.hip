@@ -143,7 +143,9 @@ struct RepPair {
 // Velocity Verlet, one thread per atom (original order).  With END the
 // second half-kick of the previous step, v += dt/2 F/m, is applied; the
 // kinetic energy of the resulting v is summed per block; with START the
-// first half-kick of the next step and the drift x += dt v follow.
+// first half-kick of the next step and the drift x += dt v follow.  Multiple
+// time stepping adds the slow force's half-kicks of its outer step, after the
+// fast END kick (SLOW_END) and before the fast START kick (SLOW_START).
 struct MdStep {
   using Args = MdStepArgs;
   static constexpr int kThreads = kBlock;
@@ -163,14 +165,18 @@ struct MdStep {
       if (bad) atomicOr(a.flags, 8);
       if (a.mode & kMdEnd)
         for (int d = 0; d < 3; ++d) v[d] = v[d] + a.hdt * f[d] * im;
+      if (a.mode & kMdSlowEnd)
+        for (int d = 0; d < 3; ++d) v[d] = v[d] + a.hslow * a.fslow[3 * (size_t)i + d] * im;
       k = (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / im;
+      if (a.mode & kMdSlowStart)
+        for (int d = 0; d < 3; ++d) v[d] = v[d] + a.hslow * a.fslow[3 * (size_t)i + d] * im;
       if (a.mode & kMdStart) {
         for (int d = 0; d < 3; ++d) {
           v[d] = v[d] + a.hdt * f[d] * im;
           a.pos[3 * (size_t)i + d] = a.pos[3 * (size_t)i + d] + a.dt * v[d];
         }
       }
-      if (a.mode & (kMdEnd | kMdStart))
+      if (a.mode & (kMdEnd | kMdStart | kMdSlowEnd | kMdSlowStart))
         for (int d = 0; d < 3; ++d) a.vel[3 * (size_t)i + d] = v[d];
     }
     const double t = block_sum(k, sh);
@@ -188,6 +194,52 @@ struct MdKinetic {
     for (int i = threadIdx.x; i < a.npartial; i += kBlock) v += a.partial[i];
     const double t = block_sum(v, sh);
     if (threadIdx.x == 0) *a.out = 0.5 * t;
+  }
+};
+
+// The local part alone (multiple time stepping's fast force): forces[perm[s]]
+// = local + repulsive force of sorted atom s, block sums of xi_s e0_s.
+struct LocalOut {
+  using Args = LocalOutArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    __shared__ double sh[kBlock];
+    const int s = blk * kBlock + threadIdx.x;
+    double u = 0.0;
+    if (s < a.n) {
+      const int i = a.perm[s];
+      double f[3];
+      for (int d = 0; d < 3; ++d) f[d] = a.floc[3 * (size_t)s + d] + a.frep[3 * (size_t)s + d];
+      for (int d = 0; d < 3; ++d) a.forces[3 * (size_t)i + d] = f[d];
+      u = a.xs[s].w * a.e0[s];
+    }
+    const double t = block_sum(u, sh);
+    if (threadIdx.x == 0) a.partial[blk] = t;
+  }
+};
+
+// E_local + E_rep = -1/2 sum_i xi_i e0_i + 1/2 (the repulsion's block sums)
+struct LocalEnergy {
+  using Args = LocalEnergyArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int) {
+    __shared__ double sh[kBlock];
+    double u = 0.0, r = 0.0;
+    for (int i = threadIdx.x; i < a.nb; i += kBlock) u += a.partial[i];
+    for (int i = threadIdx.x; i < a.rep_nb; i += kBlock) r += a.rep_partial[i];
+    const double tu = block_sum(u, sh);
+    __syncthreads();
+    const double tr = block_sum(r, sh);
+    if (threadIdx.x == 0) *a.energy = -0.5 * tu + 0.5 * tr;
+  }
+};
+
+struct AddForces {
+  using Args = AddForcesArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    const int i = blk * kBlock + threadIdx.x;
+    if (i < a.n3) a.forces[i] += a.add[i];
   }
 };
 
@@ -217,14 +269,31 @@ hipError_t launch_repulsion(mls_plan_s* P, int n, double rc, hipStream_t s) {
 }
 
 hipError_t launch_md_step(mls_plan_s* P, int n, double* pos, double* vel, const double* forces,
-                          const double* inv_mass, double dt, int mode, double* kinetic, hipStream_t s) {
+                          const double* inv_mass, double dt, int mode, double* kinetic, hipStream_t s,
+                          const double* fslow, double hslow) {
   double* part = P->d_md_partial + P->rep_cap;
   if (n > 0) {
-    MdStepArgs ma{pos, vel, forces, inv_mass, n, 0.5 * dt, dt, mode, part, P->d_flags};
+    MdStepArgs ma{pos, vel, forces, inv_mass, n, 0.5 * dt, dt, mode, part, P->d_flags, fslow, hslow};
     hipError_t e = launch_one<MdStep>(ma, nblocks(n, kBlock), s);
     if (e != hipSuccess) return e;
   }
+  if (!kinetic) return hipSuccess;
   return launch_one<MdKinetic>(MdKineticArgs{part, nblocks(n, kBlock), kinetic}, 1, s);
+}
+
+hipError_t launch_local_out(mls_plan_s* P, int n, double* energy, double* forces, hipStream_t s) {
+  double* part = P->d_md_partial + P->rep_cap + P->n_partial;
+  const int nb = nblocks(n, kBlock);
+  if (n > 0) {
+    LocalOutArgs la{P->d_xs, P->d_perm, n, P->d_e0, P->d_floc, P->d_frep, forces, part};
+    hipError_t e = launch_one<LocalOut>(la, nb, s);
+    if (e != hipSuccess) return e;
+  }
+  return launch_one<LocalEnergy>(LocalEnergyArgs{part, nb, P->d_md_partial, n > 0 ? P->rep_nb : 0, energy}, 1, s);
+}
+
+hipError_t launch_add_forces(double* forces, const double* add, int n, hipStream_t s) {
+  return launch_one<AddForces>(AddForcesArgs{forces, add, 3 * n}, nblocks(3 * (int64_t)n, kBlock), s);
 }
 
 }  // namespace mls

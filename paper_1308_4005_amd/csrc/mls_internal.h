@@ -116,11 +116,21 @@ struct RepPairArgs {
   const double4* xs; const double* x12s; const int* cell_s; const int* cell_start; CellGeom g;
   int nr[3]; double rc2; int n; double* frep; double* partial;
 };
-constexpr int kMdEnd = 1, kMdStart = 2;
+constexpr int kMdEnd = 1, kMdStart = 2, kMdSlowEnd = 4, kMdSlowStart = 8;
 struct MdStepArgs {
   double* pos; double* vel; const double* forces; const double* inv_mass; int n;
   double hdt, dt; int mode; double* partial; int* flags;
+  const double* fslow = nullptr;   // multiple time stepping: slow forces and their half-kick factor
+  double hslow = 0.0;
 };
+struct LocalOutArgs {
+  const double4* xs; const int* perm; int n; const double* e0; const double* floc; const double* frep;
+  double* forces; double* partial;
+};
+struct LocalEnergyArgs {
+  const double* partial; int nb; const double* rep_partial; int rep_nb; double* energy;
+};
+struct AddForcesArgs { double* forces; const double* add; int n3; };
 struct MdKineticArgs { const double* partial; int npartial; double* out; };
 struct LbGatherArgs { const int* perm; int n; const double* sigma; double* sig_s; int* flags; };
 struct LbChargeArgs { const double4* xs; const double* sig_s; int n; int k; double* charge; };
@@ -185,11 +195,13 @@ struct InterpArgs {
   const double4* xs; const int* perm; int n; GridGeom gg; const double* E1; const double* e0;
   const double* floc; double cself; OutPtrs out; double* partial;
   const double* frep = nullptr;   // sorted (n,3) repulsive forces added to the output, or null
+  int grid_only = 0;              // 1: the grid part alone (no e0, no local forces)
 };
 struct EnergyArgs {
   const double* partial; int nb; double cself; double* energy;
   const double* rep_partial = nullptr;  // block sums of the repulsive energy (twice E_rep), or null
   int rep_nb = 0;
+  int add = 0;                          // 1: add to *energy instead of overwriting it
 };
 struct InterpLbArgs {
   const double4* xs; const double* sig; const int* perm; int n; GridGeom gg; const double* E1[7];
@@ -351,7 +363,10 @@ struct mls_plan_s {
   int rep_cap = 0;                 // repulsion energy block sums d_md_partial holds before the kinetic ones
   int rep_nb = 0;                  // block sums written by the last repulsion launch
   double* d_frep = nullptr;        // geometric mixing: sorted repulsive forces (n_max,3)
-  double* d_md_partial = nullptr;  // geometric mixing: repulsion energy (rep_cap) and kinetic (n_partial) block sums
+  double* d_md_partial = nullptr;  // geometric mixing: repulsion energy (rep_cap), kinetic and local-energy
+                                   // (n_partial each) block sums
+  double* d_fslow = nullptr;       // geometric mixing: grid-part forces of multiple time stepping (n_max,3)
+  double* d_efast = nullptr;       // geometric mixing: energy of an inner step's fast evaluation
   bool ant_tiles = false;          // two-phase anterpolation tables built
   mls::AntTiles ant{};
   int* d_ant_tab = nullptr;
@@ -402,8 +417,11 @@ hipError_t launch_restrict(mls_plan_s* P, int k_fine, hipStream_t s);
 hipError_t launch_stencils(mls_plan_s* P, hipStream_t s);
 hipError_t launch_coarsest(mls_plan_s* P, hipStream_t s);
 hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s);
+// mode: 0 the full evaluation, kInterpRep with the repulsion of the MD entry
+// points, kInterpGridOnly the grid part alone (energy added to *energy)
+constexpr int kInterpRep = 1, kInterpGridOnly = 2;
 hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forces,
-                              double* potential, double* dE_dc6, hipStream_t s, bool with_repulsion = false);
+                              double* potential, double* dE_dc6, hipStream_t s, int mode = 0);
 // Lorentz-Berthelot pieces: sorted sigma and flags, the sorted charges of
 // vector k, and the interpolation of all seven vectors with the energy
 hipError_t launch_lb_gather(mls_plan_s* P, int n, const double* sigma, hipStream_t s);
@@ -422,7 +440,12 @@ hipError_t launch_copy_stage(mls_plan_s* P, int what, int level, void* dst, hipS
 hipError_t launch_rep_gather(mls_plan_s* P, int n, const double* c12, hipStream_t s);
 hipError_t launch_repulsion(mls_plan_s* P, int n, double rc, hipStream_t s);
 hipError_t launch_md_step(mls_plan_s* P, int n, double* pos, double* vel, const double* forces,
-                          const double* inv_mass, double dt, int mode, double* kinetic, hipStream_t s);
+                          const double* inv_mass, double dt, int mode, double* kinetic, hipStream_t s,
+                          const double* fslow = nullptr, double hslow = 0.0);
+// the local part alone as MD's fast force: forces = local + repulsive forces,
+// *energy = local + repulsive energy; forces += add
+hipError_t launch_local_out(mls_plan_s* P, int n, double* energy, double* forces, hipStream_t s);
+hipError_t launch_add_forces(double* forces, const double* add, int n, hipStream_t s);
 
 // owner-computes anterpolation blocking of a plan (false: use the atomic kernel)
 bool anterp_owned_geom(const mls_plan_s* P, AntGeom& ag);

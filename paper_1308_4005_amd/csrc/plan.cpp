@@ -412,7 +412,9 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
     if (P->precision == MLS_MIXED) ALLOC(P->d_x12f, N + kSortedPad);
     ALLOC(P->d_frep, 3 * N);
     P->rep_cap = (int)((N + 63) / 64);   // one sum per wave of the pair kernels
-    ALLOC(P->d_md_partial, (size_t)P->rep_cap + P->n_partial);
+    ALLOC(P->d_md_partial, (size_t)P->rep_cap + 2 * (size_t)P->n_partial);
+    ALLOC(P->d_fslow, 3 * N);
+    ALLOC(P->d_efast, 1);
   }
   if (P->mixing == MLS_LORENTZ_BERTHELOT) {
     // seven charge vectors: one set of grids each (Sec. II.D)

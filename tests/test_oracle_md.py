@@ -115,3 +115,48 @@ def test_shifting_atoms_by_box_vectors_changes_nothing():
     Es, Fs = MD.repulsion(shifted, c12, w.box, 2.5)
     assert Es == pytest.approx(E, rel=1e-12)
     np.testing.assert_allclose(Fs, F, rtol=0, atol=1e-10 * np.abs(F).max())
+
+
+def test_mts_with_one_inner_step_is_velocity_verlet(system):
+    w, vel, c12, inv_m = system
+    prm = (w.box, 2.5, 0.9, 4, 2)
+    x1, v1, F1, ep1, ek1 = MD.md_run(w.pos, vel, w.c6, c12, inv_m, *prm, 0.002, 4)
+    x2, v2, F2, ep2, ek2 = MD.md_run_mts(w.pos, vel, w.c6, c12, inv_m, *prm, 0.002, 4, 1)
+    np.testing.assert_allclose(x2, x1, rtol=0, atol=1e-13 * np.abs(x1).max())
+    np.testing.assert_allclose(v2, v1, rtol=0, atol=1e-12 * np.abs(v1).max())
+    np.testing.assert_allclose(F2, F1, rtol=0, atol=1e-12 * np.abs(F1).max())
+    np.testing.assert_allclose(ep2, ep1, rtol=1e-12)
+    np.testing.assert_allclose(ek2, ek1, rtol=1e-12)
+
+
+def test_split_adds_up_and_the_slow_part_is_smooth(system):
+    w, vel, c12, inv_m = system
+    Ef, Ff, Es, Fs = MD.split_forces(w.pos, w.c6, c12, w.box, 2.5, 0.9, 4, 2)
+    E, F = MD.forces(w.pos, w.c6, c12, w.box, 2.5, 0.9, 4, 2)
+    assert Ef + Es == pytest.approx(E, rel=1e-12)
+    np.testing.assert_allclose(Ff + Fs, F, rtol=0, atol=1e-11 * np.abs(F).max())
+    # the grid part is the smooth remainder: far weaker than the local part
+    assert np.abs(Fs).max() < 0.1 * np.abs(Ff).max()
+
+
+def test_mts_is_time_reversible(system):
+    w, vel, c12, inv_m = system
+    prm = (w.box, 2.5, 0.9, 4, 2)
+    x1, v1, _, _, _ = MD.md_run_mts(w.pos, vel, w.c6, c12, inv_m, *prm, 0.002, 6, 3)
+    x0, v0, _, _, _ = MD.md_run_mts(x1, -v1, w.c6, c12, inv_m, *prm, 0.002, 6, 3)
+    np.testing.assert_allclose(x0, w.pos, rtol=0, atol=1e-11 * np.abs(w.pos).max())
+    np.testing.assert_allclose(-v0, vel, rtol=0, atol=1e-9 * np.abs(vel).max())
+
+
+def test_mts_conserves_energy_like_verlet(system):
+    # the slow force is smooth, so an outer step of 4 dt keeps the energy about
+    # as well as velocity Verlet at dt
+    w, vel, c12, inv_m = system
+    prm = (w.box, 2.5, 0.9, 4, 2)
+    _, _, _, ep, ek = MD.md_run(w.pos, vel, w.c6, c12, inv_m, *prm, 0.002, 16)
+    tot = ep + ek
+    d_vv = np.max(np.abs(tot - tot[0]))
+    _, _, _, ep, ek = MD.md_run_mts(w.pos, vel, w.c6, c12, inv_m, *prm, 0.002, 16, 4)
+    tot = ep + ek
+    d_mts = np.max(np.abs(tot - tot[0]))
+    assert d_mts < 3.0 * d_vv
