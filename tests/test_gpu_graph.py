@@ -53,3 +53,51 @@ def test_graph_replays_equal_eager(precision):
     del g
     plan.close()
     other.close()
+
+
+@pytest.mark.parametrize("mode", ["md_run", "md_run_mts"])
+def test_md_graph_replays_equal_eager(mode):
+    """The MD entry points captured into a graph (the benchmark's MD timing
+    mode): every replay, started from reset positions and velocities, equals
+    an eager call from the same state."""
+    import torch
+    from paper_1308_4005_amd import Plan
+    say(f"[graph] {mode}")
+    w = W.cube(6000, 0.8, seed=42)
+    rng = np.random.default_rng(4)
+    vel0 = rng.normal(scale=0.5, size=(w.n, 3))
+    plan = Plan(w.box, 3.0, 1.0, 4, 0, precision="mixed", n_max=w.n)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    c6, c12, im = t(w.c6), t(np.full(w.n, 4.0)), t(np.ones(w.n))
+    x, v = t(w.pos), t(vel0)
+    F = torch.empty((w.n, 3), dtype=torch.float64, device="cuda")
+    nout = 5 if mode == "md_run" else 3
+    ep = torch.empty(nout, dtype=torch.float64, device="cuda")
+    ek = torch.empty(nout, dtype=torch.float64, device="cuda")
+
+    def call(xx, vv, FF, ee, kk):
+        if mode == "md_run":
+            return plan.md_run(xx, vv, c6, c12, im, 0.001, 4, forces=FF, epot=ee, ekin=kk)
+        return plan.md_run_mts(xx, vv, c6, c12, im, 0.001, 4, 2, forces=FF, epot=ee, ekin=kk)
+
+    call(x, v, F, ep, ek)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call(x, v, F, ep, ek)
+    for rep in range(3):
+        start = w.pos + rng.normal(scale=0.01, size=w.pos.shape)
+        x.copy_(t(start))
+        v.copy_(t(vel0))
+        g.replay()
+        torch.cuda.synchronize()
+        got = [a.cpu().numpy().copy() for a in (x, v, F, ep, ek)]
+        xe, ve = t(start), t(vel0)
+        Fe, epe, eke = call(xe, ve, None, None, None)
+        torch.cuda.synchronize()
+        want = [a.cpu().numpy() for a in (xe, ve, Fe, epe, eke)]
+        for a, b in zip(got, want):
+            np.testing.assert_allclose(a, b, rtol=0, atol=1e-9 * np.abs(b).max())
+    assert plan.status() == 0
+    del g
+    plan.close()
