@@ -662,7 +662,16 @@ struct EnergyFinal {
       x += a.partial[2 * i];
       y += a.partial[2 * i + 1];
     }
-    for (int i = threadIdx.x; i < a.rep_nb; i += kBlock) z += a.rep_partial[i];
+    {
+      // up to n / 64 block sums of the pair kernel: eight loads in flight
+      double zz[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int i = threadIdx.x;
+      for (; i + 7 * kBlock < a.rep_nb; i += 8 * kBlock)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) zz[u] += a.rep_partial[i + u * kBlock];
+      for (; i < a.rep_nb; i += kBlock) zz[0] += a.rep_partial[i];
+      z = ((zz[0] + zz[1]) + (zz[2] + zz[3])) + ((zz[4] + zz[5]) + (zz[6] + zz[7]));
+    }
     r1[threadIdx.x] = x;
     r2[threadIdx.x] = y;
     r3[threadIdx.x] = z;

@@ -55,6 +55,19 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return sh[0];
 }
 
+// This thread's share of sum_{i < n} p[i] over a kBlock-thread block: eight
+// independent loads in flight per step (the one-block reductions below sum up
+// to n / 64 block sums of the pair kernel).
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int n) {
+  double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int i = threadIdx.x;
+  for (; i + 7 * kBlock < n; i += 8 * kBlock)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] += p[i + u * kBlock];
+  for (; i < n; i += kBlock) v[0] += p[i];
+  return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+}
+
 __device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
 // One thread per cell-sorted atom.  The neighbour cells of one (dy, dz) pair
@@ -190,9 +203,7 @@ struct MdKinetic {
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int) {
     __shared__ double sh[kBlock];
-    double v = 0.0;
-    for (int i = threadIdx.x; i < a.npartial; i += kBlock) v += a.partial[i];
-    const double t = block_sum(v, sh);
+    const double t = block_sum(strided_sum(a.partial, a.npartial), sh);
     if (threadIdx.x == 0) *a.out = 0.5 * t;
   }
 };
@@ -224,9 +235,8 @@ struct LocalEnergy {
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int) {
     __shared__ double sh[kBlock];
-    double u = 0.0, r = 0.0;
-    for (int i = threadIdx.x; i < a.nb; i += kBlock) u += a.partial[i];
-    for (int i = threadIdx.x; i < a.rep_nb; i += kBlock) r += a.rep_partial[i];
+    const double u = strided_sum(a.partial, a.nb);
+    const double r = strided_sum(a.rep_partial, a.rep_nb);
     const double tu = block_sum(u, sh);
     __syncthreads();
     const double tr = block_sum(r, sh);
