@@ -105,3 +105,29 @@ def test_mts_mixed_and_edges():
         plan.md_run_mts(x, v, _t(w.c6), _t(c12), _t(im), dt=0.002, nsteps=5, k_slow=2)
     with pytest.raises(_lib.MLSError):
         plan.md_run_mts(x, v, _t(w.c6), _t(c12), _t(im), dt=0.002, nsteps=4, k_slow=0)
+
+
+@pytest.mark.timeout(600)
+def test_full_size_one_inner_step_matches_md_run():
+    """cube1M (10^6 atoms, the measured workload), FP64: multiple time stepping
+    with k_slow = 1 (split forces: local part and repulsion, then the grid part
+    alone, kicked separately) equals mls_md_run (one fused evaluation) over two
+    steps, and its kinetic energy matches its own final velocities."""
+    import torch
+    from paper_1308_4005_amd import Plan
+    w = W.named("cube1M")
+    prm = w.params
+    say(f"[mts] full size: n={w.n}")
+    vel, c12, im = _inputs(w, 10)
+    plan = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], n_max=w.n)
+    c6t, c12t, imt = _t(w.c6), _t(c12), _t(im)
+    x1, v1 = _t(w.pos), _t(vel)
+    F1, ep1, ek1 = plan.md_run(x1, v1, c6t, c12t, imt, dt=0.001, nsteps=2)
+    x2, v2 = _t(w.pos), _t(vel)
+    F2, ep2, ek2 = plan.md_run_mts(x2, v2, c6t, c12t, imt, dt=0.001, nsteps=2, k_slow=1)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    for a, b in ((x2, x1), (v2, v1), (F2, F1), (ep2, ep1), (ek2, ek1)):
+        assert rel_err(a.cpu().numpy(), b.cpu().numpy()) < 1e-10
+    vv = v2.cpu().numpy()
+    assert float(ek2.cpu()[-1]) == pytest.approx(0.5 * np.sum(np.sum(vv * vv, axis=1) / im), rel=1e-12)
