@@ -1,8 +1,10 @@
 // Molecular dynamics around the MLS dispersion (Sec. II.D, eq:disp-pair-pot;
 // the MD runs of Sec. III.A): the short-ranged repulsive term C^rep_ij r^-12
 // with geometric mixing C^rep_ij = sqrt(C12_i C12_j), summed over every
-// periodic image closer than a cutoff r_c <= a, and the velocity-Verlet
-// integrator.
+// periodic image closer than a cutoff r_c <= a; the velocity-Verlet
+// integrator; and the pieces of multiple time stepping on the MLS split (the
+// local part's forces and energy alone, the slow half-kicks, the final force
+// sum).
 //
 // The repulsion reuses the cell-sorted atoms of the evaluation it belongs to
 // (binning's wrapped positions, cell starts and permutation).  The half-cell
