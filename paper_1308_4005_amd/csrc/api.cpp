@@ -163,6 +163,7 @@ mls_status evaluate_geometric(mls_plan_t P, int64_t n, const double* pos, const 
   };
   mls_status st;
   if (after == 0 && (st = pair()) != MLS_OK) return st;
+  HIP_TRY(launch_sum_xi(P, ni, g), "sum of xi");
   HIP_TRY(launch_anterpolate(P, ni, g), "anterpolation");
   HIP_TRY(mark(1 + MLS_T_ANTERP), "timing event");
   if (after == 1 && (st = pair()) != MLS_OK) return st;
@@ -215,6 +216,7 @@ hipError_t evaluate_split(mls_plan_t P, int n, const double* pos, const double* 
   if ((e = launch_binning(P, n, pos, c6, s)) != hipSuccess) return e;
   if ((e = hipEventRecord(P->ev_fork, s)) != hipSuccess) return e;
   if ((e = hipStreamWaitEvent(g, P->ev_fork, 0)) != hipSuccess) return e;
+  if ((e = launch_sum_xi(P, n, g)) != hipSuccess) return e;
   if ((e = launch_anterpolate(P, n, g)) != hipSuccess) return e;
   if ((e = launch_rep_gather(P, n, rep.c12, s)) != hipSuccess) return e;
   const PairRep prep{P->d_x12s, P->d_x12f, rep.rc * rep.rc, P->d_frep, P->d_md_partial};

@@ -380,13 +380,14 @@ hipError_t launch_binning_scaled(mls_plan_s* P, int n, const double* pos, const 
   const bool mixed = P->precision == MLS_MIXED;
   GatherArgs ga{P->d_perm, n, P->d_xw, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, g,
                 mixed ? P->d_partial : nullptr};
-  if ((e = launch_one<GatherSorted>(ga, nblocks(n + kSortedPad, kBlock), s)) != hipSuccess) return e;
-  if (mixed) {
-    // sum of xi: the mean of every grid level's charges (partition of unity)
-    SumXiArgs sa{n + kSortedPad, P->d_partial, P->d_scratch};
-    if ((e = launch_one<SumXiFinal>(sa, 1, s)) != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return launch_one<GatherSorted>(ga, nblocks(n + kSortedPad, kBlock), s);
+}
+
+hipError_t launch_sum_xi(mls_plan_s* P, int n, hipStream_t s) {
+  if (P->precision != MLS_MIXED || n == 0) return hipSuccess;
+  // sum of xi: the mean of every grid level's charges (partition of unity)
+  SumXiArgs sa{n + kSortedPad, P->d_partial, P->d_scratch};
+  return launch_one<SumXiFinal>(sa, 1, s);
 }
 
 hipError_t launch_scan(mls_plan_s* P, const int* count, int m, int* start, hipStream_t s) {

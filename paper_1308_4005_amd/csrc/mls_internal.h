@@ -408,6 +408,9 @@ int stencil_tile_zc(int R, bool f64);
 
 // kernel launchers (one per file); all enqueue on `s` and return the launch status
 hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double* c6, hipStream_t s);
+// mixed precision: sum of xi from binning's block sums, needed by the grid
+// part only (launched on the grid chain's stream, after binning)
+hipError_t launch_sum_xi(mls_plan_s* P, int n, hipStream_t s);
 // With `rep`, the FP32 and FP64 half-cell kernels also evaluate the repulsion
 // (*fused set); other kernels leave it to launch_repulsion.
 hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s, const PairRep* rep = nullptr, bool* fused = nullptr);
