@@ -225,7 +225,9 @@ struct PairWave {
 // is at least a, and trims every other row to the cells the cutoff sphere
 // can reach along x (at most two runs of cells: one per periodic image).  A
 // cheap distance test appends sources inside the cutoff to the lane's LDS
-// queue (a ring), four candidates per step so four loads are in flight;
+// queue (a ring), kBatch candidates per step with their loads in flight
+// together (2 for FP64, 4 for FP32: measured at 10^6 atoms, FP64 0.867 ms
+// with 2 against 0.893 ms with 4, FP32 0.499 ms with 4 against 0.502 with 2);
 // whenever a queue may overflow all lanes drain up to kDrain of their oldest
 // entries through the full g_0 evaluation, and at the end everything left,
 // so the expensive arithmetic runs on nearly full waves instead of being
@@ -233,7 +235,8 @@ struct PairWave {
 // bits per dimension for its image.
 constexpr int kWaveQ = 64;    // lanes per block (one wave)
 constexpr int kQueue = 32;    // entries per lane
-constexpr int kBatch = 4;     // candidates per filter step
+constexpr int kBatch = 2;     // candidates per filter step (FP64 kernel)
+constexpr int kBatchF = 4;    // candidates per filter step (FP32 kernel)
 
 __device__ __forceinline__ int image_bits(int ix, int iy, int iz) { return (ix + 1) | ((iy + 1) << 2) | ((iz + 1) << 4); }
 
@@ -569,11 +572,11 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
     const int head = A.head;
     bool full = false;
     while (__any(j < j1)) {
-      float4 xj[kBatch];
+      float4 xj[kBatchF];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) xj[b] = xr[j + b];
+      for (int b = 0; b < kBatchF; ++b) xj[b] = xr[j + b];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
+      for (int b = 0; b < kBatchF; ++b) {
         const float dxv = fmaf(bx - xj[b].w, pc.w[0], L.xx) - xj[b].x;
         const float dyv = ay - xj[b].y, dzv = az - xj[b].z;
         const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
@@ -581,8 +584,8 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
         qlane[kWaveQ * ((head + cnt) & (kQueue - 1))] = ((j + b) << 8) | bits;
         cnt += hit ? 1 : 0;
       }
-      j += j < j1 ? kBatch : 0;
-      if (__any(cnt > kQueue - kBatch)) {
+      j += j < j1 ? kBatchF : 0;
+      if (__any(cnt > kQueue - kBatchF)) {
         full = true;
         break;
       }
