@@ -322,12 +322,26 @@ def named_batch(name: str = "batch256"):
     return ws
 
 
+_MEMO = {}
+
+
 def named(name: str) -> Workload:
     """Build one of the named workloads (see ``NAMED``).
 
-    If the environment variable MLS_WORKLOAD_CACHE names a directory, the
-    generated arrays are stored there and reused by later calls.
+    Generated arrays are kept for the life of the process (each call returns
+    its own copies).  If the environment variable MLS_WORKLOAD_CACHE names a
+    directory, they are also stored there and reused by later processes.
     """
+    import os
+    if name in _MEMO:
+        wname, pos, c6, box, params = _MEMO[name]
+        return Workload(wname, pos.copy(), c6.copy(), box.copy(), dict(params))
+    w = _named_uncached(name)
+    _MEMO[name] = (w.name, w.pos.copy(), w.c6.copy(), np.array(w.box, dtype=np.float64), dict(w.params))
+    return w
+
+
+def _named_uncached(name: str) -> Workload:
     import os
     cache = os.environ.get("MLS_WORKLOAD_CACHE")
     if cache:
