@@ -182,3 +182,22 @@ def test_full_size_sampled():
     vv = v.cpu().numpy()
     assert float(ek.cpu()[-1]) == pytest.approx(0.5 * np.sum(np.sum(vv * vv, axis=1) / im), rel=1e-12)
     assert np.all(np.isfinite(ep.cpu().numpy()))
+
+
+def test_unwrapped_positions_give_the_wrapped_result():
+    """An MD trajectory is not wrapped: atoms moved by whole box vectors (and
+    just across the box faces) give the energy and forces of the originals."""
+    import torch
+    from paper_1308_4005_amd import Plan
+    w = W.named("cube1k")
+    _, c12, _ = _inputs(w, 11)
+    rng = np.random.default_rng(6)
+    shifted = w.pos + rng.integers(-3, 4, size=(w.n, 3)) * w.box
+    plan = Plan(w.box, 3.0, 1.0, 4, 2, n_max=w.n)
+    r0 = plan.evaluate_md(_t(w.pos), _t(w.c6), _t(c12))
+    E0, F0 = float(r0.energy.cpu()[0]), r0.forces.cpu().numpy()
+    r1 = plan.evaluate_md(_t(shifted), _t(w.c6), _t(c12))
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    assert abs(float(r1.energy.cpu()[0]) - E0) <= 1e-10 * abs(E0)
+    assert rel_err(r1.forces.cpu().numpy(), F0) < 1e-10
