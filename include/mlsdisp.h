@@ -245,6 +245,29 @@ enum {
 mls_status mls_plan_copy_stage(mls_plan_t plan, int what, int level, void* dst, int64_t capacity,
                                void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * evaluation of mls_evaluate for the parameters in *params (host), with the
+ * plan's workspace in a 64 MiB device array that the library holds per
+ * device until the process ends, instead of memory from mls_plan_create.
+ * Calls no hipMalloc, hipFree or other allocating routine, and creates no
+ * stream or event: every stage runs in order on `stream`.  Each call waits
+ * for `stream` (an earlier call's work on it still reads the array),
+ * rebuilds the plan's tables on the host (the coarsest lattice kernel among
+ * them, so each call costs a plan creation: suited to small systems),
+ * uploads them, clears what must start at zero, and enqueues the
+ * evaluation.  Arguments as for mls_evaluate (n atoms, device pos, c6,
+ * energy, forces, potential, dE_dc6; outputs overwritten).  All calls on one
+ * device share the array: calls that overlap on one device (different
+ * streams or threads) race.  The data flags of mls_plan_status are not
+ * reported.
+ * Errors: MLS_ERR_INVALID_ARG (as mls_evaluate, or Lorentz-Berthelot mixing),
+ * MLS_ERR_UNSUPPORTED when the workspace for n atoms and these grids exceeds
+ * the 64 MiB array (the message says so), MLS_ERR_HIP. */
+mls_status mls_evaluate_noalloc(const mls_params* params, int64_t n, const double* pos, const double* c6,
+                                double* energy, double* forces, double* potential, double* dE_dc6,
+                                void* stream);
+
 /* Synchronise the plan's last stream and report the device flags set by
  * evaluations since the previous call (bit 0: non-finite position, bit 1:
  * non-finite or negative C6, bit 2: internal consistency check of the

@@ -36,7 +36,7 @@ EXPORTS = [
     "mls_batch_set_graph", "mls_batch_get_tuning", "mls_batch_set_tuning", "mls_batch_box_info",
     "mls_batch_status", "mls_batch_destroy", "mls_status_string", "mls_last_error",
     "mls_plan_set_timing", "mls_plan_read_timing", "mls_evaluate_md", "mls_md_run",
-    "mls_md_run_mts",
+    "mls_md_run_mts", "mls_evaluate_noalloc",
 ]
 
 STAGE_NAMES = ["binning", "pair", "anterpolation", "restriction", "stencil", "coarsest",
@@ -110,6 +110,7 @@ def load():
     lib.mls_plan_create.argtypes = [ctypes.POINTER(MLSParams), i64, ctypes.POINTER(P)]
     lib.mls_plan_get_info.argtypes = [P, ctypes.POINTER(MLSPlanInfo)]
     lib.mls_evaluate.argtypes = [P, i64, dp, dp, dp, dp, dp, dp, P]
+    lib.mls_evaluate_noalloc.argtypes = [ctypes.POINTER(MLSParams), i64, dp, dp, dp, dp, dp, dp, P]
     lib.mls_evaluate_lb.argtypes = [P, i64, dp, dp, dp, dp, dp, P]
     dbl = ctypes.c_double
     lib.mls_evaluate_md.argtypes = [P, i64, dp, dp, dp, dbl, dp, dp, P]

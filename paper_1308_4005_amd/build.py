@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmlsdisp.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "plan.cpp", "batch.cpp", "binning.hip", "pair.hip", "grid.hip", "stencil.hip", "md.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "batch.cpp", "binning.hip", "pair.hip", "grid.hip", "stencil.hip", "md.hip",
+           "noalloc.cpp"]
 
 ARCH = os.environ.get("MLS_OFFLOAD_ARCH", "gfx950")
 

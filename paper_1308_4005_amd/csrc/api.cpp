@@ -130,7 +130,7 @@ mls_status evaluate_geometric(mls_plan_t P, int64_t n, const double* pos, const 
   // with per-stage timing every stage runs in order on the caller's stream;
   // otherwise the grid chain runs on the plan's second stream, concurrently
   // with the local part
-  const bool fork = !ev;
+  const bool fork = !ev && !P->serial;
   if (fork && !P->side) {
     HIP_TRY(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
     HIP_TRY(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming), "hipEventCreateWithFlags");
@@ -236,6 +236,13 @@ hipError_t evaluate_split(mls_plan_t P, int n, const double* pos, const double* 
 }
 
 }  // namespace
+
+namespace mls {
+mls_status evaluate_plan(mls_plan_s* P, int64_t n, const double* pos, const double* c6, double* energy,
+                         double* forces, double* potential, double* dE_dc6, void* stream) {
+  return evaluate_geometric(P, n, pos, c6, energy, forces, potential, dE_dc6, stream, nullptr);
+}
+}  // namespace mls
 
 extern "C" {
 

@@ -388,6 +388,15 @@ struct mls_plan_s {
   int64_t last_n = -1;
   hipStream_t last_stream = nullptr;
   std::vector<void*> allocations;
+
+  // Workspace placement: with `arena` set, build_plan carves every device
+  // buffer out of [arena, arena + arena_cap) (256-byte aligned) instead of
+  // calling hipMalloc (mls_evaluate_noalloc); `serial` keeps every stage on
+  // the caller's stream (no second stream, no events).
+  unsigned char* arena = nullptr;
+  size_t arena_cap = 0;
+  size_t arena_used = 0;
+  bool serial = false;
 };
 
 namespace mls {
@@ -399,6 +408,10 @@ mls_status hip_fail(hipError_t e, const char* what);
 // plan construction (plan.cpp)
 mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* plan);
 void free_plan(mls_plan_s* plan);
+
+// mls_evaluate on a built plan (api.cpp)
+mls_status evaluate_plan(mls_plan_s* P, int64_t n, const double* pos, const double* c6, double* energy,
+                         double* forces, double* potential, double* dE_dc6, void* stream);
 
 // number of blocks of the cell-count scan
 int scan_blocks(int ncell);

@@ -131,6 +131,18 @@ mls_status dalloc(mls_plan_s* P, T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
   size_t bytes = count * sizeof(T);
+  if (P->arena) {
+    // carve from the caller-provided arena (no allocation)
+    const size_t off = (P->arena_used + 255) & ~(size_t)255;
+    if (off > P->arena_cap || bytes > P->arena_cap - off) {
+      set_error("workspace exceeds the static scratch of " + std::to_string(P->arena_cap) + " bytes");
+      return MLS_ERR_UNSUPPORTED;
+    }
+    *p = (T*)(P->arena + off);
+    P->arena_used = off + bytes;
+    P->bytes += (int64_t)bytes;
+    return MLS_OK;
+  }
   hipError_t e = hipMalloc((void**)p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
