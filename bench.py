@@ -65,6 +65,34 @@ def work_model(plan_info, n, pairs, order):
     }
 
 
+def stage_rooflines(stage_ms, model, precision):
+    """Achieved rate of every timed stage against its roofline: ALU stages in
+    TFLOP/s of the stage's algorithmic flops (against the published FP64
+    peak, or for FP32 against the published 157.3 TFLOP/s, which needs packed
+    FP32, and the 78.6 TFLOP/s of unpacked FP32 that this build issues);
+    HBM stages in GB/s of algorithmic bytes against 8 TB/s."""
+    out = {}
+    for st, ms in stage_ms.items():
+        m = model.get(st)
+        if m is None or ms <= 0:
+            continue
+        dt = ms * 1e-3
+        if m["bound"] == "hbm":
+            a = m["bytes"] / dt / 1e9
+            out[st] = {"bound": "hbm", "ms": ms, "bytes": m["bytes"], "achieved": a, "unit": "GB/s",
+                       "peak": PEAK["hbm"], "frac": a / PEAK["hbm"]}
+        else:
+            a = m["flops"] / dt / 1e12
+            peak = PEAK["fp32" if precision == "mixed" else "fp64"]
+            r = {"bound": "alu", "ms": ms, "flops": m["flops"], "achieved": a, "unit": "TFLOP/s", "peak": peak,
+                 "frac": a / peak}
+            if precision == "mixed":
+                r["peak_unpacked_fp32"] = PEAK["fp64"]
+                r["frac_unpacked_fp32"] = a / PEAK["fp64"]
+            out[st] = r
+    return out
+
+
 # kernels that carry each stage of the 10^6-atom cube (cell width a/2 there)
 STAGE_KERNEL = {("pair", "mixed"): ["void k_one<PairTrimF32<2, false> >"],
                 ("pair", "fp64"): ["void k_one<PairTrimF64<2, false, false> >"],
@@ -333,10 +361,31 @@ def run_selection(w, head, steps, dev, target=1e-4):
     wall = time.time() - t
     prm = dict(a=s.a, h=s.h, order=4, levels=0)
     r = time_precision(w, prm, head, max(50, steps // 5), 5, dev, stages=False, blocks=5)
-    return {"target_rms_rel_F": target, "a": s.a, "h": s.h, "levels": s.levels, "measured_rms_rel_F": s.error,
-            "C_local_s": s.C_local, "C_grids_s": s.C_grids, "C_accuracy": s.C, "iterations": len(s.history),
-            "selection_wall_s": wall, "ms_per_step": r["ms"], "evals_per_s": 1000.0 / r["ms"],
-            "reference": f"error against an evaluation with a cutoff 1.7x larger (same h), {head}"}
+    out = {"target_rms_rel_F": target, "a": s.a, "h": s.h, "levels": s.levels, "measured_rms_rel_F": s.error,
+           "C_local_s": s.C_local, "C_grids_s": s.C_grids, "C_accuracy": s.C, "iterations": len(s.history),
+           "selection_wall_s": wall, "ms_per_step": r["ms"], "evals_per_s": 1000.0 / r["ms"],
+           "reference": f"error against an evaluation with a cutoff 1.7x larger (same h), {head}"}
+    # the same selection on the 32,000-atom cube whose exact periodic forces
+    # (Ewald, 512 sampled atoms) are stored: the error of eq:accuracy-tolerance
+    import numpy as np
+    from paper_1308_4005_amd import Plan
+    from paper_1308_4005_amd import workloads as W
+    path = os.path.join(ROOT, "tests", "golden", "cube32k_exact.json")
+    if os.path.exists(path):
+        gold = json.load(open(path))
+        w32 = W.cube(gold["n"], gold["density"], seed=gold["seed"])
+        p32 = torch.tensor(w32.pos, dtype=torch.float64, device=dev)
+        c32 = torch.tensor(w32.c6, dtype=torch.float64, device=dev)
+        s32 = select_parameters(p32, c32, w32.box, target, precision=head, device=dev.index)
+        plan = Plan(w32.box, s32.a, s32.h, 4, 0, precision=head, n_max=w32.n, device=dev.index)
+        F = plan.evaluate(p32, c32).forces.cpu().numpy()[np.asarray(gold["sample"])]
+        plan.close()
+        Fx = np.asarray(gold["forces"])
+        out["exact_check_cube32k"] = {
+            "a": s32.a, "h": s32.h, "levels": s32.levels, "proxy_rms_rel_F": s32.error,
+            "exact_rms_rel_F": float(np.sqrt(np.sum((F - Fx) ** 2) / np.sum(Fx ** 2))),
+            "reference": "exact periodic sum by Ewald at 512 sampled atoms (tests/golden/cube32k_exact.json)"}
+    return out
 
 
 def golden_errors(E, F, gold):
@@ -387,29 +436,82 @@ def discretisation(prm, precisions, dev):
     return out
 
 
-def cpu_baseline(prm, target_n):
-    """The FP64 oracle, timed on a bounded sample: a 32,000-atom cube of the
-    same density with the same a, h, p (3 levels), scaled by the atom ratio
-    to evaluations of the full workload (the method is linear in N)."""
-    import numpy as np
+def cpu_baseline(prm, target):
+    """The FP64 oracle, timed on a bounded sample of the headline workload:
+    evaluations (median of 3) of a 125,000-atom cube (one eighth of the atoms) with the same
+    density, a, effective spacing and order, and a hierarchy one level
+    shorter that ends in the same coarsest grid (56^3 -> 7^3 in four levels
+    against 112^3 -> 7^3 in five).  Every stage of the method is linear in
+    N except the coarsest all-to-all, whose size is the same in both, so the
+    rate is extrapolated by the atom ratio."""
     from threadpoolctl import threadpool_limits
     from oracle import mls as oracle_mls
     from paper_1308_4005_amd import workloads as W
-    w = W.cube(32000, 0.8, seed=31)
+    n_s = target.n // 8
+    w = W.cube(n_s, 0.8, seed=33)
+    levels = max(1, prm["levels"] - 1)
     times = []
     with threadpool_limits(limits=1):
         for _ in range(3):
             t0 = time.perf_counter()
-            oracle_mls.mls(w.pos, w.c6, w.box, prm["a"], prm["h"], prm["order"], 3)
+            r = oracle_mls.mls(w.pos, w.c6, w.box, prm["a"], prm["h"], prm["order"], levels)
             times.append(time.perf_counter() - t0)
-    dt = float(np.median(times))
+    dt = sorted(times)[1]
     avail = len(os.sched_getaffinity(0))
-    return {"value": (1.0 / dt) * (w.n / target_n), "unit": "evals/s (1M-atom equivalent)",
-            "cores": 1, "cores_available": avail, "kind": "oracle",
-            "sample": f"oracle.mls FP64 on a {w.n}-atom cube (rho 0.8, a={prm['a']}, h={prm['h']}, "
-                      f"p={prm['order']}, 3 levels): median of 3 runs {dt:.2f} s per evaluation, scaled by "
-                      f"{w.n}/{target_n} atoms; numpy single thread (BLAS limited to 1, no process pool) "
-                      f"of {avail} cores available"}
+    return {"value": (1.0 / dt) * (w.n / target.n), "unit": "evals/s (1M-atom equivalent)",
+            "cores": 1, "cores_available": avail, "kind": "oracle", "extrapolated": True,
+            "sample": f"EXTRAPOLATED: oracle.mls FP64 evaluations of a {w.n}-atom cube (rho 0.8, L="
+                      f"{w.box[0]:.3f}, a={prm['a']}, h={prm['h']} -> grid {list(map(int, r['n1']))}, "
+                      f"p={prm['order']}, {levels} levels, coarsest "
+                      f"{[int(x) >> (levels - 1) for x in r['n1']]}): median of 3 runs {dt:.1f} s; scaled by {w.n}/{target.n} "
+                      f"atoms to the {target.n}-atom headline; numpy single thread (BLAS limited to 1, no "
+                      f"process pool) of {avail} cores available"}
+
+
+SWEEP_A = (2.5, 3.0, 4.0)
+SWEEP_H = (0.8, 1.0, 1.25)
+SWEEP_P = (4, 6)
+
+
+def _tag(x):
+    return f"{x:g}".replace(".", "p")
+
+
+def precision_sweep(w, dev, steps, blocks):
+    """The precision-at-scale sweep on the 10^6-atom cube: a in {2.5, 3, 4},
+    h in {0.8, 1, 1.25}, p in {4, 6}, five levels.  Per setting and precision:
+    ms per evaluation (graph replays), and the energy and force errors against
+    the FP64 oracle at the stored sample of 512 atoms (tests/golden/
+    cube1M_a*_h*_p*_l5.json, written by the oracle alone) and of the mixed
+    path against the FP64 path on all atoms."""
+    import numpy as np
+    out = []
+    for a in SWEEP_A:
+        for h in SWEEP_H:
+            for p in SWEEP_P:
+                prm = dict(a=a, h=h, order=p, levels=5)
+                gpath = os.path.join(ROOT, "tests", "golden", f"cube1M_a{_tag(a)}_h{_tag(h)}_p{p}_l5.json")
+                gold = json.load(open(gpath)) if os.path.exists(gpath) else None
+                row = {"a": a, "h": h, "order": p}
+                F = {}
+                for prec in ("fp64", "mixed"):
+                    r = time_precision(w, prm, prec, steps, 3, dev, stages=False, blocks=blocks)
+                    F[prec] = (r["E"], r["F"])
+                    row[prec] = {"ms_per_step": r["ms"], "evals_per_s": 1000.0 / r["ms"],
+                                 "vs_oracle": golden_errors(r["E"], r["F"], gold)}
+                    row["grid"] = list(r["info"]["grid"])
+                    row["taps"] = r["info"]["taps"]
+                    row[prec]["stencil_path"] = r["info"]["stencil_path"]
+                (Ed, Fd), (Em, Fm) = F["fp64"], F["mixed"]
+                dif = np.linalg.norm(Fm - Fd, axis=1)
+                row["mixed_vs_fp64_gpu"] = {"dE": abs(Em - Ed) / abs(Ed),
+                                            "rms_rel_F": float(np.sqrt(np.sum(dif ** 2) / np.sum(Fd ** 2)))}
+                row["mixed_over_fp64"] = row["fp64"]["ms_per_step"] / row["mixed"]["ms_per_step"]
+                log(f"[bench] sweep a={a} h={h} p={p}: fp64 {row['fp64']['ms_per_step']:.3f} ms, mixed "
+                    f"{row['mixed']['ms_per_step']:.3f} ms, mixed-vs-fp64 rms F {row['mixed_vs_fp64_gpu']['rms_rel_F']:.1e}"
+                    f", oracle sample {'yes' if gold else 'missing'}")
+                out.append(row)
+    return out
 
 
 def main():
@@ -430,6 +532,8 @@ def main():
     ap.add_argument("--no-lb", action="store_true", help="leave out the Lorentz-Berthelot measurement")
     ap.add_argument("--no-select", action="store_true", help="leave out the parameter-selection measurement")
     ap.add_argument("--no-md", action="store_true", help="leave out the molecular-dynamics measurement")
+    ap.add_argument("--no-sweep", action="store_true", help="leave out the 18-setting precision sweep")
+    ap.add_argument("--sweep-steps", type=int, default=100, help="graph replays per sweep setting")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: MLS here is a single-GPU path "
@@ -478,6 +582,10 @@ def main():
                 "frac": achieved / peak, "traffic": measured_traffic(dom, head), "traffic_unit": "bytes",
                 "work_per_launch": m.get("flops", m.get("bytes")),
                 "avg_launch_ms": sm[dom]}
+    if m["bound"] != "hbm" and head == "mixed":
+        roofline["peak_unpacked_fp32"] = PEAK["fp64"]
+        roofline["frac_unpacked_fp32"] = achieved / PEAK["fp64"]
+    per_stage_roofline = {p: stage_rooflines(res[p]["stage_ms"], model, p) for p in res}
 
     accuracy = {}
     for p in res:
@@ -542,10 +650,16 @@ def main():
             log(f"[bench] batched {p}: {batched[p]['ms_per_step']:.3f} ms/step, sequential single plans "
                 f"{batched[p]['sequential_single_plans_ms']:.3f} ms")
 
+    sweep = None
+    if not args.no_sweep and args.workload == "cube1M":
+        log("[bench] precision-at-scale sweep (18 settings x 2 precisions)")
+        sweep = precision_sweep(w, dev, args.sweep_steps, min(args.blocks, 5))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
-        cpu = cpu_baseline(prm, w.n)
+        cpu = cpu_baseline(prm, w)
+        log(f"[bench] cpu baseline: {cpu['sample']}")
 
     ms = res[head]["ms"]
     line = {
@@ -576,6 +690,8 @@ def main():
         "accuracy": accuracy,
         "discretisation_error": disc,
         "roofline": roofline,
+        "stage_roofline": per_stage_roofline,
+        "precision_sweep": sweep,
         "continuity_family": family,
         "lorentz_berthelot": lb,
         "molecular_dynamics": md,

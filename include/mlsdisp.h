@@ -107,7 +107,22 @@ typedef struct {
   double cell_width[3];    /* linked-cell width L_d / cells_d */
   int continuity;          /* k of gamma_k */
   int mixing;              /* mls_mixing */
+  int stencil_path;        /* mls_stencil_path: kernel and arithmetic of the
+                              level stencils of levels 1..l-1 */
 } mls_plan_info;
+
+/* Level-stencil kernels (mls_plan_info.stencil_path).  R is the stencil's
+ * half width in finest-grid points, ceil(2a / h) per dimension at most.
+ * FP32 tiles serve MLS_MIXED plans up to R = 12, FP64 tiles FP64 plans up
+ * to R = 8; beyond that both precisions run FP64 kernels (a streaming kernel
+ * up to R = 12, then one thread per output point over the tap table). */
+typedef enum {
+  MLS_STENCIL_NONE = 0,        /* l = 1: no level stencils */
+  MLS_STENCIL_TILE_F32 = 1,
+  MLS_STENCIL_TILE_F64 = 2,
+  MLS_STENCIL_STREAM_F64 = 3,
+  MLS_STENCIL_TAPS_F64 = 4
+} mls_stencil_path;
 
 /* Build a plan on the current HIP device: resolves grids, levels and linked
  * cells, tabulates the level-1 stencil g_1 (eq:g_k; the same table serves

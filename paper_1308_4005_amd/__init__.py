@@ -80,7 +80,8 @@ class Plan:
                          n_max=int(inf.n_max), workspace_bytes=int(inf.workspace_bytes),
                          precision=int(inf.precision), order=int(inf.order),
                          cell_width=tuple(inf.cell_width), continuity=int(inf.continuity),
-                         mixing=int(inf.mixing))
+                         mixing=int(inf.mixing),
+                         stencil_path=_lib.STENCIL_PATHS.get(int(inf.stencil_path), int(inf.stencil_path)))
         self.n_max = int(inf.n_max)
 
     # ------------------------------------------------------------------

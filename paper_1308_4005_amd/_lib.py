@@ -72,7 +72,11 @@ class MLSPlanInfo(ctypes.Structure):
         ("cell_width", ctypes.c_double * 3),
         ("continuity", ctypes.c_int),
         ("mixing", ctypes.c_int),
+        ("stencil_path", ctypes.c_int),
     ]
+
+
+STENCIL_PATHS = {0: "none", 1: "tile_f32", 2: "tile_f64", 3: "stream_f64", 4: "taps_f64"}
 
 
 class MLSBatchTuning(ctypes.Structure):

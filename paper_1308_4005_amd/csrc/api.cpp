@@ -82,6 +82,7 @@ mls_status mls_plan_get_info(mls_plan_t P, mls_plan_info* info) {
   info->order = P->order;
   info->continuity = P->continuity;
   info->mixing = P->mixing;
+  info->stencil_path = stencil_path(P);
   return MLS_OK;
 }
 

@@ -431,6 +431,7 @@ hipError_t launch_scan(mls_plan_s* P, const int* count, int m, int* start, hipSt
 hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s);
 hipError_t launch_restrict(mls_plan_s* P, int k_fine, hipStream_t s);
 hipError_t launch_stencils(mls_plan_s* P, hipStream_t s);
+int stencil_path(const mls_plan_s* P);   // mls_stencil_path of the plan
 hipError_t launch_coarsest(mls_plan_s* P, hipStream_t s);
 hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s);
 // mode: 0 the full evaluation, kInterpRep with the repulsion of the MD entry

@@ -393,29 +393,51 @@ hipError_t launch_tile(mls_plan_s* P, const T* wts, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_tile_r(mls_plan_s* P, int R, const T* wts, hipStream_t s) {
+hipError_t launch_tile_f64(mls_plan_s* P, int R, hipStream_t s) {
+  const double* w = P->d_row_w_tile;
   switch (R) {
-    case 1: case 2: case 3: case 4: return launch_tile<T, 4>(P, wts, s);
-    case 5: case 6: return launch_tile<T, 6>(P, wts, s);
-    case 7: case 8: return launch_tile<T, 8>(P, wts, s);
+    case 1: case 2: case 3: case 4: return launch_tile<double, 4>(P, w, s);
+    case 5: case 6: return launch_tile<double, 6>(P, w, s);
+    case 7: case 8: return launch_tile<double, 8>(P, w, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// FP32 tiles reach R = 12: (8 + 2R)^2 (8 + 2R) floats, 88 KB at R = 10 and
+// 128 KB at R = 12 (one block per CU; an FP64 tile of that size does not fit)
+hipError_t launch_tile_f32(mls_plan_s* P, int R, hipStream_t s) {
+  const float* w = P->d_row_wf_tile;
+  switch (R) {
+    case 1: case 2: case 3: case 4: return launch_tile<float, 4>(P, w, s);
+    case 5: case 6: return launch_tile<float, 6>(P, w, s);
+    case 7: case 8: return launch_tile<float, 8>(P, w, s);
+    case 9: case 10: return launch_tile<float, 10>(P, w, s);
+    case 11: case 12: return launch_tile<float, 12>(P, w, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int stencil_path(const mls_plan_s* P) {
+  if (P->levels < 2) return MLS_STENCIL_NONE;
+  const int R = stencil_window(P);
+  if (P->stencil_kernel == 1 && P->precision == MLS_MIXED && R >= 1 && R <= 12) return MLS_STENCIL_TILE_F32;
+  if (P->stencil_kernel == 1 && R >= 1 && R <= 8) return MLS_STENCIL_TILE_F64;
+  if (R >= 1 && R <= 12) return MLS_STENCIL_STREAM_F64;
+  return MLS_STENCIL_TAPS_F64;
 }
 
 hipError_t launch_stencils(mls_plan_s* P, hipStream_t s) {
   if (P->levels < 2) return hipSuccess;
   const int R = stencil_window(P);
-  if (P->stencil_kernel == 1 && R >= 1 && R <= 8) {
-    if (P->precision == MLS_MIXED) return launch_tile_r<float>(P, R, P->d_row_wf_tile, s);
-    return launch_tile_r<double>(P, R, P->d_row_w_tile, s);
-  }
+  const int path = stencil_path(P);
+  if (path == MLS_STENCIL_TILE_F32) return launch_tile_f32(P, R, s);
+  if (path == MLS_STENCIL_TILE_F64) return launch_tile_f64(P, R, s);
   const int ntaps = (int)P->taps.size();
   for (int k = 1; k < P->levels; ++k) {
     Level& L = P->lv[k - 1];
     const double scale = std::ldexp(1.0, -6 * (k - 1));
     hipError_t e;
-    if (R >= 1 && R <= 12) {
+    if (path == MLS_STENCIL_STREAM_F64) {
       e = launch_stream_r<double>(P, R, L.q, L.g, P->d_row_w, scale, L.e, s);
     } else {
       k_stencil_taps_f64<<<nblocks(L.g.size, kBlock), kBlock, 0, s>>>(L.q, L.g, P->d_taps, ntaps, scale, L.e);

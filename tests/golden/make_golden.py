@@ -23,11 +23,21 @@ from paper_1308_4005_amd import workloads as W  # noqa: E402
 
 SPECS = {
     # name: (workload, a, h, order, levels)
-    "cube1M_a3_h1_p4_l5": ("cube1M", 3.0, 1.0, 4, 5),
-    "cube1M_a3_h1_p6_l5": ("cube1M", 3.0, 1.0, 6, 5),
     "slab32k_a3_h1_p4_l4": ("slab32k", 3.0, 1.0, 4, 4),
     "mixture100k_a3_h1_p4_l0": ("mixture100k", 3.0, 1.0, 4, 0),
 }
+
+
+def _tag(x):
+    return f"{x:g}".replace(".", "p")
+
+
+# the precision-at-scale sweep: 10^6 atoms, a in {2.5, 3, 4}, h in {0.8, 1,
+# 1.25}, p in {4, 6}, five levels
+for _a in (2.5, 3.0, 4.0):
+    for _h in (0.8, 1.0, 1.25):
+        for _p in (4, 6):
+            SPECS[f"cube1M_a{_tag(_a)}_h{_tag(_h)}_p{_p}_l5"] = ("cube1M", _a, _h, _p, 5)
 NSAMPLE = 512
 
 

@@ -38,7 +38,12 @@ def _run(w, gold, precision):
     return out, q
 
 
-@pytest.fixture(scope="module", params=["slab32k_a3_h1_p4_l4", "cube1M_a3_h1_p4_l5"])
+# the precision-at-scale sweep: every stored 10^6-atom setting (a in {2.5, 3,
+# 4}, h in {0.8, 1, 1.25}, p in {4, 6}, five levels) besides the slab
+_SWEEP = sorted(f[:-5] for f in os.listdir(GOLDEN) if f.startswith("cube1M_a") and f.endswith("_l5.json"))
+
+
+@pytest.fixture(scope="module", params=["slab32k_a3_h1_p4_l4"] + _SWEEP)
 def golden_case(request):
     gold = json.load(open(os.path.join(GOLDEN, request.param + ".json")))
     say(f"[fullsize] {request.param}: building workload")
