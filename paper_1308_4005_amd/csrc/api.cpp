@@ -168,7 +168,7 @@ mls_status evaluate_geometric(mls_plan_t P, int64_t n, const double* pos, const 
   HIP_TRY(launch_anterpolate(P, ni, g), "anterpolation");
   HIP_TRY(mark(1 + MLS_T_ANTERP), "timing event");
   if (after == 1 && (st = pair()) != MLS_OK) return st;
-  for (int k = 2; k <= P->levels; ++k) HIP_TRY(launch_restrict(P, k - 1, g), "restriction");
+  HIP_TRY(launch_restrictions(P, g), "restriction");
   HIP_TRY(mark(1 + MLS_T_RESTRICT), "timing event");
   if (after == 2 && (st = pair()) != MLS_OK) return st;
   HIP_TRY(launch_stencils(P, g), "level stencils");
@@ -177,7 +177,7 @@ mls_status evaluate_geometric(mls_plan_t P, int64_t n, const double* pos, const 
   HIP_TRY(launch_coarsest(P, g), "coarsest grid");
   HIP_TRY(mark(1 + MLS_T_COARSEST), "timing event");
   if (after == 4 && (st = pair()) != MLS_OK) return st;
-  for (int k = P->levels - 1; k >= 1; --k) HIP_TRY(launch_prolong(P, k, g), "prolongation");
+  HIP_TRY(launch_prolongations(P, g), "prolongation");
   HIP_TRY(mark(1 + MLS_T_PROLONG), "timing event");
   if (fork) HIP_TRY(hipEventRecord(P->ev_join, g), "join");
   if (after == 5 && (st = pair()) != MLS_OK) return st;
@@ -224,12 +224,10 @@ hipError_t evaluate_split(mls_plan_t P, int n, const double* pos, const double* 
   bool fused = false;
   if ((e = launch_pair(P, n, s, &prep, &fused)) != hipSuccess) return e;
   if (!fused && (e = launch_repulsion(P, n, rep.rc, s)) != hipSuccess) return e;
-  for (int k = 2; k <= P->levels; ++k)
-    if ((e = launch_restrict(P, k - 1, g)) != hipSuccess) return e;
+  if ((e = launch_restrictions(P, g)) != hipSuccess) return e;
   if ((e = launch_stencils(P, g)) != hipSuccess) return e;
   if ((e = launch_coarsest(P, g)) != hipSuccess) return e;
-  for (int k = P->levels - 1; k >= 1; --k)
-    if ((e = launch_prolong(P, k, g)) != hipSuccess) return e;
+  if ((e = launch_prolongations(P, g)) != hipSuccess) return e;
   if ((e = hipEventRecord(P->ev_join, g)) != hipSuccess) return e;
   if ((e = launch_local_out(P, n, energy, forces, s)) != hipSuccess) return e;
   if ((e = hipStreamWaitEvent(s, P->ev_join, 0)) != hipSuccess) return e;
@@ -409,10 +407,10 @@ mls_status mls_evaluate_lb(mls_plan_t P, int64_t n, const double* pos, const dou
     std::swap(P->lv, P->lb_lv[k]);
     P->charge = P->d_charge;
     hipError_t e = launch_anterpolate(P, ni, g);
-    for (int j = 2; e == hipSuccess && j <= P->levels; ++j) e = launch_restrict(P, j - 1, g);
+    if (e == hipSuccess) e = launch_restrictions(P, g);
     if (e == hipSuccess) e = launch_stencils(P, g);
     if (e == hipSuccess) e = launch_coarsest(P, g);
-    for (int j = P->levels - 1; e == hipSuccess && j >= 1; --j) e = launch_prolong(P, j, g);
+    if (e == hipSuccess) e = launch_prolongations(P, g);
     P->charge = nullptr;
     std::swap(P->lv, P->lb_lv[k]);
     if (e != hipSuccess) return hip_fail(e, "grid part");

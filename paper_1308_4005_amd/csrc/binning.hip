@@ -66,19 +66,33 @@ struct BinCount {
   using Args = BinCountArgs;
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int blk) {
+    __shared__ double sh[kBlock];
     const int i = blk * kBlock + threadIdx.x;
-    if (i >= a.n) return;
-    const CellGeom& g = a.g;
-    int bad;
-    const double4 p = wrapped_atom(a.pos, a.c6, i, g, a.c6_scale, bad);
-    if (bad) atomicOr(a.flags, bad);
-    int cx = max(0, min((int)(p.x * g.inv_w[0]), g.nc[0] - 1));
-    int cy = max(0, min((int)(p.y * g.inv_w[1]), g.nc[1] - 1));
-    int cz = max(0, min((int)(p.z * g.inv_w[2]), g.nc[2] - 1));
-    int id = (cz * g.nc[1] + cy) * g.nc[0] + cx;
-    a.cid[i] = id;
-    a.xw[i] = p;
-    a.slot[i] = atomicAdd(&a.count[id], 1);
+    double xi = 0.0;
+    if (i < a.n) {
+      const CellGeom& g = a.g;
+      int bad;
+      const double4 p = wrapped_atom(a.pos, a.c6, i, g, a.c6_scale, bad);
+      if (bad) atomicOr(a.flags, bad);
+      int cx = max(0, min((int)(p.x * g.inv_w[0]), g.nc[0] - 1));
+      int cy = max(0, min((int)(p.y * g.inv_w[1]), g.nc[1] - 1));
+      int cz = max(0, min((int)(p.z * g.inv_w[2]), g.nc[2] - 1));
+      int id = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+      a.cid[i] = id;
+      a.xw[i] = p;
+      a.slot[i] = atomicAdd(&a.count[id], 1);
+      xi = p.w;
+    }
+    if (a.xi_partial) {
+      // per-block sum of xi over atoms in original order (fixed order)
+      sh[threadIdx.x] = xi;
+      __syncthreads();
+      for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) a.xi_partial[blk] = sh[0];
+    }
   }
 };
 
@@ -129,6 +143,10 @@ struct ScanBlocks {
       sum += v[k];
       mx = max(mx, v[k]);
     }
+    // the counts are consumed here: leave them zero for the next binning
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+      if (base + k < a.m) a.count[base + k] = 0;
     int total;
     int run = block_exclusive_scan(sum, sh, total);
 #pragma unroll
@@ -205,6 +223,45 @@ struct CellRank {
     int rank = 0;
     for (int j = b; j < e; ++j) rank += a.perm_tmp[j].x < v;
     a.perm[b + rank] = v;
+  }
+};
+
+struct RankGather {
+  using Args = RankGatherArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    const int s = blk * kBlock + threadIdx.x;
+    if (s < a.n) {
+      const int2 vc = a.perm_tmp[s];
+      const int v = vc.x, c = vc.y;
+      const int b = a.start[c], e = a.start[c + 1];
+      int rank = 0;
+      for (int j = b; j < e; ++j) rank += a.perm_tmp[j].x < v;
+      const int d = b + rank;   // stable position of atom v
+      a.perm[d] = v;
+      const double4 p = a.xw[v];
+      a.xs[d] = p;
+      a.cell_s[d] = c;
+      if (a.xr) {
+        // cell-relative FP32 coordinates and the cell x index (exact in FP32)
+        // for the mixed-precision pair kernel; the cell from the same
+        // wrapped position as BinCount
+        const CellGeom& g = a.g;
+        const int cx = max(0, min((int)(p.x * g.inv_w[0]), g.nc[0] - 1));
+        const int cy = max(0, min((int)(p.y * g.inv_w[1]), g.nc[1] - 1));
+        const int cz = max(0, min((int)(p.z * g.inv_w[2]), g.nc[2] - 1));
+        a.xr[d] = make_float4((float)(p.x - cx * g.w[0]), (float)(p.y - cy * g.w[1]), (float)(p.z - cz * g.w[2]),
+                              (float)cx);
+        a.xif[d] = (float)p.w;
+      }
+    } else if (s < a.n + kSortedPad) {
+      // padding rows: far outside any cutoff, zero weight
+      a.xs[s] = make_double4(1e300, 1e300, 1e300, 0.0);
+      if (a.xr) {
+        a.xr[s] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+        a.xif[s] = 0.0f;
+      }
+    }
   }
 };
 
@@ -362,11 +419,14 @@ hipError_t launch_lb_charge(mls_plan_s* P, int n, int k, hipStream_t s) {
 
 hipError_t launch_binning_scaled(mls_plan_s* P, int n, const double* pos, const double* c6, double scale,
                                  hipStream_t s) {
+  // The cell counts start at zero: cleared once at plan creation, then by
+  // every scan after it has read them.
   const CellGeom& g = P->cg;
+  const bool mixed = P->precision == MLS_MIXED;
   hipError_t e;
-  if ((e = launch_zero_i(P->d_count, g.ncell, s)) != hipSuccess) return e;
   if (n > 0) {
-    BinCountArgs a{pos, c6, n, g, P->d_cid, P->d_slot, P->d_count, P->d_xw, P->d_flags, scale};
+    BinCountArgs a{pos, c6, n, g, P->d_cid, P->d_slot, P->d_count, P->d_xw, P->d_flags, scale,
+                   mixed ? P->d_partial : nullptr};
     if ((e = launch_one<BinCount>(a, nblocks(n, kBlock), s)) != hipSuccess) return e;
   }
   if ((e = launch_scan(P, P->d_count, g.ncell, P->d_cell_start, s)) != hipSuccess) return e;
@@ -374,23 +434,20 @@ hipError_t launch_binning_scaled(mls_plan_s* P, int n, const double* pos, const 
   if ((e = launch_one<BinScatter>(ScatterArgs{P->d_cid, P->d_slot, n, P->d_cell_start, P->d_perm_tmp},
                                   nblocks(n, kBlock), s)) != hipSuccess)
     return e;
-  if ((e = launch_one<CellRank>(RankArgs{P->d_cell_start, P->d_perm_tmp, n, P->d_perm},
-                                nblocks(n, kBlock), s)) != hipSuccess)
-    return e;
-  const bool mixed = P->precision == MLS_MIXED;
-  GatherArgs ga{P->d_perm, n, P->d_xw, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, g,
-                mixed ? P->d_partial : nullptr};
-  return launch_one<GatherSorted>(ga, nblocks(n + kSortedPad, kBlock), s);
+  RankGatherArgs ra{P->d_cell_start, P->d_perm_tmp, n, P->d_perm, P->d_xw, P->d_xs, P->d_cell_s, P->d_xr,
+                    P->d_xif, g};
+  return launch_one<RankGather>(ra, nblocks(n + kSortedPad, kBlock), s);
 }
 
 hipError_t launch_sum_xi(mls_plan_s* P, int n, hipStream_t s) {
   if (P->precision != MLS_MIXED || n == 0) return hipSuccess;
-  // sum of xi: the mean of every grid level's charges (partition of unity)
-  SumXiArgs sa{n + kSortedPad, P->d_partial, P->d_scratch};
+  // sum of xi: the mean of every grid level's charges (partition of unity),
+  // from the binning's per-block partial sums
+  SumXiArgs sa{n, P->d_partial, P->d_scratch};
   return launch_one<SumXiFinal>(sa, 1, s);
 }
 
-hipError_t launch_scan(mls_plan_s* P, const int* count, int m, int* start, hipStream_t s) {
+hipError_t launch_scan(mls_plan_s* P, int* count, int m, int* start, hipStream_t s) {
   ScanArgs a{count, m, start, P->d_bsum, P->d_bmax, P->d_ncell_max};
   hipError_t e;
   if ((e = launch_one<ScanBlocks>(a, scan_blocks(m), s)) != hipSuccess) return e;

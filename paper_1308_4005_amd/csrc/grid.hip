@@ -356,14 +356,9 @@ struct AnterpCollect {
 // ------------------------------------------------------------ restriction
 // Per-dimension taps around fine index 2M: offsets 0, +-1, +-3 (, +-5).
 template <int P>
-struct Restrict {
-  using Args = TransferArgs;
-  static constexpr int kThreads = kBlock;
-  static __device__ void run(const Args& a, int blk) {
+__device__ __forceinline__ void restrict_at(const TransferArgs& a, int M) {
     const GridDims& f = a.gs;
     const GridDims& c = a.gd;
-    const int M = blk * kBlock + threadIdx.x;
-    if (M >= c.size) return;
     const int X = M % c.n[0], Y = (M / c.n[0]) % c.n[1], Z = M / (c.n[0] * c.n[1]);
     constexpr int K = P + 1;  // 0, +-1, +-3, (+-5)
     int ix[K], iy[K], iz[K];
@@ -398,6 +393,15 @@ struct Restrict {
       acc += w[i] * sy;
     }
     a.dst[M] = acc;
+}
+
+template <int P>
+struct Restrict {
+  using Args = TransferArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    const int M = blk * kBlock + threadIdx.x;
+    if (M < a.gd.size) restrict_at<P>(a, M);
   }
 };
 
@@ -409,14 +413,9 @@ struct Restrict {
 // thread walks those P z-planes, interpolates each plane in x then y, and
 // adds it into the 8 outputs.
 template <int P>
-struct Prolong {
-  using Args = TransferArgs;
-  static constexpr int kThreads = kBlock;
-  static __device__ void run(const Args& a, int blk) {
+__device__ __forceinline__ void prolong_at(const TransferArgs& a, int M) {
     const GridDims& c = a.gs;
     const GridDims& f = a.gd;
-    const int M = blk * kBlock + threadIdx.x;
-    if (M >= c.size) return;
     const int X = M % c.n[0], Y = (M / c.n[0]) % c.n[1], Z = M / (c.n[0] * c.n[1]);
     constexpr int H = P / 2;
     double w[P];   // weight of coarse M - H + 1 + t for the odd fine point 2M + 1
@@ -473,6 +472,15 @@ struct Prolong {
         a.dst[J] = a.add[J] + acc[pz][py][0];
         a.dst[J + 1] = a.add[J + 1] + acc[pz][py][1];
       }
+}
+
+template <int P>
+struct Prolong {
+  using Args = TransferArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    const int M = blk * kBlock + threadIdx.x;
+    if (M < a.gs.size) prolong_at<P>(a, M);
   }
 };
 
@@ -830,6 +838,22 @@ hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s) {
   if (e != hipSuccess || n == 0) return e;
   if (P->order == 4) return launch_one<AnterpAtomic<4>>(a, nblocks(n, kBlock), s);
   return launch_one<AnterpAtomic<6>>(a, nblocks(n, kBlock), s);
+}
+
+hipError_t launch_restrictions(mls_plan_s* P, hipStream_t s) {
+  for (int k = 2; k <= P->levels; ++k) {
+    hipError_t e = launch_restrict(P, k - 1, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_prolongations(mls_plan_s* P, hipStream_t s) {
+  for (int k = P->levels - 1; k >= 1; --k) {
+    hipError_t e = launch_prolong(P, k, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_restrict(mls_plan_s* P, int k_fine, hipStream_t s) {

@@ -109,6 +109,7 @@ struct BinCountArgs {
   const double* pos; const double* c6; int n; CellGeom g;
   int* cid; int* slot; int* count; double4* xw; int* flags;
   double c6_scale;   // xi = sqrt(c6_scale * c6): 1 for C6, 2 for Lorentz-Berthelot epsilon
+  double* xi_partial = nullptr;   // per-block sums of xi in original order (single plans, mixed)
 };
 // molecular dynamics (md.hip): repulsion of eq:disp-pair-pot and velocity Verlet
 struct RepGatherArgs { const int* perm; const double* c12; int n; double* x12s; float* x12f; int* flags; };
@@ -134,9 +135,15 @@ struct AddForcesArgs { double* forces; const double* add; int n3; };
 struct MdKineticArgs { const double* partial; int npartial; double* out; };
 struct LbGatherArgs { const int* perm; int n; const double* sigma; double* sig_s; int* flags; };
 struct LbChargeArgs { const double4* xs; const double* sig_s; int n; int k; double* charge; };
-struct ScanArgs { const int* count; int m; int* start; int* bsum; int* bmax; int* max_count; };
+struct ScanArgs { int* count; int m; int* start; int* bsum; int* bmax; int* max_count; };
 struct ScatterArgs { const int* cid; const int* slot; int n; const int* start; int2* perm_tmp; };
 struct RankArgs { const int* start; const int2* perm_tmp; int n; int* perm; };
+// Rank of each atom among its cell's atoms by original index, fused with the
+// gather of the sorted arrays (single plans).
+struct RankGatherArgs {
+  const int* start; const int2* perm_tmp; int n; int* perm; const double4* xw;
+  double4* xs; int* cell_s; float4* xr; float* xif; CellGeom g;
+};
 struct GatherArgs {
   const int* perm; int n; const double4* xw;
   double4* xs; int* cell_s; float4* xr; float* xif; CellGeom g;
@@ -427,13 +434,16 @@ hipError_t launch_sum_xi(mls_plan_s* P, int n, hipStream_t s);
 // With `rep`, the FP32 and FP64 half-cell kernels also evaluate the repulsion
 // (*fused set); other kernels leave it to launch_repulsion.
 hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s, const PairRep* rep = nullptr, bool* fused = nullptr);
-hipError_t launch_scan(mls_plan_s* P, const int* count, int m, int* start, hipStream_t s);
+hipError_t launch_scan(mls_plan_s* P, int* count, int m, int* start, hipStream_t s);
 hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s);
 hipError_t launch_restrict(mls_plan_s* P, int k_fine, hipStream_t s);
 hipError_t launch_stencils(mls_plan_s* P, hipStream_t s);
 int stencil_path(const mls_plan_s* P);   // mls_stencil_path of the plan
 hipError_t launch_coarsest(mls_plan_s* P, hipStream_t s);
 hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s);
+// All restrictions (levels 2..l) and all prolongations (l-1..1) of an evaluation.
+hipError_t launch_restrictions(mls_plan_s* P, hipStream_t s);
+hipError_t launch_prolongations(mls_plan_s* P, hipStream_t s);
 // mode: 0 the full evaluation, kInterpRep with the repulsion of the MD entry
 // points, kInterpGridOnly the grid part alone (energy added to *energy)
 constexpr int kInterpRep = 1, kInterpGridOnly = 2;

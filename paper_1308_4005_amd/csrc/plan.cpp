@@ -493,6 +493,9 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
       (e = hipMemcpy(P->d_ant_tab, ant_tab.data(), ant_tab.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "copy anterpolation tables");
   if ((e = hipMemset(P->d_flags, 0, 4 * sizeof(int))) != hipSuccess) return hip_fail(e, "clear flags");
+  // the binning's cell counts: zero here, and zero again after every scan
+  if ((e = hipMemset(P->d_count, 0, (size_t)cg.ncell * sizeof(int))) != hipSuccess)
+    return hip_fail(e, "clear cell counts");
   if ((e = hipMemset(P->d_scratch, 0, 64 * sizeof(double))) != hipSuccess) return hip_fail(e, "clear scratch");
   return MLS_OK;
 }

@@ -316,14 +316,24 @@ struct Coarsest {
     if (mu >= g.size) return;
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], n01 = n0 * n1;
     const int x = mu % n0, y = (mu / n0) % n1, z = mu / n01;
+    // the lane's source nu = lane + 64 t walks the grid as (nx, ny, nz),
+    // advanced by 64 points per step with carries (no division per term)
+    const int a0 = 64 % n0, a1 = (64 / n0) % n1, a2 = 64 / n01;
+    int nx = lane % n0, ny = (lane / n0) % n1, nz = lane / n01;
     double acc = 0.0;
     for (int nu = lane; nu < g.size; nu += 64) {
-      const int nz = nu / n01, r = nu - nz * n01, ny = r / n0, nx = r - ny * n0;
       int dx = x - nx, dy = y - ny, dz = z - nz;
       dx += dx < 0 ? n0 : 0;
       dy += dy < 0 ? n1 : 0;
       dz += dz < 0 ? n2 : 0;
       acc = fma(K[((size_t)dz * n1 + dy) * n0 + dx], q[nu], acc);
+      nx += a0;
+      const int cx = nx >= n0;
+      nx -= cx ? n0 : 0;
+      ny += a1 + cx;
+      const int cy = ny >= n1;
+      ny -= cy ? n1 : 0;
+      nz += a2 + cy;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);

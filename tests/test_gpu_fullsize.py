@@ -71,8 +71,11 @@ def test_golden_sample(golden_case, precision):
         assert dE < MIXED_E_BOUND
         assert rms < MIXED_RMS_BOUND
     # properties at any size: partition of unity on every level, Euler's
-    # relation for the degree-1 homogeneity in C6
+    # relation for the degree-1 homogeneity in C6.  The mixed path computes
+    # the anterpolation weights in FP32, so its grid sums keep the partition
+    # of unity to FP32 rounding (about 2e-7 for the quintic basis at 10^6
+    # atoms), the FP64 path to FP64 rounding
     xi_sum = float(np.sum(np.sqrt(w.c6)))
     for s in qsums:
-        assert s == pytest.approx(xi_sum, rel=1e-9)
+        assert s == pytest.approx(xi_sum, rel=1e-9 if precision == "fp64" else 1e-6)
     assert float(np.dot(w.c6, out["d"])) == pytest.approx(out["E"], rel=1e-9)
