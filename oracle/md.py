@@ -19,7 +19,8 @@ import numpy as np
 
 from . import mls as M
 
-__all__ = ["repulsion", "forces", "md_run", "split_forces", "md_run_mts"]
+__all__ = ["repulsion", "forces", "md_run", "split_forces", "md_run_mts", "split_forces_levels",
+           "md_run_mts_levels"]
 
 
 def repulsion(pos, c12, box, rc, targets=None):
@@ -134,3 +135,75 @@ def md_run_mts(pos, vel, c6, c12, inv_mass, box, a, h, order, levels, dt, nsteps
         epot.append(Ef + Es)
         kin.append(ekin(v))
     return x, v, Ff + Fs, np.array(epot), np.array(kin)
+
+
+def split_forces_levels(pos, c6, c12, box, a, h, order, levels, continuity=2, rc=None):
+    """The split of multiple time stepping by MLS level: fast = the local part
+    (eq:evaluation with k = 0) plus the repulsion, as in ``split_forces``;
+    mid = the level-1 grid part alone, the interpolation (eq:interpolation)
+    of e^1 (for l >= 2; with l = 1 the only grid is the coarsest and the mid
+    class is empty); slow = the rest of the MLS result, the interpolation of
+    the prolongation of E^2 (levels 2..l, without e^1) with the self-energy
+    term.  Interpolation is linear, so mid + slow is the whole grid part.
+    Returns (E_fast, F_fast, E_mid, F_mid, E_slow, F_slow)."""
+    r = M.mls(pos, c6, box, a, h, order, levels, continuity=continuity)
+    xi = np.sqrt(np.asarray(c6, dtype=np.float64))
+    l = r["levels"]
+    E_loc = -0.5 * float(np.dot(xi, r["e0"]))
+    Er, Fr = repulsion(pos, c12, box, a if rc is None else rc)
+    E_fast, F_fast = E_loc + Er, np.array(r["Floc"], dtype=np.float64) + Fr
+    if l >= 2:
+        u1, g1 = M.interpolate(r["xw"], r["e"][0], box, r["n1"], order)
+        E_mid, F_mid = -0.5 * float(np.dot(xi, u1)), xi[:, None] * g1
+    else:
+        E_mid, F_mid = 0.0, np.zeros_like(F_fast)
+    E_slow = r["energy"] - E_loc - E_mid
+    F_slow = r["F"] - np.array(r["Floc"], dtype=np.float64) - F_mid
+    return E_fast, F_fast, E_mid, F_mid, E_slow, F_slow
+
+
+def md_run_mts_levels(pos, vel, c6, c12, inv_mass, box, a, h, order, levels, dt, nsteps, k_mid, k_slow,
+                      continuity=2, rc=None):
+    """r-RESPA with three time scales on the split of ``split_forces_levels``:
+    the fast force every step dt, the mid force every k_mid steps and the
+    slow force every k_mid k_slow steps.  Per outer step of k_slow k_mid dt:
+        v += (k_slow k_mid dt/2) F_slow/m
+        k_slow times:
+            v += (k_mid dt/2) F_mid/m
+            k_mid times: v += dt/2 F_fast/m; x += dt v; F_fast(x); v += dt/2 F_fast/m
+            F_mid(x); v += (k_mid dt/2) F_mid/m
+        F_slow(x); v += (k_slow k_mid dt/2) F_slow/m.
+    nsteps (inner steps) is a multiple of k_mid k_slow.  Returns the final x,
+    v, the total force at the final positions, and E_pot, E_kin at the
+    nsteps / (k_mid k_slow) + 1 outer-step boundaries."""
+    outer = k_mid * k_slow
+    assert nsteps % outer == 0
+    x = np.array(pos, dtype=np.float64)
+    v = np.array(vel, dtype=np.float64)
+    im = np.asarray(inv_mass, dtype=np.float64)[:, None]
+    hs, hm = 0.5 * outer * dt, 0.5 * k_mid * dt
+
+    def ekin(v_):
+        return 0.5 * float(np.sum(np.sum(v_ * v_, axis=1) / im[:, 0]))
+
+    def split(x_):
+        return split_forces_levels(x_, c6, c12, box, a, h, order, levels, continuity, rc)
+
+    Ef, Ff, Em, Fm, Es, Fs = split(x)
+    epot, kin = [Ef + Em + Es], [ekin(v)]
+    for _ in range(nsteps // outer):
+        v = v + hs * Fs * im
+        for _ in range(k_slow):
+            v = v + hm * Fm * im
+            for _ in range(k_mid):
+                v = v + 0.5 * dt * Ff * im
+                x = x + dt * v
+                Ef, Ff, _, _, _, _ = split(x)
+                v = v + 0.5 * dt * Ff * im
+            _, _, Em, Fm, _, _ = split(x)
+            v = v + hm * Fm * im
+        _, _, _, _, Es, Fs = split(x)
+        v = v + hs * Fs * im
+        epot.append(Ef + Em + Es)
+        kin.append(ekin(v))
+    return x, v, Ff + Fm + Fs, np.array(epot), np.array(kin)

@@ -160,3 +160,76 @@ def test_mts_conserves_energy_like_verlet(system):
     tot = ep + ek
     d_mts = np.max(np.abs(tot - tot[0]))
     assert d_mts < 3.0 * d_vv
+
+
+# ---------------------------------------------------------------- multiple time steps per level
+
+PRM3 = lambda w: (w.box, 2.5, 0.9, 4, 3)   # three grid levels: level 1 and levels 2..3 both present
+
+
+def test_level_split_adds_up_and_is_the_grid_energy_by_level(system):
+    from oracle import mls as M
+    w, vel, c12, inv_m = system
+    Ef, Ff, Em, Fm, Es, Fs = MD.split_forces_levels(w.pos, w.c6, c12, *PRM3(w))
+    E, F = MD.forces(w.pos, w.c6, c12, *PRM3(w))
+    assert Ef + Em + Es == pytest.approx(E, rel=1e-12)
+    np.testing.assert_allclose(Ff + Fm + Fs, F, rtol=0, atol=1e-11 * np.abs(F).max())
+    # mid + slow is the two-scale split's slow part
+    Ef2, Ff2, Es2, Fs2 = MD.split_forces(w.pos, w.c6, c12, *PRM3(w))
+    assert Em + Es == pytest.approx(Es2, rel=1e-11)
+    np.testing.assert_allclose(Fm + Fs, Fs2, rtol=0, atol=1e-11 * np.abs(Fs2).max())
+    # independent of the atom-side interpolation: interpolation is the
+    # transpose of anterpolation, so the mid energy is -1/2 <q^1, e^1> and the
+    # slow energy -1/2 sum_{k>=2} <q^k, e^k> plus the self term
+    r = M.mls(w.pos, w.c6, *PRM3(w))
+    qe = [float(np.sum(q * e)) for q, e in zip(r["q"], r["e"])]
+    xi = np.sqrt(w.c6)
+    cself = M.gamma(np.zeros(1))[0] / 2.5 ** 6
+    assert Em == pytest.approx(-0.5 * qe[0], rel=1e-11)
+    assert Es == pytest.approx(-0.5 * sum(qe[1:]) + 0.5 * cself * float(xi @ xi), rel=1e-11)
+    # ordered by smoothness: each class is far weaker than the faster one
+    assert np.abs(Fs).max() < 0.1 * np.abs(Fm).max()
+    assert np.abs(Fm).max() < 0.1 * np.abs(Ff).max()
+
+
+def test_level_split_with_one_level_has_no_mid_class():
+    w = W.cube(60, 0.5, seed=9)
+    c12 = np.full(w.n, 4.0)
+    Ef, Ff, Em, Fm, Es, Fs = MD.split_forces_levels(w.pos, w.c6, c12, w.box, 2.0, 0.8, 4, 1)
+    assert Em == 0.0 and not np.any(Fm)
+    Ef2, Ff2, Es2, Fs2 = MD.split_forces(w.pos, w.c6, c12, w.box, 2.0, 0.8, 4, 1)
+    assert Es == pytest.approx(Es2, rel=1e-12)
+    np.testing.assert_allclose(Fs, Fs2, rtol=0, atol=1e-12 * np.abs(Fs2).max())
+
+
+def test_levels_mts_reduces_to_verlet_and_to_two_scales(system):
+    w, vel, c12, inv_m = system
+    a = MD.md_run(w.pos, vel, w.c6, c12, inv_m, *PRM3(w), 0.002, 2)
+    b = MD.md_run_mts_levels(w.pos, vel, w.c6, c12, inv_m, *PRM3(w), 0.002, 2, 1, 1)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(y, x, rtol=1e-12, atol=1e-12 * np.abs(x).max())
+    # with k_slow = 1 the mid and slow kicks fall on the same instants: the
+    # two-scale scheme with the whole grid part every k_mid steps
+    a = MD.md_run_mts(w.pos, vel, w.c6, c12, inv_m, *PRM3(w), 0.002, 4, 2)
+    b = MD.md_run_mts_levels(w.pos, vel, w.c6, c12, inv_m, *PRM3(w), 0.002, 4, 2, 1)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(y, x, rtol=1e-12, atol=1e-11 * np.abs(x).max())
+
+
+def test_levels_mts_is_time_reversible(system):
+    w, vel, c12, inv_m = system
+    x1, v1, _, _, _ = MD.md_run_mts_levels(w.pos, vel, w.c6, c12, inv_m, *PRM3(w), 0.002, 8, 2, 2)
+    x0, v0, _, _, _ = MD.md_run_mts_levels(x1, -v1, w.c6, c12, inv_m, *PRM3(w), 0.002, 8, 2, 2)
+    np.testing.assert_allclose(x0, w.pos, rtol=0, atol=1e-11 * np.abs(w.pos).max())
+    np.testing.assert_allclose(-v0, vel, rtol=0, atol=1e-9 * np.abs(vel).max())
+
+
+def test_levels_mts_conserves_energy_like_verlet(system):
+    # level 1 every 2 steps and levels 2..3 every 4: the energy stays about as
+    # well conserved as velocity Verlet at dt
+    w, vel, c12, inv_m = system
+    _, _, _, ep, ek = MD.md_run(w.pos, vel, w.c6, c12, inv_m, *PRM3(w), 0.002, 16)
+    d_vv = np.max(np.abs((ep + ek) - (ep[0] + ek[0])))
+    _, _, _, ep, ek = MD.md_run_mts_levels(w.pos, vel, w.c6, c12, inv_m, *PRM3(w), 0.002, 16, 2, 2)
+    d_lv = np.max(np.abs((ep + ek) - (ep[0] + ek[0])))
+    assert d_lv < 3.0 * d_vv
