@@ -336,6 +336,17 @@ def time_md(w, prm, precision, steps, warmup, dev, blocks, chunk=50, dt=0.001):
     torch.cuda.synchronize()
     flags |= plan.status()
     totm = (epm + ekm).cpu().numpy()
+    # multiple time stepping per level: level 1 every 2 steps, levels 2..l
+    # every 4 steps
+    k_mid, k_sl = 2, 2
+    epl = torch.empty(chunk_m // (k_mid * k_sl) + 1, dtype=torch.float64, device=dev)
+    ekl = torch.empty(chunk_m // (k_mid * k_sl) + 1, dtype=torch.float64, device=dev)
+    ms_l, block_l = time_graph(lambda: plan.md_run_mts_levels(x, v, c6, c12, im, dt, chunk_m, k_mid, k_sl, forces=F,
+                                                              epot=epl, ekin=ekl),
+                               max(blocks, steps // chunk_m), max(1, warmup // chunk_m), blocks, dev)
+    torch.cuda.synchronize()
+    flags |= plan.status()
+    totl = (epl + ekl).cpu().numpy()
     plan.close()
     return {"workload": f"{w.name} positions, LJ C6 = C12 = 4, unit masses, velocities N(0, 0.8) (seed 29), "
                         f"repulsion cutoff {prm['a']}, dt {dt}",
@@ -346,7 +357,11 @@ def time_md(w, prm, precision, steps, warmup, dev, blocks, chunk=50, dt=0.001):
             "multiple_time_stepping": {
                 "k_slow": k_slow, "ms_per_step": ms_m / chunk_m, "steps_per_s": 1000.0 * chunk_m / ms_m,
                 "block_ms_per_step": [b / chunk_m for b in block_m], "steps_per_replay": chunk_m,
-                "last_replay_total_energy_spread_rel": float((totm.max() - totm.min()) / abs(totm.mean()))}}
+                "last_replay_total_energy_spread_rel": float((totm.max() - totm.min()) / abs(totm.mean()))},
+            "multiple_time_stepping_per_level": {
+                "k_mid": k_mid, "k_slow": k_sl, "ms_per_step": ms_l / chunk_m, "steps_per_s": 1000.0 * chunk_m / ms_l,
+                "block_ms_per_step": [b / chunk_m for b in block_l], "steps_per_replay": chunk_m,
+                "last_replay_total_energy_spread_rel": float((totl.max() - totl.min()) / abs(totl.mean()))}}
 
 
 def run_selection(w, head, steps, dev, target=1e-4):
@@ -626,7 +641,8 @@ def main():
         log("[bench] molecular dynamics (velocity Verlet, dispersion + repulsion)")
         md = time_md(w, prm, head, args.steps, args.warmup, dev, args.blocks)
         log(f"[bench] md: {md['ms_per_step']:.3f} ms/step, evaluate_md {md['evaluate_md_ms']:.3f} ms, "
-            f"multiple time stepping (k=4) {md['multiple_time_stepping']['ms_per_step']:.3f} ms/step")
+            f"multiple time stepping (k=4) {md['multiple_time_stepping']['ms_per_step']:.3f} ms/step, per level "
+            f"(2, 2) {md['multiple_time_stepping_per_level']['ms_per_step']:.3f} ms/step")
 
     selection = None
     if not args.no_select:

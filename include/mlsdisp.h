@@ -222,6 +222,37 @@ mls_status mls_md_run_mts(mls_plan_t plan, int64_t n, double* pos, double* vel, 
                           const double* c12, double rc, const double* inv_mass, double dt, int nsteps, int k_slow,
                           double* forces, double* epot, double* ekin, void* stream);
 
+/* Multiple time stepping per MLS level (r-RESPA with three nested time
+ * steps), the level-by-level version of mls_md_run_mts's split:
+ *   fast = the local part of eq:evaluation (k = 0) plus the repulsion,
+ *          every step dt;
+ *   mid  = the level-1 grid part, the interpolation (eq:interpolation) of
+ *          the level-1 stencil result e^1 alone, every k_mid steps (empty,
+ *          zero, for l = 1);
+ *   slow = the rest of the grid part: the interpolation of E^1 prolongated
+ *          from E^2 without e^1 (levels 2..l; for l = 1 the coarsest level,
+ *          which is level 1), with the self-energy term, every k_mid k_slow
+ *          steps.
+ * Interpolation is linear, so mid + slow is the whole grid part.  One outer
+ * step of k_mid k_slow dt:
+ *   v += (k_mid k_slow dt/2) F_slow/m;
+ *   k_slow times: v += (k_mid dt/2) F_mid/m;
+ *                 k_mid times: v += dt/2 F_fast/m; x += dt v; F_fast(x); v += dt/2 F_fast/m;
+ *                 F_mid(x); v += (k_mid dt/2) F_mid/m;
+ *   F_slow(x); v += (k_mid k_slow dt/2) F_slow/m.
+ * k_slow = 1 is mls_md_run_mts with k_slow = k_mid; k_mid = k_slow = 1 is
+ * mls_md_run (up to rounding order).  nsteps counts inner steps and must be a
+ * multiple of k_mid k_slow.  Outputs (device FP64): forces (n,3) = F_fast +
+ * F_mid + F_slow at the final positions; epot and ekin
+ * (nsteps / (k_mid k_slow) + 1): E_fast + E_mid + E_slow and the kinetic
+ * energy at the outer-step boundaries (index 0: initial positions).
+ * Arguments, flags, ordering and errors as mls_md_run_mts, plus
+ * MLS_ERR_INVALID_ARG for k_mid < 1, k_slow < 1 or nsteps not a multiple of
+ * k_mid k_slow.  Plan: geometric mixing. */
+mls_status mls_md_run_mts_levels(mls_plan_t plan, int64_t n, double* pos, double* vel, const double* c6,
+                                 const double* c12, double rc, const double* inv_mass, double dt, int nsteps,
+                                 int k_mid, int k_slow, double* forces, double* epot, double* ekin, void* stream);
+
 /* One evaluation under Lorentz-Berthelot mixing (Sec. II.D,
  * eq:disp-pair-pot-multilevel-LorentzBerthelot): pair coefficient
  * C_ij = 2 sqrt(eps_i eps_j) ((sigma_i + sigma_j)/2)^6 (eq:xi-lj), so

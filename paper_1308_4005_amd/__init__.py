@@ -215,6 +215,40 @@ class Plan:
                        "mls_md_run_mts")
         return forces, epot, ekin
 
+    def md_run_mts_levels(self, pos, vel, c6, c12, inv_mass, dt, nsteps, k_mid, k_slow, rc=None, forces=None,
+                          epot=None, ekin=None, stream=None):
+        """Enqueue ``nsteps`` inner steps of multiple time stepping per level
+        (``mls_md_run_mts_levels``): local part + repulsion every step, the
+        level-1 grid part every ``k_mid`` steps, levels 2..l every
+        ``k_mid * k_slow`` steps.  Returns (forces, epot, ekin) with
+        nsteps // (k_mid * k_slow) + 1 energies."""
+        import torch
+        self._check_inputs(pos, c6)
+        n = pos.shape[0]
+        self._check_vec(vel, (n, 3), "vel")
+        self._check_vec(c12, (n,), "c12")
+        self._check_vec(inv_mass, (n,), "inv_mass")
+        rc = self.params.cutoff if rc is None else float(rc)
+        nsteps, k_mid, k_slow = int(nsteps), int(k_mid), int(k_slow)
+        nout = max(nsteps, 0) // max(k_mid * k_slow, 1) + 1
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        if epot is None:
+            epot = torch.empty(nout, dtype=torch.float64, device=self.device)
+        if ekin is None:
+            ekin = torch.empty(nout, dtype=torch.float64, device=self.device)
+        self._check_vec(forces, (n, 3), "forces")
+        self._check_vec(epot, (nout,), "epot")
+        self._check_vec(ekin, (nout,), "ekin")
+        s = (stream if stream is not None else torch.cuda.current_stream(self.device)).cuda_stream
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.mls_md_run_mts_levels(self._plan, n, _ptr(pos), _ptr(vel), _ptr(c6), _ptr(c12),
+                                                       ctypes.c_double(rc), _ptr(inv_mass), ctypes.c_double(dt),
+                                                       nsteps, k_mid, k_slow, _ptr(forces), _ptr(epot), _ptr(ekin),
+                                                       ctypes.c_void_p(s)),
+                       "mls_md_run_mts_levels")
+        return forces, epot, ekin
+
     def copy_stage(self, what, level=1, n=None):
         """Intermediate array of the last evaluation (``mls_plan_copy_stage``)."""
         import torch

@@ -36,7 +36,7 @@ EXPORTS = [
     "mls_batch_set_graph", "mls_batch_get_tuning", "mls_batch_set_tuning", "mls_batch_box_info",
     "mls_batch_status", "mls_batch_destroy", "mls_status_string", "mls_last_error",
     "mls_plan_set_timing", "mls_plan_read_timing", "mls_evaluate_md", "mls_md_run",
-    "mls_md_run_mts", "mls_evaluate_noalloc",
+    "mls_md_run_mts", "mls_evaluate_noalloc", "mls_md_run_mts_levels",
 ]
 
 STAGE_NAMES = ["binning", "pair", "anterpolation", "restriction", "stencil", "coarsest",
@@ -120,6 +120,8 @@ def load():
     lib.mls_evaluate_md.argtypes = [P, i64, dp, dp, dp, dbl, dp, dp, P]
     lib.mls_md_run.argtypes = [P, i64, dp, dp, dp, dp, dbl, dp, dbl, ctypes.c_int, dp, dp, dp, P]
     lib.mls_md_run_mts.argtypes = [P, i64, dp, dp, dp, dp, dbl, dp, dbl, ctypes.c_int, ctypes.c_int, dp, dp, dp, P]
+    lib.mls_md_run_mts_levels.argtypes = [P, i64, dp, dp, dp, dp, dbl, dp, dbl, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, dp, dp, dp, P]
     lib.mls_plan_copy_stage.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, i64, P]
     lib.mls_plan_status.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
     lib.mls_plan_destroy.argtypes = [P]

@@ -234,6 +234,83 @@ hipError_t evaluate_split(mls_plan_t P, int n, const double* pos, const double* 
   return launch_interpolate(P, n, energy, fslow, nullptr, nullptr, s, kInterpGridOnly);
 }
 
+hipError_t ensure_side(mls_plan_s* P) {
+  hipError_t e = hipSuccess;
+  if (!P->side) {
+    if ((e = hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming)) != hipSuccess) return e;
+    e = hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming);
+  }
+  return e;
+}
+
+// Multiple time stepping per level, fast and mid forces at the same
+// positions from one binning: the local part (and repulsion) on stream s, the
+// level-1 grid part (anterpolation and the level-1 stencil; none with one
+// level) on the second stream; *energy = E_fast + E_mid, fmid = the
+// interpolated e^1 forces.
+hipError_t evaluate_fast_mid(mls_plan_s* P, int n, const double* pos, const double* c6, const Repulsion& rep,
+                             double* energy, double* forces, double* fmid, hipStream_t s) {
+  hipError_t e;
+  if (P->levels < 2) {
+    if ((e = evaluate_fast(P, n, pos, c6, rep, energy, forces, s)) != hipSuccess) return e;
+    return launch_zero(fmid, 3 * (int64_t)n, s);
+  }
+  if ((e = ensure_side(P)) != hipSuccess) return e;
+  const hipStream_t g = P->side;
+  if ((e = launch_binning(P, n, pos, c6, s)) != hipSuccess) return e;
+  if ((e = hipEventRecord(P->ev_fork, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(g, P->ev_fork, 0)) != hipSuccess) return e;
+  if ((e = launch_sum_xi(P, n, g)) != hipSuccess) return e;
+  if ((e = launch_anterpolate(P, n, g)) != hipSuccess) return e;
+  if ((e = launch_rep_gather(P, n, rep.c12, s)) != hipSuccess) return e;
+  const PairRep prep{P->d_x12s, P->d_x12f, rep.rc * rep.rc, P->d_frep, P->d_md_partial};
+  bool fused = false;
+  if ((e = launch_pair(P, n, s, &prep, &fused)) != hipSuccess) return e;
+  if (!fused && (e = launch_repulsion(P, n, rep.rc, s)) != hipSuccess) return e;
+  if ((e = launch_stencils(P, g, 1)) != hipSuccess) return e;
+  if ((e = hipEventRecord(P->ev_join, g)) != hipSuccess) return e;
+  if ((e = launch_local_out(P, n, energy, forces, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(s, P->ev_join, 0)) != hipSuccess) return e;
+  return launch_interpolate(P, n, energy, fmid, nullptr, nullptr, s, kInterpGridOnly | kInterpLevel1 | kInterpNoSelf);
+}
+
+// All three classes at the same positions: fast as above; mid = the
+// interpolated e^1 (l >= 2, else zero); slow = the interpolated prolongation
+// of E^2 without e^1 (l = 1: the coarsest level, which is level 1) with the
+// self-energy term.  *energy = E_fast + E_mid + E_slow.
+hipError_t evaluate_split3(mls_plan_s* P, int n, const double* pos, const double* c6, const Repulsion& rep,
+                           double* energy, double* forces, double* fmid, double* fslow, hipStream_t s) {
+  hipError_t e;
+  if ((e = ensure_side(P)) != hipSuccess) return e;
+  const hipStream_t g = P->side;
+  const bool two = P->levels >= 2;
+  if ((e = launch_binning(P, n, pos, c6, s)) != hipSuccess) return e;
+  if ((e = hipEventRecord(P->ev_fork, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(g, P->ev_fork, 0)) != hipSuccess) return e;
+  if ((e = launch_sum_xi(P, n, g)) != hipSuccess) return e;
+  if ((e = launch_anterpolate(P, n, g)) != hipSuccess) return e;
+  if ((e = launch_rep_gather(P, n, rep.c12, s)) != hipSuccess) return e;
+  const PairRep prep{P->d_x12s, P->d_x12f, rep.rc * rep.rc, P->d_frep, P->d_md_partial};
+  bool fused = false;
+  if ((e = launch_pair(P, n, s, &prep, &fused)) != hipSuccess) return e;
+  if (!fused && (e = launch_repulsion(P, n, rep.rc, s)) != hipSuccess) return e;
+  if ((e = launch_restrictions(P, g)) != hipSuccess) return e;
+  if ((e = launch_stencils(P, g)) != hipSuccess) return e;
+  if ((e = launch_coarsest(P, g)) != hipSuccess) return e;
+  if ((e = launch_prolongations(P, g, two)) != hipSuccess) return e;
+  if ((e = hipEventRecord(P->ev_join, g)) != hipSuccess) return e;
+  if ((e = launch_local_out(P, n, energy, forces, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(s, P->ev_join, 0)) != hipSuccess) return e;
+  if (two) {
+    e = launch_interpolate(P, n, energy, fmid, nullptr, nullptr, s, kInterpGridOnly | kInterpLevel1 | kInterpNoSelf);
+  } else {
+    e = launch_zero(fmid, 3 * (int64_t)n, s);
+  }
+  if (e != hipSuccess) return e;
+  return launch_interpolate(P, n, energy, fslow, nullptr, nullptr, s, kInterpGridOnly);
+}
+
 }  // namespace
 
 namespace mls {
@@ -359,6 +436,89 @@ mls_status mls_md_run_mts(mls_plan_t P, int64_t n, double* pos, double* vel, con
           "integrator");
   // the total force at the final positions
   if (ni > 0) HIP_TRY(launch_add_forces(forces, fs, ni, s), "forces");
+  return MLS_OK;
+}
+
+mls_status mls_md_run_mts_levels(mls_plan_t P, int64_t n, double* pos, double* vel, const double* c6,
+                                 const double* c12, double rc, const double* inv_mass, double dt, int nsteps, int k_mid,
+                                 int k_slow, double* forces, double* epot, double* ekin, void* stream) {
+  mls_status st = check_rep(P, n, c12, rc, "mls_md_run_mts_levels");
+  if (st != MLS_OK) return st;
+  if (k_mid < 1 || k_slow < 1 || nsteps < 0 || (int64_t)k_mid * k_slow > (1 << 20) ||
+      nsteps % (k_mid * k_slow) != 0 || !(std::isfinite(dt))) {
+    set_error("mls_md_run_mts_levels: need k_mid, k_slow >= 1, nsteps >= 0 a multiple of k_mid k_slow, finite dt");
+    return MLS_ERR_INVALID_ARG;
+  }
+  if (!epot || !ekin || (n > 0 && (!pos || !vel || !inv_mass || !forces || !c6))) {
+    set_error("mls_md_run_mts_levels: null pos, vel, c6, inv_mass, forces, epot or ekin");
+    return MLS_ERR_INVALID_ARG;
+  }
+  if (n > P->n_max) {
+    set_error("mls_md_run_mts_levels: n = " + std::to_string(n) + " above n_max = " + std::to_string(P->n_max));
+    return MLS_ERR_INVALID_ARG;
+  }
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != P->device) {
+    set_error("mls_md_run_mts_levels: current device differs from the plan's device");
+    return MLS_ERR_INVALID_ARG;
+  }
+  if (P->mixing != MLS_GEOMETRIC) {
+    set_error("mls_md_run_mts_levels: the plan uses Lorentz-Berthelot mixing");
+    return MLS_ERR_INVALID_ARG;
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  P->last_stream = s;
+  P->last_n = n;
+  const int ni = (int)std::max<int64_t>(n, 0);
+  const Repulsion rep{c12, rc};
+  const double hslow = 0.5 * k_mid * k_slow * dt, hmid = 0.5 * k_mid * dt;
+  double* fs = P->d_fslow;
+  double* fm = P->d_fmid;
+  HIP_TRY(evaluate_split3(P, ni, pos, c6, rep, epot, forces, fm, fs, s), "forces");
+  const int nout = nsteps / (k_mid * k_slow);
+  for (int o = 1; o <= nout; ++o) {
+    for (int m = 1; m <= k_slow; ++m) {
+      for (int i = 1; i <= k_mid; ++i) {
+        int mode = kMdStart;
+        double* kin = nullptr;
+        if (i == 1) {
+          // a middle step begins: the end of the previous one (and at an
+          // outer boundary the previous outer step's end, E_kin, and the
+          // slow half-kick of outer step o), then its mid half-kick
+          mode |= kMdMidStart;
+          if (m == 1) {
+            mode |= kMdSlowStart;
+            if (o > 1) mode |= kMdEnd | kMdMidEnd | kMdSlowEnd;
+            kin = ekin + (o - 1);
+          } else {
+            mode |= kMdEnd | kMdMidEnd;
+          }
+        } else {
+          mode |= kMdEnd;
+        }
+        HIP_TRY(launch_md_step(P, ni, pos, vel, forces, inv_mass, dt, mode, kin, s, fs, hslow, fm, hmid),
+                "integrator");
+        hipError_t e;
+        if (i < k_mid) {
+          e = evaluate_fast(P, ni, pos, c6, rep, P->d_efast, forces, s);
+        } else if (m < k_slow) {
+          e = evaluate_fast_mid(P, ni, pos, c6, rep, P->d_efast, forces, fm, s);
+        } else {
+          e = evaluate_split3(P, ni, pos, c6, rep, epot + o, forces, fm, fs, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "forces");
+      }
+    }
+  }
+  HIP_TRY(launch_md_step(P, ni, pos, vel, forces, inv_mass, dt, nout > 0 ? (kMdEnd | kMdMidEnd | kMdSlowEnd) : 0,
+                         ekin + nout, s, fs, hslow, fm, hmid),
+          "integrator");
+  // the total force at the final positions
+  if (ni > 0) {
+    HIP_TRY(launch_add_forces(forces, fm, ni, s), "forces");
+    HIP_TRY(launch_add_forces(forces, fs, ni, s), "forces");
+  }
   return MLS_OK;
 }
 

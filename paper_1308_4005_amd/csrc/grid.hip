@@ -469,8 +469,8 @@ __device__ __forceinline__ void prolong_at(const TransferArgs& a, int M) {
 #pragma unroll
       for (int py = 0; py < 2; ++py) {
         const size_t J = ((size_t)(2 * Z + pz) * f.n[1] + (2 * Y + py)) * f.n[0] + 2 * X;
-        a.dst[J] = a.add[J] + acc[pz][py][0];
-        a.dst[J + 1] = a.add[J + 1] + acc[pz][py][1];
+        a.dst[J] = (a.add ? a.add[J] : 0.0) + acc[pz][py][0];
+        a.dst[J + 1] = (a.add ? a.add[J + 1] : 0.0) + acc[pz][py][1];
       }
 }
 
@@ -848,9 +848,18 @@ hipError_t launch_restrictions(mls_plan_s* P, hipStream_t s) {
   return hipSuccess;
 }
 
-hipError_t launch_prolongations(mls_plan_s* P, hipStream_t s) {
+hipError_t launch_prolongations(mls_plan_s* P, hipStream_t s, bool drop_e1) {
   for (int k = P->levels - 1; k >= 1; --k) {
-    hipError_t e = launch_prolong(P, k, s);
+    hipError_t e;
+    if (k == 1 && drop_e1) {
+      Level& F = P->lv[0];
+      Level& C = P->lv[1];
+      TransferArgs a{C.E, C.g, nullptr, F.E, F.g};
+      e = P->order == 4 ? launch_one<Prolong<4>>(a, nblocks(C.g.size, kBlock), s)
+                        : launch_one<Prolong<6>>(a, nblocks(C.g.size, kBlock), s);
+    } else {
+      e = launch_prolong(P, k, s);
+    }
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -877,8 +886,8 @@ hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forc
   const bool with_repulsion = (mode & kInterpRep) != 0;
   const int nb = nblocks(n, kBlock);
   if (n > 0) {
-    InterpArgs a{P->d_xs, P->d_perm, n, finest_geom(P), P->lv[0].E, P->d_e0, P->d_floc, P->cself,
-                 OutPtrs{forces, potential, dE_dc6}, P->d_partial};
+    InterpArgs a{P->d_xs, P->d_perm, n, finest_geom(P), (mode & kInterpLevel1) ? P->lv[0].e : P->lv[0].E,
+                 P->d_e0, P->d_floc, P->cself, OutPtrs{forces, potential, dE_dc6}, P->d_partial};
     if (with_repulsion) a.frep = P->d_frep;
     a.grid_only = (mode & kInterpGridOnly) ? 1 : 0;
     const bool mixed = P->precision == MLS_MIXED;
@@ -890,7 +899,7 @@ hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forc
     if (e != hipSuccess) return e;
   }
   // no atoms: an empty sum, E = 0
-  EnergyArgs ea{P->d_partial, nb, P->cself, energy};
+  EnergyArgs ea{P->d_partial, nb, (mode & kInterpNoSelf) ? 0.0 : P->cself, energy};
   if (with_repulsion) {
     ea.rep_partial = P->d_md_partial;
     ea.rep_nb = n > 0 ? P->rep_nb : 0;

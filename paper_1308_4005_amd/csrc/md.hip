@@ -160,7 +160,9 @@ struct RepPair {
 // kinetic energy of the resulting v is summed per block; with START the
 // first half-kick of the next step and the drift x += dt v follow.  Multiple
 // time stepping adds the slow force's half-kicks of its outer step, after the
-// fast END kick (SLOW_END) and before the fast START kick (SLOW_START).
+// fast END kick (SLOW_END) and before the fast START kick (SLOW_START), and
+// with three time scales the mid force's half-kicks of its middle step
+// (MID_END, MID_START) between them.
 struct MdStep {
   using Args = MdStepArgs;
   static constexpr int kThreads = kBlock;
@@ -180,18 +182,22 @@ struct MdStep {
       if (bad) atomicOr(a.flags, 8);
       if (a.mode & kMdEnd)
         for (int d = 0; d < 3; ++d) v[d] = v[d] + a.hdt * f[d] * im;
+      if (a.mode & kMdMidEnd)
+        for (int d = 0; d < 3; ++d) v[d] = v[d] + a.hmid * a.fmid[3 * (size_t)i + d] * im;
       if (a.mode & kMdSlowEnd)
         for (int d = 0; d < 3; ++d) v[d] = v[d] + a.hslow * a.fslow[3 * (size_t)i + d] * im;
       k = (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / im;
       if (a.mode & kMdSlowStart)
         for (int d = 0; d < 3; ++d) v[d] = v[d] + a.hslow * a.fslow[3 * (size_t)i + d] * im;
+      if (a.mode & kMdMidStart)
+        for (int d = 0; d < 3; ++d) v[d] = v[d] + a.hmid * a.fmid[3 * (size_t)i + d] * im;
       if (a.mode & kMdStart) {
         for (int d = 0; d < 3; ++d) {
           v[d] = v[d] + a.hdt * f[d] * im;
           a.pos[3 * (size_t)i + d] = a.pos[3 * (size_t)i + d] + a.dt * v[d];
         }
       }
-      if (a.mode & (kMdEnd | kMdStart | kMdSlowEnd | kMdSlowStart))
+      if (a.mode & (kMdEnd | kMdStart | kMdSlowEnd | kMdSlowStart | kMdMidEnd | kMdMidStart))
         for (int d = 0; d < 3; ++d) a.vel[3 * (size_t)i + d] = v[d];
     }
     const double t = block_sum(k, sh);
@@ -282,10 +288,10 @@ hipError_t launch_repulsion(mls_plan_s* P, int n, double rc, hipStream_t s) {
 
 hipError_t launch_md_step(mls_plan_s* P, int n, double* pos, double* vel, const double* forces,
                           const double* inv_mass, double dt, int mode, double* kinetic, hipStream_t s,
-                          const double* fslow, double hslow) {
+                          const double* fslow, double hslow, const double* fmid, double hmid) {
   double* part = P->d_md_partial + P->rep_cap;
   if (n > 0) {
-    MdStepArgs ma{pos, vel, forces, inv_mass, n, 0.5 * dt, dt, mode, part, P->d_flags, fslow, hslow};
+    MdStepArgs ma{pos, vel, forces, inv_mass, n, 0.5 * dt, dt, mode, part, P->d_flags, fslow, hslow, fmid, hmid};
     hipError_t e = launch_one<MdStep>(ma, nblocks(n, kBlock), s);
     if (e != hipSuccess) return e;
   }

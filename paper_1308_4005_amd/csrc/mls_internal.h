@@ -117,12 +117,14 @@ struct RepPairArgs {
   const double4* xs; const double* x12s; const int* cell_s; const int* cell_start; CellGeom g;
   int nr[3]; double rc2; int n; double* frep; double* partial;
 };
-constexpr int kMdEnd = 1, kMdStart = 2, kMdSlowEnd = 4, kMdSlowStart = 8;
+constexpr int kMdEnd = 1, kMdStart = 2, kMdSlowEnd = 4, kMdSlowStart = 8, kMdMidEnd = 16, kMdMidStart = 32;
 struct MdStepArgs {
   double* pos; double* vel; const double* forces; const double* inv_mass; int n;
   double hdt, dt; int mode; double* partial; int* flags;
   const double* fslow = nullptr;   // multiple time stepping: slow forces and their half-kick factor
   double hslow = 0.0;
+  const double* fmid = nullptr;    // three time scales: the level-1 grid forces and their factor
+  double hmid = 0.0;
 };
 struct LocalOutArgs {
   const double4* xs; const int* perm; int n; const double* e0; const double* floc; const double* frep;
@@ -373,6 +375,7 @@ struct mls_plan_s {
   double* d_md_partial = nullptr;  // geometric mixing: repulsion energy (rep_cap), kinetic and local-energy
                                    // (n_partial each) block sums
   double* d_fslow = nullptr;       // geometric mixing: grid-part forces of multiple time stepping (n_max,3)
+  double* d_fmid = nullptr;        // multiple time stepping per level: the level-1 grid forces (n_max,3)
   double* d_efast = nullptr;       // geometric mixing: energy of an inner step's fast evaluation
   bool ant_tiles = false;          // two-phase anterpolation tables built
   mls::AntTiles ant{};
@@ -437,16 +440,21 @@ hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s, const PairRep* rep =
 hipError_t launch_scan(mls_plan_s* P, int* count, int m, int* start, hipStream_t s);
 hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s);
 hipError_t launch_restrict(mls_plan_s* P, int k_fine, hipStream_t s);
-hipError_t launch_stencils(mls_plan_s* P, hipStream_t s);
+// Level stencils of levels 1..kmax (kmax = 0: all levels below the coarsest).
+hipError_t launch_stencils(mls_plan_s* P, hipStream_t s, int kmax = 0);
 int stencil_path(const mls_plan_s* P);   // mls_stencil_path of the plan
 hipError_t launch_coarsest(mls_plan_s* P, hipStream_t s);
 hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s);
 // All restrictions (levels 2..l) and all prolongations (l-1..1) of an evaluation.
 hipError_t launch_restrictions(mls_plan_s* P, hipStream_t s);
-hipError_t launch_prolongations(mls_plan_s* P, hipStream_t s);
+// drop_e1: the last prolongation writes E^1 = prolongated E^2 without e^1
+// (the levels 2..l part of multiple time stepping per level)
+hipError_t launch_prolongations(mls_plan_s* P, hipStream_t s, bool drop_e1 = false);
 // mode: 0 the full evaluation, kInterpRep with the repulsion of the MD entry
 // points, kInterpGridOnly the grid part alone (energy added to *energy)
-constexpr int kInterpRep = 1, kInterpGridOnly = 2;
+// kInterpLevel1: interpolate e^1 (the level-1 stencil alone) instead of E^1;
+// kInterpNoSelf: leave the self-energy term out of the energy
+constexpr int kInterpRep = 1, kInterpGridOnly = 2, kInterpLevel1 = 4, kInterpNoSelf = 8;
 hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forces,
                               double* potential, double* dE_dc6, hipStream_t s, int mode = 0);
 // Lorentz-Berthelot pieces: sorted sigma and flags, the sorted charges of
@@ -468,7 +476,8 @@ hipError_t launch_rep_gather(mls_plan_s* P, int n, const double* c12, hipStream_
 hipError_t launch_repulsion(mls_plan_s* P, int n, double rc, hipStream_t s);
 hipError_t launch_md_step(mls_plan_s* P, int n, double* pos, double* vel, const double* forces,
                           const double* inv_mass, double dt, int mode, double* kinetic, hipStream_t s,
-                          const double* fslow = nullptr, double hslow = 0.0);
+                          const double* fslow = nullptr, double hslow = 0.0, const double* fmid = nullptr,
+                          double hmid = 0.0);
 // the local part alone as MD's fast force: forces = local + repulsive forces,
 // *energy = local + repulsive energy; forces += add
 hipError_t launch_local_out(mls_plan_s* P, int n, double* energy, double* forces, hipStream_t s);

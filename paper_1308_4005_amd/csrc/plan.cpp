@@ -426,6 +426,7 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
     P->rep_cap = (int)((N + 63) / 64);   // one sum per wave of the pair kernels
     ALLOC(P->d_md_partial, (size_t)P->rep_cap + 2 * (size_t)P->n_partial);
     ALLOC(P->d_fslow, 3 * N);
+    ALLOC(P->d_fmid, 3 * N);
     ALLOC(P->d_efast, 1);
   }
   if (P->mixing == MLS_LORENTZ_BERTHELOT) {

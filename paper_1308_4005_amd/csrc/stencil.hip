@@ -377,7 +377,7 @@ int stencil_window(const mls_plan_s* P) {
 }
 
 template <class T, int R>
-hipError_t launch_tile(mls_plan_s* P, const T* wts, hipStream_t s) {
+hipError_t launch_tile(mls_plan_s* P, const T* wts, hipStream_t s, int kmax) {
   constexpr int kTileZ = tile_zc(R, sizeof(T) == 8);
   StencilLaunch L{};
   L.nlev = P->levels - 1;
@@ -398,31 +398,33 @@ hipError_t launch_tile(mls_plan_s* P, const T* wts, hipStream_t s) {
     V.sum_xi = P->d_scratch;
     V.wsum = P->taps_wsum;
     t += nblocks(Lv.g.n[0], 8) * nblocks(Lv.g.n[1], 8) * V.tiles_z;
+    // the tile table lists the levels in order: levels 1..kmax are its head
+    if (k == kmax) break;
   }
   k_stencil_tile<T, R, kTileZ, kStencilWaves><<<t, 64 * kStencilWaves, 0, s>>>(L, P->d_tiles);
   return hipGetLastError();
 }
 
-hipError_t launch_tile_f64(mls_plan_s* P, int R, hipStream_t s) {
+hipError_t launch_tile_f64(mls_plan_s* P, int R, hipStream_t s, int kmax) {
   const double* w = P->d_row_w_tile;
   switch (R) {
-    case 1: case 2: case 3: case 4: return launch_tile<double, 4>(P, w, s);
-    case 5: case 6: return launch_tile<double, 6>(P, w, s);
-    case 7: case 8: return launch_tile<double, 8>(P, w, s);
+    case 1: case 2: case 3: case 4: return launch_tile<double, 4>(P, w, s, kmax);
+    case 5: case 6: return launch_tile<double, 6>(P, w, s, kmax);
+    case 7: case 8: return launch_tile<double, 8>(P, w, s, kmax);
     default: return hipErrorInvalidValue;
   }
 }
 
 // FP32 tiles reach R = 12: (8 + 2R)^2 (8 + 2R) floats, 88 KB at R = 10 and
 // 128 KB at R = 12 (one block per CU; an FP64 tile of that size does not fit)
-hipError_t launch_tile_f32(mls_plan_s* P, int R, hipStream_t s) {
+hipError_t launch_tile_f32(mls_plan_s* P, int R, hipStream_t s, int kmax) {
   const float* w = P->d_row_wf_tile;
   switch (R) {
-    case 1: case 2: case 3: case 4: return launch_tile<float, 4>(P, w, s);
-    case 5: case 6: return launch_tile<float, 6>(P, w, s);
-    case 7: case 8: return launch_tile<float, 8>(P, w, s);
-    case 9: case 10: return launch_tile<float, 10>(P, w, s);
-    case 11: case 12: return launch_tile<float, 12>(P, w, s);
+    case 1: case 2: case 3: case 4: return launch_tile<float, 4>(P, w, s, kmax);
+    case 5: case 6: return launch_tile<float, 6>(P, w, s, kmax);
+    case 7: case 8: return launch_tile<float, 8>(P, w, s, kmax);
+    case 9: case 10: return launch_tile<float, 10>(P, w, s, kmax);
+    case 11: case 12: return launch_tile<float, 12>(P, w, s, kmax);
     default: return hipErrorInvalidValue;
   }
 }
@@ -436,14 +438,15 @@ int stencil_path(const mls_plan_s* P) {
   return MLS_STENCIL_TAPS_F64;
 }
 
-hipError_t launch_stencils(mls_plan_s* P, hipStream_t s) {
+hipError_t launch_stencils(mls_plan_s* P, hipStream_t s, int kmax) {
   if (P->levels < 2) return hipSuccess;
+  if (kmax <= 0 || kmax > P->levels - 1) kmax = P->levels - 1;
   const int R = stencil_window(P);
   const int path = stencil_path(P);
-  if (path == MLS_STENCIL_TILE_F32) return launch_tile_f32(P, R, s);
-  if (path == MLS_STENCIL_TILE_F64) return launch_tile_f64(P, R, s);
+  if (path == MLS_STENCIL_TILE_F32) return launch_tile_f32(P, R, s, kmax);
+  if (path == MLS_STENCIL_TILE_F64) return launch_tile_f64(P, R, s, kmax);
   const int ntaps = (int)P->taps.size();
-  for (int k = 1; k < P->levels; ++k) {
+  for (int k = 1; k <= kmax; ++k) {
     Level& L = P->lv[k - 1];
     const double scale = std::ldexp(1.0, -6 * (k - 1));
     hipError_t e;
