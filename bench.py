@@ -348,6 +348,22 @@ def time_md(w, prm, precision, steps, warmup, dev, blocks, chunk=50, dt=0.001):
     flags |= plan.status()
     totl = (epl + ekl).cpu().numpy()
     plan.close()
+    # neighbour reuse: velocity Verlet with plans that keep one binning while
+    # no atom has moved more than skin/2 (0.07 keeps the 70 half-cells per
+    # side of the 10^6-atom cube, 0.3 widens them), same trajectory start
+    reuse = {}
+    for skin in (0.07, 0.3):
+        rp = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], precision=precision, n_max=w.n,
+                  device=dev.index, skin=skin)
+        xr_ = torch.tensor(w.pos, dtype=torch.float64, device=dev)
+        vr_ = torch.tensor(rng.normal(scale=np.sqrt(0.8), size=(w.n, 3)), dtype=torch.float64, device=dev)
+        ms_r, block_r = time_graph(lambda: rp.md_run(xr_, vr_, c6, c12, im, dt, chunk, forces=F, epot=ep, ekin=ek),
+                                   max(blocks, steps // chunk), max(1, warmup // chunk), blocks, dev)
+        torch.cuda.synchronize()
+        flags |= rp.status()
+        reuse[str(skin)] = {"ms_per_step": ms_r / chunk, "steps_per_s": 1000.0 * chunk / ms_r,
+                            "cells": list(rp.info["cells"]), "block_ms_per_step": [b / chunk for b in block_r]}
+        rp.close()
     return {"workload": f"{w.name} positions, LJ C6 = C12 = 4, unit masses, velocities N(0, 0.8) (seed 29), "
                         f"repulsion cutoff {prm['a']}, dt {dt}",
             "precision": precision, "ms_per_step": ms / chunk, "steps_per_s": 1000.0 * chunk / ms,
@@ -358,6 +374,9 @@ def time_md(w, prm, precision, steps, warmup, dev, blocks, chunk=50, dt=0.001):
                 "k_slow": k_slow, "ms_per_step": ms_m / chunk_m, "steps_per_s": 1000.0 * chunk_m / ms_m,
                 "block_ms_per_step": [b / chunk_m for b in block_m], "steps_per_replay": chunk_m,
                 "last_replay_total_energy_spread_rel": float((totm.max() - totm.min()) / abs(totm.mean()))},
+            "neighbour_reuse": {"note": "mls_md_run with a skin: binning kept while no atom moved more than "
+                                        "skin/2, checked every step", "by_skin": reuse,
+                                "without_skin_ms_per_step": ms / chunk},
             "multiple_time_stepping_per_level": {
                 "k_mid": k_mid, "k_slow": k_sl, "ms_per_step": ms_l / chunk_m, "steps_per_s": 1000.0 * chunk_m / ms_l,
                 "block_ms_per_step": [b / chunk_m for b in block_l], "steps_per_replay": chunk_m,
@@ -642,7 +661,8 @@ def main():
         md = time_md(w, prm, head, args.steps, args.warmup, dev, args.blocks)
         log(f"[bench] md: {md['ms_per_step']:.3f} ms/step, evaluate_md {md['evaluate_md_ms']:.3f} ms, "
             f"multiple time stepping (k=4) {md['multiple_time_stepping']['ms_per_step']:.3f} ms/step, per level "
-            f"(2, 2) {md['multiple_time_stepping_per_level']['ms_per_step']:.3f} ms/step")
+            f"(2, 2) {md['multiple_time_stepping_per_level']['ms_per_step']:.3f} ms/step, neighbour reuse "
+            f"{json.dumps({k: round(v['ms_per_step'], 4) for k, v in md['neighbour_reuse']['by_skin'].items()})}")
 
     selection = None
     if not args.no_select:

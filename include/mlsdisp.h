@@ -90,6 +90,16 @@ typedef struct {
   int mixing;     /* mls_mixing: MLS_GEOMETRIC (per-atom C6, mls_evaluate) or
                      MLS_LORENTZ_BERTHELOT (per-atom epsilon and sigma,
                      mls_evaluate_lb; FP64 plans only) */
+  double skin;    /* >= 0, below a (0: none).  Linked cells at least (a + skin)/2
+                     wide (a + skin where the box is narrow) and every cell
+                     search widened by skin/2, so the sorted atoms and cells
+                     of one binning stay valid while no atom has moved more
+                     than skin/2: mls_md_run then bins again only when an
+                     atom has moved that far since the last binning (checked
+                     on the device every step) and otherwise re-gathers the
+                     new positions through the stored order.  Other entry
+                     points bin on every call.  Results do not depend on the
+                     skin beyond rounding. */
 } mls_params;
 
 /* Resolved plan geometry (host struct filled by mls_plan_get_info). */

@@ -32,8 +32,9 @@ def precision_code(precision) -> int:
     raise ValueError(f"unknown precision {precision!r}")
 
 
-def _params(box, cutoff, h, order, levels, grid, precision, continuity=2, mixing=0):
+def _params(box, cutoff, h, order, levels, grid, precision, continuity=2, mixing=0, skin=0.0):
     p = _lib.MLSParams()
+    p.skin = float(skin)
     for d in range(3):
         p.box[d] = float(box[d])
         p.grid[d] = int(grid[d]) if grid is not None else 0
@@ -64,11 +65,11 @@ class Plan:
     """A resolved MLS setup for one periodic box (``mls_plan_create``)."""
 
     def __init__(self, box, cutoff, h=1.0, order=4, levels=0, grid=None, precision="fp64",
-                 n_max=0, device=None, continuity=2, mixing="geometric"):
+                 n_max=0, device=None, continuity=2, mixing="geometric", skin=0.0):
         import torch
         self._lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        self.params = _params(box, cutoff, h, order, levels, grid, precision, continuity, mixing)
+        self.params = _params(box, cutoff, h, order, levels, grid, precision, continuity, mixing, skin)
         self._plan = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(self._lib.mls_plan_create(ctypes.byref(self.params), int(n_max),

@@ -54,6 +54,7 @@ class MLSParams(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("continuity", ctypes.c_int),
         ("mixing", ctypes.c_int),
+        ("skin", ctypes.c_double),
     ]
 
 

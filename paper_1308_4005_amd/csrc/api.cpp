@@ -98,9 +98,13 @@ struct Repulsion {
 
 // mls_evaluate, optionally with the repulsion (rep non-null) run after the
 // local part on the caller's stream and added in the interpolation.
+// binning of an evaluation: a fresh one, one that records the positions
+// (first step of an MD run with neighbour reuse), or the reuse check
+enum { kBinFresh = 0, kBinRecord = 1, kBinReuse = 2 };
+
 mls_status evaluate_geometric(mls_plan_t P, int64_t n, const double* pos, const double* c6, double* energy,
                               double* forces, double* potential, double* dE_dc6, void* stream,
-                              const Repulsion* rep) {
+                              const Repulsion* rep, int binmode = kBinFresh) {
   if (!P) { set_error("mls_evaluate: null plan"); return MLS_ERR_INVALID_ARG; }
   if (n < 0 || n > P->n_max) {
     set_error("mls_evaluate: n = " + std::to_string(n) + " outside [0, n_max = " + std::to_string(P->n_max) + "]");
@@ -139,7 +143,13 @@ mls_status evaluate_geometric(mls_plan_t P, int64_t n, const double* pos, const 
   }
   const hipStream_t g = fork ? P->side : s;
   HIP_TRY(mark(0), "timing event");
-  HIP_TRY(launch_binning(P, ni, pos, c6, s), "binning");
+  if (binmode == kBinRecord) {
+    HIP_TRY(launch_binning_ref(P, ni, pos, c6, s), "binning");
+  } else if (binmode == kBinReuse) {
+    HIP_TRY(launch_binning_reuse(P, ni, pos, c6, s), "binning");
+  } else {
+    HIP_TRY(launch_binning(P, ni, pos, c6, s), "binning");
+  }
   HIP_TRY(mark(1 + MLS_T_BINNING), "timing event");
   if (fork) {
     HIP_TRY(hipEventRecord(P->ev_fork, s), "fork");
@@ -358,13 +368,19 @@ mls_status mls_md_run(mls_plan_t P, int64_t n, double* pos, double* vel, const d
   const Repulsion rep{c12, rc};
   const hipStream_t s = (hipStream_t)stream;
   const int ni = (int)std::min<int64_t>(std::max<int64_t>(n, 0), P->n_max);
-  if ((st = evaluate_geometric(P, n, pos, c6, epot, forces, nullptr, nullptr, stream, &rep)) != MLS_OK) return st;
+  // with a skin the binning of the first evaluation is kept while no atom
+  // has moved more than skin/2 since (checked on the device every step)
+  const bool reuse = P->skin > 0.0;
+  if ((st = evaluate_geometric(P, n, pos, c6, epot, forces, nullptr, nullptr, stream, &rep,
+                               reuse ? kBinRecord : kBinFresh)) != MLS_OK)
+    return st;
   for (int k = 1; k <= nsteps; ++k) {
     // end of step k-1 (k > 1): second half-kick, E_kin(k-1); step k: first
     // half-kick and drift
     const int mode = (k > 1 ? kMdEnd : 0) | kMdStart;
     HIP_TRY(launch_md_step(P, ni, pos, vel, forces, inv_mass, dt, mode, ekin + (k - 1), s), "integrator");
-    if ((st = evaluate_geometric(P, n, pos, c6, epot + k, forces, nullptr, nullptr, stream, &rep)) != MLS_OK)
+    if ((st = evaluate_geometric(P, n, pos, c6, epot + k, forces, nullptr, nullptr, stream, &rep,
+                                 reuse ? kBinReuse : kBinFresh)) != MLS_OK)
       return st;
   }
   HIP_TRY(launch_md_step(P, ni, pos, vel, forces, inv_mass, dt, nsteps > 0 ? kMdEnd : 0, ekin + nsteps, s),

@@ -67,10 +67,13 @@ struct BinCount {
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int blk) {
     __shared__ double sh[kBlock];
+    if (a.cond && *a.cond == 0) return;   // neighbour reuse: no binning this time
     const int i = blk * kBlock + threadIdx.x;
     double xi = 0.0;
     if (i < a.n) {
       const CellGeom& g = a.g;
+      if (a.xref)
+        for (int d = 0; d < 3; ++d) a.xref[3 * (size_t)i + d] = a.pos[3 * (size_t)i + d];
       int bad;
       const double4 p = wrapped_atom(a.pos, a.c6, i, g, a.c6_scale, bad);
       if (bad) atomicOr(a.flags, bad);
@@ -134,6 +137,7 @@ struct ScanBlocks {
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int blk) {
     __shared__ int sh[kBlock];
+    if (a.cond && *a.cond == 0) return;
     const int base = blk * kScanItems + threadIdx.x * kScanPer;
     int v[kScanPer];
     int sum = 0, mx = 0;
@@ -169,6 +173,7 @@ struct ScanSums {
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int) {
     __shared__ int sh[kBlock];
+    if (a.cond && *a.cond == 0) return;
     const int nb = (a.m + kScanItems - 1) / kScanItems;
     int carry = 0, mx = 0;
     for (int b0 = 0; b0 < nb; b0 += kBlock) {
@@ -193,6 +198,7 @@ struct ScanAdd {
   using Args = ScanArgs;
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int blk) {
+    if (a.cond && *a.cond == 0) return;
     const int c = blk * kBlock + threadIdx.x;
     if (c < a.m) a.start[c] += a.bsum[c / kScanItems];
   }
@@ -202,6 +208,7 @@ struct BinScatter {
   using Args = ScatterArgs;
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int blk) {
+    if (a.cond && *a.cond == 0) return;
     const int i = blk * kBlock + threadIdx.x;
     if (i >= a.n) return;
     const int c = a.cid[i];
@@ -230,6 +237,7 @@ struct RankGather {
   using Args = RankGatherArgs;
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int blk) {
+    if (a.cond && *a.cond == 0) return;
     const int s = blk * kBlock + threadIdx.x;
     if (s < a.n) {
       const int2 vc = a.perm_tmp[s];
@@ -262,6 +270,59 @@ struct RankGather {
         a.xif[s] = 0.0f;
       }
     }
+  }
+};
+
+// Neighbour reuse: *cond = 1 when some atom has moved more than skin/2
+// since the positions of the last binning (or a position is not finite).
+struct DispCheck {
+  using Args = DispCheckArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    const int i = blk * kBlock + threadIdx.x;
+    bool far = false;
+    if (i < a.n) {
+      double d2 = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        const double u = a.pos[3 * (size_t)i + d] - a.xref[3 * (size_t)i + d];
+        d2 += u * u;
+      }
+      far = !(d2 <= a.lim2);
+    }
+    if (__any(far) && (threadIdx.x & 63) == 0) atomicOr(a.cond, 1);
+  }
+};
+
+// Neighbour reuse without a binning (*cond == 0): the atom in sorted slot s
+// keeps its cell; its new position is stored as the cell centre plus the
+// periodic image of its offset from the centre nearest to the centre, so it
+// lies within skin/2 of its cell (positions may leave [0, L) by as much).
+// The image is unique: the atom is within w/2 + skin/2 < L/2 of the centre
+// (cells at least a + skin wide when there are fewer than five per side, at
+// least (a + skin)/2 otherwise; one cell per side is the whole box).
+struct Regather {
+  using Args = RegatherArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    if (*a.cond != 0) return;
+    const int s = blk * kBlock + threadIdx.x;
+    if (s >= a.n) return;
+    const CellGeom& g = a.g;
+    const int i = a.perm[s], c = a.cell_s[s];
+    const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
+    const int cc[3] = {cx, cy, cz};
+    double x[3], r[3];
+    for (int d = 0; d < 3; ++d) {
+      const double corner = cc[d] * g.w[d];
+      const double centre = corner + 0.5 * g.w[d];
+      double rel = a.pos[3 * (size_t)i + d] - centre;
+      rel -= g.L[d] * rint(rel * g.invL[d]);
+      x[d] = centre + rel;
+      r[d] = x[d] - corner;
+    }
+    const double w = a.xs[s].w;
+    a.xs[s] = make_double4(x[0], x[1], x[2], w);
+    if (a.xr) a.xr[s] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)cx);
   }
 };
 
@@ -417,8 +478,10 @@ hipError_t launch_lb_charge(mls_plan_s* P, int n, int k, hipStream_t s) {
   return launch_one<LbCharge>(LbChargeArgs{P->d_xs, P->d_sig, n, k, P->d_charge}, nblocks(n + kSortedPad, kBlock), s);
 }
 
-hipError_t launch_binning_scaled(mls_plan_s* P, int n, const double* pos, const double* c6, double scale,
-                                 hipStream_t s) {
+// The binning kernels; with `cond` they all do nothing when *cond == 0, and
+// with `xref` the count kernel records the positions.
+static hipError_t binning_core(mls_plan_s* P, int n, const double* pos, const double* c6, double scale,
+                               const int* cond, double* xref, hipStream_t s) {
   // The cell counts start at zero: cleared once at plan creation, then by
   // every scan after it has read them.
   const CellGeom& g = P->cg;
@@ -426,17 +489,43 @@ hipError_t launch_binning_scaled(mls_plan_s* P, int n, const double* pos, const 
   hipError_t e;
   if (n > 0) {
     BinCountArgs a{pos, c6, n, g, P->d_cid, P->d_slot, P->d_count, P->d_xw, P->d_flags, scale,
-                   mixed ? P->d_partial : nullptr};
+                   mixed ? P->d_partial : nullptr, cond, xref};
     if ((e = launch_one<BinCount>(a, nblocks(n, kBlock), s)) != hipSuccess) return e;
   }
-  if ((e = launch_scan(P, P->d_count, g.ncell, P->d_cell_start, s)) != hipSuccess) return e;
+  ScanArgs sa{P->d_count, g.ncell, P->d_cell_start, P->d_bsum, P->d_bmax, P->d_ncell_max, cond};
+  if ((e = launch_one<ScanBlocks>(sa, scan_blocks(g.ncell), s)) != hipSuccess) return e;
+  if ((e = launch_one<ScanSums>(sa, 1, s)) != hipSuccess) return e;
+  if ((e = launch_one<ScanAdd>(sa, nblocks(g.ncell, kBlock), s)) != hipSuccess) return e;
   if (n == 0) return hipSuccess;
-  if ((e = launch_one<BinScatter>(ScatterArgs{P->d_cid, P->d_slot, n, P->d_cell_start, P->d_perm_tmp},
+  if ((e = launch_one<BinScatter>(ScatterArgs{P->d_cid, P->d_slot, n, P->d_cell_start, P->d_perm_tmp, cond},
                                   nblocks(n, kBlock), s)) != hipSuccess)
     return e;
   RankGatherArgs ra{P->d_cell_start, P->d_perm_tmp, n, P->d_perm, P->d_xw, P->d_xs, P->d_cell_s, P->d_xr,
-                    P->d_xif, g};
+                    P->d_xif, g, cond};
   return launch_one<RankGather>(ra, nblocks(n + kSortedPad, kBlock), s);
+}
+
+hipError_t launch_binning_scaled(mls_plan_s* P, int n, const double* pos, const double* c6, double scale,
+                                 hipStream_t s) {
+  return binning_core(P, n, pos, c6, scale, nullptr, nullptr, s);
+}
+
+hipError_t launch_binning_ref(mls_plan_s* P, int n, const double* pos, const double* c6, hipStream_t s) {
+  return binning_core(P, n, pos, c6, 1.0, nullptr, P->d_xref, s);
+}
+
+hipError_t launch_binning_reuse(mls_plan_s* P, int n, const double* pos, const double* c6, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_one<FillI>(FillArgs{P->d_rebin, 1}, 1, s)) != hipSuccess) return e;
+  if (n > 0) {
+    const double half = 0.5 * P->skin;
+    DispCheckArgs da{pos, P->d_xref, n, half * half, P->d_rebin};
+    if ((e = launch_one<DispCheck>(da, nblocks(n, kBlock), s)) != hipSuccess) return e;
+  }
+  if ((e = binning_core(P, n, pos, c6, 1.0, P->d_rebin, P->d_xref, s)) != hipSuccess) return e;
+  if (n == 0) return hipSuccess;
+  RegatherArgs ra{pos, P->d_perm, P->d_cell_s, n, P->cg, P->d_rebin, P->d_xs, P->d_xr};
+  return launch_one<Regather>(ra, nblocks(n, kBlock), s);
 }
 
 hipError_t launch_sum_xi(mls_plan_s* P, int n, hipStream_t s) {

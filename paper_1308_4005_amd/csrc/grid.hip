@@ -735,8 +735,10 @@ bool anterp_owned_geom(const mls_plan_s* P, AntGeom& ag) {
     if (cb == 0) return false;
     ag.cb[d] = cb;
     ag.nb[d] = (nc + cb - 1) / cb;
-    // atoms within (half + 1) grid spacings of the owned range
-    ag.nh[d] = (int)(((int64_t)(half + 1) * nc + n - 1) / n);
+    // atoms within (half + 1) grid spacings of the owned range, plus the
+    // skin margin by which an atom may sit outside its cell
+    const double hw = P->cg.L[d] / n;
+    ag.nh[d] = (int)std::ceil(((half + 1) * hw + P->cg.margin) / P->cg.w[d] - 1e-12);
     const int span = cb + 2 * ag.nh[d];
     // rows along x split at every periodic wrap
     segs *= (d == 0 ? std::min(span, (span + nc - 1) / nc + 1) : span);
@@ -759,7 +761,9 @@ bool ant_tiles_build(const mls_plan_s* P, AntTiles& T, std::vector<int>& tab, si
       for (int b = 0; b < nb; ++b) {
         // finest points reached by atoms with c0 w <= x < c1 w: floor(x/h) in
         // [lo, hi], taps floor(x/h) - (p/2 - 1) .. floor(x/h) + p/2
-        const double t0 = c[d][b] * cg.w[d] * gg.invh[d], t1 = c[d][b + 1] * cg.w[d] * gg.invh[d];
+        // (widened by the skin margin: atoms may sit that far outside their cells)
+        const double t0 = (c[d][b] * cg.w[d] - cg.margin) * gg.invh[d];
+        const double t1 = (c[d][b + 1] * cg.w[d] + cg.margin) * gg.invh[d];
         const int lo = (int)std::floor(t0 - 1e-7), hi = (int)std::floor(t1 + 1e-7);
         e[d].push_back(lo - (half - 1));
         len[d].push_back(hi - lo + P->order);

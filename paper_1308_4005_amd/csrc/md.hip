@@ -96,7 +96,9 @@ struct RepPair {
       const int cx = c % g.nc[0];
       const int cy = (c / g.nc[0]) % g.nc[1];
       const int cz = c / (g.nc[0] * g.nc[1]);
-      const double my = 1e-6 * g.w[1], mz = 1e-6 * g.w[2], mx = 1e-6 * g.w[0];
+      // margins above the cell rounding, plus how far atoms may sit outside
+      // their cells (the skin margin of neighbour reuse)
+      const double my = 1e-6 * g.w[1] + g.margin, mz = 1e-6 * g.w[2] + g.margin, mx = 1e-6 * g.w[0] + g.margin;
       for (int dz = -a.nr[2]; dz <= a.nr[2]; ++dz) {
         const int uz = cz + dz;  // unwrapped cell index
         const double gz = fmax(0.0, fmax(uz * g.w[2] - p.z, p.z - (uz + 1) * g.w[2]) - mz);
@@ -277,7 +279,7 @@ hipError_t launch_repulsion(mls_plan_s* P, int n, double rc, hipStream_t s) {
   ra.cell_s = P->d_cell_s;
   ra.cell_start = P->d_cell_start;
   ra.g = P->cg;
-  for (int d = 0; d < 3; ++d) ra.nr[d] = (int)std::ceil(rc * P->cg.inv_w[d]);
+  for (int d = 0; d < 3; ++d) ra.nr[d] = (int)std::ceil((rc + 2.0 * P->cg.margin) * P->cg.inv_w[d]);
   ra.rc2 = rc * rc;
   ra.n = n;
   ra.frep = P->d_frep;

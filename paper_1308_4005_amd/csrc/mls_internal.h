@@ -22,8 +22,9 @@ struct CellGeom {
   double inv_w[3];   // nc / L: cell index = trunc(x_w * inv_w)
   double w[3];       // L / nc
   int nc[3];         // cells per dimension
-  int noff[3];       // neighbour-cell reach: ceil(a / w)
+  int noff[3];       // neighbour-cell reach: ceil((a + skin) / w)
   int ncell;
+  double margin = 0.0;   // skin / 2: how far an atom may sit outside its cell
 };
 
 struct GridDims {
@@ -110,6 +111,16 @@ struct BinCountArgs {
   int* cid; int* slot; int* count; double4* xw; int* flags;
   double c6_scale;   // xi = sqrt(c6_scale * c6): 1 for C6, 2 for Lorentz-Berthelot epsilon
   double* xi_partial = nullptr;   // per-block sums of xi in original order (single plans, mixed)
+  const int* cond = nullptr;      // if set and *cond == 0 the binning is skipped (neighbour reuse)
+  double* xref = nullptr;         // if set: the positions of this binning (neighbour reuse)
+};
+// Neighbour reuse (plans with a skin): after a binning the atoms keep their
+// sorted slots and cells; each later evaluation either bins again (*cond set
+// by the displacement check) or re-gathers the new positions through perm.
+struct DispCheckArgs { const double* pos; const double* xref; int n; double lim2; int* cond; };
+struct RegatherArgs {
+  const double* pos; const int* perm; const int* cell_s; int n; CellGeom g; const int* cond;
+  double4* xs; float4* xr;
 };
 // molecular dynamics (md.hip): repulsion of eq:disp-pair-pot and velocity Verlet
 struct RepGatherArgs { const int* perm; const double* c12; int n; double* x12s; float* x12f; int* flags; };
@@ -137,14 +148,15 @@ struct AddForcesArgs { double* forces; const double* add; int n3; };
 struct MdKineticArgs { const double* partial; int npartial; double* out; };
 struct LbGatherArgs { const int* perm; int n; const double* sigma; double* sig_s; int* flags; };
 struct LbChargeArgs { const double4* xs; const double* sig_s; int n; int k; double* charge; };
-struct ScanArgs { int* count; int m; int* start; int* bsum; int* bmax; int* max_count; };
-struct ScatterArgs { const int* cid; const int* slot; int n; const int* start; int2* perm_tmp; };
+struct ScanArgs { int* count; int m; int* start; int* bsum; int* bmax; int* max_count; const int* cond = nullptr; };
+struct ScatterArgs { const int* cid; const int* slot; int n; const int* start; int2* perm_tmp; const int* cond = nullptr; };
 struct RankArgs { const int* start; const int2* perm_tmp; int n; int* perm; };
 // Rank of each atom among its cell's atoms by original index, fused with the
 // gather of the sorted arrays (single plans).
 struct RankGatherArgs {
   const int* start; const int2* perm_tmp; int n; int* perm; const double4* xw;
   double4* xs; int* cell_s; float4* xr; float* xif; CellGeom g;
+  const int* cond = nullptr;
 };
 struct GatherArgs {
   const int* perm; int n; const double4* xw;
@@ -376,6 +388,9 @@ struct mls_plan_s {
                                    // (n_partial each) block sums
   double* d_fslow = nullptr;       // geometric mixing: grid-part forces of multiple time stepping (n_max,3)
   double* d_fmid = nullptr;        // multiple time stepping per level: the level-1 grid forces (n_max,3)
+  double skin = 0.0;               // neighbour reuse: see mls_params.skin
+  double* d_xref = nullptr;        // positions of the last binning (n_max,3), plans with a skin
+  int* d_rebin = nullptr;          // 1: the next conditional binning runs
   double* d_efast = nullptr;       // geometric mixing: energy of an inner step's fast evaluation
   bool ant_tiles = false;          // two-phase anterpolation tables built
   mls::AntTiles ant{};
@@ -431,6 +446,11 @@ int stencil_tile_zc(int R, bool f64);
 
 // kernel launchers (one per file); all enqueue on `s` and return the launch status
 hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double* c6, hipStream_t s);
+// Neighbour reuse (plans with a skin): binning that records the positions
+// (first evaluation of an MD run), and the per-step alternative: check the
+// displacements since then and either bin again or re-gather.
+hipError_t launch_binning_ref(mls_plan_s* P, int n, const double* pos, const double* c6, hipStream_t s);
+hipError_t launch_binning_reuse(mls_plan_s* P, int n, const double* pos, const double* c6, hipStream_t s);
 // mixed precision: sum of xi from binning's block sums, needed by the grid
 // part only (launched on the grid chain's stream, after binning)
 hipError_t launch_sum_xi(mls_plan_s* P, int n, hipStream_t s);

@@ -410,17 +410,19 @@ struct PairTrimF64 {
     const int uz = cz + dz;
     const int iz = uz < 0 ? -1 : (uz >= g.nc[2] ? 1 : 0);
     const int tz = uz - iz * g.nc[2];
-    const double gz = gap1(xi.z, uz * g.w[2], g.w[2], 1e-12 * g.L[2]);
+    // gaps shrunk (and the reach below grown) by the skin margin: with
+    // neighbour reuse atoms may sit that far outside their cells
+    const double gz = gap1(xi.z, uz * g.w[2], g.w[2], 1e-12 * g.L[2] + g.margin);
     for (int dy = -2; dy <= 2; ++dy) {
       const int uy = cy + dy;
       const int iy = uy < 0 ? -1 : (uy >= g.nc[1] ? 1 : 0);
       const int ty = uy - iy * g.nc[1];
-      const double gy = gap1(xi.y, uy * g.w[1], g.w[1], 1e-12 * g.L[1]);
+      const double gy = gap1(xi.y, uy * g.w[1], g.w[1], 1e-12 * g.L[1] + g.margin);
       const double rem = pc.a2 - (gy * gy + gz * gz);
       int clo = 0, chi = -1;
       if (active && rem > 0.0) {
         // x cells the cutoff sphere reaches in this row (conservatively widened)
-        const double rx = (double)(sqrtf((float)rem) * reach) + 1e-6 * g.w[0];
+        const double rx = (double)(sqrtf((float)rem) * reach) + 1e-6 * g.w[0] + g.margin;
         clo = max(cx - 2, (int)floor((xi.x - rx) * g.inv_w[0]));
         chi = min(cx + 2, (int)floor((xi.x + rx) * g.inv_w[0]));
       }
@@ -632,25 +634,28 @@ struct PairTrimF32 {
   const float a2m = pc.a2 * (1.0f + 2e-5f);
   const float reach = 1.0f + 2e-5f;
   const float inv_wx = 1.0f / pc.w[0];
+  // the skin margin of neighbour reuse (atoms may sit that far outside their
+  // cells): shrinks the gaps and grows the reach
+  const float mg = (float)g.margin;
   const int nc0 = g.nc[0], nc1 = g.nc[1], nc2 = g.nc[2];
   for (int dz = -2; dz <= 2; ++dz) {
     const int uz = cz + dz;
     const int tz = uz < 0 ? uz + nc2 : (uz >= nc2 ? uz - nc2 : uz);
     const float gz = dz == 0 ? 0.0f
                              : fmaxf(0.0f, (dz > 0 ? fmaf((float)dz, pc.w[2], -xi.z)
-                                                   : fmaf((float)(-dz - 1), pc.w[2], xi.z)) - 1e-5f * pc.w[2]);
+                                                   : fmaf((float)(-dz - 1), pc.w[2], xi.z)) - 1e-5f * pc.w[2] - mg);
     const float rem_z = a2m - gz * gz;
     const int rowz = tz * nc1;
     int ty = cy - 2 < 0 ? cy - 2 + nc1 : cy - 2;
     for (int dy = -2; dy <= 2; ++dy) {
       const float gy = dy == 0 ? 0.0f
                                : fmaxf(0.0f, (dy > 0 ? fmaf((float)dy, pc.w[1], -xi.y)
-                                                     : fmaf((float)(-dy - 1), pc.w[1], xi.y)) - 1e-5f * pc.w[1]);
+                                                     : fmaf((float)(-dy - 1), pc.w[1], xi.y)) - 1e-5f * pc.w[1] - mg);
       const float rem = rem_z - gy * gy;
       int clo = 0, chi = -1;
       if (active && rem > 0.0f) {
         // hardware square root (about 1 ulp): far inside the margin
-        const float rx = fmaf(__builtin_amdgcn_sqrtf(rem), reach, 1e-5f * pc.w[0]);
+        const float rx = fmaf(__builtin_amdgcn_sqrtf(rem), reach, 1e-5f * pc.w[0] + mg);
         clo = cx + max(-2, (int)floorf((xi.x - rx) * inv_wx));
         chi = cx + min(2, (int)floorf((xi.x + rx) * inv_wx));
       }

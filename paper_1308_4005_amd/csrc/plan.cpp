@@ -180,6 +180,15 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
     return MLS_ERR_UNSUPPORTED;
   }
   P->mixing = p.mixing;
+  if (!(std::isfinite(p.skin) && p.skin >= 0.0 && p.skin < p.cutoff)) {
+    set_error("skin must be finite with 0 <= skin < a");
+    return MLS_ERR_INVALID_ARG;
+  }
+  if (p.skin > 0.0 && p.mixing != MLS_GEOMETRIC) {
+    set_error("a skin (neighbour reuse in molecular dynamics) needs geometric mixing");
+    return MLS_ERR_UNSUPPORTED;
+  }
+  P->skin = p.skin;
 
   P->params = p;
   P->order = p.order;
@@ -240,12 +249,16 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   // cells are made half as wide (the smallest width >= a/2 dividing the box):
   // the pair kernel then trims each neighbour row to the cutoff sphere, which
   // examines far fewer candidates.  The pairs found are the same.
+  // With a skin s (neighbour reuse) every width is taken for a + s, so that
+  // atoms up to s/2 outside their cells are still found by the same window.
   CellGeom& cg = P->cg;
+  const double reach = p.cutoff + P->skin;
   bool fast = true;
   for (int d = 0; d < 3; ++d)
-    if (std::floor(p.box[d] / (0.5 * p.cutoff * (1.0 + 1e-12))) < 5.0) fast = false;
+    if (std::floor(p.box[d] / (0.5 * reach * (1.0 + 1e-12))) < 5.0) fast = false;
   P->pair_fast = fast;
-  const double cw = fast ? 0.5 * p.cutoff : p.cutoff;
+  const double cw = fast ? 0.5 * reach : reach;
+  cg.margin = 0.5 * P->skin;
   cg.ncell = 1;
   for (int d = 0; d < 3; ++d) {
     cg.L[d] = p.box[d];
@@ -254,7 +267,7 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
     cg.nc[d] = (int)std::max(1.0, std::min(c, 2048.0));
     cg.inv_w[d] = (double)cg.nc[d] / p.box[d];
     cg.w[d] = p.box[d] / cg.nc[d];
-    cg.noff[d] = std::max(1, (int)std::ceil(p.cutoff / cg.w[d] - 1e-12));
+    cg.noff[d] = std::max(1, (int)std::ceil(reach / cg.w[d] - 1e-12));
     if ((double)cg.ncell * cg.nc[d] > 2.0e8) { set_error("too many linked cells"); return MLS_ERR_INVALID_ARG; }
     cg.ncell *= cg.nc[d];
   }
@@ -427,6 +440,10 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
     ALLOC(P->d_md_partial, (size_t)P->rep_cap + 2 * (size_t)P->n_partial);
     ALLOC(P->d_fslow, 3 * N);
     ALLOC(P->d_fmid, 3 * N);
+    if (P->skin > 0.0) {
+      ALLOC(P->d_xref, 3 * N);
+      ALLOC(P->d_rebin, 1);
+    }
     ALLOC(P->d_efast, 1);
   }
   if (P->mixing == MLS_LORENTZ_BERTHELOT) {
