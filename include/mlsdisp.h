@@ -270,8 +270,10 @@ mls_status mls_md_run_mts_levels(mls_plan_t plan, int64_t n, double* pos, double
  * local part uses C_ij directly; the grid part runs the steps of Sec. II.B
  * once per charge vector xi_{i,k} = sigma_i^k sqrt(binom(6,k) 2 eps_i) / 8,
  * k = 0..6, pairing vector k with vector 6 - k (seven instances, as the paper
- * states).  The plan must have mixing = MLS_LORENTZ_BERTHELOT and precision
- * MLS_FP64.
+ * states).  The plan must have mixing = MLS_LORENTZ_BERTHELOT.  In MLS_MIXED
+ * precision the pair kernel evaluates C_ij and g_0 in FP32 and the level
+ * stencils work in FP32 on the charges minus their mean, as under geometric
+ * mixing; anterpolation sums, the coarsest level and interpolation stay FP64.
  *   eps, sigma  device (n) FP64, finite and >= 0 (else a device flag, as C6)
  *   energy      device, 1 FP64 (overwritten); forces device (n,3) or NULL
  * Same ordering, threading and error behaviour as mls_evaluate. */
@@ -370,8 +372,8 @@ mls_status mls_plan_destroy(mls_plan_t plan);
  * into a hipGraph on first use and replayed.
  *
  *   nbox       1 .. 2^20 boxes
- *   per_box    host (nbox) parameter sets; precision, order and continuity
- *              must agree
+ *   per_box    host (nbox) parameter sets; precision, order, continuity and
+ *              mixing must agree
  *   n_per_box  host (nbox) atom counts >= 0 (total < 2^31)
  *   autotune   nonzero: the first mls_batch_evaluate times every stage over
  *              a set of persistent grid sizes and stencil tile depths on the
@@ -399,6 +401,18 @@ mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* 
                             int autotune, mls_batch_t* out);
 mls_status mls_batch_evaluate(mls_batch_t batch, const double* pos, const double* c6,
                               double* energies, double* forces, double* dE_dc6, void* stream);
+/* Batched Lorentz-Berthelot evaluation (Sec. II.D, as mls_evaluate_lb per
+ * box): the boxes were created with mixing = MLS_LORENTZ_BERTHELOT (FP64 or
+ * mixed precision).  Every chain phase (charges, anterpolation, restrictions,
+ * level stencils, coarsest level, prolongations) covers the seven charge
+ * vectors of every box in one launch.
+ *   eps, sigma  device (n) FP64 in the batch's row layout, finite and >= 0
+ *   energies    device (nbox); forces device (n,3) or NULL
+ * Changing any of the six pointers rebuilds the launch tables as above.
+ * Errors: as mls_batch_evaluate; MLS_ERR_INVALID_ARG on a geometric batch
+ * (and mls_batch_evaluate on a Lorentz-Berthelot batch). */
+mls_status mls_batch_evaluate_lb(mls_batch_t batch, const double* pos, const double* eps, const double* sigma,
+                                 double* energies, double* forces, void* stream);
 /* enable (default) or disable graph replay; disabled, every call launches eagerly */
 mls_status mls_batch_set_graph(mls_batch_t batch, int enable);
 /* current launch shape (after autotuning: the tuned one) / force a shape (cancels a pending autotune) */

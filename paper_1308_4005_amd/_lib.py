@@ -36,7 +36,7 @@ EXPORTS = [
     "mls_batch_set_graph", "mls_batch_get_tuning", "mls_batch_set_tuning", "mls_batch_box_info",
     "mls_batch_status", "mls_batch_destroy", "mls_status_string", "mls_last_error",
     "mls_plan_set_timing", "mls_plan_read_timing", "mls_evaluate_md", "mls_md_run",
-    "mls_md_run_mts", "mls_evaluate_noalloc", "mls_md_run_mts_levels",
+    "mls_md_run_mts", "mls_evaluate_noalloc", "mls_md_run_mts_levels", "mls_batch_evaluate_lb",
 ]
 
 STAGE_NAMES = ["binning", "pair", "anterpolation", "restriction", "stencil", "coarsest",
@@ -129,6 +129,7 @@ def load():
     lib.mls_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(MLSParams), ctypes.POINTER(i64),
                                      ctypes.c_int, ctypes.POINTER(P)]
     lib.mls_batch_evaluate.argtypes = [P, dp, dp, dp, dp, dp, P]
+    lib.mls_batch_evaluate_lb.argtypes = [P, dp, dp, dp, dp, dp, P]
     lib.mls_batch_set_graph.argtypes = [P, ctypes.c_int]
     lib.mls_batch_get_tuning.argtypes = [P, ctypes.POINTER(MLSBatchTuning)]
     lib.mls_batch_set_tuning.argtypes = [P, ctypes.POINTER(MLSBatchTuning)]

@@ -3,7 +3,9 @@
 ``BatchPlan(boxes, n_per_box, cutoff, h, order, levels, precision)`` wraps
 ``mls_batch_create``; ``evaluate(pos, c6)`` takes the atoms of all boxes
 concatenated (box b owns rows ``offsets[b]:offsets[b+1]``) and returns the
-per-box energies and the concatenated forces (and dE/dC6 on request).
+per-box energies and the concatenated forces (and dE/dC6 on request).  A
+batch created with ``mixing="lorentz-berthelot"`` takes ``evaluate_lb(pos,
+eps, sigma)`` instead.
 Argument marshalling only: every step runs in the library's HIP kernels.
 """
 from __future__ import annotations
@@ -77,6 +79,27 @@ class BatchPlan:
             _lib.check(self._lib.mls_batch_evaluate(self._batch, _ptr(pos), _ptr(c6), _ptr(out.energies),
                                                     _ptr(out.forces), _ptr(out.dE_dc6), ctypes.c_void_p(s)),
                        "mls_batch_evaluate")
+        return out
+
+    def evaluate_lb(self, pos, eps, sigma, forces=True, out=None, stream=None):
+        """Enqueue one batched Lorentz-Berthelot evaluation (``mls_batch_evaluate_lb``):
+        per-atom epsilon and sigma in the batch's row layout."""
+        import torch
+        for name, t, shape in (("pos", pos, (self.n_total, 3)), ("eps", eps, (self.n_total,)),
+                               ("sigma", sigma, (self.n_total,))):
+            if t.device != self.device or t.dtype != torch.float64 or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float64 tensor on the batch's device")
+            if tuple(t.shape) != shape:
+                raise ValueError(f"{name} must have shape {shape}")
+        if out is None:
+            out = BatchResult(torch.empty(self.nbox, dtype=torch.float64, device=self.device),
+                              torch.empty((self.n_total, 3), dtype=torch.float64, device=self.device)
+                              if forces else None)
+        s = (stream if stream is not None else torch.cuda.current_stream(self.device)).cuda_stream
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.mls_batch_evaluate_lb(self._batch, _ptr(pos), _ptr(eps), _ptr(sigma),
+                                                       _ptr(out.energies), _ptr(out.forces), ctypes.c_void_p(s)),
+                       "mls_batch_evaluate_lb")
         return out
 
     def set_graph(self, enable=True):

@@ -581,13 +581,17 @@ mls_status mls_evaluate_lb(mls_plan_t P, int64_t n, const double* pos, const dou
   for (int k = 0; k < 7; ++k) {
     HIP_TRY(launch_lb_charge(P, ni, k, g), "charges");
     std::swap(P->lv, P->lb_lv[k]);
-    P->charge = P->d_charge;
+    P->charge = lb_charge_buf(P, k);
+    P->ant_scratch = lb_ant_scratch(P, k);
+    if (P->precision == MLS_MIXED) P->sum_q = lb_sum_buf(P, k);
     hipError_t e = launch_anterpolate(P, ni, g);
     if (e == hipSuccess) e = launch_restrictions(P, g);
     if (e == hipSuccess) e = launch_stencils(P, g);
     if (e == hipSuccess) e = launch_coarsest(P, g);
     if (e == hipSuccess) e = launch_prolongations(P, g);
     P->charge = nullptr;
+    P->ant_scratch = nullptr;
+    P->sum_q = nullptr;
     std::swap(P->lv, P->lb_lv[k]);
     if (e != hipSuccess) return hip_fail(e, "grid part");
   }

@@ -34,6 +34,7 @@ struct mls_batch_s {
   int device = 0;
   int precision = 0;
   int order = 4;
+  int mixing = 0;                    // mls_mixing, shared by every box
   std::vector<mls_plan_s*> plans;
   std::vector<int64_t> off;          // nbox + 1 atom offsets
 
@@ -44,7 +45,8 @@ struct mls_batch_s {
 
   // caller buffers the phases were built for
   const double* pos = nullptr;
-  const double* c6 = nullptr;
+  const double* c6 = nullptr;        // C6, or epsilon under Lorentz-Berthelot mixing
+  const double* sigma = nullptr;     // Lorentz-Berthelot: sigma
   double* energies = nullptr;
   double* forces = nullptr;
   double* dE_dc6 = nullptr;
@@ -120,6 +122,19 @@ GridGeom finest(const mls_plan_s* P) {
 
 int stencil_template(int R) { return R <= 4 ? 4 : (R <= 6 ? 6 : 8); }
 
+// One grid chain (anterpolation .. prolongation) of the batch: per box under
+// geometric mixing, per box and charge vector under Lorentz-Berthelot mixing
+// (Sec. II.D), each vector with its own slot of buffers.  `id` indexes the
+// chain phases' argument arrays.
+struct Chain {
+  int id;
+  mls_plan_s* P;
+  std::vector<Level>* lv;
+  const double* charge;   // null: the xi of the binning
+  double* scratch;        // expanded anterpolation grid
+  const double* sum;      // mixed precision: sum of the charges
+};
+
 // Build the phase list of one evaluation for the current caller buffers and
 // tuning, and upload it (one arena).  Boxes are visited largest first so the
 // work lists start with the longest items.
@@ -137,6 +152,18 @@ mls_status build_phases(mls_batch_s* B) {
 
   std::vector<HostPhase> hp;
   auto n_of = [&](int b) { return (int)(B->off[b + 1] - B->off[b]); };
+  const bool lb = B->mixing == MLS_LORENTZ_BERTHELOT;
+  std::vector<Chain> chains;
+  for (int b : order) {
+    mls_plan_s* P = B->plans[b];
+    if (!lb) {
+      chains.push_back(Chain{b, P, &P->lv, nullptr, P->d_ant_scratch, P->d_scratch});
+      continue;
+    }
+    for (int k = 0; k < 7; ++k)
+      chains.push_back(Chain{7 * b + k, P, &P->lb_lv[k], lb_charge_buf(P, k), lb_ant_scratch(P, k), lb_sum_buf(P, k)});
+  }
+  const int nchain = lb ? 7 * nb : nb;   // entries of the chain phases' argument arrays
 
   // ------------------------------------------------ binning (Sec. III.D)
   {
@@ -149,31 +176,38 @@ mls_status build_phases(mls_batch_s* B) {
     HostPhase rk = make_phase<RankArgs>(BK_RANK, MLS_T_BINNING, 0, nb);
     HostPhase ga = make_phase<GatherArgs>(BK_GATHER, MLS_T_BINNING, 0, nb);
     HostPhase x2 = make_phase<SumXiArgs>(BK_SUM_XI_FINAL, MLS_T_BINNING, 0, nb);
+    HostPhase sg = make_phase<LbGatherArgs>(BK_LB_GATHER, MLS_T_BINNING, 0, nb);
     for (int b : order) {
       mls_plan_s* P = B->plans[b];
       const int n = n_of(b);
       const int nc = P->cg.ncell;
       const int64_t o = B->off[b];
       set_box(fill, b, FillArgs{P->d_count, nc}, nblk(nc, 256));
+      // xi = sqrt(C6), or e = sqrt(2 eps) under Lorentz-Berthelot mixing
       set_box(cnt, b, BinCountArgs{B->pos + 3 * o, B->c6 + o, n, P->cg, P->d_cid, P->d_slot, P->d_count, P->d_xw,
-                                   P->d_flags, 1.0}, nblk(n, 256));
+                                   P->d_flags, lb ? 2.0 : 1.0}, nblk(n, 256));
       ScanArgs sa{P->d_count, nc, P->d_cell_start, P->d_bsum, P->d_bmax, P->d_ncell_max};
       set_box(s1, b, sa, scan_blocks(nc));
       set_box(s2, b, sa, 1);
       set_box(s3, b, sa, nblk(nc, 256));
       set_box(sc, b, ScatterArgs{P->d_cid, P->d_slot, n, P->d_cell_start, P->d_perm_tmp}, nblk(n, 256));
       set_box(rk, b, RankArgs{P->d_cell_start, P->d_perm_tmp, n, P->d_perm}, nblk(n, 256));
+      const bool xi_sum = mixed && !lb;
       set_box(ga, b, GatherArgs{P->d_perm, n, P->d_xw, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, P->cg,
-                                mixed ? P->d_partial : nullptr}, nblk(n + kSortedPad, 256));
-      if (mixed) set_box(x2, b, SumXiArgs{n + kSortedPad, P->d_partial, P->d_scratch}, 1);
+                                xi_sum ? P->d_partial : nullptr}, nblk(n + kSortedPad, 256));
+      if (xi_sum) set_box(x2, b, SumXiArgs{n + kSortedPad, P->d_partial, P->d_scratch}, 1);
+      if (lb)
+        set_box(sg, b, LbGatherArgs{P->d_perm, n, B->sigma + o, P->d_sig, P->d_flags, P->d_sigf},
+                nblk(n + kSortedPad, 256));
     }
-    for (HostPhase* h : {&fill, &cnt, &s1, &s2, &s3, &sc, &rk, &ga, &x2})
+    for (HostPhase* h : {&fill, &cnt, &s1, &s2, &s3, &sc, &rk, &ga, &x2, &sg})
       hp.push_back(std::move(*h));
   }
 
   // ------------------------------------------------ local part (eq:g_0)
   {
-    const int pv = pair_variant(B->plans[0]);   // boxes share the smoothing function
+    // boxes share the smoothing function; 0x10 selects the LB source weight
+    const int pv = pair_variant(B->plans[0]) | (lb ? 0x10 : 0);
     HostPhase f32 = make_phase<PairArgsF>(BK_PAIR_TRIM_F32, MLS_T_PAIR, pv, nb);
     HostPhase f64 = make_phase<PairArgs>(BK_PAIR_TRIM_F64, MLS_T_PAIR, pv, nb);
     HostPhase gen = make_phase<PairArgs>(BK_PAIR_GENERIC, MLS_T_PAIR, pv, nb);
@@ -183,10 +217,13 @@ mls_status build_phases(mls_batch_s* B) {
       const int n = n_of(b);
       if (n == 0) continue;
       const CellGeom& g = P->cg;
-      PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const(P), P->d_e0, P->d_floc, nullptr};
+      PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const(P), P->d_e0, P->d_floc,
+                 lb ? P->d_sig : nullptr};
       if (mixed && P->pair_fast && n < (1 << 24)) {
-        set_box(f32, b, PairArgsF{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const_f(P),
-                                  P->d_e0, P->d_floc}, nblk(n, 64));
+        PairArgsF af{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const_f(P), P->d_e0,
+                     P->d_floc};
+        af.sig = lb ? P->d_sigf : nullptr;
+        set_box(f32, b, af, nblk(n, 64));
       } else if (P->pair_fast && n < (1 << 25)) {
         set_box(f64, b, a, nblk(n, 64));
       } else if (!P->pair_fast) {
@@ -202,29 +239,45 @@ mls_status build_phases(mls_batch_s* B) {
   }
 
   const int gvar = B->order | (mixed ? 0x100 : 0);
+  // ------------------------------------------------ Lorentz-Berthelot charge vectors (Sec. II.D)
+  if (lb) {
+    HostPhase chg = make_phase<LbChargeArgs>(BK_LB_CHARGE, MLS_T_ANTERP, 0, nchain);
+    HostPhase sq = make_phase<SumXiArgs>(BK_SUM_XI_FINAL, MLS_T_ANTERP, 0, nchain);
+    for (const Chain& c : chains) {
+      const int b = c.id / 7, k = c.id % 7, n = n_of(b);
+      mls_plan_s* P = c.P;
+      double* part = mixed ? lb_partial_buf(P, k) : nullptr;
+      if (n > 0) set_box(chg, c.id, LbChargeArgs{P->d_xs, P->d_sig, n, k, lb_charge_buf(P, k), part}, nblk(n + kSortedPad, 256));
+      // mixed precision: the mean the stencils subtract (0 without atoms)
+      if (mixed) set_box(sq, c.id, SumXiArgs{n > 0 ? n + kSortedPad : 0, part, lb_sum_buf(P, k)}, 1);
+    }
+    hp.push_back(std::move(chg));
+    hp.push_back(std::move(sq));
+  }
+
   // ------------------------------------------------ anterpolation (eq:anterpolation)
   {
-    HostPhase tile = make_phase<AnterpTileArgs>(BK_ANT_TILE, MLS_T_ANTERP, gvar, nb);
-    HostPhase coll = make_phase<AnterpCollectArgs>(BK_ANT_COLLECT, MLS_T_ANTERP, gvar, nb);
-    HostPhase own = make_phase<AnterpArgs>(BK_ANT_OWNED, MLS_T_ANTERP, gvar, nb);
-    HostPhase zero = make_phase<FillDArgs>(BK_FILL_D, MLS_T_ANTERP, 0, nb);
-    HostPhase atom = make_phase<AnterpArgs>(BK_ANT_ATOMIC, MLS_T_ANTERP, gvar, nb);
-    for (int b : order) {
-      mls_plan_s* P = B->plans[b];
-      const int n = n_of(b);
-      AnterpArgs a{P->d_xs, P->d_cell_start, n, P->cg, finest(P), AntGeom{}, P->lv[0].q, nullptr};
+    HostPhase tile = make_phase<AnterpTileArgs>(BK_ANT_TILE, MLS_T_ANTERP, gvar, nchain);
+    HostPhase coll = make_phase<AnterpCollectArgs>(BK_ANT_COLLECT, MLS_T_ANTERP, gvar, nchain);
+    HostPhase own = make_phase<AnterpArgs>(BK_ANT_OWNED, MLS_T_ANTERP, gvar, nchain);
+    HostPhase zero = make_phase<FillDArgs>(BK_FILL_D, MLS_T_ANTERP, 0, nchain);
+    HostPhase atom = make_phase<AnterpArgs>(BK_ANT_ATOMIC, MLS_T_ANTERP, gvar, nchain);
+    for (const Chain& c : chains) {
+      mls_plan_s* P = c.P;
+      const int n = n_of(lb ? c.id / 7 : c.id);
+      Level& L1 = (*c.lv)[0];
+      AnterpArgs a{P->d_xs, P->d_cell_start, n, P->cg, finest(P), AntGeom{}, L1.q, c.charge};
       if (P->ant_tiles) {
         // two phases: per cell block into the expanded grid, then per point
-        set_box(tile, b, AnterpTileArgs{P->d_xs, P->d_cell_start, P->cg, finest(P), P->ant, P->d_ant_tab,
-                                        P->d_ant_scratch, nullptr, P->d_flags},
+        set_box(tile, c.id, AnterpTileArgs{P->d_xs, P->d_cell_start, P->cg, finest(P), P->ant, P->d_ant_tab,
+                                           c.scratch, c.charge, P->d_flags},
                 P->ant.nb[0] * P->ant.nb[1] * P->ant.nb[2]);
-        set_box(coll, b, AnterpCollectArgs{P->ant, P->d_ant_tab, P->d_ant_scratch, P->lv[0].q, P->lv[0].g},
-                nblk(P->lv[0].g.size, 256));
+        set_box(coll, c.id, AnterpCollectArgs{P->ant, P->d_ant_tab, c.scratch, L1.q, L1.g}, nblk(L1.g.size, 256));
       } else if (anterp_owned_geom(P, a.ag)) {
-        set_box(own, b, a, a.ag.nb[0] * a.ag.nb[1] * a.ag.nb[2]);
+        set_box(own, c.id, a, a.ag.nb[0] * a.ag.nb[1] * a.ag.nb[2]);
       } else {
-        set_box(zero, b, FillDArgs{P->lv[0].q, P->lv[0].g.size}, nblk(P->lv[0].g.size, 256));
-        set_box(atom, b, a, nblk(n, 256));
+        set_box(zero, c.id, FillDArgs{L1.q, L1.g.size}, nblk(L1.g.size, 256));
+        set_box(atom, c.id, a, nblk(n, 256));
       }
     }
     hp.push_back(std::move(tile));
@@ -236,18 +289,17 @@ mls_status build_phases(mls_batch_s* B) {
 
   // ------------------------------------------------ restrictions, level by level
   for (int k = 1; k < max_levels; ++k) {
-    HostPhase r = make_phase<TransferArgs>(BK_RESTRICT, MLS_T_RESTRICT, gvar, nb);
-    for (int b : order) {
-      mls_plan_s* P = B->plans[b];
-      if (P->levels <= k) continue;
-      Level& F = P->lv[k - 1];
-      Level& C = P->lv[k];
-      set_box(r, b, TransferArgs{F.q, F.g, nullptr, C.q, C.g}, nblk(C.g.size, 256));
+    HostPhase r = make_phase<TransferArgs>(BK_RESTRICT, MLS_T_RESTRICT, gvar, nchain);
+    for (const Chain& c : chains) {
+      if (c.P->levels <= k) continue;
+      Level& F = (*c.lv)[k - 1];
+      Level& C = (*c.lv)[k];
+      set_box(r, c.id, TransferArgs{F.q, F.g, nullptr, C.q, C.g}, nblk(C.g.size, 256));
     }
     hp.push_back(std::move(r));
   }
 
-  // ------------------------------------------------ level stencils (all levels < l of all boxes)
+  // ------------------------------------------------ level stencils (all levels < l of all chains)
   for (int Rt : {8, 6, 4}) {
     int zc = B->tune.stencil_zc;
     if (!stencil_tile_ok(Rt, zc)) zc = 8;
@@ -257,12 +309,12 @@ mls_status build_phases(mls_batch_s* B) {
     st.ph.stage = MLS_T_STENCIL;
     st.ph.variant = var;
     std::vector<StencilLevel> desc;
-    for (int b : order) {
-      mls_plan_s* P = B->plans[b];
+    for (const Chain& c : chains) {
+      mls_plan_s* P = c.P;
       if (P->levels < 2) continue;
       if (stencil_template(stencil_window(P)) != Rt) continue;
       for (int k = 1; k < P->levels; ++k) {
-        Level& Lv = P->lv[k - 1];
+        Level& Lv = (*c.lv)[k - 1];
         StencilLevel V{};
         V.q = Lv.q;
         V.e = Lv.e;
@@ -274,7 +326,7 @@ mls_status build_phases(mls_batch_s* B) {
         V.rows = P->d_rows;
         V.wave_rows = P->d_wave_rows;
         V.wts = mixed ? (const void*)P->d_row_wf_tile : (const void*)P->d_row_w_tile;
-        V.sum_xi = P->d_scratch;
+        V.sum_xi = c.sum;
         V.wsum = P->taps_wsum;
         const int id = (int)desc.size();
         desc.push_back(V);
@@ -290,25 +342,23 @@ mls_status build_phases(mls_batch_s* B) {
 
   // ------------------------------------------------ coarsest level (eq:last-grid-periodic-transformed)
   {
-    HostPhase c = make_phase<CoarsestArgs>(BK_COARSEST, MLS_T_COARSEST, 0, nb);
-    for (int b : order) {
-      mls_plan_s* P = B->plans[b];
-      Level& L = P->lv[P->levels - 1];
-      set_box(c, b, CoarsestArgs{L.q, L.g, P->d_Kl, L.e}, nblk(L.g.size, kCoarsestPerBlock));
+    HostPhase c = make_phase<CoarsestArgs>(BK_COARSEST, MLS_T_COARSEST, 0, nchain);
+    for (const Chain& ch : chains) {
+      Level& L = (*ch.lv)[ch.P->levels - 1];
+      set_box(c, ch.id, CoarsestArgs{L.q, L.g, ch.P->d_Kl, L.e}, nblk(L.g.size, kCoarsestPerBlock));
     }
     hp.push_back(std::move(c));
   }
 
   // ------------------------------------------------ prolongations: step s brings level l-s+1 to l-s
   for (int s = 1; s < max_levels; ++s) {
-    HostPhase p = make_phase<TransferArgs>(BK_PROLONG, MLS_T_PROLONG, gvar, nb);
-    for (int b : order) {
-      mls_plan_s* P = B->plans[b];
-      const int k = P->levels - s;   // fine level
+    HostPhase p = make_phase<TransferArgs>(BK_PROLONG, MLS_T_PROLONG, gvar, nchain);
+    for (const Chain& c : chains) {
+      const int k = c.P->levels - s;   // fine level
       if (k < 1) continue;
-      Level& F = P->lv[k - 1];
-      Level& C = P->lv[k];
-      set_box(p, b, TransferArgs{C.E, C.g, F.e, F.E, F.g}, nblk(C.g.size, 256));
+      Level& F = (*c.lv)[k - 1];
+      Level& C = (*c.lv)[k];
+      set_box(p, c.id, TransferArgs{C.E, C.g, F.e, F.E, F.g}, nblk(C.g.size, 256));
     }
     hp.push_back(std::move(p));
   }
@@ -316,17 +366,26 @@ mls_status build_phases(mls_batch_s* B) {
   // ------------------------------------------------ interpolation, outputs, energies (eq:interpolation)
   {
     HostPhase in = make_phase<InterpArgs>(BK_INTERP, MLS_T_INTERP, gvar, nb);
+    HostPhase il = make_phase<InterpLbArgs>(BK_INTERP_LB, MLS_T_INTERP, gvar, nb);
     HostPhase en = make_phase<EnergyArgs>(BK_ENERGY, MLS_T_INTERP, 0, nb);
     for (int b : order) {
       mls_plan_s* P = B->plans[b];
       const int n = n_of(b);
       const int64_t o = B->off[b];
-      OutPtrs out{B->forces ? B->forces + 3 * o : nullptr, nullptr, B->dE_dc6 ? B->dE_dc6 + o : nullptr};
-      set_box(in, b, InterpArgs{P->d_xs, P->d_perm, n, finest(P), P->lv[0].E, P->d_e0, P->d_floc, P->cself, out,
-                                P->d_partial}, nblk(n, 256));
+      if (lb) {
+        InterpLbArgs a{P->d_xs, P->d_sig, P->d_perm, n, finest(P), {}, P->d_e0, P->d_floc,
+                       B->forces ? B->forces + 3 * o : nullptr, P->d_partial};
+        for (int k = 0; k < 7; ++k) a.E1[k] = P->lb_lv[k][0].E;
+        set_box(il, b, a, nblk(n, 256));
+      } else {
+        OutPtrs out{B->forces ? B->forces + 3 * o : nullptr, nullptr, B->dE_dc6 ? B->dE_dc6 + o : nullptr};
+        set_box(in, b, InterpArgs{P->d_xs, P->d_perm, n, finest(P), P->lv[0].E, P->d_e0, P->d_floc, P->cself, out,
+                                  P->d_partial}, nblk(n, 256));
+      }
       set_box(en, b, EnergyArgs{P->d_partial, nblk(n, 256), P->cself, B->energies + b}, 1);
     }
     hp.push_back(std::move(in));
+    hp.push_back(std::move(il));
     hp.push_back(std::move(en));
   }
 
@@ -390,6 +449,7 @@ hipError_t launch_phase(const BatchPhase& ph, hipStream_t s) {
     case BK_RESTRICT:
     case BK_PROLONG:
     case BK_INTERP:
+    case BK_INTERP_LB:
     case BK_ENERGY: return launch_batched_grid(ph, s);
     case BK_STENCIL:
     case BK_COARSEST: return launch_batched_stencil(ph, s);
@@ -540,10 +600,11 @@ mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* 
       set_error("mls_batch_create: all boxes must share precision, order and continuity");
       return MLS_ERR_INVALID_ARG;
     }
-    if (per_box[b].mixing != MLS_GEOMETRIC) {
-      set_error("mls_batch_create: the batched form takes geometric mixing only");
-      return MLS_ERR_UNSUPPORTED;
+    if (per_box[b].mixing != per_box[0].mixing) {
+      set_error("mls_batch_create: all boxes must share the mixing rule");
+      return MLS_ERR_INVALID_ARG;
     }
+
     total += n_per_box[b];
   }
   if (total > ((int64_t)1 << 31) - 1) { set_error("mls_batch_create: more than 2^31 - 1 atoms"); return MLS_ERR_INVALID_ARG; }
@@ -552,6 +613,7 @@ mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* 
   B->nbox = nbox;
   B->precision = per_box[0].precision;
   B->order = per_box[0].order;
+  B->mixing = per_box[0].mixing;
   (void)hipGetDevice(&B->device);
   B->off.assign(nbox + 1, 0);
   for (int b = 0; b < nbox; ++b) B->off[b + 1] = B->off[b] + n_per_box[b];
@@ -564,6 +626,9 @@ mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* 
     mls_plan_s* P = new (std::nothrow) mls_plan_s();
     if (!P) { set_error("host allocation failed"); return fail(MLS_ERR_OOM); }
     B->plans[b] = P;
+    // Lorentz-Berthelot: one buffer slot per charge vector, so each chain
+    // phase runs the seven vectors of every box in one launch
+    P->lb_slots = 7;
     mls_status st = build_plan(per_box[b], n_per_box[b], P);
     if (st != MLS_OK) {
       set_error("box " + std::to_string(b) + ": " + mls_last_error());
@@ -589,24 +654,33 @@ mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* 
   return MLS_OK;
 }
 
-mls_status mls_batch_evaluate(mls_batch_t B, const double* pos, const double* c6, double* energies, double* forces,
-                              double* dE_dc6, void* stream) {
-  if (!B) { set_error("mls_batch_evaluate: null batch"); return MLS_ERR_INVALID_ARG; }
-  if (!energies) { set_error("mls_batch_evaluate: energies pointer is required"); return MLS_ERR_INVALID_ARG; }
-  if (B->off[B->nbox] > 0 && (!pos || !c6)) { set_error("mls_batch_evaluate: null pos or c6"); return MLS_ERR_INVALID_ARG; }
+}  // extern "C"
+
+namespace {
+
+mls_status batch_evaluate(mls_batch_t B, const double* pos, const double* c6, const double* sigma, double* energies,
+                          double* forces, double* dE_dc6, void* stream, const char* who) {
+  const std::string w(who);
+  if (!energies) { set_error(w + ": energies pointer is required"); return MLS_ERR_INVALID_ARG; }
+  const bool lb = B->mixing == MLS_LORENTZ_BERTHELOT;
+  if (B->off[B->nbox] > 0 && (!pos || !c6 || (lb && !sigma))) {
+    set_error(w + (lb ? ": null pos, eps or sigma" : ": null pos or c6"));
+    return MLS_ERR_INVALID_ARG;
+  }
   int dev = -1;
   HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-  if (dev != B->device) { set_error("mls_batch_evaluate: current device differs from the batch's device"); return MLS_ERR_INVALID_ARG; }
+  if (dev != B->device) { set_error(w + ": current device differs from the batch's device"); return MLS_ERR_INVALID_ARG; }
   hipStream_t s = (hipStream_t)stream;
   mls_status st;
-  const bool same_io = B->built && pos == B->pos && c6 == B->c6 && energies == B->energies && forces == B->forces &&
-                       dE_dc6 == B->dE_dc6;
+  const bool same_io = B->built && pos == B->pos && c6 == B->c6 && sigma == B->sigma && energies == B->energies &&
+                       forces == B->forces && dE_dc6 == B->dE_dc6;
   if (!same_io) {
     // the phase tables hold the caller's pointers: wait for work that may
     // still read the old tables before replacing them
     if (B->built) HIP_TRY(hipDeviceSynchronize(), "batch: synchronise");
     B->pos = pos;
     B->c6 = c6;
+    B->sigma = sigma;
     B->energies = energies;
     B->forces = forces;
     B->dE_dc6 = dE_dc6;
@@ -633,6 +707,30 @@ mls_status mls_batch_evaluate(mls_batch_t B, const double* pos, const double* c6
   }
   HIP_TRY(hipGraphLaunch(B->exec, s), "batch: graph launch");
   return MLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mls_status mls_batch_evaluate(mls_batch_t B, const double* pos, const double* c6, double* energies, double* forces,
+                              double* dE_dc6, void* stream) {
+  if (!B) { set_error("mls_batch_evaluate: null batch"); return MLS_ERR_INVALID_ARG; }
+  if (B->mixing != MLS_GEOMETRIC) {
+    set_error("mls_batch_evaluate: the batch uses Lorentz-Berthelot mixing (call mls_batch_evaluate_lb)");
+    return MLS_ERR_INVALID_ARG;
+  }
+  return batch_evaluate(B, pos, c6, nullptr, energies, forces, dE_dc6, stream, "mls_batch_evaluate");
+}
+
+mls_status mls_batch_evaluate_lb(mls_batch_t B, const double* pos, const double* eps, const double* sigma,
+                                 double* energies, double* forces, void* stream) {
+  if (!B) { set_error("mls_batch_evaluate_lb: null batch"); return MLS_ERR_INVALID_ARG; }
+  if (B->mixing != MLS_LORENTZ_BERTHELOT) {
+    set_error("mls_batch_evaluate_lb: the batch was not created with Lorentz-Berthelot mixing");
+    return MLS_ERR_INVALID_ARG;
+  }
+  return batch_evaluate(B, pos, eps, sigma, energies, forces, nullptr, stream, "mls_batch_evaluate_lb");
 }
 
 mls_status mls_batch_set_graph(mls_batch_t B, int enable) {

@@ -390,6 +390,7 @@ struct LbGather {
       }
     }
     a.sig_s[s] = v;
+    if (a.sig_f) a.sig_f[s] = (float)v;
   }
 };
 
@@ -411,6 +412,17 @@ struct LbCharge {
       q = sk * sqrt((double)binom) * a.xs[s].w * 0.125;
     }
     a.charge[s] = q;
+    if (a.partial) {
+      // per-block sum of the charges (fixed order; padding rows add 0)
+      __shared__ double sh[kBlock];
+      sh[threadIdx.x] = q;
+      __syncthreads();
+      for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) a.partial[blk] = sh[0];
+    }
   }
 };
 
@@ -469,13 +481,22 @@ hipError_t launch_binning(mls_plan_s* P, int n, const double* pos, const double*
 
 hipError_t launch_lb_gather(mls_plan_s* P, int n, const double* sigma, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  return launch_one<LbGather>(LbGatherArgs{P->d_perm, n, sigma, P->d_sig, P->d_flags}, nblocks(n + kSortedPad, kBlock),
-                              s);
+  return launch_one<LbGather>(LbGatherArgs{P->d_perm, n, sigma, P->d_sig, P->d_flags, P->d_sigf},
+                              nblocks(n + kSortedPad, kBlock), s);
 }
 
 hipError_t launch_lb_charge(mls_plan_s* P, int n, int k, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  return launch_one<LbCharge>(LbChargeArgs{P->d_xs, P->d_sig, n, k, P->d_charge}, nblocks(n + kSortedPad, kBlock), s);
+  const bool mixed = P->precision == MLS_MIXED;
+  if (n > 0) {
+    hipError_t e = launch_one<LbCharge>(
+        LbChargeArgs{P->d_xs, P->d_sig, n, k, lb_charge_buf(P, k), mixed ? lb_partial_buf(P, k) : nullptr},
+        nblocks(n + kSortedPad, kBlock), s);
+    if (e != hipSuccess) return e;
+  }
+  // mixed precision: the sum of this vector's charges, the mean the stencil
+  // subtracts (0 without atoms)
+  if (!mixed) return hipSuccess;
+  return launch_one<SumXiFinal>(SumXiArgs{n > 0 ? n + kSortedPad : 0, lb_partial_buf(P, k), lb_sum_buf(P, k)}, 1, s);
 }
 
 // The binning kernels; with `cond` they all do nothing when *cond == 0, and
@@ -556,6 +577,8 @@ hipError_t launch_batched_binning(const BatchPhase& ph, hipStream_t s) {
     case BK_RANK: return launch_batched_phase<CellRank>(ph, s);
     case BK_GATHER: return launch_batched_phase<GatherSorted>(ph, s);
     case BK_SUM_XI_FINAL: return launch_batched_phase<SumXiFinal>(ph, s);
+    case BK_LB_GATHER: return launch_batched_phase<LbGather>(ph, s);
+    case BK_LB_CHARGE: return launch_batched_phase<LbCharge>(ph, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -817,15 +817,16 @@ bool ant_tiles_build(const mls_plan_s* P, AntTiles& T, std::vector<int>& tab, si
 hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s) {
   Level& L1 = P->lv[0];
   if (P->ant_tiles) {
-    AnterpTileArgs t{P->d_xs, P->d_cell_start, P->cg, finest_geom(P), P->ant, P->d_ant_tab, P->d_ant_scratch,
-                     P->charge, P->d_flags};
+    double* scratch = P->ant_scratch ? P->ant_scratch : P->d_ant_scratch;
+    AnterpTileArgs t{P->d_xs, P->d_cell_start, P->cg, finest_geom(P), P->ant, P->d_ant_tab, scratch, P->charge,
+                     P->d_flags};
     const int nb = P->ant.nb[0] * P->ant.nb[1] * P->ant.nb[2];
     const bool mixed = P->precision == MLS_MIXED;
     hipError_t e;
     if (P->order == 4) e = mixed ? launch_one<AnterpTile<4, float>>(t, nb, s) : launch_one<AnterpTile<4, double>>(t, nb, s);
     else e = mixed ? launch_one<AnterpTile<6, float>>(t, nb, s) : launch_one<AnterpTile<6, double>>(t, nb, s);
     if (e != hipSuccess) return e;
-    AnterpCollectArgs c{P->ant, P->d_ant_tab, P->d_ant_scratch, L1.q, L1.g};
+    AnterpCollectArgs c{P->ant, P->d_ant_tab, scratch, L1.q, L1.g};
     return launch_one<AnterpCollect>(c, nblocks(L1.g.size, kBlock), s);
   }
   AnterpArgs a{P->d_xs, P->d_cell_start, n, P->cg, finest_geom(P), AntGeom{}, L1.q, P->charge};
@@ -949,6 +950,7 @@ hipError_t launch_batched_grid(const BatchPhase& ph, hipStream_t s) {
                            : launch_batched_phase<Interp<6, double>>(ph, s);
       return mixed ? launch_batched_phase<Interp<4, float>>(ph, s) : launch_batched_phase<Interp<4, double>>(ph, s);
     case BK_ENERGY: return launch_batched_phase<EnergyFinal>(ph, s);
+    case BK_INTERP_LB: return p6 ? launch_batched_phase<InterpLb<6>>(ph, s) : launch_batched_phase<InterpLb<4>>(ph, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -62,8 +62,6 @@ struct Level {
   double* q = nullptr;   // charges q^k
   double* e = nullptr;   // evaluation e^k
   double* E = nullptr;   // prolongated total E^k (aliases e on the coarsest level)
-  float* qf = nullptr;   // mixed precision: q^k - mean, FP32
-  float* ef = nullptr;   // mixed precision: e^k (FP32 stencil output)
 };
 
 // ---------------------------------------------------------------------------
@@ -146,8 +144,10 @@ struct LocalEnergyArgs {
 };
 struct AddForcesArgs { double* forces; const double* add; int n3; };
 struct MdKineticArgs { const double* partial; int npartial; double* out; };
-struct LbGatherArgs { const int* perm; int n; const double* sigma; double* sig_s; int* flags; };
-struct LbChargeArgs { const double4* xs; const double* sig_s; int n; int k; double* charge; };
+struct LbGatherArgs { const int* perm; int n; const double* sigma; double* sig_s; int* flags; float* sig_f; };
+// partial: if set, per-block sums of the charges (the mean the mixed stencil
+// subtracts)
+struct LbChargeArgs { const double4* xs; const double* sig_s; int n; int k; double* charge; double* partial; };
 struct ScanArgs { int* count; int m; int* start; int* bsum; int* bmax; int* max_count; const int* cond = nullptr; };
 struct ScatterArgs { const int* cid; const int* slot; int n; const int* start; int2* perm_tmp; const int* cond = nullptr; };
 struct RankArgs { const int* start; const int2* perm_tmp; int n; int* perm; };
@@ -181,6 +181,7 @@ struct PairArgsF {
   const float4* xr; const float* xif; const double4* xs; const int* cell_s; const int* cstart;
   int n; CellGeom g; PairConstF pc; double* e0; double* floc;
   PairRep rep{};
+  const float* sig = nullptr;   // Lorentz-Berthelot: sorted sigma in FP32
 };
 struct AnterpArgs {
   const double4* xs; const int* cstart; int n; CellGeom cg; GridGeom gg; AntGeom ag; double* q;
@@ -256,7 +257,8 @@ enum BatchKernel {
   BK_SUM_XI_FINAL,
   BK_PAIR_GENERIC, BK_PAIR_WAVE, BK_PAIR_TRIM_F64, BK_PAIR_TRIM_F32,
   BK_ANT_ATOMIC, BK_ANT_OWNED, BK_ANT_TILE, BK_ANT_COLLECT, BK_RESTRICT, BK_PROLONG, BK_INTERP, BK_ENERGY,
-  BK_STENCIL, BK_COARSEST
+  BK_STENCIL, BK_COARSEST,
+  BK_LB_GATHER, BK_LB_CHARGE, BK_INTERP_LB
 };
 
 struct BatchPhase {
@@ -325,8 +327,20 @@ struct mls_plan_s {
   int mixing = 0;                  // mls_mixing
   std::vector<mls::Level> lb_lv[7];  // Lorentz-Berthelot: grids of charge vector k
   double* d_sig = nullptr;         // Lorentz-Berthelot: sorted sigma (n_max + pad)
-  double* d_charge = nullptr;      // Lorentz-Berthelot: sorted charges of one vector (n_max + pad)
+  float* d_sigf = nullptr;         // Lorentz-Berthelot, mixed precision: the same in FP32
+  // Lorentz-Berthelot work slots: the single-plan path runs the seven charge
+  // vectors one after another through slot 0; the batched form gives each
+  // vector its own slot (charges, partial sums, their sum, expanded
+  // anterpolation grid) so one launch covers all seven.
+  int lb_slots = 1;
+  size_t lb_stride = 0;            // doubles per slot of d_charge (n_max + pad)
+  int lb_npart = 0;                // partial sums per slot of d_lb_partial
+  size_t ant_scratch_n = 0;        // doubles of one expanded anterpolation grid
+  double* d_charge = nullptr;      // Lorentz-Berthelot: sorted charges, lb_slots x lb_stride
+  double* d_lb_partial = nullptr;  // Lorentz-Berthelot, mixed: per-block charge sums per slot
   const double* charge = nullptr;  // charges the anterpolation reads (null: xi)
+  double* ant_scratch = nullptr;   // expanded grid the anterpolation uses (null: d_ant_scratch)
+  const double* sum_q = nullptr;   // mixed: sum of the charges the stencils read (null: Sigma xi)
   double gamma_c[5]{};             // gamma_k inside the unit ball: sum_j gamma_c[j] rho^(12 j)
   mls::CellGeom cg{};
   double invh1[3]{};               // n_1 / L
@@ -507,6 +521,18 @@ hipError_t launch_add_forces(double* forces, const double* add, int n, hipStream
 bool anterp_owned_geom(const mls_plan_s* P, AntGeom& ag);
 // tables of the two-phase anterpolation; false when no blocking fits
 bool ant_tiles_build(const mls_plan_s* P, AntTiles& t, std::vector<int>& tab, size_t& scratch);
+
+// Lorentz-Berthelot slot of charge vector k and its buffers.
+inline int lb_slot(const mls_plan_s* P, int k) { return P->lb_slots > 1 ? k : 0; }
+inline double* lb_charge_buf(const mls_plan_s* P, int k) { return P->d_charge + (size_t)lb_slot(P, k) * P->lb_stride; }
+inline double* lb_partial_buf(const mls_plan_s* P, int k) {
+  return P->d_lb_partial ? P->d_lb_partial + (size_t)lb_slot(P, k) * P->lb_npart : nullptr;
+}
+// the sum of the charges of vector k (mixed precision; after Sigma xi in slot 0)
+inline double* lb_sum_buf(const mls_plan_s* P, int k) { return P->d_scratch + 8 + lb_slot(P, k); }
+inline double* lb_ant_scratch(const mls_plan_s* P, int k) {
+  return P->d_ant_scratch ? P->d_ant_scratch + (size_t)lb_slot(P, k) * P->ant_scratch_n : nullptr;
+}
 // z extent candidates of a stencil tile for window R
 bool stencil_tile_ok(int R, int zc);
 

@@ -493,6 +493,7 @@ struct PairLaneF {
   float cxf, ncf;       // target cell x index, cells along x
   int self_ent;         // the target's own home-row entry (-1 for idle lanes)
   int safe_j;           // a valid source index for idle drain slots
+  float sig_i;          // Lorentz-Berthelot: the target's sigma
 };
 
 // Queue entry: source index << 8 | x image ix (2 bits) | dy (3 bits) | dz (3
@@ -503,11 +504,11 @@ __device__ __forceinline__ int entry_bits(int ix, int dy, int dz) { return (ix &
 // The loop body has no branches: slots past a lane's count (and the target
 // itself) evaluate a harmless pair with zero weight, so every lane adds
 // exactly 0 for them.
-template <int K, bool R>
+template <int K, bool R, bool LB>
 __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, int limit, int lane,
                                                const PairLaneF& L, const float4* __restrict__ xr,
-                                               const float* __restrict__ xif, const PairConstF& pc, PairAccM& A,
-                                               const PairRep& rp, RepAcc& B) {
+                                               const float* __restrict__ xif, const float* __restrict__ sig,
+                                               const PairConstF& pc, PairAccM& A, const PairRep& rp, RepAcc& B) {
   const float r2_idle = 0.25f * pc.a2;
   const float rc2 = (float)rp.rc2;
   const int cnt = A.cnt;
@@ -529,7 +530,13 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
     const float r2 = ok ? dxv * dxv + dyv * dyv + dzv * dzv : r2_idle;
     float gg, fr;
     g0_pair<float, K>(r2, pc, gg, fr);
-    const float wj = ok ? xif[j] : 0.0f;
+    float wj = ok ? xif[j] : 0.0f;
+    if constexpr (LB) {
+      // source weight e_j ((sigma_i + sigma_j) / 2)^6, as in the FP64 kernels
+      const float m = 0.5f * (L.sig_i + sig[j]);
+      const float m3 = m * m * m;
+      wj *= m3 * m3;
+    }
     e = fmaf(wj, gg, e);
     const float f = wj * fr;
     fx = fmaf(f, dxv, fx);
@@ -564,11 +571,11 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
 // Scan sources [j, j1) of one row run (image ix along x, row offsets dy, dz).
 // The filter loop touches no accumulator: it stops when a queue may
 // overflow, the queues are partly drained, and the filter resumes.
-template <int K, bool R>
+template <int K, bool R, bool LB>
 __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int dz, int* __restrict__ queue,
                                               int lane, const PairLaneF& L, const float4* __restrict__ xr,
-                                              const float* __restrict__ xif, const PairConstF& pc, PairAccM& A,
-                                              const PairRep& rp, RepAcc& B) {
+                                              const float* __restrict__ xif, const float* __restrict__ sig,
+                                              const PairConstF& pc, PairAccM& A, const PairRep& rp, RepAcc& B) {
   // the drain rebuilds these with the same operations
   const float bx = fmaf((float)ix, -L.ncf, L.cxf);
   const float ay = fmaf((float)-dy, pc.w[1], L.yy);
@@ -600,11 +607,11 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
     }
     A.cnt = cnt;
     if (!full) break;
-    pair_drain_f32<K, R>(queue, kDrainF, lane, L, xr, xif, pc, A, rp, B);
+    pair_drain_f32<K, R, LB>(queue, kDrainF, lane, L, xr, xif, sig, pc, A, rp, B);
   }
 }
 
-template <int K, bool R = false>
+template <int K, bool R = false, bool LB = false>
 struct PairTrimF32 {
   using Args = PairArgsF;
   static constexpr int kThreads = kWaveQ;
@@ -623,7 +630,9 @@ struct PairTrimF32 {
   const float4 xi = xr[sc];
   const int c = ar.cell_s[sc];
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
-  const PairLaneF L{xi.x, xi.y, xi.z, (float)cx, (float)g.nc[0], active ? ((sc << 8) | entry_bits(0, 0, 0)) : -1, sc};
+  const float* __restrict__ sig = ar.sig;
+  const PairLaneF L{xi.x, xi.y, xi.z, (float)cx, (float)g.nc[0], active ? ((sc << 8) | entry_bits(0, 0, 0)) : -1, sc,
+                    LB ? sig[sc] : 0.0f};
   PairAccM A{0.0, 0.0, 0.0, 0.0, 0};
   RepAcc B{0.0, 0.0, 0.0, 0.0};
   const PairRep& rp = ar.rep;
@@ -679,11 +688,11 @@ struct PairTrimF32 {
         k0 = cstart[row + lo2];
         k1 = cstart[row + hi2 + 1];
       }
-      pair_scan_f32<K, R>(j0, j1, ix1, dy, dz, queue, lane, L, xr, xif, pc, A, rp, B);
-      pair_scan_f32<K, R>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xif, pc, A, rp, B);
+      pair_scan_f32<K, R, LB>(j0, j1, ix1, dy, dz, queue, lane, L, xr, xif, sig, pc, A, rp, B);
+      pair_scan_f32<K, R, LB>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xif, sig, pc, A, rp, B);
     }
   }
-  pair_drain_f32<K, R>(queue, kQueue, lane, L, xr, xif, pc, A, rp, B);
+  pair_drain_f32<K, R, LB>(queue, kQueue, lane, L, xr, xif, sig, pc, A, rp, B);
   if (active) {
     const double wi = (double)xif[sc];
     ar.e0[sc] = A.e;
@@ -740,9 +749,15 @@ hipError_t launch_pair_k(mls_plan_s* P, int n, hipStream_t s, const PairRep* rep
   return launch_one<PairGeneric<K>>(a, (n + kBlock - 1) / kBlock, s);
 }
 
-// Lorentz-Berthelot (FP64 plans): the same kernels with the LB source weight.
+// Lorentz-Berthelot: the same kernels with the LB source weight.
 template <int K>
 hipError_t launch_pair_lb_k(mls_plan_s* P, int n, hipStream_t s) {
+  if (P->precision == MLS_MIXED && P->pair_fast && n < (1 << 24)) {
+    PairArgsF a{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, P->cg, pair_const_f(P), P->d_e0,
+                P->d_floc};
+    a.sig = P->d_sigf;
+    return launch_one<PairTrimF32<K, false, true>>(a, (n + kWaveQ - 1) / kWaveQ, s);
+  }
   PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, P->cg, pair_const(P), P->d_e0, P->d_floc, P->d_sig};
   if (P->pair_fast && n < (1 << 25)) return launch_one<PairTrimF64<K, true>>(a, (n + kWaveQ - 1) / kWaveQ, s);
   if (!P->pair_fast) return launch_one<PairWave<K, true>>(a, n, s);
@@ -763,19 +778,26 @@ hipError_t launch_pair(mls_plan_s* P, int n, hipStream_t s, const PairRep* rep, 
 }
 
 template <int K>
-hipError_t launch_batched_pair_k(const BatchPhase& ph, hipStream_t s) {
+hipError_t launch_batched_pair_k(const BatchPhase& ph, hipStream_t s, bool lb) {
   switch (ph.kernel) {
-    case BK_PAIR_GENERIC: return launch_batched_phase<PairGeneric<K>>(ph, s);
-    case BK_PAIR_WAVE: return launch_batched_phase<PairWave<K>>(ph, s);
-    case BK_PAIR_TRIM_F64: return launch_batched_phase<PairTrimF64<K>>(ph, s);
-    case BK_PAIR_TRIM_F32: return launch_batched_phase<PairTrimF32<K>>(ph, s);
+    case BK_PAIR_GENERIC:
+      return lb ? launch_batched_phase<PairGeneric<K, true>>(ph, s) : launch_batched_phase<PairGeneric<K>>(ph, s);
+    case BK_PAIR_WAVE:
+      return lb ? launch_batched_phase<PairWave<K, true>>(ph, s) : launch_batched_phase<PairWave<K>>(ph, s);
+    case BK_PAIR_TRIM_F64:
+      return lb ? launch_batched_phase<PairTrimF64<K, true>>(ph, s) : launch_batched_phase<PairTrimF64<K>>(ph, s);
+    case BK_PAIR_TRIM_F32:
+      return lb ? launch_batched_phase<PairTrimF32<K, false, true>>(ph, s)
+                : launch_batched_phase<PairTrimF32<K>>(ph, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-// Batched phases of this file; variant = the pair_variant of its boxes.
+// Batched phases of this file; variant = the pair_variant of its boxes, | 0x10
+// under Lorentz-Berthelot mixing.
 hipError_t launch_batched_pair(const BatchPhase& ph, hipStream_t s) {
-  return ph.variant == 2 ? launch_batched_pair_k<2>(ph, s) : launch_batched_pair_k<0>(ph, s);
+  const bool lb = (ph.variant & 0x10) != 0;
+  return (ph.variant & 0xf) == 2 ? launch_batched_pair_k<2>(ph, s, lb) : launch_batched_pair_k<0>(ph, s, lb);
 }
 
 }  // namespace mls

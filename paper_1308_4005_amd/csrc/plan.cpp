@@ -175,10 +175,6 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
     set_error("mixing must be MLS_GEOMETRIC or MLS_LORENTZ_BERTHELOT");
     return MLS_ERR_INVALID_ARG;
   }
-  if (p.mixing == MLS_LORENTZ_BERTHELOT && p.precision != MLS_FP64) {
-    set_error("Lorentz-Berthelot mixing is available in FP64 plans only");
-    return MLS_ERR_UNSUPPORTED;
-  }
   P->mixing = p.mixing;
   if (!(std::isfinite(p.skin) && p.skin >= 0.0 && p.skin < p.cutoff)) {
     set_error("skin must be finite with 0 <= skin < a");
@@ -427,9 +423,6 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
     } else {
       L.E = L.e;  // the coarsest level has nothing to prolongate into it
     }
-    if (P->precision == MLS_MIXED && k < l) {
-      ALLOC(L.qf, L.g.size);
-    }
   }
   if (P->mixing == MLS_GEOMETRIC) {
     // molecular dynamics: repulsive term and integrator (mls_evaluate_md, mls_md_run)
@@ -449,12 +442,19 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   if (P->mixing == MLS_LORENTZ_BERTHELOT) {
     // seven charge vectors: one set of grids each (Sec. II.D)
     ALLOC(P->d_sig, N + kSortedPad);
-    ALLOC(P->d_charge, N + kSortedPad);
+    const int slots = P->lb_slots > 1 ? 7 : 1;
+    P->lb_slots = slots;
+    P->lb_stride = N + kSortedPad;
+    ALLOC(P->d_charge, (size_t)slots * P->lb_stride);
+    if (P->precision == MLS_MIXED) {
+      ALLOC(P->d_sigf, N + kSortedPad);
+      P->lb_npart = (int)((P->lb_stride + 255) / 256);
+      ALLOC(P->d_lb_partial, (size_t)slots * P->lb_npart);
+    }
     for (int r = 0; r < 7; ++r) {
       P->lb_lv[r] = P->lv;
       for (int k = 1; k <= l; ++k) {
         Level& L = P->lb_lv[r][k - 1];
-        L.qf = L.ef = nullptr;
         ALLOC(L.q, L.g.size);
         ALLOC(L.e, L.g.size);
         if (k < l) {
@@ -476,7 +476,8 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   ALLOC(P->d_Kl, P->Kl.size());
   if (P->ant_tiles) {
     ALLOC(P->d_ant_tab, ant_tab.size());
-    ALLOC(P->d_ant_scratch, ant_scratch);
+    P->ant_scratch_n = ant_scratch;
+    ALLOC(P->d_ant_scratch, ant_scratch * (P->mixing == MLS_LORENTZ_BERTHELOT ? P->lb_slots : 1));
   }
 #undef ALLOC
   hipError_t e;

@@ -395,7 +395,7 @@ hipError_t launch_tile(mls_plan_s* P, const T* wts, hipStream_t s, int kmax) {
     V.rows = P->d_rows;
     V.wave_rows = P->d_wave_rows;
     V.wts = wts;
-    V.sum_xi = P->d_scratch;
+    V.sum_xi = P->sum_q ? P->sum_q : P->d_scratch;
     V.wsum = P->taps_wsum;
     t += nblocks(Lv.g.n[0], 8) * nblocks(Lv.g.n[1], 8) * V.tiles_z;
     // the tile table lists the levels in order: levels 1..kmax are its head
