@@ -53,7 +53,7 @@ constexpr int kSortedPad = 16;
 
 // Waves per block of the level-stencil kernel; the tap columns are split
 // into this many cost-balanced contiguous ranges at plan time.
-constexpr int kStencilWaves = 4;
+constexpr int kStencilWaves = 8;
 
 // Per-level bookkeeping of the grid hierarchy.
 struct Level {

@@ -216,8 +216,9 @@ template <class T, int R, int ZC, int W>
 __device__ __forceinline__ void stencil_tile(const StencilLevel& V, const int4 tinfo) {
   constexpr int SX = 8 + 2 * R, SY = 8 + 2 * R, SZ = ZC + 2 * R;
   constexpr int PS = SX * SY, NP = PS * SZ, NT = 64 * W;
-  static_assert(W * ZC * 64 <= NP, "reduction buffer must fit in the tile");
-  __shared__ T tile[NP];
+  // the tile doubles as the reduction buffer of the W partial sums
+  constexpr int NL = NP > W * ZC * 64 ? NP : W * ZC * 64;
+  __shared__ T tile[NL];
   __shared__ int wrapx[SX], wrapy[SY], wrapz[SZ];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -229,9 +230,23 @@ __device__ __forceinline__ void stencil_tile(const StencilLevel& V, const int4 t
   const size_t gps = (size_t)V.n[0] * V.n[1];
   const double* __restrict__ q = V.q;
   const double mean = sizeof(T) < sizeof(double) ? *V.sum_xi * V.inv_size : 0.0;
-  for (int i = tid; i < NP; i += NT) {
-    const int lx = i % SX, ly = (i / SX) % SY, lz = i / PS;
-    tile[i] = (T)(q[(size_t)wrapz[lz] * gps + (size_t)wrapy[ly] * V.n[0] + wrapx[lx]] - mean);
+  // the fill issues kFill global loads per thread before it waits for them
+  // (one load per wait leaves the block waiting on memory latency NP / NT
+  // times); indexes past the box are clamped, so every load is in range
+  constexpr int kIters = (NP + NT - 1) / NT, kFill = 8;
+  for (int b0 = 0; b0 < kIters; b0 += kFill) {
+    double v[kFill];
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const int i = min(tid + (b0 + u) * NT, NP - 1);
+      const int lx = i % SX, ly = (i / SX) % SY, lz = i / PS;
+      v[u] = q[(size_t)wrapz[lz] * gps + (size_t)wrapy[ly] * V.n[0] + wrapx[lx]];
+    }
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const int i = tid + (b0 + u) * NT;
+      if (i < NP) tile[i] = (T)(v[u] - mean);
+    }
   }
   __syncthreads();
   // lanes 0-31 take the even rows, 32-63 the odd ones: with a row pitch of
@@ -241,6 +256,8 @@ __device__ __forceinline__ void stencil_tile(const StencilLevel& V, const int4 t
   T acc[ZC];
 #pragma unroll
   for (int k = 0; k < ZC; ++k) acc[k] = T(0);
+  // the column index is wave-uniform, so the rows and weights are scalar
+  // loads (staging them in LDS measured slower)
   const StencilRow* __restrict__ rows = V.rows;
   const T* __restrict__ wts = (const T*)V.wts;
   const int r0 = V.wave_rows[wv], r1 = V.wave_rows[wv + 1];
