@@ -194,7 +194,8 @@ mls_status build_phases(mls_batch_s* B) {
       set_box(rk, b, RankArgs{P->d_cell_start, P->d_perm_tmp, n, P->d_perm}, nblk(n, 256));
       const bool xi_sum = mixed && !lb;
       set_box(ga, b, GatherArgs{P->d_perm, n, P->d_xw, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, P->cg,
-                                xi_sum ? P->d_partial : nullptr}, nblk(n + kSortedPad, 256));
+                                xi_sum ? P->d_partial : nullptr, P->d_xf, P->xf_stride},
+              nblk(n + kSortedPad, 256));
       if (xi_sum) set_box(x2, b, SumXiArgs{n + kSortedPad, P->d_partial, P->d_scratch}, 1);
       if (lb)
         set_box(sg, b, LbGatherArgs{P->d_perm, n, B->sigma + o, P->d_sig, P->d_flags, P->d_sigf},
@@ -223,6 +224,8 @@ mls_status build_phases(mls_batch_s* B) {
         PairArgsF af{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const_f(P), P->d_e0,
                      P->d_floc};
         af.sig = lb ? P->d_sigf : nullptr;
+        af.xf = P->d_xf;
+        af.xf_stride = P->xf_stride;
         set_box(f32, b, af, nblk(n, 64));
       } else if (P->pair_fast && n < (1 << 25)) {
         set_box(f64, b, a, nblk(n, 64));

@@ -258,8 +258,12 @@ struct RankGather {
         const int cx = max(0, min((int)(p.x * g.inv_w[0]), g.nc[0] - 1));
         const int cy = max(0, min((int)(p.y * g.inv_w[1]), g.nc[1] - 1));
         const int cz = max(0, min((int)(p.z * g.inv_w[2]), g.nc[2] - 1));
-        a.xr[d] = make_float4((float)(p.x - cx * g.w[0]), (float)(p.y - cy * g.w[1]), (float)(p.z - cz * g.w[2]),
-                              (float)cx);
+        const float4 r = make_float4((float)(p.x - cx * g.w[0]), (float)(p.y - cy * g.w[1]),
+                                     (float)(p.z - cz * g.w[2]), (float)cx);
+        a.xr[d] = r;
+        a.xf[d] = (float)p.x;
+        a.xf[a.xf_stride + d] = r.y;
+        a.xf[2 * a.xf_stride + d] = r.z;
         a.xif[d] = (float)p.w;
       }
     } else if (s < a.n + kSortedPad) {
@@ -267,6 +271,7 @@ struct RankGather {
       a.xs[s] = make_double4(1e300, 1e300, 1e300, 0.0);
       if (a.xr) {
         a.xr[s] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+        for (int k = 0; k < 3; ++k) a.xf[k * a.xf_stride + s] = 1e30f;
         a.xif[s] = 0.0f;
       }
     }
@@ -322,7 +327,12 @@ struct Regather {
     }
     const double w = a.xs[s].w;
     a.xs[s] = make_double4(x[0], x[1], x[2], w);
-    if (a.xr) a.xr[s] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)cx);
+    if (a.xr) {
+      a.xr[s] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)cx);
+      a.xf[s] = (float)x[0];
+      a.xf[a.xf_stride + s] = (float)r[1];
+      a.xf[2 * a.xf_stride + s] = (float)r[2];
+    }
   }
 };
 
@@ -349,8 +359,12 @@ struct GatherSorted {
       if (a.xr) {
         // cell-relative FP32 coordinates and the cell x index (exact in FP32)
         // for the mixed-precision pair kernel
-        a.xr[s] = make_float4((float)(p.x - cx * g.w[0]), (float)(p.y - cy * g.w[1]),
-                              (float)(p.z - cz * g.w[2]), (float)cx);
+        const float4 r = make_float4((float)(p.x - cx * g.w[0]), (float)(p.y - cy * g.w[1]),
+                                     (float)(p.z - cz * g.w[2]), (float)cx);
+        a.xr[s] = r;
+        a.xf[s] = (float)p.x;
+        a.xf[a.xf_stride + s] = r.y;
+        a.xf[2 * a.xf_stride + s] = r.z;
         a.xif[s] = (float)p.w;
       }
     } else if (s < a.n + kSortedPad) {
@@ -358,6 +372,7 @@ struct GatherSorted {
       a.xs[s] = make_double4(1e300, 1e300, 1e300, 0.0);
       if (a.xr) {
         a.xr[s] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+        for (int k = 0; k < 3; ++k) a.xf[k * a.xf_stride + s] = 1e30f;
         a.xif[s] = 0.0f;
       }
     }
@@ -522,7 +537,7 @@ static hipError_t binning_core(mls_plan_s* P, int n, const double* pos, const do
                                   nblocks(n, kBlock), s)) != hipSuccess)
     return e;
   RankGatherArgs ra{P->d_cell_start, P->d_perm_tmp, n, P->d_perm, P->d_xw, P->d_xs, P->d_cell_s, P->d_xr,
-                    P->d_xif, g, cond};
+                    P->d_xif, g, cond, P->d_xf, P->xf_stride};
   return launch_one<RankGather>(ra, nblocks(n + kSortedPad, kBlock), s);
 }
 
@@ -545,7 +560,8 @@ hipError_t launch_binning_reuse(mls_plan_s* P, int n, const double* pos, const d
   }
   if ((e = binning_core(P, n, pos, c6, 1.0, P->d_rebin, P->d_xref, s)) != hipSuccess) return e;
   if (n == 0) return hipSuccess;
-  RegatherArgs ra{pos, P->d_perm, P->d_cell_s, n, P->cg, P->d_rebin, P->d_xs, P->d_xr};
+  RegatherArgs ra{pos, P->d_perm, P->d_cell_s, n, P->cg, P->d_rebin, P->d_xs, P->d_xr, P->d_xf,
+                  P->xf_stride};
   return launch_one<Regather>(ra, nblocks(n, kBlock), s);
 }
 

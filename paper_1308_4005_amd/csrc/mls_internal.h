@@ -94,6 +94,8 @@ struct PairConstF {
   float a2, inv_a2, inv_a6, inv_a8;
   float w[3];
   float gc[5], gq[4];
+  float a2f;    // filter threshold: a^2 widened by the FP32 rounding of absolute x
+  float L[3];   // box (periodic image shift of the filter's x)
 };
 
 struct OutPtrs {
@@ -118,7 +120,7 @@ struct BinCountArgs {
 struct DispCheckArgs { const double* pos; const double* xref; int n; double lim2; int* cond; };
 struct RegatherArgs {
   const double* pos; const int* perm; const int* cell_s; int n; CellGeom g; const int* cond;
-  double4* xs; float4* xr;
+  double4* xs; float4* xr; float* xf; int xf_stride;
 };
 // molecular dynamics (md.hip): repulsion of eq:disp-pair-pot and velocity Verlet
 struct RepGatherArgs { const int* perm; const double* c12; int n; double* x12s; float* x12f; int* flags; };
@@ -157,11 +159,15 @@ struct RankGatherArgs {
   const int* start; const int2* perm_tmp; int n; int* perm; const double4* xw;
   double4* xs; int* cell_s; float4* xr; float* xif; CellGeom g;
   const int* cond = nullptr;
+  float* xf = nullptr;    // mixed precision: filter coordinates x, y, z (absolute x, cell-relative y, z), SoA
+  int xf_stride = 0;      // floats per coordinate array of xf
 };
 struct GatherArgs {
   const int* perm; int n; const double4* xw;
   double4* xs; int* cell_s; float4* xr; float* xif; CellGeom g;
   double* xi_partial;   // mixed precision: per-block sums of xi (else null)
+  float* xf = nullptr;  // mixed precision: filter coordinates, SoA
+  int xf_stride = 0;
 };
 struct SumXiArgs { int rows; const double* partial; double* out; };   // partials of ceil(rows / 256) gather blocks
 // The repulsive term of the MD entry points, evaluated by the pair kernels on
@@ -182,6 +188,8 @@ struct PairArgsF {
   int n; CellGeom g; PairConstF pc; double* e0; double* floc;
   PairRep rep{};
   const float* sig = nullptr;   // Lorentz-Berthelot: sorted sigma in FP32
+  const float* xf = nullptr;    // filter coordinates: x (absolute), y, z (cell-relative) arrays
+  int xf_stride = 0;            // floats per array
 };
 struct AnterpArgs {
   const double4* xs; const int* cstart; int n; CellGeom cg; GridGeom gg; AntGeom ag; double* q;
@@ -385,6 +393,8 @@ struct mls_plan_s {
   int* d_cell_s = nullptr;         // n_max: cell of sorted atom
   double4* d_xs = nullptr;         // n_max: sorted
   float4* d_xr = nullptr;          // n_max + pad: sorted, cell-relative FP32 x,y,z and cell x index (mixed)
+  float* d_xf = nullptr;           // 3 x xf_stride: sorted FP32 filter coordinates, absolute x, cell-relative y, z (mixed)
+  int xf_stride = 0;               // floats per coordinate array of d_xf (n_max + pad)
   float* d_xif = nullptr;          // n_max + pad: sorted xi in FP32 (mixed)
   double* d_e0 = nullptr;          // n_max sorted local potential
   double* d_floc = nullptr;        // 3 n_max sorted local force / (xi_i)

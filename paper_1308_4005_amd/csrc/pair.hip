@@ -494,6 +494,7 @@ struct PairLaneF {
   int self_ent;         // the target's own home-row entry (-1 for idle lanes)
   int safe_j;           // a valid source index for idle drain slots
   float sig_i;          // Lorentz-Berthelot: the target's sigma
+  float xa;             // target absolute x (filter)
 };
 
 // Queue entry: source index << 8 | x image ix (2 bits) | dy (3 bits) | dz (3
@@ -521,7 +522,13 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
     const bool ok = (t < cnt) & (q != L.self_ent);
     const int ent = ok ? q : 0;
     const int j = ok ? (int)((unsigned)ent >> 8) : L.safe_j;
-    const float4 xj = xr[j];
+    // idle slots load nothing (they take a harmless far pair of weight 0)
+    float4 xj = make_float4(L.xx + pc.w[0], L.yy, L.zz, L.cxf);
+    float wsrc = 0.0f;
+    if (ok) {
+      xj = xr[j];
+      wsrc = xif[j];
+    }
     const int ix = (ent << 30) >> 30, dy = (ent << 27) >> 29, dz = (ent << 24) >> 29;
     const float bx = fmaf((float)ix, -L.ncf, L.cxf);
     const float dxv = fmaf(bx - xj.w, pc.w[0], L.xx) - xj.x;
@@ -530,7 +537,7 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
     const float r2 = ok ? dxv * dxv + dyv * dyv + dzv * dzv : r2_idle;
     float gg, fr;
     g0_pair<float, K>(r2, pc, gg, fr);
-    float wj = ok ? xif[j] : 0.0f;
+    float wj = wsrc;
     if constexpr (LB) {
       // source weight e_j ((sigma_i + sigma_j) / 2)^6, as in the FP64 kernels
       const float m = 0.5f * (L.sig_i + sig[j]);
@@ -571,31 +578,50 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
 // Scan sources [j, j1) of one row run (image ix along x, row offsets dy, dz).
 // The filter loop touches no accumulator: it stops when a queue may
 // overflow, the queues are partly drained, and the filter resumes.
+// The filter takes x from the absolute FP32 coordinates (one subtraction per
+// candidate instead of rebuilding the cell offset) and y, z cell-relative;
+// its threshold a2f covers the rounding of absolute x (a few ulp of L), and
+// the few extra pairs it passes, just outside a, add g_0 ~ 0 in the drain,
+// which rebuilds the displacement exactly from the cell-relative data.  The
+// coordinates are three arrays, so one 16-byte load brings one coordinate of
+// a batch of four candidates; lanes past the end of their run load nothing.
+// The vector memory pipeline, as much as the ALU, bounds this loop.
+__device__ __forceinline__ float4 load4f(const float* p) {
+  float4 v;
+  __builtin_memcpy(&v, p, sizeof(v));   // 4-byte aligned 16-byte load
+  return v;
+}
+
 template <int K, bool R, bool LB>
 __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int dz, int* __restrict__ queue,
                                               int lane, const PairLaneF& L, const float4* __restrict__ xr,
-                                              const float* __restrict__ xif, const float* __restrict__ sig,
-                                              const PairConstF& pc, PairAccM& A, const PairRep& rp, RepAcc& B) {
-  // the drain rebuilds these with the same operations
-  const float bx = fmaf((float)ix, -L.ncf, L.cxf);
+                                              const float* __restrict__ xf, int xfs, const float* __restrict__ xif,
+                                              const float* __restrict__ sig, const PairConstF& pc, PairAccM& A,
+                                              const PairRep& rp, RepAcc& B) {
+  static_assert(kBatchF == 4, "one 16-byte load per coordinate and batch");
+  const float ax = fmaf((float)-ix, pc.L[0], L.xa);
   const float ay = fmaf((float)-dy, pc.w[1], L.yy);
   const float az = fmaf((float)-dz, pc.w[2], L.zz);
   const int bits = entry_bits(ix, dy, dz);
   int* const qlane = queue + lane;
+  // loop-carried, so a finished lane keeps stale values; j + b < j1 masks them
+  float4 X = make_float4(0.0f, 0.0f, 0.0f, 0.0f), Y = X, Z = X;
   for (;;) {
     int cnt = A.cnt;
     const int head = A.head;
     bool full = false;
     while (__any(j < j1)) {
-      float4 xj[kBatchF];
-#pragma unroll
-      for (int b = 0; b < kBatchF; ++b) xj[b] = xr[j + b];
+      if (j < j1) {
+        X = load4f(xf + j);
+        Y = load4f(xf + xfs + j);
+        Z = load4f(xf + 2 * xfs + j);
+      }
+      const float xb[4] = {X.x, X.y, X.z, X.w}, yb[4] = {Y.x, Y.y, Y.z, Y.w}, zb[4] = {Z.x, Z.y, Z.z, Z.w};
 #pragma unroll
       for (int b = 0; b < kBatchF; ++b) {
-        const float dxv = fmaf(bx - xj[b].w, pc.w[0], L.xx) - xj[b].x;
-        const float dyv = ay - xj[b].y, dzv = az - xj[b].z;
+        const float dxv = ax - xb[b], dyv = ay - yb[b], dzv = az - zb[b];
         const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
-        const bool hit = (j + b < j1) & (r2 < pc.a2);
+        const bool hit = (j + b < j1) & (r2 < pc.a2f);
         qlane[kWaveQ * ((head + cnt) & (kQueue - 1))] = ((j + b) << 8) | bits;
         cnt += hit ? 1 : 0;
       }
@@ -631,8 +657,10 @@ struct PairTrimF32 {
   const int c = ar.cell_s[sc];
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
   const float* __restrict__ sig = ar.sig;
+  const float* __restrict__ xf = ar.xf;
+  const int xfs = ar.xf_stride;
   const PairLaneF L{xi.x, xi.y, xi.z, (float)cx, (float)g.nc[0], active ? ((sc << 8) | entry_bits(0, 0, 0)) : -1, sc,
-                    LB ? sig[sc] : 0.0f};
+                    LB ? sig[sc] : 0.0f, xf[sc]};
   PairAccM A{0.0, 0.0, 0.0, 0.0, 0};
   RepAcc B{0.0, 0.0, 0.0, 0.0};
   const PairRep& rp = ar.rep;
@@ -688,8 +716,8 @@ struct PairTrimF32 {
         k0 = cstart[row + lo2];
         k1 = cstart[row + hi2 + 1];
       }
-      pair_scan_f32<K, R, LB>(j0, j1, ix1, dy, dz, queue, lane, L, xr, xif, sig, pc, A, rp, B);
-      pair_scan_f32<K, R, LB>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xif, sig, pc, A, rp, B);
+      pair_scan_f32<K, R, LB>(j0, j1, ix1, dy, dz, queue, lane, L, xr, xf, xfs, xif, sig, pc, A, rp, B);
+      pair_scan_f32<K, R, LB>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xf, xfs, xif, sig, pc, A, rp, B);
     }
   }
   pair_drain_f32<K, R, LB>(queue, kQueue, lane, L, xr, xif, sig, pc, A, rp, B);
@@ -719,6 +747,15 @@ PairConstF pair_const_f(const mls_plan_s* P) {
                 {(float)P->cg.w[0], (float)P->cg.w[1], (float)P->cg.w[2]}, {}, {}};
   for (int j = 0; j < 5; ++j) pf.gc[j] = (float)pc.gc[j];
   for (int j = 0; j < 4; ++j) pf.gq[j] = (float)pc.gq[j];
+  for (int d = 0; d < 3; ++d) pf.L[d] = (float)P->cg.L[d];
+  // filter threshold: |dx| of the filter is within ex of the exact value
+  // (absolute coordinates and the image shift rounded to FP32, at most a few
+  // ulp of L + a; neighbour reuse lets atoms sit skin/2 outside the box), so
+  // r^2 < a^2 + 2 a ex + ex^2 plus FP32 rounding of the sum catches every pair
+  // inside the cutoff
+  const double a = std::sqrt(pc.a2);
+  const double ex = 4.0 * (P->cg.L[0] + P->cg.margin + a) * std::ldexp(1.0, -24);
+  pf.a2f = std::nextafter((float)(pc.a2 * (1.0 + 4.0 * std::ldexp(1.0, -23)) + 2.0 * a * ex + ex * ex), INFINITY);
   return pf;
 }
 
@@ -731,6 +768,8 @@ hipError_t launch_pair_k(mls_plan_s* P, int n, hipStream_t s, const PairRep* rep
   if (P->precision == MLS_MIXED && P->pair_fast && n < (1 << 24)) {
     PairArgsF a{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const_f(P), P->d_e0,
                 P->d_floc};
+    a.xf = P->d_xf;
+    a.xf_stride = P->xf_stride;
     if (!rep) return launch_one<PairTrimF32<K>>(a, waves, s);
     a.rep = *rep;
     *fused = true;
@@ -756,6 +795,8 @@ hipError_t launch_pair_lb_k(mls_plan_s* P, int n, hipStream_t s) {
     PairArgsF a{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, P->cg, pair_const_f(P), P->d_e0,
                 P->d_floc};
     a.sig = P->d_sigf;
+    a.xf = P->d_xf;
+    a.xf_stride = P->xf_stride;
     return launch_one<PairTrimF32<K, false, true>>(a, (n + kWaveQ - 1) / kWaveQ, s);
   }
   PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, P->cg, pair_const(P), P->d_e0, P->d_floc, P->d_sig};

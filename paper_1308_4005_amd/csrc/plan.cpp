@@ -407,6 +407,8 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   ALLOC(P->d_floc, 3 * N);
   if (P->precision == MLS_MIXED) {
     ALLOC(P->d_xr, N + kSortedPad);
+    P->xf_stride = (int)(N + kSortedPad);
+    ALLOC(P->d_xf, 3 * (size_t)P->xf_stride);
     ALLOC(P->d_xif, N + kSortedPad);
   }
   P->n_partial = (int)((N + 255) / 256);
