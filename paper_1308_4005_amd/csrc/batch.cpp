@@ -220,6 +220,8 @@ mls_status build_phases(mls_batch_s* B) {
       const CellGeom& g = P->cg;
       PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const(P), P->d_e0, P->d_floc,
                  lb ? P->d_sig : nullptr};
+      a.xf = P->d_xf;
+      a.xf_stride = P->xf_stride;
       if (mixed && P->pair_fast && n < (1 << 24)) {
         PairArgsF af{P->d_xr, P->d_xif, P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const_f(P), P->d_e0,
                      P->d_floc};

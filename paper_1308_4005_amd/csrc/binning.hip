@@ -233,6 +233,37 @@ struct CellRank {
   }
 };
 
+// FP32 rows of sorted atom d from its wrapped position p: the filter
+// coordinates of the pair kernels (absolute x, cell-relative y and z; three
+// arrays of xf_stride floats) and, for mixed-precision plans, the
+// cell-relative coordinates with the cell x index (exact in FP32) and xi.
+// The cell is the one BinCount took from the same wrapped position.
+__device__ __forceinline__ void store_fp32_rows(float4* xr, float* xif, float* xf, int xfs, const CellGeom& g, int d,
+                                                const double4& p) {
+  if (!xf) return;
+  const int cx = max(0, min((int)(p.x * g.inv_w[0]), g.nc[0] - 1));
+  const int cy = max(0, min((int)(p.y * g.inv_w[1]), g.nc[1] - 1));
+  const int cz = max(0, min((int)(p.z * g.inv_w[2]), g.nc[2] - 1));
+  const float ry = (float)(p.y - cy * g.w[1]), rz = (float)(p.z - cz * g.w[2]);
+  xf[d] = (float)p.x;
+  xf[xfs + d] = ry;
+  xf[2 * xfs + d] = rz;
+  if (xr) {
+    xr[d] = make_float4((float)(p.x - cx * g.w[0]), ry, rz, (float)cx);
+    xif[d] = (float)p.w;
+  }
+}
+
+// Padding rows: far outside any cutoff, zero weight.
+__device__ __forceinline__ void store_fp32_pad(float4* xr, float* xif, float* xf, int xfs, int s) {
+  if (xf)
+    for (int k = 0; k < 3; ++k) xf[k * xfs + s] = 1e30f;
+  if (xr) {
+    xr[s] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+    xif[s] = 0.0f;
+  }
+}
+
 struct RankGather {
   using Args = RankGatherArgs;
   static constexpr int kThreads = kBlock;
@@ -250,30 +281,11 @@ struct RankGather {
       const double4 p = a.xw[v];
       a.xs[d] = p;
       a.cell_s[d] = c;
-      if (a.xr) {
-        // cell-relative FP32 coordinates and the cell x index (exact in FP32)
-        // for the mixed-precision pair kernel; the cell from the same
-        // wrapped position as BinCount
-        const CellGeom& g = a.g;
-        const int cx = max(0, min((int)(p.x * g.inv_w[0]), g.nc[0] - 1));
-        const int cy = max(0, min((int)(p.y * g.inv_w[1]), g.nc[1] - 1));
-        const int cz = max(0, min((int)(p.z * g.inv_w[2]), g.nc[2] - 1));
-        const float4 r = make_float4((float)(p.x - cx * g.w[0]), (float)(p.y - cy * g.w[1]),
-                                     (float)(p.z - cz * g.w[2]), (float)cx);
-        a.xr[d] = r;
-        a.xf[d] = (float)p.x;
-        a.xf[a.xf_stride + d] = r.y;
-        a.xf[2 * a.xf_stride + d] = r.z;
-        a.xif[d] = (float)p.w;
-      }
+      store_fp32_rows(a.xr, a.xif, a.xf, a.xf_stride, a.g, d, p);
     } else if (s < a.n + kSortedPad) {
       // padding rows: far outside any cutoff, zero weight
       a.xs[s] = make_double4(1e300, 1e300, 1e300, 0.0);
-      if (a.xr) {
-        a.xr[s] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
-        for (int k = 0; k < 3; ++k) a.xf[k * a.xf_stride + s] = 1e30f;
-        a.xif[s] = 0.0f;
-      }
+      store_fp32_pad(a.xr, a.xif, a.xf, a.xf_stride, s);
     }
   }
 };
@@ -327,8 +339,8 @@ struct Regather {
     }
     const double w = a.xs[s].w;
     a.xs[s] = make_double4(x[0], x[1], x[2], w);
-    if (a.xr) {
-      a.xr[s] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)cx);
+    if (a.xr) a.xr[s] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)cx);
+    if (a.xf) {
       a.xf[s] = (float)x[0];
       a.xf[a.xf_stride + s] = (float)r[1];
       a.xf[2 * a.xf_stride + s] = (float)r[2];
@@ -356,25 +368,11 @@ struct GatherSorted {
       a.xs[s] = p;
       a.cell_s[s] = c;
       xi = p.w;
-      if (a.xr) {
-        // cell-relative FP32 coordinates and the cell x index (exact in FP32)
-        // for the mixed-precision pair kernel
-        const float4 r = make_float4((float)(p.x - cx * g.w[0]), (float)(p.y - cy * g.w[1]),
-                                     (float)(p.z - cz * g.w[2]), (float)cx);
-        a.xr[s] = r;
-        a.xf[s] = (float)p.x;
-        a.xf[a.xf_stride + s] = r.y;
-        a.xf[2 * a.xf_stride + s] = r.z;
-        a.xif[s] = (float)p.w;
-      }
+      store_fp32_rows(a.xr, a.xif, a.xf, a.xf_stride, g, s, p);
     } else if (s < a.n + kSortedPad) {
       // padding rows: far outside any cutoff, zero weight
       a.xs[s] = make_double4(1e300, 1e300, 1e300, 0.0);
-      if (a.xr) {
-        a.xr[s] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
-        for (int k = 0; k < 3; ++k) a.xf[k * a.xf_stride + s] = 1e30f;
-        a.xif[s] = 0.0f;
-      }
+      store_fp32_pad(a.xr, a.xif, a.xf, a.xf_stride, s);
     }
     if (a.xi_partial) {
       // per-block sum of xi (fixed order)

@@ -88,6 +88,9 @@ struct AntGeom {
 struct PairConst {
   double a2, inv_a2, inv_a6, inv_a8;
   double gc[5], gq[4];
+  // FP32 candidate filter of the FP64 kernel: threshold (a^2 widened by the
+  // FP32 rounding of the filter coordinates), cell widths, box
+  float a2f, wf[3], Lf[3];
 };
 
 struct PairConstF {
@@ -182,6 +185,8 @@ struct PairArgs {
   double* e0; double* floc;
   const double* sig;      // Lorentz-Berthelot: sorted sigma (source weight e_j s_ij^6)
   PairRep rep{};
+  const float* xf = nullptr;   // FP32 filter coordinates (three arrays of xf_stride floats)
+  int xf_stride = 0;
 };
 struct PairArgsF {
   const float4* xr; const float* xif; const double4* xs; const int* cell_s; const int* cstart;

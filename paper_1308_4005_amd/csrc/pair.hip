@@ -227,19 +227,23 @@ struct PairWave {
 // of cells around its target's cell, skips rows whose y/z gap to the target
 // is at least a, and trims every other row to the cells the cutoff sphere
 // can reach along x (at most two runs of cells: one per periodic image).  A
-// cheap distance test appends sources inside the cutoff to the lane's LDS
-// queue (a ring), kBatch candidates per step with their loads in flight
-// together (2 for FP64, 4 for FP32: measured at 10^6 atoms, FP64 0.867 ms
-// with 2 against 0.893 ms with 4, FP32 0.499 ms with 4 against 0.502 with 2);
-// whenever a queue may overflow all lanes drain up to kDrain of their oldest
-// entries through the full g_0 evaluation, and at the end everything left,
-// so the expensive arithmetic runs on nearly full waves instead of being
-// masked per candidate.  An entry packs the source index (< 2^25) with two
-// bits per dimension for its image.
+// cheap FP32 distance test (both precisions; see pair_scan_f32) appends
+// sources inside the cutoff to the lane's LDS queue (a ring), four
+// candidates per step; whenever a queue may overflow all lanes drain up to
+// kDrain of their oldest entries through the full g_0 evaluation, and at the
+// end everything left, so the expensive arithmetic runs on nearly full waves
+// instead of being masked per candidate.  An FP64 entry packs the source
+// index (< 2^25) with two bits per dimension for its image.
 constexpr int kWaveQ = 64;    // lanes per block (one wave)
 constexpr int kQueue = 32;    // entries per lane
-constexpr int kBatch = 2;     // candidates per filter step (FP64 kernel)
-constexpr int kBatchF = 4;    // candidates per filter step (FP32 kernel)
+constexpr int kBatchF = 4;    // candidates per filter step
+
+// 16-byte load from a 4-byte aligned address (four consecutive floats)
+__device__ __forceinline__ float4 load4f(const float* p) {
+  float4 v;
+  __builtin_memcpy(&v, p, sizeof(v));   // 4-byte aligned 16-byte load
+  return v;
+}
 
 __device__ __forceinline__ int image_bits(int ix, int iy, int iz) { return (ix + 1) | ((iy + 1) << 2) | ((iz + 1) << 4); }
 
@@ -279,14 +283,17 @@ __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, in
     const double sy = (double)(((ent >> 2) & 3) - 1) * g.L[1];
     const double sz = (double)(((ent >> 4) & 3) - 1) * g.L[2];
     const double4 xj = xs[j];
-    // same arithmetic as the filter
     const double dx = (xi.x - sx) - xj.x;
     const double dy = (xi.y - sy) - xj.y;
     const double dz = (xi.z - sz) - xj.z;
-    const double r2 = ok ? dx * dx + dy * dy + dz * dz : r2_idle;
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    // the FP32 filter passes a superset: the pair set is decided here, in
+    // FP64, by r^2 < a^2 (rejected entries add exactly 0)
+    const bool in = ok & (d2 < pc.a2);
+    const double r2 = in ? d2 : r2_idle;
     double gg, fr;
     g0_pair<double, K>(r2, pc, gg, fr);
-    const double wj = ok ? src_weight<LB>(xj.w, sig, sig_i, j) : 0.0;
+    const double wj = in ? src_weight<LB>(xj.w, sig, sig_i, j) : 0.0;
     A.e += wj * gg;
     const double f = wj * fr;
     A.fx += f * dx;
@@ -295,7 +302,7 @@ __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, in
     if constexpr (R) {
       const double ir2 = recip(r2);
       const double ir6 = ir2 * ir2 * ir2;
-      const double v = (ok && r2 < rp.rc2 ? rp.x12[j] : 0.0) * ir6 * ir6;
+      const double v = (in && r2 < rp.rc2 ? rp.x12[j] : 0.0) * ir6 * ir6;
       const double fv = 12.0 * v * ir2;
       B.e += v;
       B.fx += fv * dx;
@@ -308,43 +315,51 @@ __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, in
   A.cnt = cnt - done;
 }
 
-// Scan sources [j, j1) seen through image bits `img` (convergent: every lane
-// calls it; lanes with an empty range just take part in the votes).  Reads
-// may run up to kBatch - 1 rows past j1: the sorted array is padded with
-// far-away rows, and rows past j1 are never kept.  The filter loop touches no
-// accumulator: it stops when a queue may overflow, the queues are partly
-// drained, and the filter resumes.
+// Scan sources [j, j1) seen through image bits `img`, row offsets dy, dz
+// (convergent: every lane calls it; lanes with an empty range just take part
+// in the votes).  Candidates are tested by the FP32 filter of the mixed
+// kernel (absolute x, cell-relative y and z, one 16-byte load per coordinate
+// and batch of four, threshold a2f widened for FP32 rounding): it passes a
+// superset of the pairs inside the cutoff, and the drain decides each pair
+// in FP64.  Reads may run up to three rows past j1 (padded array); lanes
+// past their range load nothing.  The filter loop touches no accumulator: it
+// stops when a queue may overflow, the queues are partly drained, and the
+// filter resumes.
 template <int K, bool LB, bool R>
-__device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int* __restrict__ queue, int lane,
-                                              int self_ent, int safe_j, const double4& xi,
-                                              const double4* __restrict__ xs, const CellGeom& g, const PairConst& pc,
+__device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int dy, int dz, int* __restrict__ queue,
+                                              int lane, int self_ent, int safe_j, const double4& xi, const float3& xf_i,
+                                              const double4* __restrict__ xs, const float* __restrict__ xf, int xfs,
+                                              const CellGeom& g, const PairConst& pc,
                                               const double* __restrict__ sig, double sig_i, PairAcc& A,
                                               const PairRep& rp, RepAcc& B) {
-  const double ax = xi.x - (double)((img & 3) - 1) * g.L[0];
-  const double ay = xi.y - (double)(((img >> 2) & 3) - 1) * g.L[1];
-  const double az = xi.z - (double)(((img >> 4) & 3) - 1) * g.L[2];
+  const float ax = fmaf((float)-((img & 3) - 1), pc.Lf[0], xf_i.x);
+  const float ay = fmaf((float)-dy, pc.wf[1], xf_i.y);
+  const float az = fmaf((float)-dz, pc.wf[2], xf_i.z);
   int* const qlane = queue + lane;
+  // loop-carried, so a finished lane keeps stale values; j + b < j1 masks them
+  float4 X = make_float4(0.0f, 0.0f, 0.0f, 0.0f), Y = X, Z = X;
   for (;;) {
     int cnt = A.cnt;
     const int head = A.head;
     bool full = false;
     while (__any(j < j1)) {
-      double4 xj[kBatch];
+      if (j < j1) {
+        X = load4f(xf + j);
+        Y = load4f(xf + xfs + j);
+        Z = load4f(xf + 2 * xfs + j);
+      }
+      const float xb[4] = {X.x, X.y, X.z, X.w}, yb[4] = {Y.x, Y.y, Y.z, Y.w}, zb[4] = {Z.x, Z.y, Z.z, Z.w};
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) xj[b] = xs[j + b];
-#pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
-        const double dx = ax - xj[b].x, dy = ay - xj[b].y, dz = az - xj[b].z;
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        const bool hit = (j + b < j1) & (r2 < pc.a2);
+      for (int b = 0; b < 4; ++b) {
+        const float dxv = ax - xb[b], dyv = ay - yb[b], dzv = az - zb[b];
+        const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
+        const bool hit = (j + b < j1) & (r2 < pc.a2f);
         // the next free slot: write unconditionally, keep on a hit
         qlane[kWaveQ * ((head + cnt) & (kQueue - 1))] = ((j + b) << 6) | img;
         cnt += hit ? 1 : 0;
       }
-      // lanes past their range stay put (j <= j1 + kBatch - 1): reads stay
-      // within the padding however long other lanes keep scanning
-      j += j < j1 ? kBatch : 0;
-      if (__any(cnt > kQueue - kBatch)) {
+      j += j < j1 ? 4 : 0;
+      if (__any(cnt > kQueue - 4)) {
         full = true;
         break;
       }
@@ -398,6 +413,9 @@ struct PairTrimF64 {
   const int sc = active ? k : n - 1;
   const double4 xi = xs[sc];
   const double sig_i = LB ? ar.sig[sc] : 0.0;
+  const float* __restrict__ xf = ar.xf;
+  const int xfs = ar.xf_stride;
+  const float3 xf_i = make_float3(xf[sc], xf[xfs + sc], xf[2 * xfs + sc]);
   const int c = ar.cell_s[sc];
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
   // the target itself, seen in the home image, is skipped in the drain
@@ -446,10 +464,10 @@ struct PairTrimF64 {
         k0 = cstart[row + lo2];
         k1 = cstart[row + hi2 + 1];
       }
-      pair_scan_f64<K, LB, R>(j0, j1, image_bits(ix1, iy, iz), queue, lane, self_ent, sc, xi, xs, g, pc, ar.sig,
-                              sig_i, A, rp, B);
-      pair_scan_f64<K, LB, R>(k0, k1, image_bits(ix2, iy, iz), queue, lane, self_ent, sc, xi, xs, g, pc, ar.sig,
-                              sig_i, A, rp, B);
+      pair_scan_f64<K, LB, R>(j0, j1, image_bits(ix1, iy, iz), dy, dz, queue, lane, self_ent, sc, xi, xf_i, xs, xf,
+                              xfs, g, pc, ar.sig, sig_i, A, rp, B);
+      pair_scan_f64<K, LB, R>(k0, k1, image_bits(ix2, iy, iz), dy, dz, queue, lane, self_ent, sc, xi, xf_i, xs, xf,
+                              xfs, g, pc, ar.sig, sig_i, A, rp, B);
     }
   }
   pair_drain_f64<K, LB, R>(queue, kQueue, lane, self_ent, sc, xi, xs, g, pc, ar.sig, sig_i, A, rp, B);
@@ -586,11 +604,6 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
 // coordinates are three arrays, so one 16-byte load brings one coordinate of
 // a batch of four candidates; lanes past the end of their run load nothing.
 // The vector memory pipeline, as much as the ALU, bounds this loop.
-__device__ __forceinline__ float4 load4f(const float* p) {
-  float4 v;
-  __builtin_memcpy(&v, p, sizeof(v));   // 4-byte aligned 16-byte load
-  return v;
-}
 
 template <int K, bool R, bool LB>
 __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int dz, int* __restrict__ queue,
@@ -734,10 +747,25 @@ struct PairTrimF32 {
 
 }  // namespace
 
+// Threshold of the FP32 candidate filters: the filter's |dx| is within ex of
+// the exact value (absolute coordinates and the image shift rounded to FP32,
+// at most a few ulp of L + a; neighbour reuse lets atoms sit skin/2 outside
+// the box), so r^2 < a^2 + 2 a ex + ex^2, plus FP32 rounding of the sum,
+// keeps every pair inside the cutoff.
+float filter_a2(const mls_plan_s* P) {
+  const double a = std::sqrt(P->a2);
+  const double ex = 4.0 * (P->cg.L[0] + P->cg.margin + a) * std::ldexp(1.0, -24);
+  return std::nextafter((float)(P->a2 * (1.0 + 4.0 * std::ldexp(1.0, -23)) + 2.0 * a * ex + ex * ex), INFINITY);
+}
+
 PairConst pair_const(const mls_plan_s* P) {
-  PairConst pc{P->a2, P->inv_a2, P->inv_a6, P->inv_a8, {}, {}};
+  PairConst pc{P->a2, P->inv_a2, P->inv_a6, P->inv_a8, {}, {}, filter_a2(P), {}, {}};
   for (int j = 0; j < 5; ++j) pc.gc[j] = P->gamma_c[j];
   for (int j = 0; j < 4; ++j) pc.gq[j] = 12.0 * (j + 1) * P->gamma_c[j + 1];
+  for (int d = 0; d < 3; ++d) {
+    pc.wf[d] = (float)P->cg.w[d];
+    pc.Lf[d] = (float)P->cg.L[d];
+  }
   return pc;
 }
 
@@ -748,14 +776,7 @@ PairConstF pair_const_f(const mls_plan_s* P) {
   for (int j = 0; j < 5; ++j) pf.gc[j] = (float)pc.gc[j];
   for (int j = 0; j < 4; ++j) pf.gq[j] = (float)pc.gq[j];
   for (int d = 0; d < 3; ++d) pf.L[d] = (float)P->cg.L[d];
-  // filter threshold: |dx| of the filter is within ex of the exact value
-  // (absolute coordinates and the image shift rounded to FP32, at most a few
-  // ulp of L + a; neighbour reuse lets atoms sit skin/2 outside the box), so
-  // r^2 < a^2 + 2 a ex + ex^2 plus FP32 rounding of the sum catches every pair
-  // inside the cutoff
-  const double a = std::sqrt(pc.a2);
-  const double ex = 4.0 * (P->cg.L[0] + P->cg.margin + a) * std::ldexp(1.0, -24);
-  pf.a2f = std::nextafter((float)(pc.a2 * (1.0 + 4.0 * std::ldexp(1.0, -23)) + 2.0 * a * ex + ex * ex), INFINITY);
+  pf.a2f = pc.a2f;
   return pf;
 }
 
@@ -777,6 +798,8 @@ hipError_t launch_pair_k(mls_plan_s* P, int n, hipStream_t s, const PairRep* rep
     return launch_one<PairTrimF32<K, true>>(a, waves, s);
   }
   PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const(P), P->d_e0, P->d_floc, nullptr};
+  a.xf = P->d_xf;
+  a.xf_stride = P->xf_stride;
   if (P->pair_fast && n < (1 << 25)) {
     if (!rep) return launch_one<PairTrimF64<K>>(a, waves, s);
     a.rep = *rep;
@@ -800,6 +823,8 @@ hipError_t launch_pair_lb_k(mls_plan_s* P, int n, hipStream_t s) {
     return launch_one<PairTrimF32<K, false, true>>(a, (n + kWaveQ - 1) / kWaveQ, s);
   }
   PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, P->cg, pair_const(P), P->d_e0, P->d_floc, P->d_sig};
+  a.xf = P->d_xf;
+  a.xf_stride = P->xf_stride;
   if (P->pair_fast && n < (1 << 25)) return launch_one<PairTrimF64<K, true>>(a, (n + kWaveQ - 1) / kWaveQ, s);
   if (!P->pair_fast) return launch_one<PairWave<K, true>>(a, n, s);
   return launch_one<PairGeneric<K, true>>(a, (n + kBlock - 1) / kBlock, s);

@@ -407,10 +407,11 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   ALLOC(P->d_floc, 3 * N);
   if (P->precision == MLS_MIXED) {
     ALLOC(P->d_xr, N + kSortedPad);
-    P->xf_stride = (int)(N + kSortedPad);
-    ALLOC(P->d_xf, 3 * (size_t)P->xf_stride);
     ALLOC(P->d_xif, N + kSortedPad);
   }
+  // filter coordinates of the pair kernels (both precisions)
+  P->xf_stride = (int)(N + kSortedPad);
+  ALLOC(P->d_xf, 3 * (size_t)P->xf_stride);
   P->n_partial = (int)((N + 255) / 256);
   ALLOC(P->d_partial, 2 * (size_t)P->n_partial + 2);
   ALLOC(P->d_scratch, 64);
