@@ -131,7 +131,10 @@ typedef enum {
   MLS_STENCIL_TILE_F32 = 1,
   MLS_STENCIL_TILE_F64 = 2,
   MLS_STENCIL_STREAM_F64 = 3,
-  MLS_STENCIL_TAPS_F64 = 4
+  MLS_STENCIL_TAPS_F64 = 4,
+  MLS_STENCIL_TILE_MFMA_F32 = 5  /* mixed, R <= 6: the FP32 tile on v_mfma_f32_16x16x4_f32
+                                   (z band x folded mirror images), selected at plan
+                                   creation by MLS_STENCIL_MFMA=1 in the environment */
 } mls_stencil_path;
 
 /* Build a plan on the current HIP device: resolves grids, levels and linked

@@ -77,7 +77,7 @@ class MLSPlanInfo(ctypes.Structure):
     ]
 
 
-STENCIL_PATHS = {0: "none", 1: "tile_f32", 2: "tile_f64", 3: "stream_f64", 4: "taps_f64"}
+STENCIL_PATHS = {0: "none", 1: "tile_f32", 2: "tile_f64", 3: "stream_f64", 4: "taps_f64", 5: "tile_mfma_f32"}
 
 
 class MLSBatchTuning(ctypes.Structure):

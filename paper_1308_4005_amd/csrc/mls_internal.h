@@ -369,6 +369,12 @@ struct mls_plan_s {
   mls::Tap* d_taps = nullptr;
   mls::StencilRow* d_rows = nullptr;
   int* d_wave_rows = nullptr;      // kStencilWaves + 1 offsets into rows
+  // MFMA level stencil (mixed precision): per tap column and K-chunk the
+  // 64-lane A operand of v_mfma_f32_16x16x4_f32 (the z band of the column);
+  // the columns again, their woff being the column's offset in that table
+  bool stencil_mfma = false;
+  float* d_mfma_a = nullptr;
+  mls::StencilRow* d_rows_mfma = nullptr;
   double* d_row_w_tile = nullptr;  // weights divided by the mirror duplication on the axes
   float* d_row_wf_tile = nullptr;  // the same in FP32 (mixed precision)
   int4* d_tiles = nullptr;         // (level-1, tile x, tile y, tile z) of the tiled stencil

@@ -337,6 +337,31 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   }
   std::vector<int4> tiles;
   if (const char* env = std::getenv("MLS_STENCIL_KERNEL")) P->stencil_kernel = std::atoi(env) == 0 ? 0 : 1;
+  // MFMA recast of the FP32 tile (windows up to 6, z tiles of 16): for tap
+  // column c and chunk s of four input planes, lane i + 16 k of the A operand
+  // holds the weight of dz = 4 s + k - hz - i (zero outside [-hz, hz]): output
+  // plane i of the tile, input plane 4 s + k counted from hz below it
+  std::vector<float> mfma_a;
+  std::vector<StencilRow> rows_mfma;
+  {
+    const char* env = std::getenv("MLS_STENCIL_MFMA");
+    P->stencil_mfma = env && std::atoi(env) != 0 && P->precision == MLS_MIXED && P->stencil_kernel == 1 && l > 1 &&
+                      stencil_window(P) >= 1 && stencil_window(P) <= 6;
+  }
+  if (P->stencil_mfma) {
+    for (const auto& r : P->rows) {
+      StencilRow m = r;
+      m.woff = (int)mfma_a.size();
+      const int S = (16 + 2 * r.hz + 3) / 4;
+      for (int sc = 0; sc < S; ++sc)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int i = lane & 15, k = lane >> 4;
+          const int dz = 4 * sc + k - r.hz - i;
+          mfma_a.push_back(std::abs(dz) <= r.hz ? (float)row_w_tile[r.woff + std::abs(dz)] : 0.0f);
+        }
+      rows_mfma.push_back(m);
+    }
+  }
   if (l > 1) {
     const int Rw = stencil_window(P);
     const int zc = stencil_tile_zc(Rw, P->precision != MLS_MIXED);
@@ -477,6 +502,10 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   ALLOC(P->d_row_w, P->row_w.size());
   ALLOC(P->d_row_wf, P->row_w.size());
   ALLOC(P->d_Kl, P->Kl.size());
+  if (P->stencil_mfma) {
+    ALLOC(P->d_mfma_a, mfma_a.size());
+    ALLOC(P->d_rows_mfma, rows_mfma.size());
+  }
   if (P->ant_tiles) {
     ALLOC(P->d_ant_tab, ant_tab.size());
     P->ant_scratch_n = ant_scratch;
@@ -509,6 +538,13 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   if ((e = hipMemcpy(P->d_wave_rows, wave_rows.data(), wave_rows.size() * sizeof(int), hipMemcpyHostToDevice)) !=
       hipSuccess)
     return hip_fail(e, "copy stencil wave split");
+  if (P->stencil_mfma) {
+    if ((e = hipMemcpy(P->d_mfma_a, mfma_a.data(), mfma_a.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "copy MFMA stencil operands");
+    if ((e = hipMemcpy(P->d_rows_mfma, rows_mfma.data(), rows_mfma.size() * sizeof(StencilRow),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "copy MFMA stencil columns");
+  }
   if ((e = hipMemcpy(P->d_Kl, P->Kl.data(), P->Kl.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "copy coarsest kernel");
   if (P->ant_tiles &&

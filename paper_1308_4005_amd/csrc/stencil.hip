@@ -292,6 +292,130 @@ __global__ void __launch_bounds__(64 * W) k_stencil_tile(StencilLaunch L, const 
   stencil_tile<T, R, ZC, W>(L.lv[tinfo.x], tinfo);
 }
 
+// MFMA recast of the FP32 tile (window R <= 6, 8 x 8 x 16 outputs per block).
+// For one tap column (dx, dy) the z sum is a banded Toeplitz product:
+// e[z][xy] += sum_t A[z][t] B[t][xy] with A[z][t] = w(|t - hz - z|) (input
+// plane t counted from hz below the tile) and B[t][xy] the four mirror
+// images q[x -+ dx, y -+ dy] of plane t summed, as in the VALU tile.  Each
+// v_mfma_f32_16x16x4_f32 takes 16 output planes (M), 16 xy points (N) and
+// four input planes (K): a column needs S = ceil((16 + 2 hz) / 4) chunks for
+// each of the tile's four 16-point xy blocks.  The A operands come from a
+// host table (one coalesced load per chunk, shared by the four blocks); B is
+// folded from LDS.  The W waves split the columns and add their partial
+// tiles in LDS, as the VALU tile does.  Operand layouts (lane = row + 16 *
+// column of A, column + 16 * row of B; D[i][j] in lane j + 16 (i / 4),
+// register i % 4) were checked on the device.
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <int R, int HZ>
+__device__ __forceinline__ void mfma_column(mfma_f4 (&acc)[4], const float* __restrict__ tile, const int (&base)[4],
+                                            int o0, int o1, int o2, int o3, const float* __restrict__ at) {
+  constexpr int SX = 8 + 2 * R, PS = SX * SX;
+  constexpr int S = (16 + 2 * HZ + 3) / 4;
+#pragma unroll
+  for (int sc = 0; sc < S; ++sc) {
+    const float a = at[64 * sc];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      const float* p = tile + base[nb] + 4 * sc * PS;
+      const float b = (p[o0] + p[o1]) + (p[o2] + p[o3]);
+      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[nb], 0, 0, 0);
+    }
+  }
+}
+
+template <int R, int H = 0>
+__device__ __forceinline__ void mfma_switch(int hz, mfma_f4 (&acc)[4], const float* tile, int (&base)[4], int o0,
+                                            int o1, int o2, int o3, const float* at) {
+  if constexpr (H <= R) {
+    if (hz == H) {
+      constexpr int SX = 8 + 2 * R, PS = SX * SX;
+      // chunk 0 starts hz planes below the tile's first output plane
+      int b[4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) b[nb] = base[nb] + (R - H) * PS;
+      mfma_column<R, H>(acc, tile, b, o0, o1, o2, o3, at);
+      return;
+    }
+    mfma_switch<R, H + 1>(hz, acc, tile, base, o0, o1, o2, o3, at);
+  }
+}
+
+template <int R, int W>
+__global__ void __launch_bounds__(64 * W) k_stencil_mfma(StencilLaunch L, const int4* __restrict__ tiles) {
+  constexpr int ZC = 16;
+  // four zero planes above the halo: the last K chunk of a column may reach
+  // up to three planes past its band
+  constexpr int SX = 8 + 2 * R, SY = 8 + 2 * R, SZH = ZC + 2 * R, SZ = SZH + 4;
+  constexpr int PS = SX * SY, NP = PS * SZ, NT = 64 * W;
+  constexpr int NL = NP > W * ZC * 64 ? NP : W * ZC * 64;
+  __shared__ float tile[NL];
+  __shared__ int wrapx[SX], wrapy[SY], wrapz[SZH];
+  const int4 tinfo = tiles[xcd_block(blockIdx.x, gridDim.x)];
+  const StencilLevel& V = L.lv[tinfo.x];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int x0 = tinfo.y * 8, y0 = tinfo.z * 8, z0 = tinfo.w * ZC;
+  if (tid < SX) wrapx[tid] = wrapi(x0 - R + tid, V.n[0]);
+  if (tid < SY) wrapy[tid] = wrapi(y0 - R + tid, V.n[1]);
+  if (tid < SZH) wrapz[tid] = wrapi(z0 - R + tid, V.n[2]);
+  __syncthreads();
+  const size_t gps = (size_t)V.n[0] * V.n[1];
+  const double* __restrict__ q = V.q;
+  const double mean = *V.sum_xi * V.inv_size;
+  constexpr int kIters = (NP + NT - 1) / NT, kFill = 8;
+  for (int b0 = 0; b0 < kIters; b0 += kFill) {
+    double v[kFill];
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const int i = min(tid + (b0 + u) * NT, NP - 1);
+      const int lx = i % SX, ly = (i / SX) % SY, lz = min(i / PS, SZH - 1);
+      v[u] = q[(size_t)wrapz[lz] * gps + (size_t)wrapy[ly] * V.n[0] + wrapx[lx]];
+    }
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const int i = tid + (b0 + u) * NT;
+      if (i < NP) tile[i] = i < PS * SZH ? (float)(v[u] - mean) : 0.0f;
+    }
+  }
+  __syncthreads();
+  // B operand of lane (k = lane / 16, j = lane % 16): plane k of the chunk,
+  // xy point j of block nb (x = j % 8, y = 2 nb + j / 8)
+  const int kk = lane >> 4, j = lane & 15;
+  int base[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) base[nb] = kk * PS + (2 * nb + (j >> 3) + R) * SX + ((j & 7) + R);
+  mfma_f4 acc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+  const StencilRow* __restrict__ rows = V.rows;
+  const float* __restrict__ atab = (const float*)V.wts;
+  const int r0 = V.wave_rows[wv], r1 = V.wave_rows[wv + 1];
+  for (int r = r0; r < r1; ++r) {
+    const StencilRow row = rows[r];
+    const int o0 = -row.dy * SX - row.dx, o1 = -row.dy * SX + row.dx;
+    const int o2 = row.dy * SX - row.dx, o3 = row.dy * SX + row.dx;
+    mfma_switch<R>(row.hz, acc, tile, base, o0, o1, o2, o3, atab + row.woff + lane);
+  }
+  // add the W partial tiles (the tile is reused): D[i][j] of block nb is
+  // output plane i = 4 (lane / 16) + register, xy point 16 nb + j
+  __syncthreads();
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg) tile[(wv * ZC + 4 * kk + rg) * 64 + 16 * nb + j] = acc[nb][rg];
+  __syncthreads();
+  for (int o = tid; o < ZC * 64; o += NT) {
+    const int z = o >> 6, xy = o & 63;
+    const int x = x0 + (xy & 7), y = y0 + (xy >> 3), zz = z0 + z;
+    if (x >= V.n[0] || y >= V.n[1] || zz >= V.n[2]) continue;
+    float sum = 0.0f;
+#pragma unroll
+    for (int w2 = 0; w2 < W; ++w2) sum += tile[(w2 * ZC + z) * 64 + xy];
+    V.e[(size_t)zz * gps + (size_t)y * V.n[0] + x] = V.scale * ((double)sum + mean * V.wsum);
+  }
+}
+
 // Batched: tiles of many plans' levels; tinfo.x indexes the descriptor array.
 template <class T, int R, int ZC, int W>
 __global__ void __launch_bounds__(64 * W) k_stencil_tile_batched(const StencilLevel* __restrict__ lv,
@@ -446,9 +570,45 @@ hipError_t launch_tile_f32(mls_plan_s* P, int R, hipStream_t s, int kmax) {
   }
 }
 
+template <int R>
+hipError_t launch_mfma(mls_plan_s* P, hipStream_t s, int kmax) {
+  StencilLaunch L{};
+  L.nlev = P->levels - 1;
+  int t = 0;
+  for (int k = 1; k < P->levels; ++k) {
+    Level& Lv = P->lv[k - 1];
+    StencilLevel& V = L.lv[k - 1];
+    V.q = Lv.q;
+    V.e = Lv.e;
+    for (int d = 0; d < 3; ++d) V.n[d] = Lv.g.n[d];
+    V.tiles_z = nblocks(Lv.g.n[2], 16);
+    V.tile0 = t;
+    V.scale = std::ldexp(1.0, -6 * (k - 1));
+    V.inv_size = 1.0 / (double)Lv.g.size;
+    V.rows = P->d_rows_mfma;
+    V.wave_rows = P->d_wave_rows;
+    V.wts = P->d_mfma_a;
+    V.sum_xi = P->sum_q ? P->sum_q : P->d_scratch;
+    V.wsum = P->taps_wsum;
+    t += nblocks(Lv.g.n[0], 8) * nblocks(Lv.g.n[1], 8) * V.tiles_z;
+    if (k == kmax) break;
+  }
+  k_stencil_mfma<R, kStencilWaves><<<t, 64 * kStencilWaves, 0, s>>>(L, P->d_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_mfma(mls_plan_s* P, int R, hipStream_t s, int kmax) {
+  switch (R) {
+    case 1: case 2: case 3: case 4: return launch_mfma<4>(P, s, kmax);
+    case 5: case 6: return launch_mfma<6>(P, s, kmax);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 int stencil_path(const mls_plan_s* P) {
   if (P->levels < 2) return MLS_STENCIL_NONE;
   const int R = stencil_window(P);
+  if (P->stencil_mfma) return MLS_STENCIL_TILE_MFMA_F32;
   if (P->stencil_kernel == 1 && P->precision == MLS_MIXED && R >= 1 && R <= 12) return MLS_STENCIL_TILE_F32;
   if (P->stencil_kernel == 1 && R >= 1 && R <= 8) return MLS_STENCIL_TILE_F64;
   if (R >= 1 && R <= 12) return MLS_STENCIL_STREAM_F64;
@@ -460,6 +620,7 @@ hipError_t launch_stencils(mls_plan_s* P, hipStream_t s, int kmax) {
   if (kmax <= 0 || kmax > P->levels - 1) kmax = P->levels - 1;
   const int R = stencil_window(P);
   const int path = stencil_path(P);
+  if (path == MLS_STENCIL_TILE_MFMA_F32) return launch_tile_mfma(P, R, s, kmax);
   if (path == MLS_STENCIL_TILE_F32) return launch_tile_f32(P, R, s, kmax);
   if (path == MLS_STENCIL_TILE_F64) return launch_tile_f64(P, R, s, kmax);
   const int ntaps = (int)P->taps.size();
