@@ -616,6 +616,168 @@ struct Interp {
   }
 };
 
+// Interpolation over the anterpolation's blocks of linked cells (the same
+// tables): a block loads the finest-grid values its atoms reach (at most
+// kAntTileMax, unwrapped, with the periodic wrap applied on load) into LDS,
+// eight loads in flight per thread, then every atom of its cells gathers its
+// p^3 values from LDS instead of global memory.  Outputs as Interp; the
+// energy sums are per block (fixed order).
+template <int P, class W>
+struct InterpTile {
+  using Args = InterpTileArgs;
+  static constexpr int kThreads = kAntThreads;
+  static __device__ void run(const Args& ta, int b) {
+    __shared__ double tile[kAntTileMax];
+    __shared__ int seg_begin[kAntTileRows];
+    __shared__ int seg_off[kAntTileRows + 1];
+    const InterpArgs& a = ta.a;
+    const AntTiles& T = ta.t;
+    const int* __restrict__ tab = ta.tab;
+    const CellGeom& cg = ta.cg;
+    const GridGeom& gg = a.gg;
+    const int bi[3] = {b % T.nb[0], (b / T.nb[0]) % T.nb[1], b / (T.nb[0] * T.nb[1])};
+    int c0[3], c1[3], e0[3], len[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      c0[d] = tab[T.off_c[d] + bi[d]];
+      c1[d] = tab[T.off_c[d] + bi[d] + 1];
+      e0[d] = tab[T.off_e[d] + bi[d]];
+      len[d] = tab[T.off_len[d] + bi[d]];
+    }
+    const int vol = len[0] * len[1] * len[2];   // <= kAntTileMax (host-checked)
+    const size_t plane = (size_t)gg.n[0] * gg.n[1];
+    constexpr int kFill = 8;
+    for (int i0 = threadIdx.x; i0 < vol; i0 += kFill * kAntThreads) {
+      double v[kFill];
+#pragma unroll
+      for (int u = 0; u < kFill; ++u) {
+        const int i = min(i0 + u * kAntThreads, vol - 1);
+        const int lx = i % len[0], ly = (i / len[0]) % len[1], lz = i / (len[0] * len[1]);
+        v[u] = a.E1[(size_t)wrapi(e0[2] + lz, gg.n[2]) * plane + (size_t)wrapi(e0[1] + ly, gg.n[1]) * gg.n[0] +
+                    wrapi(e0[0] + lx, gg.n[0])];
+      }
+#pragma unroll
+      for (int u = 0; u < kFill; ++u)
+        if (i0 + u * kAntThreads < vol) tile[i0 + u * kAntThreads] = v[u];
+    }
+    // the block's atoms: one contiguous run of sorted atoms per cell row (y, z)
+    const int ny = c1[1] - c0[1];
+    const int nrows = ny * (c1[2] - c0[2]);   // <= kAntTileRows = kAntThreads (host-checked)
+    int len_r = 0;
+    if ((int)threadIdx.x < nrows) {
+      const int cy = c0[1] + threadIdx.x % ny, cz = c0[2] + threadIdx.x / ny;
+      const int row = (cz * cg.nc[1] + cy) * cg.nc[0];
+      const int a0 = ta.cstart[row + c0[0]];
+      seg_begin[threadIdx.x] = a0;
+      len_r = ta.cstart[row + c1[0]] - a0;
+    }
+    seg_off[threadIdx.x] = len_r;
+    __syncthreads();
+    for (int off = 1; off < kAntThreads; off <<= 1) {
+      const int u = (int)threadIdx.x >= off ? seg_off[threadIdx.x - off] : 0;
+      __syncthreads();
+      seg_off[threadIdx.x] += u;
+      __syncthreads();
+    }
+    const int incl = seg_off[threadIdx.x];
+    __syncthreads();
+    seg_off[threadIdx.x + 1] = incl;
+    if (threadIdx.x == 0) seg_off[0] = 0;
+    __syncthreads();
+    const int tot = seg_off[nrows];
+    const int pitch_y = len[0], pitch_z = len[0] * len[1];
+    double su = 0.0, sxx = 0.0;
+    int sg = 0;
+    for (int i = threadIdx.x; i < tot; i += kAntThreads) {
+      while (seg_off[sg + 1] <= i) ++sg;
+      const int s = seg_begin[sg] + (i - seg_off[sg]);
+      const double4 p = a.xs[s];
+      const int ia = a.perm[s];
+      double e0v = 0.0, fl0 = 0.0, fl1 = 0.0, fl2 = 0.0;
+      if (!a.grid_only) {
+        e0v = a.e0[s];
+        fl0 = a.floc[3 * (size_t)s + 0];
+        fl1 = a.floc[3 * (size_t)s + 1];
+        fl2 = a.floc[3 * (size_t)s + 2];
+      }
+      if (a.frep) {
+        fl0 += a.frep[3 * (size_t)s + 0];
+        fl1 += a.frep[3 * (size_t)s + 1];
+        fl2 += a.frep[3 * (size_t)s + 2];
+      }
+      const double pc[3] = {p.x, p.y, p.z};
+      W w[3][P], dw[3][P];
+      int l0[3];
+      bool inside = true;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double t = pc[d] * gg.invh[d];
+        const double m0 = floor(t);
+        basis_weights_d<P, W>((W)(t - m0), w[d], dw[d]);
+        l0[d] = (int)m0 - (P / 2 - 1) - e0[d];
+        inside = inside && l0[d] >= 0 && l0[d] + P <= len[d];
+      }
+      if (!inside) {
+        // cannot happen for atoms of the block's cells (the reached ranges
+        // carry a margin); reported instead of reading outside the tile
+        atomicOr(ta.flags, 4);
+        continue;
+      }
+      const double* base = tile + l0[2] * pitch_z + l0[1] * pitch_y + l0[0];
+      double u = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+      // the z planes in a loop that is not unrolled (few registers, more
+      // waves), the plane's weights rotated into slot 0
+      W wz[P], dwz[P];
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        wz[t] = w[2][t];
+        dwz[t] = dw[2][t];
+      }
+#pragma unroll 1
+      for (int jz = 0; jz < P; ++jz) {
+        double ru = 0.0, rgx = 0.0, rgy = 0.0;
+#pragma unroll
+        for (int jy = 0; jy < P; ++jy) {
+          const double* row = base + jy * pitch_y;
+          double v = 0.0, vd = 0.0;
+#pragma unroll
+          for (int jx = 0; jx < P; ++jx) {
+            const double e = row[jx];
+            v += (double)w[0][jx] * e;
+            vd += (double)dw[0][jx] * e;
+          }
+          ru += (double)w[1][jy] * v;
+          rgx += (double)w[1][jy] * vd;
+          rgy += (double)dw[1][jy] * v;
+        }
+        u += (double)wz[0] * ru;
+        gx += (double)wz[0] * rgx;
+        gy += (double)wz[0] * rgy;
+        gz += (double)dwz[0] * ru;
+        base += pitch_z;
+#pragma unroll
+        for (int t = 0; t + 1 < P; ++t) {
+          wz[t] = wz[t + 1];
+          dwz[t] = dwz[t + 1];
+        }
+      }
+      const double xi = p.w;
+      const double utot = e0v + u;
+      if (a.out.forces) {
+        a.out.forces[3 * (size_t)ia + 0] = fl0 + xi * gx * gg.invh[0];
+        a.out.forces[3 * (size_t)ia + 1] = fl1 + xi * gy * gg.invh[1];
+        a.out.forces[3 * (size_t)ia + 2] = fl2 + xi * gz * gg.invh[2];
+      }
+      if (a.out.potential) a.out.potential[ia] = utot;
+      if (a.out.dE_dc6) a.out.dE_dc6[ia] = -(utot - a.cself * xi) / (2.0 * xi);
+      su += xi * utot;
+      sxx += xi * xi;
+    }
+    __syncthreads();
+    energy_partials(su, sxx, a.partial, b);
+  }
+};
+
 // Lorentz-Berthelot: the grid potential of vector 6 - k weighted with
 // xi_{i,k} = sigma_i^k sqrt(binom(6,k)) e_i / 8 (e_i = sqrt(2 eps_i) = xs.w),
 // summed over k; the local part is e_i e0_i with e0 from the pair kernel; the
@@ -889,18 +1051,33 @@ hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s) {
 hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forces, double* potential,
                               double* dE_dc6, hipStream_t s, int mode) {
   const bool with_repulsion = (mode & kInterpRep) != 0;
-  const int nb = nblocks(n, kBlock);
+  int nb = nblocks(n, kBlock);
   if (n > 0) {
     InterpArgs a{P->d_xs, P->d_perm, n, finest_geom(P), (mode & kInterpLevel1) ? P->lv[0].e : P->lv[0].E,
                  P->d_e0, P->d_floc, P->cself, OutPtrs{forces, potential, dE_dc6}, P->d_partial};
     if (with_repulsion) a.frep = P->d_frep;
     a.grid_only = (mode & kInterpGridOnly) ? 1 : 0;
     const bool mixed = P->precision == MLS_MIXED;
+    const int nt = P->ant.nb[0] * P->ant.nb[1] * P->ant.nb[2];
     hipError_t e;
-    if (P->order == 4 && !mixed) e = launch_one<Interp<4, double>>(a, nb, s);
-    else if (P->order == 4) e = launch_one<Interp<4, float>>(a, nb, s);
-    else if (!mixed) e = launch_one<Interp<6, double>>(a, nb, s);
-    else e = launch_one<Interp<6, float>>(a, nb, s);
+    if (P->ant_tiles && nt <= P->n_partial + 1) {
+      // the anterpolation's cell blocks, their finest-grid reach staged in LDS
+      // (one energy partial per block)
+      InterpTileArgs t{a, P->d_cell_start, P->cg, P->ant, P->d_ant_tab, P->d_flags};
+      nb = nt;
+      if (P->order == 4 && !mixed) e = launch_one<InterpTile<4, double>>(t, nt, s);
+      else if (P->order == 4) e = launch_one<InterpTile<4, float>>(t, nt, s);
+      else if (!mixed) e = launch_one<InterpTile<6, double>>(t, nt, s);
+      else e = launch_one<InterpTile<6, float>>(t, nt, s);
+    } else if (P->order == 4 && !mixed) {
+      e = launch_one<Interp<4, double>>(a, nb, s);
+    } else if (P->order == 4) {
+      e = launch_one<Interp<4, float>>(a, nb, s);
+    } else if (!mixed) {
+      e = launch_one<Interp<6, double>>(a, nb, s);
+    } else {
+      e = launch_one<Interp<6, float>>(a, nb, s);
+    }
     if (e != hipSuccess) return e;
   }
   // no atoms: an empty sum, E = 0

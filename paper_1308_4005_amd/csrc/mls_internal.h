@@ -232,6 +232,11 @@ struct InterpArgs {
   const double* frep = nullptr;   // sorted (n,3) repulsive forces added to the output, or null
   int grid_only = 0;              // 1: the grid part alone (no e0, no local forces)
 };
+// Interpolation over the anterpolation's blocks of linked cells: each block
+// stages the finest-grid values its atoms reach in LDS.
+struct InterpTileArgs {
+  InterpArgs a; const int* cstart; CellGeom cg; AntTiles t; const int* tab; int* flags;
+};
 struct EnergyArgs {
   const double* partial; int nb; double cself; double* energy;
   const double* rep_partial = nullptr;  // block sums of the repulsive energy (twice E_rep), or null
