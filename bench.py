@@ -94,14 +94,14 @@ def stage_rooflines(stage_ms, model, precision):
 
 
 # kernels that carry each stage of the 10^6-atom cube (cell width a/2 there)
-STAGE_KERNEL = {("pair", "mixed"): ["void k_one<PairTrimF32<2, false> >"],
+STAGE_KERNEL = {("pair", "mixed"): ["void k_one<PairTrimF32<2, false, false> >"],
                 ("pair", "fp64"): ["void k_one<PairTrimF64<2, false, false> >"],
-                ("stencil", "mixed"): ["void k_stencil_tile<float, 6, 16, 4>"],
-                ("stencil", "fp64"): ["void k_stencil_tile<double, 6, 8, 4>"],
+                ("stencil", "mixed"): ["void k_stencil_tile<float, 6, 16, 8>"],
+                ("stencil", "fp64"): ["void k_stencil_tile<double, 6, 8, 8>"],
                 ("anterpolation", "mixed"): ["void k_one<AnterpTile<4, float> >", "void k_one<AnterpCollect>"],
                 ("anterpolation", "fp64"): ["void k_one<AnterpTile<4, double> >", "void k_one<AnterpCollect>"],
-                ("interpolation", "mixed"): ["void k_one<Interp<4, float> >"],
-                ("interpolation", "fp64"): ["void k_one<Interp<4, double> >"]}
+                ("interpolation", "mixed"): ["void k_one<InterpTile<4, float> >"],
+                ("interpolation", "fp64"): ["void k_one<InterpTile<4, double> >"]}
 
 
 def measured_traffic(stage, precision):
@@ -202,6 +202,40 @@ def time_precision(w, prm, precision, steps, warmup, dev, continuity=2, stages=T
     return dict(ms=ms, eager_ms=eager_ms, block_ms=block_ms, stage_ms=stage_ms, E=E, F=F, info=info)
 
 
+def time_stencil_mfma(w, prm, dev, steps):
+    """Stencil stage of a mixed plan on the MFMA recast of the FP32 tile
+    (selected by MLS_STENCIL_MFMA=1 at plan creation), library hipEvents as
+    for the other stage times; None where the window exceeds its range."""
+    import torch
+    from paper_1308_4005_amd import Plan, Result
+    old = os.environ.get("MLS_STENCIL_MFMA")
+    os.environ["MLS_STENCIL_MFMA"] = "1"
+    try:
+        plan = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], precision="mixed", n_max=w.n,
+                    device=dev.index)
+    finally:
+        if old is None:
+            del os.environ["MLS_STENCIL_MFMA"]
+        else:
+            os.environ["MLS_STENCIL_MFMA"] = old
+    if plan.info["stencil_path"] != "tile_mfma_f32":
+        plan.close()
+        return None
+    pos = torch.tensor(w.pos, dtype=torch.float64, device=dev)
+    c6 = torch.tensor(w.c6, dtype=torch.float64, device=dev)
+    out = Result(torch.empty(1, dtype=torch.float64, device=dev),
+                 torch.empty((w.n, 3), dtype=torch.float64, device=dev))
+    for _ in range(3):
+        plan.evaluate(pos, c6, out=out)
+    plan.set_timing(True)
+    for _ in range(steps):
+        plan.evaluate(pos, c6, out=out)
+    torch.cuda.synchronize()
+    stage_ms, cnt = plan.read_timing()
+    plan.close()
+    return stage_ms["stencil"] / max(cnt, 1)
+
+
 def time_batched(ws, precision, steps, warmup, dev):
     """The batched form on the many-box workload: one graph replay per step
     (all boxes), after autotuning on the first call; beside it the same boxes
@@ -260,18 +294,22 @@ def time_batched(ws, precision, steps, warmup, dev):
             "tuning": tuning}
 
 
-def time_lb(w, prm, steps, warmup, dev):
-    """Lorentz-Berthelot mixing (mls_evaluate_lb, FP64) on the same positions
-    with two species drawn 50/50 (seed 17): epsilon in {1.0, 0.6}, sigma in
-    {1.0, 1.25}."""
+def lb_species(n, seed):
+    """Two species drawn 50/50: epsilon in {1.0, 0.6}, sigma in {1.0, 1.25}."""
     import numpy as np
+    rng = np.random.default_rng(seed)
+    return np.where(rng.uniform(size=n) < 0.5, 1.0, 0.6), np.where(rng.uniform(size=n) < 0.5, 1.0, 1.25)
+
+
+def time_lb(w, prm, steps, warmup, dev, precision="fp64"):
+    """Lorentz-Berthelot mixing (mls_evaluate_lb) on the same positions with
+    two species drawn 50/50 (seed 17): epsilon in {1.0, 0.6}, sigma in
+    {1.0, 1.25}."""
     import torch
     from paper_1308_4005_amd import Plan, Result
-    rng = np.random.default_rng(17)
-    eps = np.where(rng.uniform(size=w.n) < 0.5, 1.0, 0.6)
-    sig = np.where(rng.uniform(size=w.n) < 0.5, 1.0, 1.25)
+    eps, sig = lb_species(w.n, 17)
     plan = Plan(w.box, prm["a"], prm["h"], prm["order"], prm["levels"], n_max=w.n, device=dev.index,
-                mixing="lorentz-berthelot")
+                mixing="lorentz-berthelot", precision=precision)
     pos = torch.tensor(w.pos, dtype=torch.float64, device=dev)
     te = torch.tensor(eps, dtype=torch.float64, device=dev)
     ts = torch.tensor(sig, dtype=torch.float64, device=dev)
@@ -292,7 +330,38 @@ def time_lb(w, prm, steps, warmup, dev):
     E = float(out.energy.cpu()[0])
     plan.close()
     return {"workload": f"{w.name} positions, two species 50/50: eps {{1.0, 0.6}}, sigma {{1.0, 1.25}} (seed 17)",
-            "precision": "fp64", "ms_per_step": ms, "evals_per_s": 1000.0 / ms, "energy": E}
+            "precision": precision, "ms_per_step": ms, "evals_per_s": 1000.0 / ms, "energy": E}
+
+
+def time_batched_lb(ws, precision, steps, warmup, dev):
+    """The batched Lorentz-Berthelot form (mls_batch_evaluate_lb) on the
+    many-box workload, two species per box as for the single plan (seed 17
+    over the concatenated atoms), after autotuning on the first call."""
+    import numpy as np
+    import torch
+    from paper_1308_4005_amd import BatchPlan
+    bp = BatchPlan([w.box for w in ws], [w.n for w in ws], 3.0, 1.0, 4, 0, precision=precision, autotune=True,
+                   device=dev.index, mixing="lorentz-berthelot")
+    n = sum(w.n for w in ws)
+    eps, sig = lb_species(n, 17)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+    pos, te, ts = t(np.concatenate([w.pos for w in ws])), t(eps), t(sig)
+    out = bp.evaluate_lb(pos, te, ts)
+    for _ in range(warmup):
+        bp.evaluate_lb(pos, te, ts, out=out)
+    stream = torch.cuda.current_stream(dev)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(steps):
+        bp.evaluate_lb(pos, te, ts, out=out)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    bp.close()
+    return {"precision": precision, "boxes": len(ws), "atoms": n, "ms_per_step": ms,
+            "batch_evals_per_s": 1000.0 / ms, "particle_evals_per_s": n * 1000.0 / ms}
 
 
 def time_md(w, prm, precision, steps, warmup, dev, blocks, chunk=50, dt=0.001):
@@ -620,6 +689,15 @@ def main():
         roofline["peak_unpacked_fp32"] = PEAK["fp64"]
         roofline["frac_unpacked_fp32"] = achieved / PEAK["fp64"]
     per_stage_roofline = {p: stage_rooflines(res[p]["stage_ms"], model, p) for p in res}
+    # the level stencil of the mixed plan two ways: the VALU tile (the
+    # default) and its MFMA recast
+    stencil_variants = None
+    if "mixed" in res:
+        mf = time_stencil_mfma(w, prm, dev, min(args.steps, 100))
+        vt = res["mixed"]["stage_ms"].get("stencil")
+        stencil_variants = {"tile_f32_valu_ms": vt, "tile_mfma_f32_ms": mf,
+                            "flops_per_launch": model["stencil"]["flops"]}
+        log(f"[bench] stencil stage: VALU tile {vt} ms, MFMA tile {mf} ms")
 
     accuracy = {}
     for p in res:
@@ -649,11 +727,26 @@ def main():
             family["ms_per_step"][f"C{k}"] = r["ms"]
             family["energy"][f"C{k}"] = r["E"]
 
+    batch_ws = []
+
+    def batch_workload():
+        # the 256-box workload, built once (the batched and the batched
+        # Lorentz-Berthelot timings share it)
+        if not batch_ws:
+            batch_ws.extend(W.named_batch("batch256"))
+        return batch_ws
+
     lb = None
     if not args.no_lb:
         log("[bench] Lorentz-Berthelot mixing")
-        lb = time_lb(w, prm, max(5, args.steps // 20), 2, dev)
-        log(f"[bench] Lorentz-Berthelot: {lb['ms_per_step']:.3f} ms/eval")
+        lb = {p: time_lb(w, prm, max(5, args.steps // 20), 2, dev, precision=p) for p in ("fp64", "mixed")}
+        log(f"[bench] Lorentz-Berthelot: FP64 {lb['fp64']['ms_per_step']:.3f}, mixed "
+            f"{lb['mixed']['ms_per_step']:.3f} ms/eval")
+        if not args.no_batch:
+            bws = batch_workload()
+            lb["batched"] = {p: time_batched_lb(bws, p, max(5, args.steps // 20), 2, dev) for p in ("fp64", "mixed")}
+            log(f"[bench] batched Lorentz-Berthelot ({len(bws)} boxes): FP64 "
+                f"{lb['batched']['fp64']['ms_per_step']:.3f}, mixed {lb['batched']['mixed']['ms_per_step']:.3f} ms")
 
     md = None
     if not args.no_md:
@@ -674,7 +767,7 @@ def main():
     batched = None
     if not args.no_batch:
         t = time.time()
-        ws = W.named_batch("batch256")
+        ws = batch_workload()
         log(f"[bench] batch256: {len(ws)} boxes, {sum(w.n for w in ws)} atoms ({time.time() - t:.1f}s)")
         batched = {"workload": "batch256: 256 periodic boxes, N ~ floor(exp U(ln 500, ln 20000)), box (L, L, aL) "
                                "with a ~ U(1,4), density ~ U(0.02,0.85), RSA min distance 0.8, C6=4; "
@@ -727,6 +820,7 @@ def main():
         "discretisation_error": disc,
         "roofline": roofline,
         "stage_roofline": per_stage_roofline,
+        "stencil_variants": stencil_variants,
         "precision_sweep": sweep,
         "continuity_family": family,
         "lorentz_berthelot": lb,
