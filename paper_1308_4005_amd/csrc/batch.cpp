@@ -350,7 +350,12 @@ mls_status build_phases(mls_batch_s* B) {
     HostPhase c = make_phase<CoarsestArgs>(BK_COARSEST, MLS_T_COARSEST, 0, nchain);
     for (const Chain& ch : chains) {
       Level& L = (*ch.lv)[ch.P->levels - 1];
-      set_box(c, ch.id, CoarsestArgs{L.q, L.g, ch.P->d_Kl, L.e}, nblk(L.g.size, kCoarsestPerBlock));
+      // the register-row form where the level allows it (each K value read
+      // serves a row of FMAs), else four output points per wave of the
+      // wave-per-point form: the boxes fill the chip, and each block's
+      // staging of q and K serves more outputs
+      const int rows = coarsest_rows_form(L.g);
+      set_box(c, ch.id, CoarsestArgs{L.q, L.g, ch.P->d_Kl, L.e, 4, rows}, coarsest_blocks(L.g, 4, rows));
     }
     hp.push_back(std::move(c));
   }

@@ -247,9 +247,11 @@ struct InterpLbArgs {
   const double4* xs; const double* sig; const int* perm; int n; GridGeom gg; const double* E1[7];
   const double* e0; const double* floc; double* forces; double* partial;
 };
-struct CoarsestArgs { const double* q; GridDims g; const double* K; double* e; };
-constexpr int kCoarsestThreads = 256;   // threads per block of the coarsest-level kernel
-constexpr int kCoarsestPerBlock = kCoarsestThreads / 64;   // output points per block (one per wave)
+// outs: points per wave of the wave-per-point form; rows: the level's x
+// extent when the register-row form runs (coarsest_rows_form), else 0
+struct CoarsestArgs { const double* q; GridDims g; const double* K; double* e; int outs; int rows; };
+constexpr int kCoarsestThreads = 512;   // threads per block of the coarsest-level kernel
+constexpr int kCoarsestWaves = kCoarsestThreads / 64;
 
 // One level of the tiled stencil: grids, scale, and the tap tables of its plan.
 struct StencilLevel {
@@ -482,6 +484,13 @@ mls_status evaluate_plan(mls_plan_s* P, int64_t n, const double* pos, const doub
 int scan_blocks(int ncell);
 // halo window of the level stencil and z extent of its LDS tile
 int stencil_window(const mls_plan_s* P);
+// blocks of the coarsest-level kernel for a grid, `outs` output points per wave
+// The register-row form serves throughput (one block per 64 output rows,
+// the source rows split over the block's waves); a lone level is done sooner
+// by the wave-per-point form, whose blocks spread over the chip.  Returns
+// the rows argument for a batched launch of level g.
+int coarsest_rows_form(const GridDims& g);
+int coarsest_blocks(const GridDims& g, int outs, int rows);
 int stencil_tile_zc(int R, bool f64);
 
 // kernel launchers (one per file); all enqueue on `s` and return the launch status

@@ -427,58 +427,184 @@ __global__ void __launch_bounds__(64 * W) k_stencil_tile_batched(const StencilLe
   }
 }
 
-// Coarsest level: all-to-all over the level, one wave per output point.  Up
-// to kCoarseLds points the charges and the kernel are staged in LDS first, so
-// the inner loop reads LDS.
+// Coarsest level: all-to-all over the level (a periodic convolution of the
+// charges with the pre-summed kernel K), with K and the charges staged in LDS
+// when they fit (kCoarseLds points each).
+//
+// Rows path (batched launches), for a level whose x extent N is at most 8
+// and whose staging fits: a lane owns one output row (y, z) and keeps its N sums in
+// registers; the eight waves of the block split the source rows (y', z').
+// Per source row a lane reads the N values of the kernel row
+// ((y - y') mod n_y, (z - z') mod n_z) and the wave reads the N charges of
+// the row (the same address in every lane), then the x-direction convolution
+// of the two rows, N^2 FMAs with the (x - x') mod N offsets fixed at compile
+// time, runs in registers.  Each K value read from LDS serves N FMAs.  The
+// waves' partial rows are added in LDS in wave order (fixed order).  K rows
+// sit at an odd stride in LDS so that the 8-byte reads of one wave spread
+// over the banks.
+//
+// General path, for single plans and the levels the rows path does not
+// take: a wave per output point (a.outs
+// points per wave, one after another): the lanes split the source rows, each
+// lane takes its (y - y', z - z') offset once per row and walks x' with
+// (x - x') mod n_x, then the lanes add their partial sums across the wave
+// (fixed order).
 constexpr int kCoarseLds = 2048;
+constexpr int kCoarseRowsMaxX = 8;
+
+// One LDS buffer for either path, declared at namespace scope so that every
+// access by name compiles to an LDS access (a pointer into it passed around
+// could be taken for a generic one and read with flat loads).
+__shared__ double coarse_lds[2 * kCoarseLds];
+
+// x extent of a level the rows path takes, else 0
+__host__ __device__ inline int coarse_rows_n(const GridDims& g) {
+  const int N = g.n[0], nrow = g.n[1] * g.n[2];
+  if (N < 1 || N > kCoarseRowsMaxX) return 0;
+  return (int64_t)nrow * (N | 1) <= kCoarseLds && (int64_t)nrow * N <= kCoarseLds ? N : 0;
+}
+
+template <int N>
+__device__ __forceinline__ void coarsest_rows(const CoarsestArgs& a, int blk) {
+  constexpr int S = N | 1;   // LDS stride of a K row, in doubles
+  constexpr int kPer = kCoarseLds / kCoarsestThreads;
+  double* const sk = coarse_lds;
+  double* const sq = coarse_lds + kCoarseLds;
+  const int n1 = a.g.n[1], n2 = a.g.n[2], nrow = n1 * n2, npt = nrow * N;
+  {
+    // every load of the staging in flight before the first store
+    double vq[kPer], vk[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int i = min((int)threadIdx.x + u * kCoarsestThreads, npt - 1);
+      vq[u] = a.q[i];
+      vk[u] = a.K[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int i = threadIdx.x + u * kCoarsestThreads;
+      if (i < npt) {
+        const int r = i / N;
+        sk[r * S + (i - r * N)] = vk[u];
+        sq[i] = vq[u];
+      }
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row = blk * 64 + lane;
+  const int y = row < nrow ? row % n1 : 0, z = row < nrow ? row / n1 : 0;
+  const int r0 = (nrow * wv) / kCoarsestWaves, r1 = (nrow * (wv + 1)) / kCoarsestWaves;
+  double acc[N];
+#pragma unroll
+  for (int x = 0; x < N; ++x) acc[x] = 0.0;
+  int ys = r0 % n1, zs = r0 / n1;
+  for (int r = r0; r < r1; ++r) {
+    const int ky = y - ys + (y < ys ? n1 : 0), kz = z - zs + (z < zs ? n2 : 0);
+    const int kb = (kz * n1 + ky) * S;
+    double k[N], q[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      k[j] = sk[kb + j];
+      q[j] = sq[r * N + j];
+    }
+#pragma unroll
+    for (int xs = 0; xs < N; ++xs)
+#pragma unroll
+      for (int x = 0; x < N; ++x) acc[x] = fma(k[(x - xs + N) % N], q[xs], acc[x]);
+    if (++ys == n1) {
+      ys = 0;
+      ++zs;
+    }
+  }
+  __syncthreads();   // staging no longer read: the buffer takes the partial rows
+  double* const red = coarse_lds;
+#pragma unroll
+  for (int x = 0; x < N; ++x) red[(wv * N + x) * 64 + lane] = acc[x];
+  __syncthreads();
+  if (threadIdx.x < 64 * N) {
+    const int x = threadIdx.x >> 6;
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kCoarsestWaves; ++w) v += red[(w * N + x) * 64 + lane];
+    if (row < nrow) a.e[row * N + x] = v;
+  }
+}
+
+template <bool STAGED>
+__device__ __forceinline__ void coarsest_sums(const CoarsestArgs& a, int blk) {
+  const GridDims& g = a.g;
+  double* const sk = coarse_lds;
+  double* const sq = coarse_lds + kCoarseLds;
+  if constexpr (STAGED) {
+    constexpr int kPer = kCoarseLds / kCoarsestThreads;
+    double vq[kPer], vk[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int i = min((int)threadIdx.x + u * kCoarsestThreads, g.size - 1);
+      vq[u] = a.q[i];
+      vk[u] = a.K[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int i = threadIdx.x + u * kCoarsestThreads;
+      if (i < g.size) {
+        sq[i] = vq[u];
+        sk[i] = vk[u];
+      }
+    }
+    __syncthreads();
+  }
+  const double* __restrict__ gK = a.K;
+  const double* __restrict__ gq = a.q;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], n01 = n0 * n1, nrow = n1 * n2;
+  const int b1 = 64 % n1, b2 = 64 / n1, ys0 = lane % n1, zs0 = lane / n1;
+  for (int m = 0; m < a.outs; ++m) {
+    const int mu = (blk * a.outs + m) * kCoarsestWaves + wv;
+    if (mu >= g.size) break;
+    const int x = mu % n0, y = (mu / n0) % n1, z = mu / n01;
+    double acc = 0.0;
+    // (ys, zs) of row r = lane + 64 t, advanced with a carry (no division
+    // per row)
+    int ys = ys0, zs = zs0;
+    for (int r = lane; r < nrow; r += 64) {
+      const int ky = y - ys + (y < ys ? n1 : 0), kz = z - zs + (z < zs ? n2 : 0);
+      const int kr = kz * n01 + ky * n0, qr = r * n0;
+#pragma unroll 4
+      for (int xs = 0; xs < n0; ++xs) {
+        const int kx = x - xs + (x < xs ? n0 : 0);
+        if constexpr (STAGED) acc = fma(sk[kr + kx], sq[qr + xs], acc);
+        else acc = fma(gK[kr + kx], gq[qr + xs], acc);
+      }
+      ys += b1;
+      const int cy = ys >= n1;
+      ys -= cy ? n1 : 0;
+      zs += b2 + cy;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) a.e[mu] = acc;
+  }
+}
 
 struct Coarsest {
   using Args = CoarsestArgs;
   static constexpr int kThreads = kCoarsestThreads;
   static __device__ void run(const Args& a, int blk) {
-    __shared__ double sq[kCoarseLds], sk[kCoarseLds];
-    const GridDims& g = a.g;
-    const bool staged = g.size <= kCoarseLds;
-    const double* q = a.q;
-    const double* K = a.K;
-    if (staged) {
-      for (int i = threadIdx.x; i < g.size; i += kThreads) {
-        sq[i] = a.q[i];
-        sk[i] = a.K[i];
-      }
-      __syncthreads();
-      q = sq;
-      K = sk;
+    switch (a.rows) {
+      case 1: coarsest_rows<1>(a, blk); break;
+      case 2: coarsest_rows<2>(a, blk); break;
+      case 3: coarsest_rows<3>(a, blk); break;
+      case 4: coarsest_rows<4>(a, blk); break;
+      case 5: coarsest_rows<5>(a, blk); break;
+      case 6: coarsest_rows<6>(a, blk); break;
+      case 7: coarsest_rows<7>(a, blk); break;
+      case 8: coarsest_rows<8>(a, blk); break;
+      default:
+        if (a.g.size <= kCoarseLds) coarsest_sums<true>(a, blk);
+        else coarsest_sums<false>(a, blk);
     }
-    // one wave per output point: the lanes split the sum over the level's
-    // points, then add their partial sums across the wave (fixed order)
-    const int lane = threadIdx.x & 63;
-    const int mu = blk * kCoarsestPerBlock + (threadIdx.x >> 6);
-    if (mu >= g.size) return;
-    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], n01 = n0 * n1;
-    const int x = mu % n0, y = (mu / n0) % n1, z = mu / n01;
-    // the lane's source nu = lane + 64 t walks the grid as (nx, ny, nz),
-    // advanced by 64 points per step with carries (no division per term)
-    const int a0 = 64 % n0, a1 = (64 / n0) % n1, a2 = 64 / n01;
-    int nx = lane % n0, ny = (lane / n0) % n1, nz = lane / n01;
-    double acc = 0.0;
-    for (int nu = lane; nu < g.size; nu += 64) {
-      int dx = x - nx, dy = y - ny, dz = z - nz;
-      dx += dx < 0 ? n0 : 0;
-      dy += dy < 0 ? n1 : 0;
-      dz += dz < 0 ? n2 : 0;
-      acc = fma(K[((size_t)dz * n1 + dy) * n0 + dx], q[nu], acc);
-      nx += a0;
-      const int cx = nx >= n0;
-      nx -= cx ? n0 : 0;
-      ny += a1 + cx;
-      const int cy = ny >= n1;
-      ny -= cy ? n1 : 0;
-      nz += a2 + cy;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) a.e[mu] = acc;
   }
 };
 inline int nblocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
@@ -512,6 +638,15 @@ hipError_t launch_stream_r(const mls_plan_s* P, int R, const T* q, GridDims g, c
 }
 
 }  // namespace
+
+// Blocks of the coarsest-level kernel for grid g with `outs` output points
+// per wave.
+int coarsest_rows_form(const GridDims& g) { return coarse_rows_n(g); }
+
+int coarsest_blocks(const GridDims& g, int outs, int rows) {
+  if (rows) return (g.n[1] * g.n[2] + 63) / 64;
+  return (int)(((int64_t)g.size + (int64_t)kCoarsestWaves * outs - 1) / ((int64_t)kCoarsestWaves * outs));
+}
 
 int stencil_window(const mls_plan_s* P) {
   return std::max(P->stencil_R[0], std::max(P->stencil_R[1], P->stencil_R[2]));
@@ -641,7 +776,7 @@ hipError_t launch_stencils(mls_plan_s* P, hipStream_t s, int kmax) {
 
 hipError_t launch_coarsest(mls_plan_s* P, hipStream_t s) {
   Level& L = P->lv[P->levels - 1];
-  return launch_one<Coarsest>(CoarsestArgs{L.q, L.g, P->d_Kl, L.e}, nblocks(L.g.size, kCoarsestPerBlock), s);
+  return launch_one<Coarsest>(CoarsestArgs{L.q, L.g, P->d_Kl, L.e, 1, 0}, coarsest_blocks(L.g, 1, 0), s);
 }
 
 bool stencil_tile_ok(int R, int zc) {
