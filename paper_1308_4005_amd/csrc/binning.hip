@@ -38,10 +38,8 @@ struct FillD {
 // Sanitised, wrapped position and xi of atom i (flags: 1 = position, 2 = C6).
 // Non-finite positions and coordinates too large for the wrap become the
 // origin, non-finite or negative C6 become 0.
-__device__ __forceinline__ double4 wrapped_atom(const double* __restrict__ pos, const double* __restrict__ c6,
-                                                int i, const CellGeom& g, double scale, int& bad) {
-  double x = pos[3 * (size_t)i], y = pos[3 * (size_t)i + 1], z = pos[3 * (size_t)i + 2];
-  double c = c6[i];
+__device__ __forceinline__ double4 wrap_values(double x, double y, double z, double c, const CellGeom& g,
+                                               double scale, int& bad) {
   bad = 0;
   if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
     bad |= 1;
@@ -62,6 +60,20 @@ __device__ __forceinline__ double4 wrapped_atom(const double* __restrict__ pos, 
   return make_double4(X, Y, Z, sqrt(scale * c));
 }
 
+__device__ __forceinline__ double4 wrapped_atom(const double* __restrict__ pos, const double* __restrict__ c6,
+                                                int i, const CellGeom& g, double scale, int& bad) {
+  return wrap_values(pos[3 * (size_t)i], pos[3 * (size_t)i + 1], pos[3 * (size_t)i + 2], c6[i], g, scale, bad);
+}
+
+// Linked cell of a wrapped position (clamped: a wrapped coordinate equal to
+// the box length after rounding stays in the last cell).
+__device__ __forceinline__ int cell_of(const double4& p, const CellGeom& g) {
+  const int cx = max(0, min((int)(p.x * g.inv_w[0]), g.nc[0] - 1));
+  const int cy = max(0, min((int)(p.y * g.inv_w[1]), g.nc[1] - 1));
+  const int cz = max(0, min((int)(p.z * g.inv_w[2]), g.nc[2] - 1));
+  return (cz * g.nc[1] + cy) * g.nc[0] + cx;
+}
+
 struct BinCount {
   using Args = BinCountArgs;
   static constexpr int kThreads = kBlock;
@@ -77,10 +89,7 @@ struct BinCount {
       int bad;
       const double4 p = wrapped_atom(a.pos, a.c6, i, g, a.c6_scale, bad);
       if (bad) atomicOr(a.flags, bad);
-      int cx = max(0, min((int)(p.x * g.inv_w[0]), g.nc[0] - 1));
-      int cy = max(0, min((int)(p.y * g.inv_w[1]), g.nc[1] - 1));
-      int cz = max(0, min((int)(p.z * g.inv_w[2]), g.nc[2] - 1));
-      int id = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+      const int id = cell_of(p, g);
       a.cid[i] = id;
       a.xw[i] = p;
       a.slot[i] = atomicAdd(&a.count[id], 1);
@@ -290,6 +299,177 @@ struct RankGather {
   }
 };
 
+// Bucketed counting sort (single plans).  Device-wide atomics on random
+// cells are the slow part of the counting sort above (a few 10^10 per second
+// on this chip, whatever their scope), so here the atoms are first ordered
+// by bucket, a run of 2^shift consecutive cell ids, with block histograms and
+// LDS atomics only; then one block orders each bucket by cell:
+//   A. BinBucket: wrapped position, cell id, the block's bucket histogram
+//      (and, in mixed precision, the per-256-atom sums of xi)
+//   B. exclusive scan of all histograms in bucket-major order
+//   C. BucketScatter: (index, cell) into the bucket's range, LDS slots
+//   D. BucketSort: per bucket, count its cells, write their starts, order
+//      the bucket by cell (LDS slots), then each atom's rank among its
+//      cell's atoms by original index gives its stable position, and the
+//      sorted arrays are gathered as in RankGather.
+// The result is the same integer permutation as the counting sort above.
+constexpr int kBinThreads = 512;
+constexpr int kBinPer = 4;
+constexpr int kBinItems = kBinThreads * kBinPer;
+constexpr int kMaxBuckets = 4096;
+constexpr int kBucketShiftMin = 9, kBucketShiftMax = 11;
+constexpr int64_t kMaxHist = (int64_t)1 << 24;
+
+struct BinBucket {
+  using Args = BinBucketArgs;
+  static constexpr int kThreads = kBinThreads;
+  static __device__ void run(const Args& a, int blk) {
+    __shared__ int hist[kMaxBuckets];
+    __shared__ double sh[kBinThreads];
+    if (a.cond && *a.cond == 0) return;
+    for (int b = threadIdx.x; b < a.nbucket; b += kBinThreads) hist[b] = 0;
+    // every load of the block in flight before the first use
+    double x[kBinPer], y[kBinPer], z[kBinPer], c[kBinPer];
+#pragma unroll
+    for (int u = 0; u < kBinPer; ++u) {
+      const size_t i = min(blk * kBinItems + u * kBinThreads + (int)threadIdx.x, a.n - 1);
+      x[u] = a.pos[3 * i];
+      y[u] = a.pos[3 * i + 1];
+      z[u] = a.pos[3 * i + 2];
+      c[u] = a.c6[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kBinPer; ++u) {
+      const int i = blk * kBinItems + u * kBinThreads + threadIdx.x;
+      double xi = 0.0;
+      if (i < a.n) {
+        if (a.xref) {
+          a.xref[3 * (size_t)i] = x[u];
+          a.xref[3 * (size_t)i + 1] = y[u];
+          a.xref[3 * (size_t)i + 2] = z[u];
+        }
+        int bad;
+        const double4 p = wrap_values(x[u], y[u], z[u], c[u], a.g, a.c6_scale, bad);
+        if (bad) atomicOr(a.flags, bad);
+        const int id = cell_of(p, a.g);
+        a.cid[i] = id;
+        a.xw[i] = p;
+        atomicAdd(&hist[id >> a.shift], 1);
+        xi = p.w;
+      }
+      if (a.xi_partial) {
+        // the sum of xi over each 256 consecutive atoms, in the tree order
+        // of BinCount
+        sh[threadIdx.x] = xi;
+        __syncthreads();
+        const int t = threadIdx.x & 255;
+        for (int off = 128; off > 0; off >>= 1) {
+          if (t < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+          __syncthreads();
+        }
+        const int base = blk * kBinItems + u * kBinThreads + (threadIdx.x & ~255);
+        if (t == 0 && base < a.n) a.xi_partial[base >> 8] = sh[threadIdx.x];
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < a.nbucket; b += kBinThreads) a.hist[(size_t)b * a.nblk + blk] = hist[b];
+  }
+};
+
+struct BucketScatter {
+  using Args = BucketScatterArgs;
+  static constexpr int kThreads = kBinThreads;
+  static __device__ void run(const Args& a, int blk) {
+    __shared__ int next[kMaxBuckets];
+    if (a.cond && *a.cond == 0) return;
+    int c[kBinPer];
+#pragma unroll
+    for (int u = 0; u < kBinPer; ++u) c[u] = a.cid[min(blk * kBinItems + u * kBinThreads + (int)threadIdx.x, a.n - 1)];
+    // where this block's atoms of each bucket start
+    for (int b = threadIdx.x; b < a.nbucket; b += kBinThreads) next[b] = a.hist[(size_t)b * a.nblk + blk];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kBinPer; ++u) {
+      const int i = blk * kBinItems + u * kBinThreads + threadIdx.x;
+      if (i < a.n) {
+        const int p = atomicAdd(&next[c[u] >> a.shift], 1);
+        a.tmp[p] = make_int2(i, c[u]);
+      }
+    }
+  }
+};
+
+struct BucketSort {
+  using Args = BucketSortArgs;
+  static constexpr int kThreads = kBlock;
+  static constexpr int kCells = 1 << kBucketShiftMax;
+  static __device__ void run(const Args& a, int b) {
+    __shared__ int cst[kCells + 1], cur[kCells];
+    __shared__ int sh[kBlock];
+    if (a.cond && *a.cond == 0) return;
+    const int c0 = b << a.shift;
+    const int nc = min(1 << a.shift, a.g.ncell - c0);
+    const int lo = a.hist[(size_t)b * a.nblk], hi = a.hist[(size_t)(b + 1) * a.nblk];
+    for (int c = threadIdx.x; c < nc; c += kBlock) cur[c] = 0;
+    __syncthreads();
+    for (int j = lo + threadIdx.x; j < hi; j += kBlock) atomicAdd(&cur[a.tmp[j].y - c0], 1);
+    __syncthreads();
+    // exclusive scan of the bucket's cell counts
+    constexpr int kPer = kCells / kBlock;
+    int v[kPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int c = threadIdx.x * kPer + k;
+      v[k] = c < nc ? cur[c] : 0;
+      sum += v[k];
+    }
+    int total;
+    int run = block_exclusive_scan(sum, sh, total);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int c = threadIdx.x * kPer + k;
+      if (c < nc) cst[c] = run;
+      run += v[k];
+    }
+    if (threadIdx.x == 0) cst[nc] = total;
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += kBlock) {
+      a.start[c0 + c] = lo + cst[c];
+      cur[c] = cst[c];
+    }
+    if (b == a.nbucket - 1 && threadIdx.x == 0) a.start[a.g.ncell] = hi;
+    __syncthreads();
+    // the bucket in cell order (arrival order within a cell)
+    for (int j = lo + threadIdx.x; j < hi; j += kBlock) {
+      const int2 t = a.tmp[j];
+      a.tmp2[lo + atomicAdd(&cur[t.y - c0], 1)] = t;
+    }
+    __syncthreads();
+    for (int s = lo + threadIdx.x; s < hi; s += kBlock) {
+      const int2 vc = a.tmp2[s];
+      const int v = vc.x, c = vc.y;
+      const int cb = lo + cst[c - c0], ce = lo + cst[c - c0 + 1];
+      int rank = 0;
+      for (int j = cb; j < ce; ++j) rank += a.tmp2[j].x < v;
+      const int d = cb + rank;   // stable position of atom v
+      a.perm[d] = v;
+      const double4 p = a.xw[v];
+      a.xs[d] = p;
+      a.cell_s[d] = c;
+      store_fp32_rows(a.xr, a.xif, a.xf, a.xf_stride, a.g, d, p);
+    }
+    if (b == a.nbucket - 1) {
+      // padding rows: far outside any cutoff, zero weight
+      for (int s = a.n + threadIdx.x; s < a.n + kSortedPad; s += kBlock) {
+        a.xs[s] = make_double4(1e300, 1e300, 1e300, 0.0);
+        store_fp32_pad(a.xr, a.xif, a.xf, a.xf_stride, s);
+      }
+    }
+  }
+};
+
 // Neighbour reuse: *cond = 1 when some atom has moved more than skin/2
 // since the positions of the last binning (or a position is not finite).
 struct DispCheck {
@@ -474,6 +654,20 @@ inline int nblocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 int scan_blocks(int ncell) { return nblocks(ncell, kScanItems); }
 
+int bin_block_items() { return kBinItems; }
+
+bool bin_buckets(int64_t ncell, int64_t n_max, int& shift, int& nbucket) {
+  for (int s = kBucketShiftMin; s <= kBucketShiftMax; ++s) {
+    const int64_t nb = (ncell + ((int64_t)1 << s) - 1) >> s;
+    if (nb > kMaxBuckets) continue;
+    if (nb * ((n_max + kBinItems - 1) / kBinItems) > kMaxHist) return false;
+    shift = s;
+    nbucket = (int)nb;
+    return true;
+  }
+  return false;
+}
+
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   int blocks = (int)std::min<int64_t>(nblocks(count, kBlock), 4096);
@@ -521,6 +715,27 @@ static hipError_t binning_core(mls_plan_s* P, int n, const double* pos, const do
   const CellGeom& g = P->cg;
   const bool mixed = P->precision == MLS_MIXED;
   hipError_t e;
+  if (P->bin_nbucket) {
+    const int nblk = nblocks(n, kBinItems), m = P->bin_nbucket * nblk;
+    if (n > 0) {
+      BinBucketArgs a{pos, c6, n, g, P->d_cid, P->d_xw, P->d_flags, scale, mixed ? P->d_partial : nullptr, cond,
+                      xref, P->bin_shift, P->bin_nbucket, nblk, P->d_bin_hist};
+      if ((e = launch_one<BinBucket>(a, nblk, s)) != hipSuccess) return e;
+    }
+    // in place: the histograms become the start of each (bucket, block) run
+    ScanArgs sa{P->d_bin_hist, m, P->d_bin_hist, P->d_bsum, P->d_bmax, P->d_ncell_max, cond};
+    if ((e = launch_one<ScanBlocks>(sa, scan_blocks(m), s)) != hipSuccess) return e;
+    if ((e = launch_one<ScanSums>(sa, 1, s)) != hipSuccess) return e;
+    if ((e = launch_one<ScanAdd>(sa, nblocks(m, kBlock), s)) != hipSuccess) return e;
+    if (n > 0) {
+      BucketScatterArgs ca{P->d_cid, n, P->bin_shift, P->bin_nbucket, nblk, P->d_bin_hist, P->d_perm_tmp, cond};
+      if ((e = launch_one<BucketScatter>(ca, nblk, s)) != hipSuccess) return e;
+    }
+    BucketSortArgs da{P->d_bin_hist, nblk, P->bin_shift, P->bin_nbucket, P->d_perm_tmp, P->d_perm_tmp2, n,
+                      P->d_cell_start, P->d_perm, P->d_xw, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, g, cond,
+                      P->d_xf, P->xf_stride};
+    return launch_one<BucketSort>(da, P->bin_nbucket, s);
+  }
   if (n > 0) {
     BinCountArgs a{pos, c6, n, g, P->d_cid, P->d_slot, P->d_count, P->d_xw, P->d_flags, scale,
                    mixed ? P->d_partial : nullptr, cond, xref};

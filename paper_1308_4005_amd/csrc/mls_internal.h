@@ -154,6 +154,20 @@ struct LbGatherArgs { const int* perm; int n; const double* sigma; double* sig_s
 // subtracts)
 struct LbChargeArgs { const double4* xs; const double* sig_s; int n; int k; double* charge; double* partial; };
 struct ScanArgs { int* count; int m; int* start; int* bsum; int* bmax; int* max_count; const int* cond = nullptr; };
+// Bucketed binning (single plans): a bucket is a run of 2^shift consecutive
+// cell ids; hist[bucket * nblk + blk] counts the atoms of block blk in the
+// bucket, then (scanned in place) holds where they start in tmp.
+struct BinBucketArgs {
+  const double* pos; const double* c6; int n; CellGeom g; int* cid; double4* xw; int* flags; double c6_scale;
+  double* xi_partial; const int* cond; double* xref;
+  int shift; int nbucket; int nblk; int* hist;
+};
+struct BucketScatterArgs { const int* cid; int n; int shift; int nbucket; int nblk; const int* hist; int2* tmp; const int* cond; };
+struct BucketSortArgs {
+  const int* hist; int nblk; int shift; int nbucket; const int2* tmp; int2* tmp2; int n; int* start;
+  int* perm; const double4* xw; double4* xs; int* cell_s; float4* xr; float* xif; CellGeom g; const int* cond;
+  float* xf; int xf_stride;
+};
 struct ScatterArgs { const int* cid; const int* slot; int n; const int* start; int2* perm_tmp; const int* cond = nullptr; };
 struct RankArgs { const int* start; const int2* perm_tmp; int n; int* perm; };
 // Rank of each atom among its cell's atoms by original index, fused with the
@@ -407,6 +421,10 @@ struct mls_plan_s {
   int pair_after = 1;              // concurrent mode: grid-chain stages submitted before the local part
   int* d_cid = nullptr;            // n_max: cell of original atom
   int2* d_perm_tmp = nullptr;      // n_max: (original index, cell) in arrival order
+  // bucketed binning (0 buckets: the counting sort with device-wide atomics)
+  int bin_shift = 0, bin_nbucket = 0;
+  int* d_bin_hist = nullptr;       // bin_nbucket * blocks + 1
+  int2* d_perm_tmp2 = nullptr;     // n_max: (original index, cell) in cell order
   int* d_perm = nullptr;           // n_max
   int* d_cell_s = nullptr;         // n_max: cell of sorted atom
   double4* d_xs = nullptr;         // n_max: sorted
@@ -482,6 +500,10 @@ mls_status evaluate_plan(mls_plan_s* P, int64_t n, const double* pos, const doub
 
 // number of blocks of the cell-count scan
 int scan_blocks(int ncell);
+// Bucketed binning: atoms per block of its per-atom kernels, and the bucket
+// geometry for ncell cells (false: too many cells for it).
+int bin_block_items();
+bool bin_buckets(int64_t ncell, int64_t n_max, int& shift, int& nbucket);
 // halo window of the level stencil and z extent of its LDS tile
 int stencil_window(const mls_plan_s* P);
 // blocks of the coarsest-level kernel for a grid, `outs` output points per wave

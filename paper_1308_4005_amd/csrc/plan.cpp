@@ -420,8 +420,24 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   ALLOC(P->d_count, cg.ncell);
   ALLOC(P->d_cell_start, cg.ncell + 1);
   ALLOC(P->d_slot, N);
-  ALLOC(P->d_bsum, scan_blocks(cg.ncell) + 1);
-  ALLOC(P->d_bmax, scan_blocks(cg.ncell) + 1);
+  {
+    // bucketed binning unless MLS_BIN_BUCKETS=0 or the cells are too many
+    const char* env = std::getenv("MLS_BIN_BUCKETS");
+    int shift = 0, nb = 0;
+    if (!(env && std::atoi(env) == 0) && bin_buckets(cg.ncell, (int64_t)N, shift, nb)) {
+      P->bin_shift = shift;
+      P->bin_nbucket = nb;
+    }
+  }
+  int64_t scan_len = cg.ncell;
+  if (P->bin_nbucket) {
+    const int64_t hist = (int64_t)P->bin_nbucket * ((N + bin_block_items() - 1) / bin_block_items());
+    ALLOC(P->d_bin_hist, hist + 1);
+    ALLOC(P->d_perm_tmp2, N);
+    scan_len = std::max<int64_t>(scan_len, hist);
+  }
+  ALLOC(P->d_bsum, scan_blocks((int)scan_len) + 1);
+  ALLOC(P->d_bmax, scan_blocks((int)scan_len) + 1);
   ALLOC(P->d_cid, N);
   ALLOC(P->d_xw, N);
   ALLOC(P->d_perm_tmp, N);
