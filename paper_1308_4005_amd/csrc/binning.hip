@@ -306,12 +306,16 @@ struct RankGather {
 // LDS atomics only; then one block orders each bucket by cell:
 //   A. BinBucket: wrapped position, cell id, the block's bucket histogram
 //      (and, in mixed precision, the per-256-atom sums of xi)
-//   B. exclusive scan of all histograms in bucket-major order
+//   B. ScanBlocks over all histograms in bucket-major order (each scan block
+//      exclusive on its own; the consumers add the totals of the scan blocks
+//      before theirs, so the two other scan phases are not needed)
 //   C. BucketScatter: (index, cell) into the bucket's range, LDS slots
 //   D. BucketSort: per bucket, count its cells, write their starts, order
 //      the bucket by cell (LDS slots), then each atom's rank among its
 //      cell's atoms by original index gives its stable position, and the
-//      sorted arrays are gathered as in RankGather.
+//      sorted arrays are gathered as in RankGather.  A bucket of up to
+//      kSortCap atoms is held in registers and LDS; a larger one goes
+//      through tmp2 in global memory.
 // The result is the same integer permutation as the counting sort above.
 constexpr int kBinThreads = 512;
 constexpr int kBinPer = 4;
@@ -319,6 +323,51 @@ constexpr int kBinItems = kBinThreads * kBinPer;
 constexpr int kMaxBuckets = 4096;
 constexpr int kBucketShiftMin = 9, kBucketShiftMax = 11;
 constexpr int64_t kMaxHist = (int64_t)1 << 24;
+constexpr int kSortThreads = 1024;
+constexpr int kSortPer = 4;
+constexpr int kSortCap = kSortThreads * kSortPer;
+
+// Exclusive scan of one value per thread over a block of T threads (a
+// multiple of 64); ws holds T / 64 ints.
+template <int T>
+__device__ __forceinline__ int block_scan_excl(int v, int* ws, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) ws[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    int t = lane < T / 64 ? ws[lane] : 0;
+#pragma unroll
+    for (int off = 1; off < T / 64; off <<= 1) {
+      const int y = __shfl_up(t, off);
+      if (lane >= off) t += y;
+    }
+    if (lane < T / 64) ws[lane] = t;
+  }
+  __syncthreads();
+  total = ws[T / 64 - 1];
+  const int before = w > 0 ? ws[w - 1] : 0;
+  __syncthreads();
+  return before + x - v;
+}
+
+template <int T>
+__device__ __forceinline__ int block_sum_i(int v, int* ws) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int t = 0;
+#pragma unroll
+  for (int w = 0; w < T / 64; ++w) t += ws[w];
+  __syncthreads();
+  return t;
+}
 
 struct BinBucket {
   using Args = BinBucketArgs;
@@ -381,14 +430,31 @@ struct BinBucket {
 struct BucketScatter {
   using Args = BucketScatterArgs;
   static constexpr int kThreads = kBinThreads;
+  static constexpr int kMaxScanBlocks = (int)(kMaxHist / kScanItems);
   static __device__ void run(const Args& a, int blk) {
     __shared__ int next[kMaxBuckets];
+    __shared__ int sbo[kMaxScanBlocks];
+    __shared__ int ws[kBinThreads / 64];
     if (a.cond && *a.cond == 0) return;
     int c[kBinPer];
 #pragma unroll
     for (int u = 0; u < kBinPer; ++u) c[u] = a.cid[min(blk * kBinItems + u * kBinThreads + (int)threadIdx.x, a.n - 1)];
+    // exclusive prefix of the scan blocks' totals
+    const int m = a.nbucket * a.nblk, nsb = (m + kScanItems - 1) / kScanItems;
+    int carry = 0;
+    for (int k0 = 0; k0 < nsb; k0 += kBinThreads) {
+      const int k = k0 + threadIdx.x;
+      int total;
+      const int ex = block_scan_excl<kBinThreads>(k < nsb ? a.bsum[k] : 0, ws, total);
+      if (k < nsb) sbo[k] = carry + ex;
+      carry += total;
+    }
+    __syncthreads();
     // where this block's atoms of each bucket start
-    for (int b = threadIdx.x; b < a.nbucket; b += kBinThreads) next[b] = a.hist[(size_t)b * a.nblk + blk];
+    for (int b = threadIdx.x; b < a.nbucket; b += kBinThreads) {
+      const int i = b * a.nblk + blk;
+      next[b] = a.hist[i] + sbo[i / kScanItems];
+    }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kBinPer; ++u) {
@@ -403,66 +469,120 @@ struct BucketScatter {
 
 struct BucketSort {
   using Args = BucketSortArgs;
-  static constexpr int kThreads = kBlock;
+  static constexpr int kThreads = kSortThreads;
   static constexpr int kCells = 1 << kBucketShiftMax;
-  static __device__ void run(const Args& a, int b) {
-    __shared__ int cst[kCells + 1], cur[kCells];
-    __shared__ int sh[kBlock];
-    if (a.cond && *a.cond == 0) return;
-    const int c0 = b << a.shift;
-    const int nc = min(1 << a.shift, a.g.ncell - c0);
-    const int lo = a.hist[(size_t)b * a.nblk], hi = a.hist[(size_t)(b + 1) * a.nblk];
-    for (int c = threadIdx.x; c < nc; c += kBlock) cur[c] = 0;
-    __syncthreads();
-    for (int j = lo + threadIdx.x; j < hi; j += kBlock) atomicAdd(&cur[a.tmp[j].y - c0], 1);
-    __syncthreads();
-    // exclusive scan of the bucket's cell counts
-    constexpr int kPer = kCells / kBlock;
-    int v[kPer], sum = 0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int c = threadIdx.x * kPer + k;
-      v[k] = c < nc ? cur[c] : 0;
-      sum += v[k];
-    }
+  static_assert(kCells == 2 * kSortThreads, "two cells per thread in the scan of the cell counts");
+
+  // Exclusive scan of the bucket's cell counts cur[0, nc) into cst (cst[nc]:
+  // the bucket's atoms), the cells' starts to global memory, cur := cst.
+  static __device__ void cell_starts(const Args& a, int b, int c0, int nc, int lo, int* cst, int* cur, int* ws) {
+    const int t2 = 2 * threadIdx.x;
+    const int v0 = t2 < nc ? cur[t2] : 0, v1 = t2 + 1 < nc ? cur[t2 + 1] : 0;
     int total;
-    int run = block_exclusive_scan(sum, sh, total);
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int c = threadIdx.x * kPer + k;
-      if (c < nc) cst[c] = run;
-      run += v[k];
-    }
+    const int ex = block_scan_excl<kSortThreads>(v0 + v1, ws, total);
+    if (t2 < nc) cst[t2] = ex;
+    if (t2 + 1 < nc) cst[t2 + 1] = ex + v0;
     if (threadIdx.x == 0) cst[nc] = total;
     __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += kBlock) {
+    for (int c = threadIdx.x; c < nc; c += kSortThreads) {
       a.start[c0 + c] = lo + cst[c];
       cur[c] = cst[c];
     }
-    if (b == a.nbucket - 1 && threadIdx.x == 0) a.start[a.g.ncell] = hi;
+    if (b == a.nbucket - 1 && threadIdx.x == 0) a.start[a.g.ncell] = a.n;
     __syncthreads();
-    // the bucket in cell order (arrival order within a cell)
-    for (int j = lo + threadIdx.x; j < hi; j += kBlock) {
-      const int2 t = a.tmp[j];
-      a.tmp2[lo + atomicAdd(&cur[t.y - c0], 1)] = t;
+  }
+
+  __device__ static void emit(const Args& a, int v, int c, int d, const double4& p) {
+    a.perm[d] = v;
+    a.xs[d] = p;
+    a.cell_s[d] = c;
+    store_fp32_rows(a.xr, a.xif, a.xf, a.xf_stride, a.g, d, p);
+  }
+
+  static __device__ void run(const Args& a, int b) {
+    __shared__ int cst[kCells + 1], cur[kCells];
+    __shared__ int2 srt[kSortCap];
+    __shared__ int ws[kSortThreads / 64];
+    if (a.cond && *a.cond == 0) return;
+    const int c0 = b << a.shift;
+    const int nc = min(1 << a.shift, a.g.ncell - c0);
+    // the bucket's range in tmp: its scanned histogram entry plus the totals
+    // of the scan blocks before it
+    const int m = a.nbucket * a.nblk;
+    const int i0 = b * a.nblk, i1 = (b + 1) * a.nblk;
+    int s0 = 0, s1 = 0;
+    for (int k = threadIdx.x; k < i1 / kScanItems; k += kSortThreads) {
+      const int v = a.bsum[k];
+      s1 += v;
+      if (k < i0 / kScanItems) s0 += v;
     }
+    s0 = block_sum_i<kSortThreads>(s0, ws);
+    s1 = block_sum_i<kSortThreads>(s1, ws);
+    const int lo = i0 < m ? s0 + a.hist[i0] : a.n;
+    const int hi = i1 < m ? s1 + a.hist[i1] : a.n;
+    const int cnt = hi - lo;
+    for (int c = threadIdx.x; c < nc; c += kSortThreads) cur[c] = 0;
     __syncthreads();
-    for (int s = lo + threadIdx.x; s < hi; s += kBlock) {
-      const int2 vc = a.tmp2[s];
-      const int v = vc.x, c = vc.y;
-      const int cb = lo + cst[c - c0], ce = lo + cst[c - c0 + 1];
-      int rank = 0;
-      for (int j = cb; j < ce; ++j) rank += a.tmp2[j].x < v;
-      const int d = cb + rank;   // stable position of atom v
-      a.perm[d] = v;
-      const double4 p = a.xw[v];
-      a.xs[d] = p;
-      a.cell_s[d] = c;
-      store_fp32_rows(a.xr, a.xif, a.xf, a.xf_stride, a.g, d, p);
+    if (cnt <= kSortCap) {
+      int2 e[kSortPer];
+#pragma unroll
+      for (int k = 0; k < kSortPer; ++k) {
+        const int j = threadIdx.x + k * kSortThreads;
+        e[k] = j < cnt ? a.tmp[lo + j] : make_int2(0, c0);
+      }
+#pragma unroll
+      for (int k = 0; k < kSortPer; ++k)
+        if ((int)threadIdx.x + k * kSortThreads < cnt) atomicAdd(&cur[e[k].y - c0], 1);
+      __syncthreads();
+      cell_starts(a, b, c0, nc, lo, cst, cur, ws);
+      // the bucket in cell order (arrival order within a cell)
+#pragma unroll
+      for (int k = 0; k < kSortPer; ++k)
+        if ((int)threadIdx.x + k * kSortThreads < cnt) srt[atomicAdd(&cur[e[k].y - c0], 1)] = e[k];
+      __syncthreads();
+      int v[kSortPer], c[kSortPer], d[kSortPer];
+#pragma unroll
+      for (int k = 0; k < kSortPer; ++k) {
+        const int s = threadIdx.x + k * kSortThreads;
+        v[k] = 0;
+        c[k] = c0;
+        d[k] = -1;
+        if (s < cnt) {
+          const int2 vc = srt[s];
+          v[k] = vc.x;
+          c[k] = vc.y;
+          const int cb = cst[vc.y - c0], ce = cst[vc.y - c0 + 1];
+          int rank = 0;
+          for (int j = cb; j < ce; ++j) rank += srt[j].x < vc.x;
+          d[k] = lo + cb + rank;   // stable position of atom v
+        }
+      }
+      double4 p[kSortPer];
+#pragma unroll
+      for (int k = 0; k < kSortPer; ++k) p[k] = a.xw[v[k]];   // every gather in flight
+#pragma unroll
+      for (int k = 0; k < kSortPer; ++k)
+        if (d[k] >= 0) emit(a, v[k], c[k], d[k], p[k]);
+    } else {
+      for (int j = lo + threadIdx.x; j < hi; j += kSortThreads) atomicAdd(&cur[a.tmp[j].y - c0], 1);
+      __syncthreads();
+      cell_starts(a, b, c0, nc, lo, cst, cur, ws);
+      for (int j = lo + threadIdx.x; j < hi; j += kSortThreads) {
+        const int2 t = a.tmp[j];
+        a.tmp2[lo + atomicAdd(&cur[t.y - c0], 1)] = t;
+      }
+      __syncthreads();
+      for (int s = lo + threadIdx.x; s < hi; s += kSortThreads) {
+        const int2 vc = a.tmp2[s];
+        const int cb = lo + cst[vc.y - c0], ce = lo + cst[vc.y - c0 + 1];
+        int rank = 0;
+        for (int j = cb; j < ce; ++j) rank += a.tmp2[j].x < vc.x;
+        emit(a, vc.x, vc.y, cb + rank, a.xw[vc.x]);
+      }
     }
     if (b == a.nbucket - 1) {
       // padding rows: far outside any cutoff, zero weight
-      for (int s = a.n + threadIdx.x; s < a.n + kSortedPad; s += kBlock) {
+      for (int s = a.n + threadIdx.x; s < a.n + kSortedPad; s += kSortThreads) {
         a.xs[s] = make_double4(1e300, 1e300, 1e300, 0.0);
         store_fp32_pad(a.xr, a.xif, a.xf, a.xf_stride, s);
       }
@@ -722,16 +842,16 @@ static hipError_t binning_core(mls_plan_s* P, int n, const double* pos, const do
                       xref, P->bin_shift, P->bin_nbucket, nblk, P->d_bin_hist};
       if ((e = launch_one<BinBucket>(a, nblk, s)) != hipSuccess) return e;
     }
-    // in place: the histograms become the start of each (bucket, block) run
+    // in place, per scan block: the histograms become the start of each
+    // (bucket, block) run within its scan block
     ScanArgs sa{P->d_bin_hist, m, P->d_bin_hist, P->d_bsum, P->d_bmax, P->d_ncell_max, cond};
     if ((e = launch_one<ScanBlocks>(sa, scan_blocks(m), s)) != hipSuccess) return e;
-    if ((e = launch_one<ScanSums>(sa, 1, s)) != hipSuccess) return e;
-    if ((e = launch_one<ScanAdd>(sa, nblocks(m, kBlock), s)) != hipSuccess) return e;
     if (n > 0) {
-      BucketScatterArgs ca{P->d_cid, n, P->bin_shift, P->bin_nbucket, nblk, P->d_bin_hist, P->d_perm_tmp, cond};
+      BucketScatterArgs ca{P->d_cid, n, P->bin_shift, P->bin_nbucket, nblk, P->d_bin_hist, P->d_bsum,
+                           P->d_perm_tmp, cond};
       if ((e = launch_one<BucketScatter>(ca, nblk, s)) != hipSuccess) return e;
     }
-    BucketSortArgs da{P->d_bin_hist, nblk, P->bin_shift, P->bin_nbucket, P->d_perm_tmp, P->d_perm_tmp2, n,
+    BucketSortArgs da{P->d_bin_hist, P->d_bsum, nblk, P->bin_shift, P->bin_nbucket, P->d_perm_tmp, P->d_perm_tmp2, n,
                       P->d_cell_start, P->d_perm, P->d_xw, P->d_xs, P->d_cell_s, P->d_xr, P->d_xif, g, cond,
                       P->d_xf, P->xf_stride};
     return launch_one<BucketSort>(da, P->bin_nbucket, s);

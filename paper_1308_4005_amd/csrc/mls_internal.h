@@ -156,15 +156,19 @@ struct LbChargeArgs { const double4* xs; const double* sig_s; int n; int k; doub
 struct ScanArgs { int* count; int m; int* start; int* bsum; int* bmax; int* max_count; const int* cond = nullptr; };
 // Bucketed binning (single plans): a bucket is a run of 2^shift consecutive
 // cell ids; hist[bucket * nblk + blk] counts the atoms of block blk in the
-// bucket, then (scanned in place) holds where they start in tmp.
+// bucket, then (scanned in place, per scan block; bsum: the scan blocks'
+// totals) gives where they start in tmp.
 struct BinBucketArgs {
   const double* pos; const double* c6; int n; CellGeom g; int* cid; double4* xw; int* flags; double c6_scale;
   double* xi_partial; const int* cond; double* xref;
   int shift; int nbucket; int nblk; int* hist;
 };
-struct BucketScatterArgs { const int* cid; int n; int shift; int nbucket; int nblk; const int* hist; int2* tmp; const int* cond; };
+struct BucketScatterArgs {
+  const int* cid; int n; int shift; int nbucket; int nblk; const int* hist; const int* bsum; int2* tmp;
+  const int* cond;
+};
 struct BucketSortArgs {
-  const int* hist; int nblk; int shift; int nbucket; const int2* tmp; int2* tmp2; int n; int* start;
+  const int* hist; const int* bsum; int nblk; int shift; int nbucket; const int2* tmp; int2* tmp2; int n; int* start;
   int* perm; const double4* xw; double4* xs; int* cell_s; float4* xr; float* xif; CellGeom g; const int* cond;
   float* xf; int xf_stride;
 };
