@@ -484,6 +484,141 @@ struct Prolong {
   }
 };
 
+// Small levels: a grid transfer of a few thousand points has too few threads
+// to hide its loads (each thread of the forms above issues (p+1)^3 or p^3 of
+// them one after another), so there a group of lanes shares one coarse point.
+// Restriction: 8 lanes per coarse point split its (p+1)^2 (z, y) rows, each
+// lane sums its rows' x taps, and the group adds its partial sums (fixed
+// order).  Prolongation: one lane per z-plane of the coarse point's p^3
+// neighbourhood (groups of 4 for p = 4, 8 for p = 6), the group adds the
+// planes' contributions to the 8 fine points, and each lane writes some of
+// them.  The sums are the same as above up to the order of the terms.
+constexpr int kRestrictGroup = 8;
+
+// tap t of a transfer in one dimension: offset 0 (t = 0), -(2k+1) (t = 1+2k),
+// +(2k+1) (t = 2+2k)
+template <int P>
+__device__ __forceinline__ void restrict_tap(int t, int& off, double& w) {
+  const int k = (t - 1) >> 1;
+  off = t == 0 ? 0 : ((t & 1) ? -(2 * k + 1) : 2 * k + 1);
+  w = t == 0 ? 1.0 : rp_weight_odd<P>(k);
+}
+
+template <int P>
+struct RestrictSplit {
+  using Args = TransferArgs;
+  static constexpr int kThreads = kBlock;
+  static __device__ void run(const Args& a, int blk) {
+    const int t = blk * kBlock + threadIdx.x;
+    const int M = t / kRestrictGroup, g = t % kRestrictGroup;
+    const GridDims& f = a.gs;
+    const GridDims& c = a.gd;
+    constexpr int K = P + 1;
+    double acc = 0.0;
+    if (M < c.size) {
+      const int X = M % c.n[0], Y = (M / c.n[0]) % c.n[1], Z = M / (c.n[0] * c.n[1]);
+      int ix[K];
+      double w[K];
+#pragma unroll
+      for (int cc = 0; cc < K; ++cc) {
+        int o;
+        restrict_tap<P>(cc, o, w[cc]);
+        ix[cc] = wrapi(2 * X + o, f.n[0]);
+      }
+      for (int r = g; r < K * K; r += kRestrictGroup) {
+        const int i = r / K, j = r - (r / K) * K;
+        int oi, oj;
+        double wi, wj;
+        restrict_tap<P>(i, oi, wi);
+        restrict_tap<P>(j, oj, wj);
+        const double* row = a.src + ((size_t)wrapi(2 * Z + oi, f.n[2]) * f.n[1] + wrapi(2 * Y + oj, f.n[1])) * f.n[0];
+        double sx = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < K; ++cc) sx += w[cc] * row[ix[cc]];
+        acc += (wi * wj) * sx;
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < kRestrictGroup; off <<= 1) acc += __shfl_xor(acc, off);
+    if (M < c.size && g == 0) a.dst[M] = acc;
+  }
+};
+
+template <int P>
+struct ProlongSplit {
+  using Args = TransferArgs;
+  static constexpr int kThreads = kBlock;
+  static constexpr int G = P <= 4 ? 4 : 8;   // lanes per coarse point, one per z-plane
+  static __device__ void run(const Args& a, int blk) {
+    const int t = blk * kBlock + threadIdx.x;
+    const int M = t / G, g = t % G;
+    const GridDims& c = a.gs;
+    const GridDims& f = a.gd;
+    constexpr int H = P / 2;
+    // this lane's plane tz = g: [z parity][y parity][x parity] contributions
+    double v8[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v8[q] = 0.0;
+    const bool live = M < c.size;
+    const int Mc = live ? M : 0;
+    const int X = Mc % c.n[0], Y = (Mc / c.n[0]) % c.n[1], Z = Mc / (c.n[0] * c.n[1]);
+    if (live && g < P) {
+      double w[P];
+      int ix[P], iy[P];
+#pragma unroll
+      for (int u = 0; u < P; ++u) {
+        const int o = 2 * H - 1 - 2 * u;
+        w[u] = rp_weight_odd<P>(((o < 0 ? -o : o) - 1) / 2);
+        ix[u] = wrapi(X - H + 1 + u, c.n[0]);
+        iy[u] = wrapi(Y - H + 1 + u, c.n[1]);
+      }
+      const int og = 2 * H - 1 - 2 * g;
+      const double wz = rp_weight_odd<P>(((og < 0 ? -og : og) - 1) / 2);
+      const int iz = wrapi(Z - H + 1 + g, c.n[2]);
+      double ye[2] = {0.0, 0.0}, yo[2] = {0.0, 0.0};
+#pragma unroll
+      for (int ty = 0; ty < P; ++ty) {
+        const double* row = a.src + ((size_t)iz * c.n[1] + iy[ty]) * c.n[0];
+        double v[P];
+#pragma unroll
+        for (int tx = 0; tx < P; ++tx) v[tx] = row[ix[tx]];
+        double xo = 0.0;
+#pragma unroll
+        for (int tx = 0; tx < P; ++tx) xo += w[tx] * v[tx];
+        const double xe = v[H - 1];
+        if (ty == H - 1) {
+          ye[0] = xe;
+          ye[1] = xo;
+        }
+        yo[0] += w[ty] * xe;
+        yo[1] += w[ty] * xo;
+      }
+      if (g == H - 1) {   // the even fine z takes the centre plane alone
+        v8[0] = ye[0];
+        v8[1] = ye[1];
+        v8[2] = yo[0];
+        v8[3] = yo[1];
+      }
+      v8[4] = wz * ye[0];
+      v8[5] = wz * ye[1];
+      v8[6] = wz * yo[0];
+      v8[7] = wz * yo[1];
+    }
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v8[q] += __shfl_xor(v8[q], off);
+    if (!live) return;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q % G != g) continue;
+      const int pz = q >> 2, py = (q >> 1) & 1, px = q & 1;
+      const size_t J = ((size_t)(2 * Z + pz) * f.n[1] + (2 * Y + py)) * f.n[0] + 2 * X + px;
+      a.dst[J] = (a.add ? a.add[J] : 0.0) + v8[q];
+    }
+  }
+};
+
 // ------------------------------------------------------------ interpolation + assembly
 // Interpolated value and gradient (in grid units) of one grid at an atom with
 // weights w, dw and wrapped indices idx.  The p z-planes are walked in a loop
@@ -1007,6 +1142,8 @@ hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s) {
   return launch_one<AnterpAtomic<6>>(a, nblocks(n, kBlock), s);
 }
 
+hipError_t launch_prolong_into(mls_plan_s* P, const TransferArgs& a, hipStream_t s);
+
 hipError_t launch_restrictions(mls_plan_s* P, hipStream_t s) {
   for (int k = 2; k <= P->levels; ++k) {
     hipError_t e = launch_restrict(P, k - 1, s);
@@ -1021,9 +1158,7 @@ hipError_t launch_prolongations(mls_plan_s* P, hipStream_t s, bool drop_e1) {
     if (k == 1 && drop_e1) {
       Level& F = P->lv[0];
       Level& C = P->lv[1];
-      TransferArgs a{C.E, C.g, nullptr, F.E, F.g};
-      e = P->order == 4 ? launch_one<Prolong<4>>(a, nblocks(C.g.size, kBlock), s)
-                        : launch_one<Prolong<6>>(a, nblocks(C.g.size, kBlock), s);
+      e = launch_prolong_into(P, TransferArgs{C.E, C.g, nullptr, F.E, F.g}, s);
     } else {
       e = launch_prolong(P, k, s);
     }
@@ -1036,16 +1171,27 @@ hipError_t launch_restrict(mls_plan_s* P, int k_fine, hipStream_t s) {
   Level& F = P->lv[k_fine - 1];
   Level& C = P->lv[k_fine];
   TransferArgs a{F.q, F.g, nullptr, C.q, C.g};
+  if (C.g.size <= P->split_restrict) {
+    const int nb = nblocks((int64_t)C.g.size * kRestrictGroup, kBlock);
+    return P->order == 4 ? launch_one<RestrictSplit<4>>(a, nb, s) : launch_one<RestrictSplit<6>>(a, nb, s);
+  }
   if (P->order == 4) return launch_one<Restrict<4>>(a, nblocks(C.g.size, kBlock), s);
   return launch_one<Restrict<6>>(a, nblocks(C.g.size, kBlock), s);
+}
+
+hipError_t launch_prolong_into(mls_plan_s* P, const TransferArgs& a, hipStream_t s) {
+  if (a.gs.size <= P->split_prolong) {
+    if (P->order == 4) return launch_one<ProlongSplit<4>>(a, nblocks((int64_t)a.gs.size * ProlongSplit<4>::G, kBlock), s);
+    return launch_one<ProlongSplit<6>>(a, nblocks((int64_t)a.gs.size * ProlongSplit<6>::G, kBlock), s);
+  }
+  if (P->order == 4) return launch_one<Prolong<4>>(a, nblocks(a.gs.size, kBlock), s);
+  return launch_one<Prolong<6>>(a, nblocks(a.gs.size, kBlock), s);
 }
 
 hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s) {
   Level& F = P->lv[k_fine - 1];
   Level& C = P->lv[k_fine];
-  TransferArgs a{C.E, C.g, F.e, F.E, F.g};
-  if (P->order == 4) return launch_one<Prolong<4>>(a, nblocks(C.g.size, kBlock), s);
-  return launch_one<Prolong<6>>(a, nblocks(C.g.size, kBlock), s);
+  return launch_prolong_into(P, TransferArgs{C.E, C.g, F.e, F.E, F.g}, s);
 }
 
 hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forces, double* potential,

@@ -345,6 +345,32 @@ hipError_t launch_one(const typename K::Args& a, int blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Persistent form of k_one for a kernel that should not fill the chip: the
+// grid holds a fixed number of blocks, and block b (on XCD b mod 8) walks the
+// items of its XCD's contiguous share of [0, nwork) with the stride of the
+// blocks on that XCD.  The wave slots it leaves free on every CU serve the
+// kernels of other streams.
+template <class K>
+__global__ void __launch_bounds__(K::kThreads) k_persist(typename K::Args a, int nwork) {
+  const int x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+  const int q = nwork / kXcds, r = nwork % kXcds;
+  const int lo = x * q + (x < r ? x : r), cnt = q + (x < r ? 1 : 0);
+  const int nbx = ((int)gridDim.x - x + kXcds - 1) / kXcds;
+  for (int w = i; w < cnt; w += nbx) {
+    K::run(a, lo + w);
+    __syncthreads();   // LDS of the item is free before the next one
+  }
+}
+
+// blocks <= 0 or >= nwork: the ordinary launch of one block per item
+template <class K>
+hipError_t launch_persist(const typename K::Args& a, int nwork, int blocks, hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  if (blocks <= 0 || blocks >= nwork) return launch_one<K>(a, nwork, s);
+  k_persist<K><<<blocks, K::kThreads, 0, s>>>(a, nwork);
+  return hipGetLastError();
+}
+
 template <class K>
 hipError_t launch_batched_phase(const BatchPhase& ph, hipStream_t s) {
   if (ph.nwork == 0) return hipSuccess;
@@ -423,6 +449,10 @@ struct mls_plan_s {
   int* d_bmax = nullptr;           // scan block maxima
   bool pair_fast = false;          // half-cutoff cells with per-atom row trimming
   int pair_after = 1;              // concurrent mode: grid-chain stages submitted before the local part
+  int pair_blocks = 0;             // > 0: the trimmed pair kernels run persistent with this many blocks
+  // coarse points up to which restriction and prolongation use the forms
+  // with a group of lanes per coarse point
+  int split_restrict = 65536, split_prolong = 0;
   int* d_cid = nullptr;            // n_max: cell of original atom
   int2* d_perm_tmp = nullptr;      // n_max: (original index, cell) in arrival order
   // bucketed binning (0 buckets: the counting sort with device-wide atomics)

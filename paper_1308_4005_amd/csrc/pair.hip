@@ -791,21 +791,21 @@ hipError_t launch_pair_k(mls_plan_s* P, int n, hipStream_t s, const PairRep* rep
                 P->d_floc};
     a.xf = P->d_xf;
     a.xf_stride = P->xf_stride;
-    if (!rep) return launch_one<PairTrimF32<K>>(a, waves, s);
+    if (!rep) return launch_persist<PairTrimF32<K>>(a, waves, P->pair_blocks, s);
     a.rep = *rep;
     *fused = true;
     P->rep_nb = waves;
-    return launch_one<PairTrimF32<K, true>>(a, waves, s);
+    return launch_persist<PairTrimF32<K, true>>(a, waves, P->pair_blocks, s);
   }
   PairArgs a{P->d_xs, P->d_cell_s, P->d_cell_start, n, g, pair_const(P), P->d_e0, P->d_floc, nullptr};
   a.xf = P->d_xf;
   a.xf_stride = P->xf_stride;
   if (P->pair_fast && n < (1 << 25)) {
-    if (!rep) return launch_one<PairTrimF64<K>>(a, waves, s);
+    if (!rep) return launch_persist<PairTrimF64<K>>(a, waves, P->pair_blocks, s);
     a.rep = *rep;
     *fused = true;
     P->rep_nb = waves;
-    return launch_one<PairTrimF64<K, false, true>>(a, waves, s);
+    return launch_persist<PairTrimF64<K, false, true>>(a, waves, P->pair_blocks, s);
   }
   if (!P->pair_fast) return launch_one<PairWave<K>>(a, n, s);
   return launch_one<PairGeneric<K>>(a, (n + kBlock - 1) / kBlock, s);

@@ -200,6 +200,14 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   P->cself = gamma_s(0.0, cont) * P->inv_a6;  // eq:self-interaction-energy
   hipGetDevice(&P->device);
   if (const char* env = std::getenv("MLS_PAIR_AFTER")) P->pair_after = std::min(5, std::max(0, std::atoi(env)));
+  if (const char* env = std::getenv("MLS_SPLIT_RESTRICT")) P->split_restrict = std::atoi(env);
+  if (const char* env = std::getenv("MLS_SPLIT_PROLONG")) P->split_prolong = std::atoi(env);
+  if (const char* env = std::getenv("MLS_PAIR_WAVES_CU")) {
+    // persistent pair kernel: this many single-wave blocks per CU
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && ncu > 0)
+      P->pair_blocks = std::max(0, std::atoi(env)) * ncu;
+  }
 
   // ---------------------------------------------------------------- levels
   int l = p.levels;
