@@ -61,7 +61,8 @@ def work_model(plan_info, n, pairs, order):
         "restriction": dict(bound="hbm", bytes=8 * sum(pts[:-1]) + 8 * sum(pts[1:])),
         "prolongation": dict(bound="hbm", bytes=16 * sum(pts[:-1]) + 8 * sum(pts[1:])),
         "binning": dict(bound="hbm", bytes=112 * n),
-        "coarsest": dict(bound="alu", flops=2 * pts[-1] ** 2),
+        # FP64 in both precisions
+        "coarsest": dict(bound="alu", flops=2 * pts[-1] ** 2, fp64=True),
     }
 
 
@@ -83,10 +84,11 @@ def stage_rooflines(stage_ms, model, precision):
                        "peak": PEAK["hbm"], "frac": a / PEAK["hbm"]}
         else:
             a = m["flops"] / dt / 1e12
-            peak = PEAK["fp32" if precision == "mixed" else "fp64"]
+            f32 = precision == "mixed" and not m.get("fp64")
+            peak = PEAK["fp32" if f32 else "fp64"]
             r = {"bound": "alu", "ms": ms, "flops": m["flops"], "achieved": a, "unit": "TFLOP/s", "peak": peak,
                  "frac": a / peak}
-            if precision == "mixed":
+            if f32:
                 r["peak_unpacked_fp32"] = PEAK["fp64"]
                 r["frac_unpacked_fp32"] = a / PEAK["fp64"]
             out[st] = r
