@@ -239,6 +239,14 @@ constexpr int kQueue = 32;    // entries per lane
 constexpr int kBatchF = 4;    // candidates per filter step
 
 // 16-byte load from a 4-byte aligned address (four consecutive floats)
+// element j of a uniform array through a 32-bit byte offset (the caller
+// guarantees j * sizeof(T) < 2^32), so the load takes its base from scalar
+// registers instead of a 64-bit per-lane address
+template <class T>
+__device__ __forceinline__ const T& at32(const T* base, int j) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (unsigned)j * (unsigned)sizeof(T));
+}
+
 __device__ __forceinline__ float4 load4f(const float* p) {
   float4 v;
   __builtin_memcpy(&v, p, sizeof(v));   // 4-byte aligned 16-byte load
@@ -282,7 +290,7 @@ __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, in
     const double sx = (double)((ent & 3) - 1) * g.L[0];
     const double sy = (double)(((ent >> 2) & 3) - 1) * g.L[1];
     const double sz = (double)(((ent >> 4) & 3) - 1) * g.L[2];
-    const double4 xj = xs[j];
+    const double4 xj = at32(xs, j);
     const double dx = (xi.x - sx) - xj.x;
     const double dy = (xi.y - sy) - xj.y;
     const double dz = (xi.z - sz) - xj.z;
@@ -336,26 +344,32 @@ __device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int dy, in
   const float ay = fmaf((float)-dy, pc.wf[1], xf_i.y);
   const float az = fmaf((float)-dz, pc.wf[2], xf_i.z);
   int* const qlane = queue + lane;
-  // loop-carried, so a finished lane keeps stale values; j + b < j1 masks them
+  const float* const xf1 = xf + xfs;
+  const float* const xf2 = xf1 + xfs;
+  // loop-carried, so a finished lane keeps stale values; b < rem masks them
   float4 X = make_float4(0.0f, 0.0f, 0.0f, 0.0f), Y = X, Z = X;
   for (;;) {
     int cnt = A.cnt;
     const int head = A.head;
     bool full = false;
     while (__any(j < j1)) {
+      const int rem = j1 - j;   // sources left in the run (<= 0: none)
       if (j < j1) {
-        X = load4f(xf + j);
-        Y = load4f(xf + xfs + j);
-        Z = load4f(xf + 2 * xfs + j);
+        // a 32-bit byte offset from the uniform array bases
+        const unsigned off = (unsigned)j * 4u;
+        X = load4f(reinterpret_cast<const float*>(reinterpret_cast<const char*>(xf) + off));
+        Y = load4f(reinterpret_cast<const float*>(reinterpret_cast<const char*>(xf1) + off));
+        Z = load4f(reinterpret_cast<const float*>(reinterpret_cast<const char*>(xf2) + off));
       }
       const float xb[4] = {X.x, X.y, X.z, X.w}, yb[4] = {Y.x, Y.y, Y.z, Y.w}, zb[4] = {Z.x, Z.y, Z.z, Z.w};
+      const int ent0 = (j << 6) | img;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const float dxv = ax - xb[b], dyv = ay - yb[b], dzv = az - zb[b];
         const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
-        const bool hit = (j + b < j1) & (r2 < pc.a2f);
+        const bool hit = (b < rem) & (r2 < pc.a2f);
         // the next free slot: write unconditionally, keep on a hit
-        qlane[kWaveQ * ((head + cnt) & (kQueue - 1))] = ((j + b) << 6) | img;
+        qlane[kWaveQ * ((head + cnt) & (kQueue - 1))] = ent0 + (b << 6);
         cnt += hit ? 1 : 0;
       }
       j += j < j1 ? 4 : 0;
@@ -544,8 +558,8 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
     float4 xj = make_float4(L.xx + pc.w[0], L.yy, L.zz, L.cxf);
     float wsrc = 0.0f;
     if (ok) {
-      xj = xr[j];
-      wsrc = xif[j];
+      xj = at32(xr, j);
+      wsrc = at32(xif, j);
     }
     const int ix = (ent << 30) >> 30, dy = (ent << 27) >> 29, dz = (ent << 24) >> 29;
     const float bx = fmaf((float)ix, -L.ncf, L.cxf);
@@ -617,37 +631,41 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
   const float az = fmaf((float)-dz, pc.w[2], L.zz);
   const int bits = entry_bits(ix, dy, dz);
   int* const qlane = queue + lane;
-  // loop-carried, so a finished lane keeps stale values; j + b < j1 masks them
+  const float* const xf1 = xf + xfs;
+  const float* const xf2 = xf1 + xfs;
+  // loop-carried, so a finished lane keeps stale values; b < rem masks them
   float4 X = make_float4(0.0f, 0.0f, 0.0f, 0.0f), Y = X, Z = X;
-  for (;;) {
-    int cnt = A.cnt;
-    const int head = A.head;
-    bool full = false;
-    while (__any(j < j1)) {
-      if (j < j1) {
-        X = load4f(xf + j);
-        Y = load4f(xf + xfs + j);
-        Z = load4f(xf + 2 * xfs + j);
-      }
-      const float xb[4] = {X.x, X.y, X.z, X.w}, yb[4] = {Y.x, Y.y, Y.z, Y.w}, zb[4] = {Z.x, Z.y, Z.z, Z.w};
-#pragma unroll
-      for (int b = 0; b < kBatchF; ++b) {
-        const float dxv = ax - xb[b], dyv = ay - yb[b], dzv = az - zb[b];
-        const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
-        const bool hit = (j + b < j1) & (r2 < pc.a2f);
-        qlane[kWaveQ * ((head + cnt) & (kQueue - 1))] = ((j + b) << 8) | bits;
-        cnt += hit ? 1 : 0;
-      }
-      j += j < j1 ? kBatchF : 0;
-      if (__any(cnt > kQueue - kBatchF)) {
-        full = true;
-        break;
-      }
+  // one loop level, the drain inside it: the accumulators change only on the
+  // drain path (a loop nest made the compiler copy them every filter step)
+  int cnt = A.cnt, head = A.head;
+  while (__any(j < j1)) {
+    const int rem = j1 - j;   // sources left in the run (<= 0: none)
+    if (j < j1) {
+      // a 32-bit byte offset from the uniform array bases
+      const unsigned off = (unsigned)j * 4u;
+      X = load4f(reinterpret_cast<const float*>(reinterpret_cast<const char*>(xf) + off));
+      Y = load4f(reinterpret_cast<const float*>(reinterpret_cast<const char*>(xf1) + off));
+      Z = load4f(reinterpret_cast<const float*>(reinterpret_cast<const char*>(xf2) + off));
     }
-    A.cnt = cnt;
-    if (!full) break;
-    pair_drain_f32<K, R, LB>(queue, kDrainF, lane, L, xr, xif, sig, pc, A, rp, B);
+    const float xb[4] = {X.x, X.y, X.z, X.w}, yb[4] = {Y.x, Y.y, Y.z, Y.w}, zb[4] = {Z.x, Z.y, Z.z, Z.w};
+    const int ent0 = (j << 8) | bits;
+#pragma unroll
+    for (int b = 0; b < kBatchF; ++b) {
+      const float dxv = ax - xb[b], dyv = ay - yb[b], dzv = az - zb[b];
+      const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
+      const bool hit = (b < rem) & (r2 < pc.a2f);
+      qlane[kWaveQ * ((head + cnt) & (kQueue - 1))] = ent0 + (b << 8);
+      cnt += hit ? 1 : 0;
+    }
+    j += j < j1 ? kBatchF : 0;
+    if (__builtin_expect(__any(cnt > kQueue - kBatchF), 0)) {
+      A.cnt = cnt;
+      pair_drain_f32<K, R, LB>(queue, kDrainF, lane, L, xr, xif, sig, pc, A, rp, B);
+      cnt = A.cnt;
+      head = A.head;
+    }
   }
+  A.cnt = cnt;
 }
 
 template <int K, bool R = false, bool LB = false>
