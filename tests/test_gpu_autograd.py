@@ -94,6 +94,27 @@ def test_backward_matches_wide_step_differences(mixture):
         assert (Ep - Em) / (2 * h) == pytest.approx(gc6[i], rel=3e-6)
 
 
+def test_backward_equals_stored_oracle_gradient(mixture):
+    # the 100,000-atom mixture: gradients on the 512 atoms the oracle stored
+    # (tests/golden/mixture100k_a3_h1_p4_l0.json, written by make_golden.py)
+    import json
+    import os
+    import torch
+    from paper_1308_4005_amd import MLSDispersion
+    w, plan, pos, c6 = mixture
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mixture100k_a3_h1_p4_l0.json")))
+    assert gold["n"] == w.n and list(plan.info["grid"]) == gold["grid"]
+    p = pos.clone().requires_grad_(True)
+    c = c6.clone().requires_grad_(True)
+    E = MLSDispersion.apply(p, c, plan)
+    E.backward()
+    idx = np.asarray(gold["sample"])
+    assert float(E.detach().cpu()) == pytest.approx(gold["energy"], rel=1e-10)
+    np.testing.assert_allclose(p.grad.cpu().numpy()[idx], -np.asarray(gold["forces"]), rtol=0,
+                               atol=1e-10 * gold["force_rms"])
+    np.testing.assert_allclose(c.grad.cpu().numpy()[idx], gold["dE_dc6"], rtol=1e-10)
+
+
 def test_backward_equals_oracle_gradient():
     import torch
     from paper_1308_4005_amd import MLSDispersion, Plan

@@ -43,7 +43,7 @@ def _run(w, gold, precision):
 _SWEEP = sorted(f[:-5] for f in os.listdir(GOLDEN) if f.startswith("cube1M_a") and f.endswith("_l5.json"))
 
 
-@pytest.fixture(scope="module", params=["slab32k_a3_h1_p4_l4"] + _SWEEP)
+@pytest.fixture(scope="module", params=["slab32k_a3_h1_p4_l4", "mixture100k_a3_h1_p4_l0"] + _SWEEP)
 def golden_case(request):
     gold = json.load(open(os.path.join(GOLDEN, request.param + ".json")))
     say(f"[fullsize] {request.param}: building workload")
