@@ -174,8 +174,10 @@ mls_status evaluate_geometric(mls_plan_t P, int64_t n, const double* pos, const 
   };
   mls_status st;
   if (after == 0 && (st = pair()) != MLS_OK) return st;
-  HIP_TRY(launch_sum_xi(P, ni, g), "sum of xi");
+  // the sum of xi is needed first by the stencils: launched after the
+  // anterpolation, whose tiles then start as soon as the binning ends
   HIP_TRY(launch_anterpolate(P, ni, g), "anterpolation");
+  HIP_TRY(launch_sum_xi(P, ni, g), "sum of xi");
   HIP_TRY(mark(1 + MLS_T_ANTERP), "timing event");
   if (after == 1 && (st = pair()) != MLS_OK) return st;
   HIP_TRY(launch_restrictions(P, g), "restriction");

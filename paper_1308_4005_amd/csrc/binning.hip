@@ -408,18 +408,19 @@ struct BinBucket {
         xi = p.w;
       }
       if (a.xi_partial) {
-        // the sum of xi over each 256 consecutive atoms, in the tree order
-        // of BinCount
-        sh[threadIdx.x] = xi;
+        // the sum of xi over each 256 consecutive atoms (fixed order: within
+        // each wave by the xor tree, then the four waves in order)
+        double v = xi;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if ((threadIdx.x & 63) == 0) sh[(u & 1) * (kBinThreads / 64) + (threadIdx.x >> 6)] = v;
         __syncthreads();
         const int t = threadIdx.x & 255;
-        for (int off = 128; off > 0; off >>= 1) {
-          if (t < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-          __syncthreads();
-        }
         const int base = blk * kBinItems + u * kBinThreads + (threadIdx.x & ~255);
-        if (t == 0 && base < a.n) a.xi_partial[base >> 8] = sh[threadIdx.x];
-        __syncthreads();
+        if (t == 0 && base < a.n) {
+          const double* w = sh + (u & 1) * (kBinThreads / 64) + (threadIdx.x >> 6);
+          a.xi_partial[base >> 8] = ((w[0] + w[1]) + w[2]) + w[3];
+        }
       }
     }
     __syncthreads();
