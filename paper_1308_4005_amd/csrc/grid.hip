@@ -412,7 +412,7 @@ struct Restrict {
 // M - P/2 + 1 .. M + P/2 per dimension (the even one uses M alone), so the
 // thread walks those P z-planes, interpolates each plane in x then y, and
 // adds it into the 8 outputs.
-template <int P>
+template <int P, bool ROLL = false>
 __device__ __forceinline__ void prolong_at(const TransferArgs& a, int M) {
     const GridDims& c = a.gs;
     const GridDims& f = a.gd;
@@ -430,11 +430,25 @@ __device__ __forceinline__ void prolong_at(const TransferArgs& a, int M) {
     }
     double acc[2][2][2];   // [z parity][y parity][x parity]
 #pragma unroll
+    for (int q = 0; q < 2; ++q) acc[1][0][q] = acc[1][1][q] = acc[0][0][q] = acc[0][1][q] = 0.0;
+    // ROLL: the z planes in a loop that is not unrolled (p = 4: 56 instead of
+    // 190 VGPRs, more waves but fewer loads in flight per thread, faster in
+    // the batched form, slower on a single plan's finest level; p = 6: 70
+    // instead of 448), the plane's weight and index rotated into slot 0
+    double wz[P];
+    int izr[P];
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      wz[t] = w[t];
+      izr[t] = iz[t];
+    }
+    constexpr int kUnrollZ = ROLL ? 1 : P;
+#pragma unroll kUnrollZ
     for (int tz = 0; tz < P; ++tz) {
       double ye[2] = {0.0, 0.0}, yo[2] = {0.0, 0.0};   // y even / odd, [x parity]
 #pragma unroll
       for (int ty = 0; ty < P; ++ty) {
-        const double* row = a.src + ((size_t)iz[tz] * c.n[1] + iy[ty]) * c.n[0];
+        const double* row = a.src + ((size_t)izr[0] * c.n[1] + iy[ty]) * c.n[0];
         double v[P];
 #pragma unroll
         for (int tx = 0; tx < P; ++tx) v[tx] = row[ix[tx]];
@@ -449,20 +463,21 @@ __device__ __forceinline__ void prolong_at(const TransferArgs& a, int M) {
         yo[0] += w[ty] * xe;
         yo[1] += w[ty] * xo;
       }
-      if (tz == 0) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) acc[1][0][q] = acc[1][1][q] = 0.0;
-      }
       if (tz == H - 1) {
         acc[0][0][0] = ye[0];
         acc[0][0][1] = ye[1];
         acc[0][1][0] = yo[0];
         acc[0][1][1] = yo[1];
       }
-      acc[1][0][0] += w[tz] * ye[0];
-      acc[1][0][1] += w[tz] * ye[1];
-      acc[1][1][0] += w[tz] * yo[0];
-      acc[1][1][1] += w[tz] * yo[1];
+      acc[1][0][0] += wz[0] * ye[0];
+      acc[1][0][1] += wz[0] * ye[1];
+      acc[1][1][0] += wz[0] * yo[0];
+      acc[1][1][1] += wz[0] * yo[1];
+#pragma unroll
+      for (int t = 0; t + 1 < P; ++t) {
+        wz[t] = wz[t + 1];
+        izr[t] = izr[t + 1];
+      }
     }
 #pragma unroll
     for (int pz = 0; pz < 2; ++pz)
@@ -474,13 +489,13 @@ __device__ __forceinline__ void prolong_at(const TransferArgs& a, int M) {
       }
 }
 
-template <int P>
+template <int P, bool ROLL = false>
 struct Prolong {
   using Args = TransferArgs;
   static constexpr int kThreads = kBlock;
   static __device__ void run(const Args& a, int blk) {
     const int M = blk * kBlock + threadIdx.x;
-    if (M < a.gs.size) prolong_at<P>(a, M);
+    if (M < a.gs.size) prolong_at<P, ROLL>(a, M);
   }
 };
 
@@ -1185,7 +1200,7 @@ hipError_t launch_prolong_into(mls_plan_s* P, const TransferArgs& a, hipStream_t
     return launch_one<ProlongSplit<6>>(a, nblocks((int64_t)a.gs.size * ProlongSplit<6>::G, kBlock), s);
   }
   if (P->order == 4) return launch_one<Prolong<4>>(a, nblocks(a.gs.size, kBlock), s);
-  return launch_one<Prolong<6>>(a, nblocks(a.gs.size, kBlock), s);
+  return launch_one<Prolong<6, true>>(a, nblocks(a.gs.size, kBlock), s);
 }
 
 hipError_t launch_prolong(mls_plan_s* P, int k_fine, hipStream_t s) {
@@ -1267,7 +1282,7 @@ hipError_t launch_batched_grid(const BatchPhase& ph, hipStream_t s) {
     case BK_RESTRICT:
       return p6 ? launch_batched_phase<Restrict<6>>(ph, s) : launch_batched_phase<Restrict<4>>(ph, s);
     case BK_PROLONG:
-      return p6 ? launch_batched_phase<Prolong<6>>(ph, s) : launch_batched_phase<Prolong<4>>(ph, s);
+      return p6 ? launch_batched_phase<Prolong<6, true>>(ph, s) : launch_batched_phase<Prolong<4, true>>(ph, s);
     case BK_INTERP:
       if (p6) return mixed ? launch_batched_phase<Interp<6, float>>(ph, s)
                            : launch_batched_phase<Interp<6, double>>(ph, s);
