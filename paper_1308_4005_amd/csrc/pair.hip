@@ -236,6 +236,11 @@ struct PairWave {
 // index (< 2^25) with two bits per dimension for its image.
 constexpr int kWaveQ = 64;    // lanes per block (one wave)
 constexpr int kQueue = 32;    // entries per lane
+// The FP32 kernel's ring is half as long: 4 KB of LDS per wave lets 24 waves
+// share a CU (its VGPRs allow 24; 8 KB queues capped it at 20): pair kernel
+// 0.46 -> 0.44 ms at 10^6 atoms.  The FP64 kernel is held to 16 waves per CU
+// by its VGPRs, and a 16-entry ring only drains it more often (0.53 -> 0.64 ms).
+constexpr int kQueueF = 16;   // entries per lane of the FP32 kernel
 constexpr int kBatchF = 4;    // candidates per filter step
 
 // 16-byte load from a 4-byte aligned address (four consecutive floats)
@@ -508,15 +513,15 @@ struct PairTrimF64 {
 struct PairAccM {
   double e, fx, fy, fz;
   int cnt;
-  int head;   // FP32 kernel: the lane's queue is a ring of kQueue slots
+  int head;   // FP32 kernel: the lane's queue is a ring of kQueueF slots
 };
 
 // An FP32 drain consumes at most this many entries per lane: the lane that
-// forced it is then below the limit again (at most 32 - 8 = 24 entries, one
-// filter step adds at most 4 to the 28 that trigger a drain), and lanes with
+// forced it is then below the limit again (at most 16 - 8 = 8 entries, one
+// filter step adds at most 4 to the 12 that trigger a drain), and lanes with
 // few entries idle for fewer steps than in a drain to empty (measured at 10^6
-// atoms: 0.8176 against 0.8204 ms per evaluation with 16, three alternating
-// runs each).
+// atoms with the 16-entry ring: pair kernel 0.44 ms with 8 and with 4, 0.46
+// ms with 12).
 constexpr int kDrainF = 8;
 
 // Per-lane target data of the FP32 scan.
@@ -550,7 +555,7 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
   float e = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
   float re = 0.0f, rfx = 0.0f, rfy = 0.0f, rfz = 0.0f;
   for (int t = 0; t < limit && __any(t < cnt); ++t) {
-    const int q = queue[((A.head + t) & (kQueue - 1)) * kWaveQ + lane];
+    const int q = queue[((A.head + t) & (kQueueF - 1)) * kWaveQ + lane];
     const bool ok = (t < cnt) & (q != L.self_ent);
     const int ent = ok ? q : 0;
     const int j = ok ? (int)((unsigned)ent >> 8) : L.safe_j;
@@ -603,7 +608,7 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
     B.fz += (double)rfz;
   }
   const int done = min(cnt, limit);
-  A.head = (A.head + done) & (kQueue - 1);
+  A.head = (A.head + done) & (kQueueF - 1);
   A.cnt = cnt - done;
 }
 
@@ -654,11 +659,11 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
       const float dxv = ax - xb[b], dyv = ay - yb[b], dzv = az - zb[b];
       const float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
       const bool hit = (b < rem) & (r2 < pc.a2f);
-      qlane[kWaveQ * ((head + cnt) & (kQueue - 1))] = ent0 + (b << 8);
+      qlane[kWaveQ * ((head + cnt) & (kQueueF - 1))] = ent0 + (b << 8);
       cnt += hit ? 1 : 0;
     }
     j += j < j1 ? kBatchF : 0;
-    if (__builtin_expect(__any(cnt > kQueue - kBatchF), 0)) {
+    if (__builtin_expect(__any(cnt > kQueueF - kBatchF), 0)) {
       A.cnt = cnt;
       pair_drain_f32<K, R, LB>(queue, kDrainF, lane, L, xr, xif, sig, pc, A, rp, B);
       cnt = A.cnt;
@@ -679,7 +684,7 @@ struct PairTrimF32 {
   const CellGeom& g = ar.g;
   const PairConstF& pc = ar.pc;
   const int n = ar.n;
-  __shared__ int queue[kQueue * kWaveQ];
+  __shared__ int queue[kQueueF * kWaveQ];
   const int lane = threadIdx.x;
   const int k = blk * kWaveQ + lane;
   const bool active = k < n;
@@ -751,7 +756,7 @@ struct PairTrimF32 {
       pair_scan_f32<K, R, LB>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xf, xfs, xif, sig, pc, A, rp, B);
     }
   }
-  pair_drain_f32<K, R, LB>(queue, kQueue, lane, L, xr, xif, sig, pc, A, rp, B);
+  pair_drain_f32<K, R, LB>(queue, kQueueF, lane, L, xr, xif, sig, pc, A, rp, B);
   if (active) {
     const double wi = (double)xif[sc];
     ar.e0[sc] = A.e;
