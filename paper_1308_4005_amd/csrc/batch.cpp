@@ -639,6 +639,7 @@ mls_status mls_batch_create(int nbox, const mls_params* per_box, const int64_t* 
     // Lorentz-Berthelot: one buffer slot per charge vector, so each chain
     // phase runs the seven vectors of every box in one launch
     P->lb_slots = 7;
+    P->ant_large_tiles = true;
     mls_status st = build_plan(per_box[b], n_per_box[b], P);
     if (st != MLS_OK) {
       set_error("box " + std::to_string(b) + ": " + mls_last_error());

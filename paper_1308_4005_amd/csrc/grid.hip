@@ -223,12 +223,13 @@ struct AnterpOwned {
 // finest point sums the (at most 4 x 4 x 4, usually 1 to 8) expanded-grid
 // values that belong to it, periodic images included, in a fixed order.
 // Weights in W (FP32 in mixed precision), charges accumulated in FP64.
-template <int P, class W>
+// CAP: the LDS tile's capacity in doubles, the one the tables were built for.
+template <int P, class W, int CAP = kAntTileMax>
 struct AnterpTile {
   using Args = AnterpTileArgs;
   static constexpr int kThreads = kAntThreads;
   static __device__ void run(const Args& a, int b) {
-    __shared__ double tile[kAntTileMax];
+    __shared__ double tile[CAP];
     __shared__ int seg_begin[kAntTileRows];
     __shared__ int seg_off[kAntTileRows + 1];
     const AntTiles& T = a.t;
@@ -244,7 +245,7 @@ struct AnterpTile {
       e0[d] = tab[T.off_e[d] + bi[d]];
       len[d] = tab[T.off_len[d] + bi[d]];
     }
-    const int vol = len[0] * len[1] * len[2];   // <= kAntTileMax (host-checked)
+    const int vol = len[0] * len[1] * len[2];   // <= CAP (host-checked)
     for (int i = threadIdx.x; i < vol; i += kAntThreads) tile[i] = 0.0;
     // the block's atoms: one contiguous run of sorted atoms per cell row (y, z)
     const int ny = c1[1] - c0[1];
@@ -768,16 +769,16 @@ struct Interp {
 
 // Interpolation over the anterpolation's blocks of linked cells (the same
 // tables): a block loads the finest-grid values its atoms reach (at most
-// kAntTileMax, unwrapped, with the periodic wrap applied on load) into LDS,
+// CAP, unwrapped, with the periodic wrap applied on load) into LDS,
 // eight loads in flight per thread, then every atom of its cells gathers its
 // p^3 values from LDS instead of global memory.  Outputs as Interp; the
 // energy sums are per block (fixed order).
-template <int P, class W>
+template <int P, class W, int CAP = kAntTileMax>
 struct InterpTile {
   using Args = InterpTileArgs;
   static constexpr int kThreads = kAntThreads;
   static __device__ void run(const Args& ta, int b) {
-    __shared__ double tile[kAntTileMax];
+    __shared__ double tile[CAP];
     __shared__ int seg_begin[kAntTileRows];
     __shared__ int seg_off[kAntTileRows + 1];
     const InterpArgs& a = ta.a;
@@ -794,7 +795,7 @@ struct InterpTile {
       e0[d] = tab[T.off_e[d] + bi[d]];
       len[d] = tab[T.off_len[d] + bi[d]];
     }
-    const int vol = len[0] * len[1] * len[2];   // <= kAntTileMax (host-checked)
+    const int vol = len[0] * len[1] * len[2];   // <= CAP (host-checked)
     const size_t plane = (size_t)gg.n[0] * gg.n[1];
     constexpr int kFill = 8;
     for (int i0 = threadIdx.x; i0 < vol; i0 += kFill * kAntThreads) {
@@ -1058,7 +1059,7 @@ bool anterp_owned_geom(const mls_plan_s* P, AntGeom& ag) {
   return segs <= kMaxSeg;
 }
 
-bool ant_tiles_build(const mls_plan_s* P, AntTiles& T, std::vector<int>& tab, size_t& scratch) {
+bool ant_tiles_build(const mls_plan_s* P, AntTiles& T, std::vector<int>& tab, size_t& scratch, int cap) {
   const GridGeom gg = finest_geom(P);
   const CellGeom& cg = P->cg;
   const int half = P->order / 2;
@@ -1083,7 +1084,7 @@ bool ant_tiles_build(const mls_plan_s* P, AntTiles& T, std::vector<int>& tab, si
         maxc[d] = std::max(maxc[d], c[d][b + 1] - c[d][b]);
       }
     }
-    if ((int64_t)maxlen[0] * maxlen[1] * maxlen[2] > kAntTileMax || maxc[1] * maxc[2] > kAntTileRows) continue;
+    if ((int64_t)maxlen[0] * maxlen[1] * maxlen[2] > cap || maxc[1] * maxc[2] > kAntTileRows) continue;
     // tables
     tab.clear();
     for (int d = 0; d < 3; ++d) {
@@ -1126,6 +1127,20 @@ bool ant_tiles_build(const mls_plan_s* P, AntTiles& T, std::vector<int>& tab, si
   return false;
 }
 
+template <int CAP>
+hipError_t launch_ant_tile(int order, bool mixed, const AnterpTileArgs& t, int nb, hipStream_t s) {
+  if (order == 4)
+    return mixed ? launch_one<AnterpTile<4, float, CAP>>(t, nb, s) : launch_one<AnterpTile<4, double, CAP>>(t, nb, s);
+  return mixed ? launch_one<AnterpTile<6, float, CAP>>(t, nb, s) : launch_one<AnterpTile<6, double, CAP>>(t, nb, s);
+}
+
+template <int CAP>
+hipError_t launch_interp_tile(int order, bool mixed, const InterpTileArgs& t, int nb, hipStream_t s) {
+  if (order == 4)
+    return mixed ? launch_one<InterpTile<4, float, CAP>>(t, nb, s) : launch_one<InterpTile<4, double, CAP>>(t, nb, s);
+  return mixed ? launch_one<InterpTile<6, float, CAP>>(t, nb, s) : launch_one<InterpTile<6, double, CAP>>(t, nb, s);
+}
+
 hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s) {
   Level& L1 = P->lv[0];
   if (P->ant_tiles) {
@@ -1135,8 +1150,8 @@ hipError_t launch_anterpolate(mls_plan_s* P, int n, hipStream_t s) {
     const int nb = P->ant.nb[0] * P->ant.nb[1] * P->ant.nb[2];
     const bool mixed = P->precision == MLS_MIXED;
     hipError_t e;
-    if (P->order == 4) e = mixed ? launch_one<AnterpTile<4, float>>(t, nb, s) : launch_one<AnterpTile<4, double>>(t, nb, s);
-    else e = mixed ? launch_one<AnterpTile<6, float>>(t, nb, s) : launch_one<AnterpTile<6, double>>(t, nb, s);
+    if (P->ant_cap == kAntTileSmall) e = launch_ant_tile<kAntTileSmall>(P->order, mixed, t, nb, s);
+    else e = launch_ant_tile<kAntTileMax>(P->order, mixed, t, nb, s);
     if (e != hipSuccess) return e;
     AnterpCollectArgs c{P->ant, P->d_ant_tab, scratch, L1.q, L1.g};
     return launch_one<AnterpCollect>(c, nblocks(L1.g.size, kBlock), s);
@@ -1226,10 +1241,8 @@ hipError_t launch_interpolate(mls_plan_s* P, int n, double* energy, double* forc
       // (one energy partial per block)
       InterpTileArgs t{a, P->d_cell_start, P->cg, P->ant, P->d_ant_tab, P->d_flags};
       nb = nt;
-      if (P->order == 4 && !mixed) e = launch_one<InterpTile<4, double>>(t, nt, s);
-      else if (P->order == 4) e = launch_one<InterpTile<4, float>>(t, nt, s);
-      else if (!mixed) e = launch_one<InterpTile<6, double>>(t, nt, s);
-      else e = launch_one<InterpTile<6, float>>(t, nt, s);
+      if (P->ant_cap == kAntTileSmall) e = launch_interp_tile<kAntTileSmall>(P->order, mixed, t, nt, s);
+      else e = launch_interp_tile<kAntTileMax>(P->order, mixed, t, nt, s);
     } else if (P->order == 4 && !mixed) {
       e = launch_one<Interp<4, double>>(a, nb, s);
     } else if (P->order == 4) {

@@ -223,7 +223,15 @@ struct AnterpArgs {
 // an expanded grid of NX[0] x NX[1] x NX[2] points; for every finest point the
 // expanded coordinates that hold its contributions (up to four per
 // dimension).  Integer tables at the offsets below.
-constexpr int kAntTileMax = 4096;   // doubles of one block's LDS tile
+// doubles of one block's LDS tile, in two capacities.  Single plans take the
+// small one where their tables fit it (14^3: blocks of 6^3 half-cutoff cells
+// at a = 3, h = 1; the 22 KB tile lets six blocks share a CU, against four for
+// 16^3 tiles: anterpolation and interpolation 5 % faster, the 10^6-atom mixed
+// evaluation 0.658 -> 0.645 ms).  The boxes of a batch take the large one:
+// their blocks then cover more of a small box, and fewer, fuller blocks made
+// the batched evaluation 4 % faster than the small tiles.
+constexpr int kAntTileSmall = 2744;
+constexpr int kAntTileMax = 4096;
 constexpr int kAntTileRows = 256;   // cell rows (y, z) of one block
 struct AntTiles {
   int nb[3];        // blocks per dimension
@@ -487,6 +495,8 @@ struct mls_plan_s {
   int* d_rebin = nullptr;          // 1: the next conditional binning runs
   double* d_efast = nullptr;       // geometric mixing: energy of an inner step's fast evaluation
   bool ant_tiles = false;          // two-phase anterpolation tables built
+  bool ant_large_tiles = false;    // set before building: tables for kAntTileMax tiles only
+  int ant_cap = 0;                 // tile capacity the tables were built for (kAntTileSmall or kAntTileMax)
   mls::AntTiles ant{};
   int* d_ant_tab = nullptr;
   double* d_ant_scratch = nullptr; // the expanded grid
@@ -611,7 +621,7 @@ hipError_t launch_add_forces(double* forces, const double* add, int n, hipStream
 // owner-computes anterpolation blocking of a plan (false: use the atomic kernel)
 bool anterp_owned_geom(const mls_plan_s* P, AntGeom& ag);
 // tables of the two-phase anterpolation; false when no blocking fits
-bool ant_tiles_build(const mls_plan_s* P, AntTiles& t, std::vector<int>& tab, size_t& scratch);
+bool ant_tiles_build(const mls_plan_s* P, AntTiles& t, std::vector<int>& tab, size_t& scratch, int cap);
 
 // Lorentz-Berthelot slot of charge vector k and its buffers.
 inline int lb_slot(const mls_plan_s* P, int k) { return P->lb_slots > 1 ? k : 0; }

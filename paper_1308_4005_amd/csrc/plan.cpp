@@ -415,7 +415,16 @@ mls_status build_plan(const mls_params& p, int64_t n_max, mls_plan_s* P) {
   P->ant_tiles = false;
   {
     const char* env = std::getenv("MLS_ANTERP_TILES");
-    if (!(env && std::atoi(env) == 0)) P->ant_tiles = ant_tiles_build(P, P->ant, ant_tab, ant_scratch);
+    if (!(env && std::atoi(env) == 0)) {
+      for (int cap : {kAntTileSmall, kAntTileMax}) {
+        if (cap == kAntTileSmall && P->ant_large_tiles) continue;
+        P->ant_tiles = ant_tiles_build(P, P->ant, ant_tab, ant_scratch, cap);
+        if (P->ant_tiles) {
+          P->ant_cap = cap;
+          break;
+        }
+      }
+    }
   }
 
   // ---------------------------------------------------------------- device memory
