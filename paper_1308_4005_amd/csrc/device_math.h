@@ -29,6 +29,34 @@ __device__ __forceinline__ int wrapi(int a, int n) {
   return r < 0 ? r + n : r;
 }
 
+// a mod n for a in [-n, 2n): one conditional add or subtract, no division
+__device__ __forceinline__ int wrap_near(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// Coordinates (x, y, z) of element i of an x-fastest box len[0] x len[1] x
+// len[2], advanced by a fixed stride without divisions: the stride is split
+// once into (sx, sy, sz) with sx < len[0], sy < len[1], so each step carries
+// at most once per dimension.
+struct BoxWalk {
+  int x, y, z, sx, sy, sz;
+  __device__ __forceinline__ BoxWalk(int i, int stride, const int len[3]) {
+    x = i % len[0];
+    y = (i / len[0]) % len[1];
+    z = i / (len[0] * len[1]);
+    sx = stride % len[0];
+    sy = (stride / len[0]) % len[1];
+    sz = stride / (len[0] * len[1]);
+  }
+  __device__ __forceinline__ void step(const int len[3]) {
+    x += sx;
+    int c = x >= len[0] ? 1 : 0;
+    x -= c * len[0];
+    y += sy + c;
+    c = y >= len[1] ? 1 : 0;
+    y -= c * len[1];
+    z += sz + c;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Basis weights.  For fractional offset f = t - floor(t) in [0,1) the touched
 // points are m = floor(t) - (P/2 - 1) + j, j = 0..P-1, at distances

@@ -325,9 +325,10 @@ struct AnterpTile {
     }
     __syncthreads();
     const int X0 = tab[T.off_x0[0] + bi[0]], Y0 = tab[T.off_x0[1] + bi[1]], Z0 = tab[T.off_x0[2] + bi[2]];
+    BoxWalk wk(threadIdx.x, kAntThreads, len);
     for (int i = threadIdx.x; i < vol; i += kAntThreads) {
-      const int lx = i % len[0], ly = (i / len[0]) % len[1], lz = i / pitch_z;
-      a.scratch[((size_t)(Z0 + lz) * T.NX[1] + (Y0 + ly)) * T.NX[0] + (X0 + lx)] = tile[i];
+      a.scratch[((size_t)(Z0 + wk.z) * T.NX[1] + (Y0 + wk.y)) * T.NX[0] + (X0 + wk.x)] = tile[i];
+      wk.step(len);
     }
   }
 };
@@ -798,14 +799,18 @@ struct InterpTile {
     const int vol = len[0] * len[1] * len[2];   // <= CAP (host-checked)
     const size_t plane = (size_t)gg.n[0] * gg.n[1];
     constexpr int kFill = 8;
+    // element coordinates stepped, not divided out; the reached ranges lie
+    // within [-n, 2n) per dimension (host-checked), so one conditional wrap
+    BoxWalk wk(threadIdx.x, kAntThreads, len);
     for (int i0 = threadIdx.x; i0 < vol; i0 += kFill * kAntThreads) {
       double v[kFill];
 #pragma unroll
       for (int u = 0; u < kFill; ++u) {
-        const int i = min(i0 + u * kAntThreads, vol - 1);
-        const int lx = i % len[0], ly = (i / len[0]) % len[1], lz = i / (len[0] * len[1]);
-        v[u] = a.E1[(size_t)wrapi(e0[2] + lz, gg.n[2]) * plane + (size_t)wrapi(e0[1] + ly, gg.n[1]) * gg.n[0] +
-                    wrapi(e0[0] + lx, gg.n[0])];
+        // past the end: an element of the last plane, loaded but not stored
+        const int lz = min(wk.z, len[2] - 1);
+        v[u] = a.E1[(size_t)wrap_near(e0[2] + lz, gg.n[2]) * plane +
+                    (size_t)wrap_near(e0[1] + wk.y, gg.n[1]) * gg.n[0] + wrap_near(e0[0] + wk.x, gg.n[0])];
+        wk.step(len);
       }
 #pragma unroll
       for (int u = 0; u < kFill; ++u)
@@ -1080,6 +1085,9 @@ bool ant_tiles_build(const mls_plan_s* P, AntTiles& T, std::vector<int>& tab, si
         const int lo = (int)std::floor(t0 - 1e-7), hi = (int)std::floor(t1 + 1e-7);
         e[d].push_back(lo - (half - 1));
         len[d].push_back(hi - lo + P->order);
+        // the interpolation tile wraps reached indices with one conditional
+        // add or subtract: they must lie in [-n, 2n)
+        if (e[d].back() < -gg.n[d] || e[d].back() + len[d].back() > 2 * gg.n[d]) return false;
         maxlen[d] = std::max(maxlen[d], len[d].back());
         maxc[d] = std::max(maxc[d], c[d][b + 1] - c[d][b]);
       }
