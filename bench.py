@@ -100,10 +100,10 @@ STAGE_KERNEL = {("pair", "mixed"): ["void k_one<PairTrimF32<2, false, false> >"]
                 ("pair", "fp64"): ["void k_one<PairTrimF64<2, false, false> >"],
                 ("stencil", "mixed"): ["void k_stencil_tile<float, 6, 16, 8>"],
                 ("stencil", "fp64"): ["void k_stencil_tile<double, 6, 8, 8>"],
-                ("anterpolation", "mixed"): ["void k_one<AnterpTile<4, float> >", "void k_one<AnterpCollect>"],
-                ("anterpolation", "fp64"): ["void k_one<AnterpTile<4, double> >", "void k_one<AnterpCollect>"],
-                ("interpolation", "mixed"): ["void k_one<InterpTile<4, float> >"],
-                ("interpolation", "fp64"): ["void k_one<InterpTile<4, double> >"]}
+                ("anterpolation", "mixed"): ["void k_one<AnterpTile<4, float, 2744> >", "void k_one<AnterpCollect>"],
+                ("anterpolation", "fp64"): ["void k_one<AnterpTile<4, double, 2744> >", "void k_one<AnterpCollect>"],
+                ("interpolation", "mixed"): ["void k_one<InterpTile<4, float, 2744> >"],
+                ("interpolation", "fp64"): ["void k_one<InterpTile<4, double, 2744> >"]}
 
 
 def measured_traffic(stage, precision):
