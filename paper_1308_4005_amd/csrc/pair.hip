@@ -260,17 +260,36 @@ __device__ __forceinline__ float4 load4f(const float* p) {
 
 __device__ __forceinline__ int image_bits(int ix, int iy, int iz) { return (ix + 1) | ((iy + 1) << 2) | ((iz + 1) << 4); }
 
+// Four FP64 sums of one lane (energy, force x, y, z), kept in LDS at stride
+// kWaveQ while the lane's rows are scanned: only the drains read and write
+// them, so the filter loop carries none of them (held in registers, the four
+// were copied on every filter step, 11 of the loop's 70 instructions).
+// Each drain starts with a compiler memory barrier (sums_fence): without it
+// the sums were hoisted out of the loop into registers again (the queue and
+// the sums are distinct LDS arrays), and volatile accesses instead made every
+// update wait for its own load.
+struct LaneSums {
+  double* s;   // slot 0 of this lane
+  __device__ __forceinline__ double& operator[](int k) const { return s[k * kWaveQ]; }
+};
+
+__device__ __forceinline__ void sums_fence() { asm volatile("" ::: "memory"); }
+
+// Per-lane sums of a pair kernel: e_0 and the force in LDS, queue state in
+// registers
 struct PairAcc {
-  double e, fx, fy, fz;
+  LaneSums a;
   int cnt;
   int head;   // the lane's queue is a ring of kQueue slots
 };
 
 // Per-lane sums of the repulsive term (MD entry points): sum_j sqrt(C12_j)
 // r^-12 and sum_j 12 sqrt(C12_j) r^-14 d over the pairs with r < rc.
-struct RepAcc {
-  double e, fx, fy, fz;
-};
+using RepAcc = LaneSums;
+
+// The kernels' LDS for the sums: four slots per lane, eight with repulsion.
+template <bool R>
+constexpr int kSumSlots = (R ? 8 : 4) * kWaveQ;
 
 // A drain during the scan consumes at most this many entries per lane: the
 // lane that forced it is then well below the limit, and lanes with few
@@ -285,8 +304,18 @@ __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, in
                                                int safe_j, const double4& xi, const double4* __restrict__ xs,
                                                const CellGeom& g, const PairConst& pc, const double* __restrict__ sig,
                                                double sig_i, PairAcc& A, const PairRep& rp, RepAcc& B) {
+  sums_fence();
   const double r2_idle = 0.25 * pc.a2;
   const int cnt = A.cnt;
+  // the lane's running sums, added to pair by pair as if held throughout
+  double ae = A.a[0], afx = A.a[1], afy = A.a[2], afz = A.a[3];
+  double be = 0.0, bfx = 0.0, bfy = 0.0, bfz = 0.0;
+  if constexpr (R) {
+    be = B[0];
+    bfx = B[1];
+    bfy = B[2];
+    bfz = B[3];
+  }
   for (int t = 0; t < limit && __any(t < cnt); ++t) {
     const int q = queue[((A.head + t) & (kQueue - 1)) * kWaveQ + lane];
     const bool ok = (t < cnt) & (q != self_ent);
@@ -307,21 +336,31 @@ __device__ __forceinline__ void pair_drain_f64(const int* __restrict__ queue, in
     double gg, fr;
     g0_pair<double, K>(r2, pc, gg, fr);
     const double wj = in ? src_weight<LB>(xj.w, sig, sig_i, j) : 0.0;
-    A.e += wj * gg;
+    ae += wj * gg;
     const double f = wj * fr;
-    A.fx += f * dx;
-    A.fy += f * dy;
-    A.fz += f * dz;
+    afx += f * dx;
+    afy += f * dy;
+    afz += f * dz;
     if constexpr (R) {
       const double ir2 = recip(r2);
       const double ir6 = ir2 * ir2 * ir2;
       const double v = (in && r2 < rp.rc2 ? rp.x12[j] : 0.0) * ir6 * ir6;
       const double fv = 12.0 * v * ir2;
-      B.e += v;
-      B.fx += fv * dx;
-      B.fy += fv * dy;
-      B.fz += fv * dz;
+      be += v;
+      bfx += fv * dx;
+      bfy += fv * dy;
+      bfz += fv * dz;
     }
+  }
+  A.a[0] = ae;
+  A.a[1] = afx;
+  A.a[2] = afy;
+  A.a[3] = afz;
+  if constexpr (R) {
+    B[0] = be;
+    B[1] = bfx;
+    B[2] = bfy;
+    B[3] = bfz;
   }
   const int done = min(cnt, limit);
   A.head = (A.head + done) & (kQueue - 1);
@@ -406,10 +445,10 @@ __device__ __forceinline__ void store_rep(const PairRep& rp, bool active, int sc
   double e = 0.0;
   if (active) {
     const double ci = rp.x12[sc];
-    e = ci * B.e;
-    rp.frep[3 * (size_t)sc + 0] = ci * B.fx;
-    rp.frep[3 * (size_t)sc + 1] = ci * B.fy;
-    rp.frep[3 * (size_t)sc + 2] = ci * B.fz;
+    e = ci * B[0];
+    rp.frep[3 * (size_t)sc + 0] = ci * B[1];
+    rp.frep[3 * (size_t)sc + 1] = ci * B[2];
+    rp.frep[3 * (size_t)sc + 2] = ci * B[3];
   }
   e = wave_sum(e);
   if (lane == 0) rp.partial[blk] = e;
@@ -439,8 +478,10 @@ struct PairTrimF64 {
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
   // the target itself, seen in the home image, is skipped in the drain
   const int self_ent = active ? ((sc << 6) | image_bits(0, 0, 0)) : -1;
-  PairAcc A{0.0, 0.0, 0.0, 0.0, 0};
-  RepAcc B{0.0, 0.0, 0.0, 0.0};
+  __shared__ double sums[kSumSlots<R>];
+  for (int k = 0; k < kSumSlots<R> / kWaveQ; ++k) sums[k * kWaveQ + lane] = 0.0;
+  PairAcc A{LaneSums{sums + lane}, 0, 0};
+  RepAcc B{sums + 4 * kWaveQ + lane};
   const PairRep& rp = ar.rep;
   const float reach = (float)(1.0 + 1e-5);
   for (int dz = -2; dz <= 2; ++dz) {
@@ -491,10 +532,10 @@ struct PairTrimF64 {
   }
   pair_drain_f64<K, LB, R>(queue, kQueue, lane, self_ent, sc, xi, xs, g, pc, ar.sig, sig_i, A, rp, B);
   if (active) {
-    ar.e0[sc] = A.e;
-    ar.floc[3 * (size_t)sc + 0] = xi.w * A.fx;
-    ar.floc[3 * (size_t)sc + 1] = xi.w * A.fy;
-    ar.floc[3 * (size_t)sc + 2] = xi.w * A.fz;
+    ar.e0[sc] = A.a[0];
+    ar.floc[3 * (size_t)sc + 0] = xi.w * A.a[1];
+    ar.floc[3 * (size_t)sc + 1] = xi.w * A.a[2];
+    ar.floc[3 * (size_t)sc + 2] = xi.w * A.a[3];
   }
   if constexpr (R) store_rep(rp, active, sc, lane, blk, B);
   }
@@ -511,9 +552,9 @@ struct PairTrimF64 {
 // offsets dy, dz.  Pair arithmetic is FP32; each drain sums its terms in
 // FP32, and e_0 and the forces accumulate the drains' sums in FP64.
 struct PairAccM {
-  double e, fx, fy, fz;
+  LaneSums a;   // e_0 and the force, FP64, in LDS
   int cnt;
-  int head;   // FP32 kernel: the lane's queue is a ring of kQueueF slots
+  int head;     // the lane's queue is a ring of kQueueF slots
 };
 
 // An FP32 drain consumes at most this many entries per lane: the lane that
@@ -547,6 +588,7 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
                                                const PairLaneF& L, const float4* __restrict__ xr,
                                                const float* __restrict__ xif, const float* __restrict__ sig,
                                                const PairConstF& pc, PairAccM& A, const PairRep& rp, RepAcc& B) {
+  sums_fence();
   const float r2_idle = 0.25f * pc.a2;
   const float rc2 = (float)rp.rc2;
   const int cnt = A.cnt;
@@ -597,15 +639,15 @@ __device__ __forceinline__ void pair_drain_f32(const int* __restrict__ queue, in
       rfz = fmaf(fv, dzv, rfz);
     }
   }
-  A.e += (double)e;
-  A.fx += (double)fx;
-  A.fy += (double)fy;
-  A.fz += (double)fz;
+  A.a[0] += (double)e;
+  A.a[1] += (double)fx;
+  A.a[2] += (double)fy;
+  A.a[3] += (double)fz;
   if constexpr (R) {
-    B.e += (double)re;
-    B.fx += (double)rfx;
-    B.fy += (double)rfy;
-    B.fz += (double)rfz;
+    B[0] += (double)re;
+    B[1] += (double)rfx;
+    B[2] += (double)rfy;
+    B[3] += (double)rfz;
   }
   const int done = min(cnt, limit);
   A.head = (A.head + done) & (kQueueF - 1);
@@ -697,8 +739,10 @@ struct PairTrimF32 {
   const int xfs = ar.xf_stride;
   const PairLaneF L{xi.x, xi.y, xi.z, (float)cx, (float)g.nc[0], active ? ((sc << 8) | entry_bits(0, 0, 0)) : -1, sc,
                     LB ? sig[sc] : 0.0f, xf[sc]};
-  PairAccM A{0.0, 0.0, 0.0, 0.0, 0};
-  RepAcc B{0.0, 0.0, 0.0, 0.0};
+  __shared__ double sums[kSumSlots<R>];
+  for (int k = 0; k < kSumSlots<R> / kWaveQ; ++k) sums[k * kWaveQ + lane] = 0.0;
+  PairAccM A{LaneSums{sums + lane}, 0, 0};
+  RepAcc B{sums + 4 * kWaveQ + lane};
   const PairRep& rp = ar.rep;
   // Rows are chosen and trimmed in the target's cell-relative FP32
   // coordinates.  The gaps are shrunk and the reach grown by margins (1e-5 of
@@ -759,10 +803,10 @@ struct PairTrimF32 {
   pair_drain_f32<K, R, LB>(queue, kQueueF, lane, L, xr, xif, sig, pc, A, rp, B);
   if (active) {
     const double wi = (double)xif[sc];
-    ar.e0[sc] = A.e;
-    ar.floc[3 * (size_t)sc + 0] = wi * A.fx;
-    ar.floc[3 * (size_t)sc + 1] = wi * A.fy;
-    ar.floc[3 * (size_t)sc + 2] = wi * A.fz;
+    ar.e0[sc] = A.a[0];
+    ar.floc[3 * (size_t)sc + 0] = wi * A.a[1];
+    ar.floc[3 * (size_t)sc + 1] = wi * A.a[2];
+    ar.floc[3 * (size_t)sc + 2] = wi * A.a[3];
   }
   if constexpr (R) store_rep(rp, active, sc, lane, blk, B);
   }
