@@ -416,7 +416,9 @@ __device__ __forceinline__ void pair_scan_f64(int j, int j1, int img, int dy, in
         qlane[kWaveQ * ((head + cnt) & (kQueue - 1))] = ent0 + (b << 6);
         cnt += hit ? 1 : 0;
       }
-      j += j < j1 ? 4 : 0;
+      // finished lanes advance too: rem <= 0 masks them and the loads stay
+      // guarded by j < j1 (j grows by at most 4 per step of the slowest lane)
+      j += 4;
       if (__any(cnt > kQueue - 4)) {
         full = true;
         break;
@@ -704,7 +706,9 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
       qlane[kWaveQ * ((head + cnt) & (kQueueF - 1))] = ent0 + (b << 8);
       cnt += hit ? 1 : 0;
     }
-    j += j < j1 ? kBatchF : 0;
+    // finished lanes advance too: rem <= 0 masks them and the loads stay
+    // guarded by j < j1 (j grows by at most 4 per step of the slowest lane)
+    j += kBatchF;
     if (__builtin_expect(__any(cnt > kQueueF - kBatchF), 0)) {
       A.cnt = cnt;
       pair_drain_f32<K, R, LB>(queue, kDrainF, lane, L, xr, xif, sig, pc, A, rp, B);
