@@ -284,12 +284,17 @@ struct PairAcc {
 };
 
 // Per-lane sums of the repulsive term (MD entry points): sum_j sqrt(C12_j)
-// r^-12 and sum_j 12 sqrt(C12_j) r^-14 d over the pairs with r < rc.
-using RepAcc = LaneSums;
+// r^-12 and sum_j 12 sqrt(C12_j) r^-14 d over the pairs with r < rc.  Kept in
+// registers: 2 KB more LDS per wave would cost these kernels occupancy (the
+// FP64 one 16 -> 13 waves per CU, the FP32 one its last wave of 20).
+struct RepAcc {
+  double v[4];
+  __device__ __forceinline__ double& operator[](int k) { return v[k]; }
+  __device__ __forceinline__ double operator[](int k) const { return v[k]; }
+};
 
-// The kernels' LDS for the sums: four slots per lane, eight with repulsion.
-template <bool R>
-constexpr int kSumSlots = (R ? 8 : 4) * kWaveQ;
+// The kernels' LDS for the sums: four slots per lane.
+constexpr int kSumSlots = 4 * kWaveQ;
 
 // A drain during the scan consumes at most this many entries per lane: the
 // lane that forced it is then well below the limit, and lanes with few
@@ -480,10 +485,10 @@ struct PairTrimF64 {
   const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
   // the target itself, seen in the home image, is skipped in the drain
   const int self_ent = active ? ((sc << 6) | image_bits(0, 0, 0)) : -1;
-  __shared__ double sums[kSumSlots<R>];
-  for (int k = 0; k < kSumSlots<R> / kWaveQ; ++k) sums[k * kWaveQ + lane] = 0.0;
+  __shared__ double sums[kSumSlots];
+  for (int k = 0; k < kSumSlots / kWaveQ; ++k) sums[k * kWaveQ + lane] = 0.0;
   PairAcc A{LaneSums{sums + lane}, 0, 0};
-  RepAcc B{sums + 4 * kWaveQ + lane};
+  RepAcc B{{0.0, 0.0, 0.0, 0.0}};
   const PairRep& rp = ar.rep;
   const float reach = (float)(1.0 + 1e-5);
   for (int dz = -2; dz <= 2; ++dz) {
@@ -743,10 +748,10 @@ struct PairTrimF32 {
   const int xfs = ar.xf_stride;
   const PairLaneF L{xi.x, xi.y, xi.z, (float)cx, (float)g.nc[0], active ? ((sc << 8) | entry_bits(0, 0, 0)) : -1, sc,
                     LB ? sig[sc] : 0.0f, xf[sc]};
-  __shared__ double sums[kSumSlots<R>];
-  for (int k = 0; k < kSumSlots<R> / kWaveQ; ++k) sums[k * kWaveQ + lane] = 0.0;
+  __shared__ double sums[kSumSlots];
+  for (int k = 0; k < kSumSlots / kWaveQ; ++k) sums[k * kWaveQ + lane] = 0.0;
   PairAccM A{LaneSums{sums + lane}, 0, 0};
-  RepAcc B{sums + 4 * kWaveQ + lane};
+  RepAcc B{{0.0, 0.0, 0.0, 0.0}};
   const PairRep& rp = ar.rep;
   // Rows are chosen and trimmed in the target's cell-relative FP32
   // coordinates.  The gaps are shrunk and the reach grown by margins (1e-5 of
