@@ -29,6 +29,35 @@ __device__ __forceinline__ int wrapi(int a, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Exclusive scan of one value per thread over a block of T threads (a
+// multiple of 64); ws holds T / 64 ints.
+template <int T>
+__device__ __forceinline__ int block_scan_excl(int v, int* ws, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) ws[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    int t = lane < T / 64 ? ws[lane] : 0;
+#pragma unroll
+    for (int off = 1; off < T / 64; off <<= 1) {
+      const int y = __shfl_up(t, off);
+      if (lane >= off) t += y;
+    }
+    if (lane < T / 64) ws[lane] = t;
+  }
+  __syncthreads();
+  total = ws[T / 64 - 1];
+  const int before = w > 0 ? ws[w - 1] : 0;
+  __syncthreads();
+  return before + x - v;
+}
+
 // a mod n for a in [-n, 2n): one conditional add or subtract, no division
 __device__ __forceinline__ int wrap_near(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 

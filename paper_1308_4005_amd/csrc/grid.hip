@@ -62,6 +62,7 @@ struct AnterpAtomic {
 // owned points into an LDS tile, and stores the tile without global atomics.
 constexpr int kAntTile = 16;     // max owned points per dimension
 constexpr int kAntThreads = 256;
+static_assert(kAntTileRows == kAntThreads, "one cell row per thread in the run scan");
 constexpr int kMaxSeg = 1024;
 constexpr int kAntScan = kMaxSeg / kAntThreads;   // scan slots per thread
 
@@ -232,6 +233,7 @@ struct AnterpTile {
     __shared__ double tile[CAP];
     __shared__ int seg_begin[kAntTileRows];
     __shared__ int seg_off[kAntTileRows + 1];
+    __shared__ int scan_ws[kAntThreads / 64];
     const AntTiles& T = a.t;
     const int* __restrict__ tab = a.tab;
     const CellGeom& cg = a.cg;
@@ -259,18 +261,12 @@ struct AnterpTile {
       len_r = a.cstart[row + c1[0]] - a0;
     }
     // exclusive scan of the run lengths (one run per thread)
-    seg_off[threadIdx.x] = len_r;
-    __syncthreads();
-    for (int off = 1; off < kAntThreads; off <<= 1) {
-      const int u = (int)threadIdx.x >= off ? seg_off[threadIdx.x - off] : 0;
-      __syncthreads();
-      seg_off[threadIdx.x] += u;
-      __syncthreads();
+    {
+      int all = 0;
+      const int ex = block_scan_excl<kAntThreads>(len_r, scan_ws, all);
+      seg_off[threadIdx.x] = ex;
+      if (threadIdx.x == kAntThreads - 1) seg_off[kAntThreads] = all;
     }
-    const int incl = seg_off[threadIdx.x];
-    __syncthreads();
-    seg_off[threadIdx.x + 1] = incl;
-    if (threadIdx.x == 0) seg_off[0] = 0;
     __syncthreads();
     const int tot = seg_off[nrows];
     // atoms far apart in the list go to the 64 lanes of a wave (their LDS
@@ -782,6 +778,7 @@ struct InterpTile {
     __shared__ double tile[CAP];
     __shared__ int seg_begin[kAntTileRows];
     __shared__ int seg_off[kAntTileRows + 1];
+    __shared__ int scan_ws[kAntThreads / 64];
     const InterpArgs& a = ta.a;
     const AntTiles& T = ta.t;
     const int* __restrict__ tab = ta.tab;
@@ -827,18 +824,12 @@ struct InterpTile {
       seg_begin[threadIdx.x] = a0;
       len_r = ta.cstart[row + c1[0]] - a0;
     }
-    seg_off[threadIdx.x] = len_r;
-    __syncthreads();
-    for (int off = 1; off < kAntThreads; off <<= 1) {
-      const int u = (int)threadIdx.x >= off ? seg_off[threadIdx.x - off] : 0;
-      __syncthreads();
-      seg_off[threadIdx.x] += u;
-      __syncthreads();
+    {
+      int all = 0;
+      const int ex = block_scan_excl<kAntThreads>(len_r, scan_ws, all);
+      seg_off[threadIdx.x] = ex;
+      if (threadIdx.x == kAntThreads - 1) seg_off[kAntThreads] = all;
     }
-    const int incl = seg_off[threadIdx.x];
-    __syncthreads();
-    seg_off[threadIdx.x + 1] = incl;
-    if (threadIdx.x == 0) seg_off[0] = 0;
     __syncthreads();
     const int tot = seg_off[nrows];
     const int pitch_y = len[0], pitch_z = len[0] * len[1];
