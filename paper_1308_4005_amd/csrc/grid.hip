@@ -429,10 +429,13 @@ __device__ __forceinline__ void prolong_at(const TransferArgs& a, int M) {
     double acc[2][2][2];   // [z parity][y parity][x parity]
 #pragma unroll
     for (int q = 0; q < 2; ++q) acc[1][0][q] = acc[1][1][q] = acc[0][0][q] = acc[0][1][q] = 0.0;
-    // ROLL: the z planes in a loop that is not unrolled (p = 4: 56 instead of
-    // 190 VGPRs, more waves but fewer loads in flight per thread, faster in
-    // the batched form, slower on a single plan's finest level; p = 6: 70
-    // instead of 448), the plane's weight and index rotated into slot 0
+    // The z planes run in a loop, the plane's weight and index rotated into
+    // slot 0.  ROLL: not unrolled (p = 4: 56 VGPRs, the batched form; p = 6:
+    // 70 instead of 448).  Otherwise two planes per iteration (p = 4: 96
+    // VGPRs, five waves per SIMD, 32 loads in flight per thread): the finest
+    // level of a 10^6-atom plan, 2744 waves, then fits the chip in one round,
+    // where all four planes unrolled (188 VGPRs, two waves per SIMD) took 1.3
+    // rounds (prolongation stage 0.036 -> 0.035 ms)
     double wz[P];
     int izr[P];
 #pragma unroll
@@ -440,7 +443,7 @@ __device__ __forceinline__ void prolong_at(const TransferArgs& a, int M) {
       wz[t] = w[t];
       izr[t] = iz[t];
     }
-    constexpr int kUnrollZ = ROLL ? 1 : P;
+    constexpr int kUnrollZ = ROLL ? 1 : 2;
 #pragma unroll kUnrollZ
     for (int tz = 0; tz < P; ++tz) {
       double ye[2] = {0.0, 0.0}, yo[2] = {0.0, 0.0};   // y even / odd, [x parity]
