@@ -805,8 +805,12 @@ struct PairTrimF32 {
         k0 = cstart[row + lo2];
         k1 = cstart[row + hi2 + 1];
       }
-      pair_scan_f32<K, R, LB>(j0, j1, ix1, dy, dz, queue, lane, L, xr, xf, xfs, xif, sig, pc, A, rp, B);
-      pair_scan_f32<K, R, LB>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xf, xfs, xif, sig, pc, A, rp, B);
+      // the second run (across the periodic edge) is empty for most waves:
+      // its set-up is skipped unless some lane has one
+      if (__any(j0 < j1))
+        pair_scan_f32<K, R, LB>(j0, j1, ix1, dy, dz, queue, lane, L, xr, xf, xfs, xif, sig, pc, A, rp, B);
+      if (__any(k0 < k1))
+        pair_scan_f32<K, R, LB>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xf, xfs, xif, sig, pc, A, rp, B);
     }
   }
   pair_drain_f32<K, R, LB>(queue, kQueueF, lane, L, xr, xif, sig, pc, A, rp, B);
