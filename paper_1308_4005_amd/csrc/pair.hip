@@ -678,7 +678,7 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
                                               int lane, const PairLaneF& L, const float4* __restrict__ xr,
                                               const float* __restrict__ xf, int xfs, const float* __restrict__ xif,
                                               const float* __restrict__ sig, const PairConstF& pc, PairAccM& A,
-                                              const PairRep& rp, RepAcc& B) {
+                                              const PairRep& rp, RepAcc& B, float4& X, float4& Y, float4& Z) {
   static_assert(kBatchF == 4, "one 16-byte load per coordinate and batch");
   const float ax = fmaf((float)-ix, pc.L[0], L.xa);
   const float ay = fmaf((float)-dy, pc.w[1], L.yy);
@@ -687,8 +687,8 @@ __device__ __forceinline__ void pair_scan_f32(int j, int j1, int ix, int dy, int
   int* const qlane = queue + lane;
   const float* const xf1 = xf + xfs;
   const float* const xf2 = xf1 + xfs;
-  // loop-carried, so a finished lane keeps stale values; b < rem masks them
-  float4 X = make_float4(0.0f, 0.0f, 0.0f, 0.0f), Y = X, Z = X;
+  // X, Y, Z are the caller's, carried across runs: a finished lane keeps
+  // stale values, which b < rem masks
   // one loop level, the drain inside it: the accumulators change only on the
   // drain path (a loop nest made the compiler copy them every filter step)
   int cnt = A.cnt, head = A.head;
@@ -764,6 +764,8 @@ struct PairTrimF32 {
   // cells): shrinks the gaps and grows the reach
   const float mg = (float)g.margin;
   const int nc0 = g.nc[0], nc1 = g.nc[1], nc2 = g.nc[2];
+  // the candidate registers of the scans, carried from run to run
+  float4 X = make_float4(0.0f, 0.0f, 0.0f, 0.0f), Y = X, Z = X;
   for (int dz = -2; dz <= 2; ++dz) {
     const int uz = cz + dz;
     const int tz = uz < 0 ? uz + nc2 : (uz >= nc2 ? uz - nc2 : uz);
@@ -797,20 +799,20 @@ struct PairTrimF32 {
       ty = ty + 1 == nc1 ? 0 : ty + 1;
       int j0 = 0, j1 = 0;
       if (lo1 <= hi1) {
-        j0 = cstart[row + lo1];
-        j1 = cstart[row + hi1 + 1];
+        j0 = at32(cstart, row + lo1);
+        j1 = at32(cstart, row + hi1 + 1);
       }
       int k0 = 0, k1 = 0;
       if (lo2 <= hi2) {
-        k0 = cstart[row + lo2];
-        k1 = cstart[row + hi2 + 1];
+        k0 = at32(cstart, row + lo2);
+        k1 = at32(cstart, row + hi2 + 1);
       }
       // the second run (across the periodic edge) is empty for most waves:
       // its set-up is skipped unless some lane has one
       if (__any(j0 < j1))
-        pair_scan_f32<K, R, LB>(j0, j1, ix1, dy, dz, queue, lane, L, xr, xf, xfs, xif, sig, pc, A, rp, B);
+        pair_scan_f32<K, R, LB>(j0, j1, ix1, dy, dz, queue, lane, L, xr, xf, xfs, xif, sig, pc, A, rp, B, X, Y, Z);
       if (__any(k0 < k1))
-        pair_scan_f32<K, R, LB>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xf, xfs, xif, sig, pc, A, rp, B);
+        pair_scan_f32<K, R, LB>(k0, k1, ix2, dy, dz, queue, lane, L, xr, xf, xfs, xif, sig, pc, A, rp, B, X, Y, Z);
     }
   }
   pair_drain_f32<K, R, LB>(queue, kQueueF, lane, L, xr, xif, sig, pc, A, rp, B);
